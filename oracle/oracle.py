@@ -1,0 +1,218 @@
+"""ctypes front-end of the plain CPU oracle (``osann_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and
+the benchmark's CPU-baseline leg, never by the product library.  It shares
+no code with the GPU path; it only receives the same numpy input arrays.
+
+Notation (paper): ``K`` vector length, ``G`` number of largest components
+hashed, ``N_C = C(K,G) 2^G`` cones.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "osann_oracle.c")
+_LIB = os.path.join(_HERE, "libosann_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+DTYPES = {np.dtype(np.float32): 0, np.dtype(np.float16): 1, np.dtype(np.uint8): 2}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no fused or re-associated FP arithmetic)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = C.CDLL(_LIB)
+            p = C.c_void_p
+            i64, i32 = C.c_int64, C.c_int
+            L.orc_binom.restype = i64
+            L.orc_binom.argtypes = [i32, i32]
+            L.orc_num_cones.restype = i64
+            L.orc_num_cones.argtypes = [i32, i32]
+            L.orc_rank_order.restype = None
+            L.orc_rank_order.argtypes = [p, i32, p]
+            L.orc_hash.restype = i32
+            L.orc_hash.argtypes = [p, i32, i64, i32, i32, p, p, p]
+            L.orc_bucket.restype = i32
+            L.orc_bucket.argtypes = [p, i64, i64, p, p]
+            L.orc_walk.restype = i64
+            L.orc_walk.argtypes = [p, i32, i32, p, i64]
+            L.orc_probe.restype = i64
+            L.orc_probe.argtypes = [p, i32, i32, p, i64, p, i64, p]
+            L.orc_search.restype = i32
+            L.orc_search.argtypes = [p, i32, i64, i32, i32, p, p, p, i32, i64, i64, p, p, p, p, i32]
+            L.orc_exhaustive.restype = i32
+            L.orc_exhaustive.argtypes = [p, i32, i64, i32, p, i32, i64, p, p, p, p, i32]
+            L.orc_pair_d64.restype = i32
+            L.orc_pair_d64.argtypes = [p, i32, i32, p, i32, p, i64, p]
+            L.orc_pair_d32.restype = i32
+            L.orc_pair_d32.argtypes = [p, i32, i32, p, i32, p, i64, p]
+            _lib = L
+    return _lib
+
+
+def _arr(a, dtype=None):
+    a = np.ascontiguousarray(a if dtype is None else np.asarray(a, dtype=dtype))
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _rows(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype not in DTYPES:
+        raise TypeError(f"oracle rows must be float32, float16 or uint8, not {a.dtype}")
+    if a.ndim != 2:
+        raise ValueError("oracle rows must be 2-D")
+    return a, a.ctypes.data_as(C.c_void_p), DTYPES[a.dtype]
+
+
+def binom(n: int, k: int) -> int:
+    return int(lib().orc_binom(n, k))
+
+
+def num_cones(K: int, G: int) -> int:
+    """N_C = C(K,G) 2^G (Section 2, Table I)."""
+    return int(lib().orc_num_cones(K, G))
+
+
+def rank_order(v) -> np.ndarray:
+    """Indices of ``v`` by decreasing magnitude, ties to the lower index."""
+    v, pv = _arr(v, np.float32)
+    out = np.empty(v.shape[0], dtype=np.int32)
+    lib().orc_rank_order(pv, v.shape[0], out.ctypes.data_as(C.c_void_p))
+    return out
+
+
+def hash_rows(X, G: int):
+    """Per row: top-G indices (decreasing magnitude), their sign bits, cone id."""
+    X, px, dt = _rows(X)
+    N, K = X.shape
+    top = np.empty((N, G), dtype=np.int32)
+    sg = np.empty((N, G), dtype=np.uint8)
+    cone = np.empty(N, dtype=np.int64)
+    rc = lib().orc_hash(px, dt, N, K, G, top.ctypes.data_as(C.c_void_p),
+                        sg.ctypes.data_as(C.c_void_p), cone.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise ValueError(f"orc_hash failed ({rc})")
+    return top, sg, cone
+
+
+def bucket(cone, n_cones: int):
+    """Stable counting sort by cone: ``(offsets[N_C+1], perm[N])``."""
+    cone, pc = _arr(cone, np.int64)
+    off = np.empty(n_cones + 1, dtype=np.int64)
+    perm = np.empty(cone.shape[0], dtype=np.int64)
+    rc = lib().orc_bucket(pc, cone.shape[0], n_cones, off.ctypes.data_as(C.c_void_p),
+                          perm.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise ValueError(f"orc_bucket failed ({rc})")
+    return off, perm
+
+
+def build_index(X, G: int):
+    """Hash + bucket: dict with top, sign, cone, offsets, perm, n_cones."""
+    K = X.shape[1]
+    nc = num_cones(K, G)
+    top, sg, cone = hash_rows(X, G)
+    off, perm = bucket(cone, nc)
+    return {"top": top, "sign": sg, "cone": cone, "offsets": off, "perm": perm,
+            "n_cones": nc, "K": K, "G": G}
+
+
+def walk(y, G: int) -> np.ndarray:
+    """All N_C cones of one query, in probe order (empty ones included)."""
+    y, py = _arr(y, np.float32)
+    K = y.shape[0]
+    nc = num_cones(K, G)
+    out = np.empty(nc, dtype=np.int64)
+    n = lib().orc_walk(py, K, G, out.ctypes.data_as(C.c_void_p), nc)
+    assert n == nc, (n, nc)
+    return out
+
+
+def probe(y, G: int, offsets, B: int):
+    """Non-empty cones probed within budget ``B`` and the candidate count."""
+    y, py = _arr(y, np.float32)
+    off, po = _arr(offsets, np.int64)
+    K = y.shape[0]
+    nc = off.shape[0] - 1
+    out = np.empty(nc, dtype=np.int64)
+    nca = np.zeros(1, dtype=np.int64)
+    n = lib().orc_probe(py, K, G, po, int(B), out.ctypes.data_as(C.c_void_p), nc,
+                        nca.ctypes.data_as(C.c_void_p))
+    return out[:n].copy(), int(nca[0])
+
+
+def search(X, index, Y, B: int, nthreads: int = 0):
+    """Algorithm 1 with one basis: ``(idx, d32, d64, ncand)`` per query."""
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    N, K = X.shape
+    Q = Y.shape[0]
+    off, po = _arr(index["offsets"], np.int64)
+    perm, pp = _arr(index["perm"], np.int64)
+    idx = np.empty(Q, dtype=np.int64)
+    d32 = np.empty(Q, dtype=np.float32)
+    d64 = np.empty(Q, dtype=np.float64)
+    nca = np.empty(Q, dtype=np.int64)
+    rc = lib().orc_search(px, xdt, N, K, index["G"], po, pp, py, ydt, Q, int(B),
+                          idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
+                          d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
+                          int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_search failed ({rc})")
+    return idx, d32, d64, nca
+
+
+def exhaustive(X, Y, nthreads: int = 0):
+    """Exact NN (eq. (1)): ``(idx32, d32, idx64, d64)`` per query."""
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    N, K = X.shape
+    Q = Y.shape[0]
+    i32 = np.empty(Q, dtype=np.int64)
+    d32 = np.empty(Q, dtype=np.float32)
+    i64 = np.empty(Q, dtype=np.int64)
+    d64 = np.empty(Q, dtype=np.float64)
+    lib().orc_exhaustive(px, xdt, N, K, py, ydt, Q, i32.ctypes.data_as(C.c_void_p),
+                         d32.ctypes.data_as(C.c_void_p), i64.ctypes.data_as(C.c_void_p),
+                         d64.ctypes.data_as(C.c_void_p), int(nthreads))
+    return i32, d32, i64, d64
+
+
+def pair_d64(X, Y, rows) -> np.ndarray:
+    """Double squared distance between query q and row ``rows[q]``."""
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    r, pr = _arr(rows, np.int64)
+    out = np.empty(Y.shape[0], dtype=np.float64)
+    lib().orc_pair_d64(px, xdt, X.shape[1], py, ydt, pr, Y.shape[0], out.ctypes.data_as(C.c_void_p))
+    return out
+
+
+def pair_d32(X, Y, rows) -> np.ndarray:
+    """FP32 squared distance (term by term, i ascending) of (q, rows[q])."""
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    r, pr = _arr(rows, np.int64)
+    out = np.empty(Y.shape[0], dtype=np.float32)
+    lib().orc_pair_d32(px, xdt, X.shape[1], py, ydt, pr, Y.shape[0], out.ctypes.data_as(C.c_void_p))
+    return out

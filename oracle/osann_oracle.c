@@ -1,0 +1,491 @@
+/*
+ * Plain CPU oracle for the order-statistics approximate nearest-neighbour
+ * search of Verdoliva, Cozzolino and Poggi (arXiv 1509.03453, "ROSANNA").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code, header,
+ * table or helper with the GPU library; the product path never calls it.
+ *
+ * It is written for a reader checking it against the paper by eye: plain
+ * loops, no blocking, no reordering of any sum.  Notation follows the paper:
+ *   K    vector length                                  (Table I)
+ *   G    number of largest-magnitude components hashed (Table I)
+ *   N_C  number of cones, C(K,G) * 2^G                  (Section 2, Table I)
+ * Indices are 0-based here; the paper counts from 1.
+ *
+ * Readings taken where the paper is silent (each one is pinned or listed as
+ * unpinned by the test-suite):
+ *   R1  equal magnitudes: the lower component index ranks first.
+ *   R2  the sign bit of a component is 1 unless the value is < 0, so zero and
+ *       negative zero count as non-negative (Fig. 2 caption: c=0 holds the
+ *       negative values, c=1 "the others").
+ *   R3  cone id = colex rank of the profile (the G indices in ascending order)
+ *       times 2^G, plus the sign bits with the lowest index as most
+ *       significant bit (Fig. 2, right table).
+ *   R4  probe order (Section 3.B): L-subsets T of query rank positions in
+ *       lexicographic order with the query's own signs (phase A), then the
+ *       same subsets with h = 1..G signs flipped (phase B).  Lexicographic
+ *       order on T is non-decreasing in the paper's profile distance.
+ *   R5  the search budget B is met with whole cones: probing stops after the
+ *       first cone at which the running candidate count reaches B.
+ *   R6  arg-min over (FP32 distance, original row) in lexicographic order.
+ *
+ * Precision: distances are produced both in double (the definition, eq. (1))
+ * and in FP32 evaluated term by term in ascending component order with each
+ * subtraction, product and sum rounded separately (the precision in which the
+ * arg-min decision is taken).  Built with -ffp-contract=off and without
+ * -ffast-math so that no operation is fused or re-associated.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORC_F32 = 0, ORC_F16 = 1, ORC_U8 = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* Scalars                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* IEEE 754 binary16 -> binary32, exact (every half is a float). */
+static float half_to_float(uint16_t h)
+{
+    int s = (h >> 15) & 1;
+    int e = (h >> 10) & 0x1f;
+    int m = h & 0x3ff;
+    float v;
+    if (e == 0)
+        v = ldexpf((float)m, -24);              /* zero and subnormals      */
+    else if (e == 31)
+        v = m ? NAN : INFINITY;
+    else
+        v = ldexpf((float)(m | 0x400), e - 25); /* (1 + m/1024) 2^(e-15)    */
+    return s ? -v : v;
+}
+
+/* Component i of row n, converted exactly to float. */
+static float elem(const void *X, int dtype, int64_t n, int K, int i)
+{
+    int64_t at = n * (int64_t)K + i;
+    if (dtype == ORC_F16)
+        return half_to_float(((const uint16_t *)X)[at]);
+    if (dtype == ORC_U8)
+        return (float)((const uint8_t *)X)[at];
+    return ((const float *)X)[at];
+}
+
+static void load_row(const void *X, int dtype, int64_t n, int K, float *out)
+{
+    for (int i = 0; i < K; i++)
+        out[i] = elem(X, dtype, n, K, i);
+}
+
+/* Binomial coefficient C(n,k); 0 when k > n or n < 0. */
+int64_t orc_binom(int n, int k)
+{
+    if (k < 0 || n < 0 || k > n)
+        return 0;
+    int64_t c = 1;
+    for (int t = 0; t < k; t++)
+        c = c * (n - t) / (t + 1);
+    return c;
+}
+
+/* Section 2, Table I: N_C = C(K,G) 2^G. */
+int64_t orc_num_cones(int K, int G)
+{
+    return orc_binom(K, G) << G;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hashing (Section 2, eq. (2), Fig. 2)                                      */
+/* ------------------------------------------------------------------------ */
+
+/* True when component i comes before component j in decreasing-magnitude
+ * order (reading R1 breaks ties by the lower index). */
+static int mag_before(const float *v, int i, int j)
+{
+    float ai = fabsf(v[i]), aj = fabsf(v[j]);
+    if (ai != aj)
+        return ai > aj;
+    return i < j;
+}
+
+/* Full decreasing-magnitude order of one vector: order[0] is the index of
+ * the largest |v_i|.  Insertion sort, K <= 256. */
+void orc_rank_order(const float *v, int K, int32_t *order)
+{
+    for (int i = 0; i < K; i++) {
+        int at = i;
+        while (at > 0 && mag_before(v, i, order[at - 1])) {
+            order[at] = order[at - 1];
+            at--;
+        }
+        order[at] = i;
+    }
+}
+
+/* Sign bit of a component under reading R2. */
+static int sign_bit(float x)
+{
+    return x < 0.0f ? 0 : 1;
+}
+
+/* Cone id of a profile given as G distinct component indices (any order)
+ * with one sign bit each (reading R3): the indices are sorted ascending,
+ * p_1 < ... < p_G, the profile's colex rank is sum_j C(p_j, j), and the sign
+ * bits follow in ascending index order, most significant first. */
+static int64_t cone_id(const int32_t *idx, const int *sgn, int G)
+{
+    int32_t p[256];
+    int s[256];
+    for (int j = 0; j < G; j++) {
+        p[j] = idx[j];
+        s[j] = sgn[j];
+    }
+    for (int a = 1; a < G; a++)          /* insertion sort, carrying signs */
+        for (int b = a; b > 0 && p[b - 1] > p[b]; b--) {
+            int32_t tp = p[b]; p[b] = p[b - 1]; p[b - 1] = tp;
+            int ts = s[b]; s[b] = s[b - 1]; s[b - 1] = ts;
+        }
+    int64_t rank = 0;
+    for (int j = 0; j < G; j++)
+        rank += orc_binom(p[j], j + 1);
+    int64_t bits = 0;
+    for (int j = 0; j < G; j++)
+        bits = (bits << 1) | s[j];
+    return (rank << G) | bits;
+}
+
+/* Hash every row: the G largest-magnitude components in decreasing order
+ * (top_idx[n*G + j]), their sign bits (top_sign) and the row's cone id. */
+int orc_hash(const void *X, int dtype, int64_t N, int K, int G,
+             int32_t *top_idx, uint8_t *top_sign, int64_t *cone)
+{
+    if (K < 1 || K > 256 || G < 1 || G > K)
+        return -1;
+    for (int64_t n = 0; n < N; n++) {
+        float v[256];
+        int32_t order[256];
+        int s[256];
+        load_row(X, dtype, n, K, v);
+        orc_rank_order(v, K, order);
+        for (int j = 0; j < G; j++) {
+            s[j] = sign_bit(v[order[j]]);
+            if (top_idx)
+                top_idx[n * G + j] = order[j];
+            if (top_sign)
+                top_sign[n * G + j] = (uint8_t)s[j];
+        }
+        cone[n] = cone_id(order, s, G);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bucketing: one hash table, rows grouped by cone (Section 4)               */
+/* ------------------------------------------------------------------------ */
+
+/* Counting sort of row ids by cone, stable (rows of one cone stay in
+ * ascending original order).  offsets has NC+1 entries; bucket c occupies
+ * perm[offsets[c] .. offsets[c+1]). */
+int orc_bucket(const int64_t *cone, int64_t N, int64_t NC, int64_t *offsets, int64_t *perm)
+{
+    for (int64_t c = 0; c <= NC; c++)
+        offsets[c] = 0;
+    for (int64_t n = 0; n < N; n++) {
+        if (cone[n] < 0 || cone[n] >= NC)
+            return -1;
+        offsets[cone[n] + 1]++;
+    }
+    for (int64_t c = 0; c < NC; c++)
+        offsets[c + 1] += offsets[c];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(NC > 0 ? NC : 1));
+    if (!fill)
+        return -2;
+    for (int64_t c = 0; c < NC; c++)
+        fill[c] = offsets[c];
+    for (int64_t n = 0; n < N; n++)
+        perm[fill[cone[n]]++] = n;
+    free(fill);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Probe order (Section 3.B, Algorithm 1)                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Lexicographic successor of a G-subset t[0] < ... < t[G-1] of {0..K-1};
+ * returns 0 when t was the last one. */
+static int lex_next(int32_t *t, int K, int G)
+{
+    int j = G - 1;
+    while (j >= 0 && t[j] == K - G + j)
+        j--;
+    if (j < 0)
+        return 0;
+    t[j]++;
+    for (int a = j + 1; a < G; a++)
+        t[a] = t[a - 1] + 1;
+    return 1;
+}
+
+static int popcount_int(int m)
+{
+    int c = 0;
+    while (m) {
+        c += m & 1;
+        m >>= 1;
+    }
+    return c;
+}
+
+/* Walks the cones of one query in probe order and calls visit(cone) for each
+ * one; stops early when visit returns nonzero.  Phase A: subsets T of query
+ * rank positions in lexicographic order, profile {order[t_j]}, the query's
+ * own signs.  Phase B: h = 1..G flipped signs; for each T in lexicographic
+ * order, flip masks of popcount h in ascending value, mask bit (G-1-j)
+ * flipping the sign of component order[t_j].  Phase A alone covers each
+ * profile once; A and B together cover all N_C cones once. */
+typedef int (*visit_fn)(int64_t cone, void *ctx);
+
+static void walk_cones(const float *y, int K, int G, visit_fn visit, void *ctx)
+{
+    int32_t order[256], t[256], idx[256];
+    int s[256];
+    orc_rank_order(y, K, order);
+    for (int h = 0; h <= G; h++) {
+        for (int j = 0; j < G; j++)
+            t[j] = j;
+        do {
+            for (int mask = 0; mask < (1 << G); mask++) {
+                if (popcount_int(mask) != h)
+                    continue;
+                for (int j = 0; j < G; j++) {
+                    idx[j] = order[t[j]];
+                    s[j] = sign_bit(y[idx[j]]) ^ ((mask >> (G - 1 - j)) & 1);
+                }
+                if (visit(cone_id(idx, s, G), ctx))
+                    return;
+            }
+        } while (lex_next(t, K, G));
+    }
+}
+
+struct collect_ctx {
+    int64_t *out;
+    int64_t cap, n;
+};
+
+static int collect_all(int64_t cone, void *vctx)
+{
+    struct collect_ctx *c = (struct collect_ctx *)vctx;
+    if (c->n < c->cap)
+        c->out[c->n] = cone;
+    c->n++;
+    return 0;
+}
+
+/* Every cone in the query's probe order, empty or not (N_C entries). */
+int64_t orc_walk(const float *y, int K, int G, int64_t *cones, int64_t cap)
+{
+    struct collect_ctx c = { cones, cap, 0 };
+    walk_cones(y, K, G, collect_all, &c);
+    return c.n;
+}
+
+struct budget_ctx {
+    const int64_t *offsets;
+    int64_t B, cum;
+    int64_t *probes;
+    int64_t cap, n;
+};
+
+/* Reading R5: empty cones are skipped; whole cones are added until the
+ * running count of candidates reaches B. */
+static int take_until_budget(int64_t cone, void *vctx)
+{
+    struct budget_ctx *c = (struct budget_ctx *)vctx;
+    int64_t size = c->offsets[cone + 1] - c->offsets[cone];
+    if (size == 0)
+        return 0;
+    if (c->n < c->cap)
+        c->probes[c->n] = cone;
+    c->n++;
+    c->cum += size;
+    return c->cum >= c->B;
+}
+
+/* Probe list of one query: the non-empty cones visited within budget B, in
+ * order.  Returns the number of probes (entries beyond cap are counted but
+ * not stored); *ncand receives the number of candidates they hold. */
+int64_t orc_probe(const float *y, int K, int G, const int64_t *offsets, int64_t B,
+                  int64_t *probes, int64_t cap, int64_t *ncand)
+{
+    struct budget_ctx c = { offsets, B, 0, probes, cap, 0 };
+    walk_cones(y, K, G, take_until_budget, &c);
+    *ncand = c.cum;
+    return c.n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Distance and arg-min (eq. (1), Algorithm 1)                               */
+/* ------------------------------------------------------------------------ */
+
+/* Squared Euclidean distance: in FP32 term by term (i ascending, each
+ * operation rounded) and in double. */
+static void dist2(const float *x, const float *y, int K, float *d32, double *d64)
+{
+    float acc = 0.0f;
+    double acc64 = 0.0;
+    for (int i = 0; i < K; i++) {
+        float diff = x[i] - y[i];
+        float sq = diff * diff;
+        acc = acc + sq;
+        double e = (double)x[i] - (double)y[i];
+        acc64 += e * e;
+    }
+    *d32 = acc;
+    *d64 = acc64;
+}
+
+/* Keeps the smaller of (d, row) pairs in lexicographic order (reading R6). */
+static void argmin_update(float d, int64_t row, float *best_d, int64_t *best_row)
+{
+    if (d < *best_d || (d == *best_d && row < *best_row)) {
+        *best_d = d;
+        *best_row = row;
+    }
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+/* Approximate NN search with one basis (Algorithm 1 with R = 1): the query's
+ * cones are probed in order until B candidates are reached, and every row
+ * of those cones is compared with the query.  Outputs per query: the row
+ * (out_idx), its FP32 and double distances, and the number of candidates. */
+int orc_search(const void *X, int xdtype, int64_t N, int K, int G,
+               const int64_t *offsets, const int64_t *perm,
+               const void *Y, int ydtype, int64_t Q, int64_t B,
+               int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
+               int nthreads)
+{
+    (void)N;
+    if (K < 1 || K > 256 || G < 1 || G > K || B < 1)
+        return -1;
+    int64_t NC = orc_num_cones(K, G);
+    set_threads(nthreads);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < Q; q++) {
+        float y[256], x[256];
+        load_row(Y, ydtype, q, K, y);
+        int64_t *probes = (int64_t *)malloc(sizeof(int64_t) * (size_t)NC);
+        if (!probes) {
+#pragma omp atomic write
+            bad = 1;
+            continue;
+        }
+        int64_t ncand = 0;
+        int64_t np = orc_probe(y, K, G, offsets, B, probes, NC, &ncand);
+        float best_d = INFINITY;
+        int64_t best_row = INT64_MAX;
+        double best_d64 = INFINITY;
+        for (int64_t k = 0; k < np; k++) {
+            int64_t c = probes[k];
+            for (int64_t pos = offsets[c]; pos < offsets[c + 1]; pos++) {
+                int64_t row = perm[pos];
+                float d32;
+                double d64;
+                load_row(X, xdtype, row, K, x);
+                dist2(x, y, K, &d32, &d64);
+                int64_t before = best_row;
+                argmin_update(d32, row, &best_d, &best_row);
+                if (best_row != before)
+                    best_d64 = d64;
+            }
+        }
+        out_idx[q] = best_row;
+        out_d32[q] = best_d;
+        out_d64[q] = best_d64;
+        out_ncand[q] = ncand;
+        free(probes);
+    }
+    return bad ? -2 : 0;
+}
+
+/* Exact NN by linear search over all rows (eq. (1)).  idx32/d32 take the
+ * arg-min decision on FP32 distances; idx64/d64 on double distances (ground
+ * truth for recall: a result is right when its double distance equals d64). */
+int orc_exhaustive(const void *X, int xdtype, int64_t N, int K,
+                   const void *Y, int ydtype, int64_t Q,
+                   int64_t *idx32, float *d32_out, int64_t *idx64, double *d64_out,
+                   int nthreads)
+{
+    if (K < 1 || K > 256)
+        return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < Q; q++) {
+        float y[256], x[256];
+        load_row(Y, ydtype, q, K, y);
+        float b32 = INFINITY;
+        int64_t r32 = INT64_MAX, r64 = INT64_MAX;
+        double b64 = INFINITY;
+        for (int64_t n = 0; n < N; n++) {
+            float d32;
+            double d64;
+            load_row(X, xdtype, n, K, x);
+            dist2(x, y, K, &d32, &d64);
+            argmin_update(d32, n, &b32, &r32);
+            if (d64 < b64 || (d64 == b64 && n < r64)) {
+                b64 = d64;
+                r64 = n;
+            }
+        }
+        idx32[q] = r32;
+        d32_out[q] = b32;
+        idx64[q] = r64;
+        d64_out[q] = b64;
+    }
+    return 0;
+}
+
+/* Double distance of given (query, row) pairs; used to score recall. */
+int orc_pair_d64(const void *X, int xdtype, int K, const void *Y, int ydtype,
+                 const int64_t *rows, int64_t Q, double *out)
+{
+    for (int64_t q = 0; q < Q; q++) {
+        float y[256], x[256];
+        float d32;
+        load_row(Y, ydtype, q, K, y);
+        load_row(X, xdtype, rows[q], K, x);
+        dist2(x, y, K, &d32, &out[q]);
+    }
+    return 0;
+}
+
+/* FP32 distance of given (query, row) pairs, same evaluation as the search. */
+int orc_pair_d32(const void *X, int xdtype, int K, const void *Y, int ydtype,
+                 const int64_t *rows, int64_t Q, float *out)
+{
+    for (int64_t q = 0; q < Q; q++) {
+        float y[256], x[256];
+        double d64;
+        load_row(Y, ydtype, q, K, y);
+        load_row(X, xdtype, rows[q], K, x);
+        dist2(x, y, K, &out[q], &d64);
+    }
+    return 0;
+}
