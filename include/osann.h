@@ -1,0 +1,207 @@
+/*
+ * osann.h -- C ABI of the MI355X (gfx950) order-statistics approximate
+ * nearest-neighbour search library (libosann.so).
+ *
+ * The method is that of Verdoliva, Cozzolino and Poggi, "A reliable
+ * order-statistics-based approximate nearest neighbor search algorithm"
+ * (arXiv 1509.03453, ROSANNA), with one basis (the original coordinates):
+ *
+ *   problem     (Section 2, eq. (1)) given N database vectors x_n in R^D
+ *               and a query y, find argmin_n ||x_n - y||^2;
+ *   hashing     (Section 2, eq. (2), Fig. 2) every vector is classified by
+ *               the indices of its L largest-magnitude components (its
+ *               profile) and the signs of those components (its cone);
+ *               there are N_C = C(D,L) * 2^L cones;
+ *   index       (Section 4) the database is bucketed by cone;
+ *   search      (Algorithm 1, Section 3.B) the query's own cone is scanned
+ *               first, then neighbouring cones in order of the paper's
+ *               profile distance, with exact Euclidean distances and a
+ *               running arg-min.
+ *
+ * The paper's K (vector length) is D here and its G (number of components
+ * hashed) is L.
+ *
+ * Conventions shared by every call:
+ *   - Array pointers are HIP device pointers on the current device unless a
+ *     comment says otherwise (e.g. torch.Tensor.data_ptr() of a CUDA tensor).
+ *   - `stream` arguments are hipStream_t passed as void*; NULL is the null
+ *     stream.
+ *   - Calls returning int give OS_ANN_OK (0) or a negative code below;
+ *     calls returning a pointer give NULL on error.  In both cases
+ *     os_ann_last_error() / os_ann_last_error_message() describe the last
+ *     failure of the calling thread.
+ *   - Keys follow these rules: equal magnitudes rank the lower component
+ *     index first; a component's sign bit is 1 unless its value is < 0
+ *     (zero and -0.0 are non-negative, Fig. 2 caption); the cone id is
+ *     colex_rank(profile indices ascending) * 2^L + sign bits, lowest index
+ *     most significant (Fig. 2, right table).
+ *   - Distances are squared Euclidean in FP32, evaluated term by term in
+ *     ascending component order with each subtraction, product and sum
+ *     rounded separately; ties in distance go to the lower original row.
+ */
+#ifndef OSANN_H
+#define OSANN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define OS_ANN_OK          0
+#define OS_ANN_EINVAL     -1  /* null pointer; N < 1 or N >= 2^31; D < 1 or D > 256;
+                                 L < 1 or L > min(D, 7); max_candidates < 1; Q < 0;
+                                 bad dtype or mode; workspace too small */
+#define OS_ANN_ENOMEM     -2  /* device allocation failed */
+#define OS_ANN_EDEVICE    -3  /* a HIP runtime call or kernel launch failed */
+#define OS_ANN_ENOTSUP    -4  /* N_C = C(D,L) * 2^L above 2^24 */
+#define OS_ANN_ENONFINITE -5  /* NaN or infinity in the database (build only) */
+
+/* Storage types of database rows and queries. */
+#define OS_ANN_F32 0
+#define OS_ANN_F16 1
+#define OS_ANN_U8  2
+
+/* Search modes. */
+#define OS_ANN_MODE_FP32   0  /* exact FP32 scan of every candidate */
+#define OS_ANN_MODE_TILED  1  /* BF16/FP16 matrix-core screening + FP32 re-rank */
+
+/* Search flags. */
+#define OS_ANN_FLAG_TIME_KERNELS 1  /* record HIP events around each kernel launch */
+
+/* Kernel ids of os_ann_kernel_time. */
+#define OS_ANN_KERNEL_PROBE 0  /* query classification + probe list */
+#define OS_ANN_KERNEL_SCAN  1  /* FP32 candidate scan + arg-min */
+#define OS_ANN_KERNEL_COUNT 2
+
+typedef struct os_ann_index os_ann_index;
+
+typedef struct os_ann_build_opts {
+    int32_t dtype;      /* OS_ANN_F32 / OS_ANN_F16 / OS_ANN_U8 storage of db rows */
+    int32_t want_lowp;  /* nonzero: also keep the BF16/FP16 copy used by
+                           OS_ANN_MODE_TILED (built on first tiled search otherwise) */
+    void *stream;       /* stream the build runs on (NULL = null stream) */
+} os_ann_build_opts;
+
+typedef struct os_ann_search_opts {
+    int32_t mode;         /* OS_ANN_MODE_FP32 or OS_ANN_MODE_TILED */
+    int32_t rerank_r;     /* tiled mode: survivors re-ranked in FP32 (1..32, default 8) */
+    int32_t query_dtype;  /* OS_ANN_F32 / OS_ANN_F16 / OS_ANN_U8 */
+    int32_t flags;        /* OS_ANN_FLAG_* bits */
+    void *stream;         /* stream the search runs on (NULL = null stream) */
+    void *workspace;      /* optional caller-owned device scratch, >= os_ann_workspace_bytes;
+                             NULL: the index's own scratch (not for concurrent calls) */
+    int64_t workspace_bytes;
+} os_ann_search_opts;
+
+/*
+ * Build an index over N FP32 rows of D components (row-major db[N][D]).
+ * Hashes every row (Section 2, eq. (2)), buckets the rows by cone with a
+ * stable sort (rows of one cone keep ascending original order; Section 4)
+ * and keeps a bucket-contiguous, permuted copy of the rows.
+ * Synchronous: returns when the index is ready.  The library copies the
+ * rows, so the caller may free db as soon as the call returns.  The index
+ * owns all its device memory until os_ann_free.
+ * Errors: EINVAL, ENOMEM, EDEVICE, ENOTSUP, ENONFINITE (returns NULL).
+ */
+os_ann_index *os_ann_build(const float *db, int64_t N, int32_t D, int32_t L);
+
+/* As os_ann_build with rows stored as opts->dtype (FP32, FP16 or uint8) and
+ * the build enqueued on opts->stream (still synchronous).  opts may be NULL
+ * (FP32, null stream). */
+os_ann_index *os_ann_build_ex(const void *db, int64_t N, int32_t D, int32_t L,
+                              const os_ann_build_opts *opts);
+
+/*
+ * Approximate NN of Q FP32 queries (row-major queries[Q][D]), Algorithm 1
+ * with one basis: each query's cones are visited in the Section 3.B order
+ * (own cone first; then the other profiles that share the query's signs, in
+ * lexicographic order of the query's rank positions, which is non-decreasing
+ * in the paper's profile distance; then the same profiles with 1..L signs
+ * flipped), skipping empty cones, until the cones visited hold at least
+ * max_candidates rows (whole cones only; every cone when max_candidates >= N).
+ * Every candidate's distance is computed and the arg-min kept.
+ * out_idx[q] in [0, N) is the original row of the nearest candidate and
+ * out_dist[q] its squared distance (FP32).
+ * Asynchronous on the null stream: outputs are valid after the stream
+ * synchronises; the caller owns queries and outputs and keeps them alive
+ * until then.  Q = 0 is a no-op.  Uses the index's own scratch, so two
+ * calls on one index must not overlap (use os_ann_search_ex with distinct
+ * workspaces for concurrent searches).
+ * Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int os_ann_search(const os_ann_index *idx, const float *queries, int64_t Q,
+                  int64_t max_candidates, int64_t *out_idx, float *out_dist);
+
+/* As os_ann_search with options (mode, query dtype, stream, workspace) and
+ * the per-query candidate count out_ncand[Q] (int64, may be NULL).
+ * opts may be NULL (FP32 mode, FP32 queries, null stream). */
+int os_ann_search_ex(const os_ann_index *idx, const void *queries, int64_t Q,
+                     int64_t max_candidates, const os_ann_search_opts *opts,
+                     int64_t *out_idx, float *out_dist, int64_t *out_ncand);
+
+/* Bytes of device scratch a search with these arguments needs (>= 0), or a
+ * negative error code.  Used to size caller-owned workspaces and by
+ * admission control. */
+int64_t os_ann_workspace_bytes(const os_ann_index *idx, int64_t Q, int64_t max_candidates,
+                               const os_ann_search_opts *opts);
+
+/*
+ * Classify Q queries without scanning (Section 2 hashing, Section 3.B
+ * probing): q_cone[Q] (uint32) own cone id, q_top[Q] (uint64) the L largest
+ * components in decreasing magnitude packed as 9-bit pairs (bits 0-7
+ * component index, bit 8 sign bit; pair j at bit 9*j), q_ncand[Q] (int64)
+ * candidates within max_candidates.  Any output may be NULL.  Asynchronous
+ * on `stream`; uses the index's scratch.
+ */
+int os_ann_classify(const os_ann_index *idx, const void *queries, int32_t query_dtype,
+                    int64_t Q, int64_t max_candidates, uint32_t *q_cone, uint64_t *q_top,
+                    int64_t *q_ncand, void *stream);
+
+/*
+ * Copy out the index for inspection: row_cone[N] (uint32) cone of each
+ * original row, row_top[N] (uint64) packed top-L pairs as in
+ * os_ann_classify, offsets[n_cones+1] (int64; bucket c holds sorted
+ * positions offsets[c] .. offsets[c+1]-1, offsets[n_cones] = N), perm[N]
+ * (int64; original row at each sorted position).  Any output may be NULL.
+ * Asynchronous on `stream`.
+ */
+int os_ann_export(const os_ann_index *idx, uint32_t *row_cone, uint64_t *row_top,
+                  int64_t *offsets, int64_t *perm, void *stream);
+
+/* Copy out the permuted rows, converted exactly to FP32: rows[N][D] with
+ * rows[pos] = db[perm[pos]].  Asynchronous on `stream`. */
+int os_ann_export_rows(const os_ann_index *idx, float *rows, void *stream);
+
+/*
+ * Per-kernel device time of the searches made on this index with
+ * OS_ANN_FLAG_TIME_KERNELS: HIP events are recorded on the search's stream
+ * immediately before and after each kernel launch.  Waits for the recorded
+ * events, then returns (host pointers) the number of launches and their
+ * summed duration in milliseconds, and forgets them.  kernel is an
+ * OS_ANN_KERNEL_* id.  Errors: EINVAL, EDEVICE.
+ */
+int os_ann_kernel_time(const os_ann_index *idx, int32_t kernel, int64_t *launches, double *total_ms);
+
+/* Host-side facts about an index (host pointers, any may be NULL):
+ * N, D, L, number of cones, number of non-empty cones, device bytes held. */
+int os_ann_info(const os_ann_index *idx, int64_t *N, int32_t *D, int32_t *L,
+                int64_t *n_cones, int64_t *n_nonempty, int64_t *device_bytes);
+
+/* Release the index.  The caller makes sure no search on it is in flight. */
+void os_ann_free(os_ann_index *idx);
+
+/* Last error code / message of the calling thread (OS_ANN_OK / "" if none). */
+int os_ann_last_error(void);
+const char *os_ann_last_error_message(void);
+
+/* Library version string (host pointer, static storage). */
+const char *os_ann_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OSANN_H */

@@ -1,0 +1,307 @@
+// Bucket build: one cone-bucketed table of the database (Section 4).
+//
+//  * sort_by_cone   stable LSD radix sort of row ids by cone, 8-bit digits.
+//                   Each block owns a contiguous chunk of the input; the rank
+//                   of an element inside its block comes from wave ballots
+//                   (lanes of equal digit below it) plus per-wave counts in
+//                   LDS, in position order, so no atomic ever decides an
+//                   order and rows of one cone keep ascending original ids.
+//  * offsets        bucket starts read off the sorted cones.
+//  * gather_planes  permuted, chunk-major copy of the rows (layout in
+//                   osann_kernels.h), staged through LDS so that both the row
+//                   reads and the plane writes are contiguous.
+//  * probe tables   lexicographic L-subsets and sign-flip masks used by the
+//                   query walk (Section 3.B).
+#include "osann_device.h"
+#include "osann_kernels.h"
+
+namespace osann {
+
+constexpr int kRadixThreads = 256;
+constexpr int kRadixChunk = 2048;  // elements per block (8 tiles of 256)
+
+static inline int64_t radix_blocks(int64_t N) { return (N + kRadixChunk - 1) / kRadixChunk; }
+int64_t radix_hist_words(int64_t N) { return 256 * radix_blocks(N); }
+
+__global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                                   int64_t N, int shift,
+                                                                   uint32_t* __restrict__ hist,
+                                                                   int64_t nb) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixChunk;
+    for (int t = 0; t < kRadixChunk; t += kRadixThreads) {
+        int64_t i = base + t + threadIdx.x;
+        if (i < N) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);  // counts only
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `n` words in place, one block of 1024 threads, each
+// thread owning a contiguous segment.
+__global__ __launch_bounds__(1024) void exclusive_scan_kernel(uint32_t* __restrict__ v, int64_t n) {
+    __shared__ uint32_t part[1024];
+    const int64_t seg = (n + 1023) / 1024;
+    const int64_t b = threadIdx.x * seg, e = b + seg < n ? b + seg : n;
+    uint32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += v[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // Hillis-Steele on the partials
+        uint32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;
+    for (int64_t i = b; i < e; ++i) {
+        uint32_t x = v[i];
+        v[i] = run;
+        run += x;
+    }
+}
+
+__global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, int64_t N, int shift,
+    const uint32_t* __restrict__ hist, int64_t nb, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out) {
+    constexpr int kWaves = kRadixThreads / 64;
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kWaves][256];
+    const int tid = threadIdx.x, w = tid / 64;
+    run[tid] = hist[(int64_t)tid * nb + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kRadixChunk;
+    for (int t = 0; t < kRadixChunk; t += kRadixThreads) {
+#pragma unroll
+        for (int a = 0; a < kWaves; ++a) wcnt[a][tid] = 0;
+        __syncthreads();
+        const int64_t i = base + t + tid;
+        const bool valid = i < N;
+        const uint32_t key = valid ? keys_in[i] : 0u;
+        const uint32_t val = valid ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+        const uint32_t dig = (key >> shift) & 255u;
+        // lanes of this wave holding the same digit
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t ones = __ballot((dig >> b) & 1u);
+            same &= ((dig >> b) & 1u) ? ones : ~ones;
+        }
+        const uint32_t below = (uint32_t)__popcll(same & lanemask_lt());
+        if (valid && below == 0) wcnt[w][dig] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = run[dig] + below;
+            for (int a = 0; a < w; ++a) off += wcnt[a][dig];
+            keys_out[off] = key;
+            vals_out[off] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int a = 0; a < kWaves; ++a) add += wcnt[a][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_cones, uint32_t* tmp,
+                               uint32_t* perm_out, uint32_t* sorted_cone_out, hipStream_t s) {
+    int bits = 1;
+    while ((int64_t(1) << bits) < n_cones) ++bits;
+    const int passes = (bits + 7) / 8;
+    const int64_t nb = radix_blocks(N);
+    uint32_t* ka = tmp;
+    uint32_t* va = tmp + N;
+    uint32_t* kb = tmp + 2 * N;
+    uint32_t* vb = tmp + 3 * N;
+    uint32_t* hist = tmp + 4 * N;
+    const uint32_t* kin = row_cone;
+    const uint32_t* vin = nullptr;  // identity on the first pass
+    for (int p = 0; p < passes; ++p) {
+        const bool last = p == passes - 1;
+        uint32_t* kout = last ? sorted_cone_out : ((p & 1) ? kb : ka);
+        uint32_t* vout = last ? perm_out : ((p & 1) ? vb : va);
+        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin, N,
+                           8 * p, hist, nb);
+        hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(1024), 0, s, hist, 256 * nb);
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin,
+                           vin, N, 8 * p, hist, nb, kout, vout);
+        kin = kout;
+        vin = vout;
+    }
+    return hipGetLastError();
+}
+
+// offsets[c] = first sorted position whose cone is >= c; offsets[NC] = N.
+__global__ void offsets_kernel(const uint32_t* __restrict__ sc, int64_t N, int64_t nc,
+                               uint32_t* __restrict__ off) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > N) return;
+    const int64_t lo = p == 0 ? 0 : (int64_t)sc[p - 1] + 1;
+    const int64_t hi = p == N ? nc : (int64_t)sc[p];
+    for (int64_t c = lo; c <= hi; ++c) off[c] = (uint32_t)p;
+}
+
+hipError_t launch_offsets(const uint32_t* sorted_cone, int64_t N, int64_t n_cones, uint32_t* offsets,
+                          hipStream_t s) {
+    const int64_t n = N + 1;
+    hipLaunchKernelGGL(offsets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sorted_cone,
+                       N, n_cones, offsets);
+    return hipGetLastError();
+}
+
+// 64 sorted positions per block: rows read element-wise (contiguous within a
+// row), parked in LDS as 16-byte chunks, then written plane by plane.
+template <typename E>
+__global__ __launch_bounds__(256) void gather_planes_kernel(const typename E::raw* __restrict__ X,
+                                                            int64_t N, int D, int nch,
+                                                            const uint32_t* __restrict__ perm,
+                                                            uint4* __restrict__ planes) {
+    constexpr int EPC = 16 / E::bytes;  // elements per chunk
+    extern __shared__ uint4 tile[];     // [nch][64]
+    typename E::raw* te = reinterpret_cast<typename E::raw*>(tile);
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const int per_row = nch * EPC;
+    for (int f = threadIdx.x; f < 64 * per_row; f += blockDim.x) {
+        const int r = f / per_row, i = f % per_row;
+        typename E::raw v = 0;
+        if (p0 + r < N && i < D) v = X[(int64_t)perm[p0 + r] * D + i];
+        te[((i / EPC) * 64 + r) * EPC + (i % EPC)] = v;
+    }
+    __syncthreads();
+    for (int f = threadIdx.x; f < nch * 64; f += blockDim.x) {
+        const int k = f / 64, r = f % 64;
+        if (p0 + r < N) planes[(int64_t)k * N + p0 + r] = tile[k * 64 + r];
+    }
+}
+
+hipError_t launch_gather_planes(const void* X, int dtype, int64_t N, int D, const uint32_t* perm,
+                                void* planes, hipStream_t s) {
+    const int epc = chunk_elems(dtype);
+    const int nch = (D + epc - 1) / epc;
+    const dim3 grid((unsigned)((N + 63) / 64));
+    const size_t lds = (size_t)nch * 64 * 16;
+    auto out = static_cast<uint4*>(planes);
+    switch (dtype) {
+        case kF32:
+            hipLaunchKernelGGL(gather_planes_kernel<F32>, grid, dim3(256), lds, s,
+                               static_cast<const uint32_t*>(X), N, D, nch, perm, out);
+            break;
+        case kF16:
+            hipLaunchKernelGGL(gather_planes_kernel<F16>, grid, dim3(256), lds, s,
+                               static_cast<const uint16_t*>(X), N, D, nch, perm, out);
+            break;
+        case kU8:
+            hipLaunchKernelGGL(gather_planes_kernel<U8>, grid, dim3(256), lds, s,
+                               static_cast<const uint8_t*>(X), N, D, nch, perm, out);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// lexsub[j] = j-th L-subset of {0..D-1} in lexicographic order (unranked by
+// counting the subsets that start with each candidate value).
+__global__ void lexsub_kernel(int D, int L, int64_t count, uint8_t* __restrict__ lexsub) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    uint64_t rem = (uint64_t)j;
+    int prev = -1;
+    for (int a = 0; a < L; ++a) {
+        for (int v = prev + 1; v < D; ++v) {
+            const uint64_t cnt = binom_dev(D - 1 - v, L - 1 - a);
+            if (rem < cnt) {
+                lexsub[j * L + a] = (uint8_t)v;
+                prev = v;
+                break;
+            }
+            rem -= cnt;
+        }
+    }
+}
+
+// maskord = all L-bit masks ordered by (popcount, value).
+__global__ void maskord_kernel(int L, uint8_t* __restrict__ maskord) {
+    const int m = threadIdx.x;
+    if (m >= (1 << L)) return;
+    int rank = 0;
+    for (int o = 0; o < (1 << L); ++o) {
+        const int po = __popc(o), pm = __popc(m);
+        rank += (po < pm) || (po == pm && o < m);
+    }
+    maskord[rank] = (uint8_t)m;
+}
+
+hipError_t launch_probe_tables(int D, int L, uint8_t* lexsub, uint8_t* maskord, hipStream_t s) {
+    const int64_t count = binom_host(D, L);
+    hipLaunchKernelGGL(lexsub_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, D, L,
+                       count, lexsub);
+    hipLaunchKernelGGL(maskord_kernel, dim3(1), dim3(128), 0, s, L, maskord);
+    return hipGetLastError();
+}
+
+__global__ void count_nonempty_kernel(const uint32_t* __restrict__ off, int64_t nc,
+                                      uint32_t* __restrict__ count) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ne = c < nc && off[c + 1] > off[c];
+    const uint64_t m = __ballot(ne);
+    if (lane_id() == 0 && m) atomicAdd(count, (uint32_t)__popcll(m));
+}
+
+hipError_t launch_count_nonempty(const uint32_t* offsets, int64_t n_cones, uint32_t* count,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(count_nonempty_kernel, dim3((unsigned)((n_cones + 255) / 256)), dim3(256), 0, s,
+                       offsets, n_cones, count);
+    return hipGetLastError();
+}
+
+__global__ void widen_kernel(const uint32_t* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int64_t)in[i];
+}
+
+hipError_t launch_widen_u32(const uint32_t* in, int64_t n, int64_t* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(widen_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+template <typename E>
+__global__ void planes_to_rows_kernel(const typename E::raw* __restrict__ planes, int64_t N, int D,
+                                      float* __restrict__ rows) {
+    constexpr int EPC = 16 / E::bytes;
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= N * D) return;
+    const int64_t pos = f / D;
+    const int i = (int)(f % D);
+    rows[f] = E::val(planes[((int64_t)(i / EPC) * N + pos) * EPC + (i % EPC)]);
+}
+
+hipError_t launch_planes_to_rows(const void* planes, int dtype, int64_t N, int D, float* rows,
+                                 hipStream_t s) {
+    const int64_t n = N * D;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    switch (dtype) {
+        case kF32:
+            hipLaunchKernelGGL(planes_to_rows_kernel<F32>, grid, dim3(256), 0, s,
+                               static_cast<const uint32_t*>(planes), N, D, rows);
+            break;
+        case kF16:
+            hipLaunchKernelGGL(planes_to_rows_kernel<F16>, grid, dim3(256), 0, s,
+                               static_cast<const uint16_t*>(planes), N, D, rows);
+            break;
+        case kU8:
+            hipLaunchKernelGGL(planes_to_rows_kernel<U8>, grid, dim3(256), 0, s,
+                               static_cast<const uint8_t*>(planes), N, D, rows);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace osann

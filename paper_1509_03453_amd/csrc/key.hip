@@ -1,0 +1,111 @@
+// Key kernel: for every database row, the L largest-magnitude components
+// (index and sign, decreasing magnitude) and the row's cone id
+// (Section 2, eq. (2); Fig. 2).
+//
+// Work split: S lanes of a wave64 share one row (S = power of two), lane t
+// reading components t, t+S, t+2S, ... so that the wave's loads are
+// contiguous.  Each lane keeps its own top-L list in registers; the group
+// then runs L rounds of a shuffle max-reduction on the packed component keys
+// and the winning lane drops its head.  Integer compares only, so the result
+// is exact and independent of the lane split.
+#include "osann_device.h"
+#include "osann_kernels.h"
+
+namespace osann {
+
+template <typename E, int L>
+__global__ __launch_bounds__(256) void row_keys_kernel(const typename E::raw* __restrict__ X,
+                                                       int64_t N, int D, int S,
+                                                       uint32_t* __restrict__ row_cone,
+                                                       uint64_t* __restrict__ row_top,
+                                                       uint32_t* __restrict__ nonfinite) {
+    const int t = threadIdx.x % S;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / S) + threadIdx.x / S;
+    const bool valid = row < N;
+
+    uint64_t top[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) top[j] = 0;  // every real key is >= 1
+    bool bad = false;
+    if (valid) {
+        const typename E::raw* xr = X + row * (int64_t)D;
+        for (int i = t; i < D; i += S) {
+            typename E::raw b = xr[i];
+            bad |= E::nonfinite(b);
+            uint64_t k = comp_key(E::mag(b), i, E::neg(b));
+            // insert into the descending list
+#pragma unroll
+            for (int j = L - 1; j >= 0; --j) {
+                uint64_t above = j > 0 ? top[j - 1] : ~0ull;
+                if (k > top[j]) top[j] = (k > above) ? above : k;
+            }
+        }
+    }
+    if (bad) atomicOr(nonfinite, 1u);
+
+    uint64_t win[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        uint64_t m = top[0];
+        for (int o = 1; o < S; o <<= 1) {
+            uint64_t other = shfl_xor_u64(m, o);
+            m = other > m ? other : m;
+        }
+        win[j] = m;
+        if (top[0] == m) {  // exactly one lane of the group holds it
+#pragma unroll
+            for (int a = 0; a < L - 1; ++a) top[a] = top[a + 1];
+            top[L - 1] = 0;
+        }
+    }
+
+    if (valid && t == 0) {
+        int idx[L], sg[L];
+        uint64_t packed = 0;
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            idx[j] = key_index(win[j]);
+            sg[j] = key_sign(win[j]);
+            packed |= (uint64_t)((uint32_t)idx[j] | ((uint32_t)sg[j] << 8)) << (9 * j);
+        }
+        row_top[row] = packed;
+        row_cone[row] = cone_of<L>(idx, sg);
+    }
+}
+
+template <typename E>
+static hipError_t dispatch_keys(const void* X, int64_t N, int D, int L, uint32_t* cone,
+                                uint64_t* top, uint32_t* flag, hipStream_t s) {
+    int S = 1;
+    while (S * 2 <= D / 4 && S < 64) S *= 2;  // about four components per lane
+    const int threads = 256;
+    const int64_t rows_per_block = threads / S;
+    const dim3 grid((unsigned)((N + rows_per_block - 1) / rows_per_block));
+    auto x = static_cast<const typename E::raw*>(X);
+    switch (L) {
+#define OSANN_KEY_CASE(LL)                                                                   \
+    case LL:                                                                                 \
+        hipLaunchKernelGGL((row_keys_kernel<E, LL>), grid, dim3(threads), 0, s, x, N, D, S, \
+                           cone, top, flag);                                                 \
+        break;
+        OSANN_KEY_CASE(1) OSANN_KEY_CASE(2) OSANN_KEY_CASE(3) OSANN_KEY_CASE(4)
+        OSANN_KEY_CASE(5) OSANN_KEY_CASE(6) OSANN_KEY_CASE(7)
+#undef OSANN_KEY_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_row_keys(const void* X, int dtype, int64_t N, int D, int L, uint32_t* row_cone,
+                           uint64_t* row_top, uint32_t* nonfinite, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    switch (dtype) {
+        case kF32: return dispatch_keys<F32>(X, N, D, L, row_cone, row_top, nonfinite, s);
+        case kF16: return dispatch_keys<F16>(X, N, D, L, row_cone, row_top, nonfinite, s);
+        case kU8: return dispatch_keys<U8>(X, N, D, L, row_cone, row_top, nonfinite, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace osann

@@ -1,0 +1,116 @@
+// Internal interface between the host ABI layer (osann_abi.cpp) and the HIP
+// kernels for gfx950.  Not installed; the public interface is include/osann.h.
+//
+// Device data layout of an index (N rows of D components, storage type T):
+//   row_cone[N]   u32  cone id of each original row
+//   row_top[N]    u64  top-L (index, sign) pairs, 9 bits each, decreasing |x|
+//   perm[N]       u32  original row at each bucket-sorted position
+//   offsets[NC+1] u32  bucket c = sorted positions [offsets[c], offsets[c+1])
+//   planes        16-byte chunks, component-chunk major:
+//                 planes[k*N + pos] holds components [k*E, k*E+E) of the row
+//                 at sorted position pos (E = 16/sizeof(T), zero padded past D).
+//                 A wave reading 64 consecutive positions of one chunk reads
+//                 1 KiB of contiguous memory, and each lane still sees its own
+//                 row's components in ascending order.
+//   lexsub[C(D,L)][L] u8  L-subsets of rank positions in lexicographic order
+//   maskord[2^L]  u8   sign-flip masks ordered by (popcount, value)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace osann {
+
+constexpr int kMaxD = 256;
+constexpr int kMaxL = 7;
+constexpr int64_t kMaxCones = int64_t(1) << 24;
+
+// Storage type codes (same values as the public OS_ANN_F32 / F16 / U8).
+enum DType : int { kF32 = 0, kF16 = 1, kU8 = 2 };
+
+inline int elem_bytes(int dtype) { return dtype == kF32 ? 4 : dtype == kF16 ? 2 : 1; }
+inline int chunk_elems(int dtype) { return 16 / elem_bytes(dtype); }
+
+// C(n, k) on the host (0 when k > n).
+inline int64_t binom_host(int n, int k) {
+    if (k < 0 || n < 0 || k > n) return 0;
+    int64_t c = 1;
+    for (int t = 0; t < k; ++t) c = c * (n - t) / (t + 1);
+    return c;
+}
+
+// ---- launchers (each enqueues on `s`, returns the hipError_t of the launch) ----
+
+// Key kernel: top-L pairs, cone id, non-finite flag (atomic OR of 1).
+hipError_t launch_row_keys(const void* X, int dtype, int64_t N, int D, int L,
+                           uint32_t* row_cone, uint64_t* row_top, uint32_t* nonfinite,
+                           hipStream_t s);
+
+// Stable LSD radix sort of (cone, row) by cone; writes perm and sorted cones.
+// tmp must hold 4 arrays of N u32 plus radix_hist_words(N) u32.
+int64_t radix_hist_words(int64_t N);
+hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_cones,
+                               uint32_t* tmp, uint32_t* perm_out, uint32_t* sorted_cone_out,
+                               hipStream_t s);
+
+// Bucket offsets from the sorted cones.
+hipError_t launch_offsets(const uint32_t* sorted_cone, int64_t N, int64_t n_cones,
+                          uint32_t* offsets, hipStream_t s);
+
+// Permuted, chunk-major copy of the rows.
+hipError_t launch_gather_planes(const void* X, int dtype, int64_t N, int D,
+                                const uint32_t* perm, void* planes, hipStream_t s);
+
+// Probe-order tables and the non-empty cone count.
+hipError_t launch_probe_tables(int D, int L, uint8_t* lexsub, uint8_t* maskord, hipStream_t s);
+hipError_t launch_count_nonempty(const uint32_t* offsets, int64_t n_cones, uint32_t* count,
+                                 hipStream_t s);
+
+// Export helpers.
+hipError_t launch_widen_u32(const uint32_t* in, int64_t n, int64_t* out, hipStream_t s);
+hipError_t launch_planes_to_rows(const void* planes, int dtype, int64_t N, int D,
+                                 float* rows, hipStream_t s);
+
+// Query classification and probe list (Section 3.B walk).
+struct ProbeArgs {
+    const void* Y;          // queries [Q][D], dtype qtype
+    int qtype;
+    int64_t Q;
+    int D, L;
+    const uint32_t* offsets;
+    int64_t n_cones, n_sub; // N_C and C(D,L)
+    int64_t N;
+    int64_t budget;         // max_candidates
+    const uint8_t* lexsub;
+    const uint8_t* maskord;
+    // outputs (any may be null except where noted)
+    float* yf;              // [Q][dpad] FP32 copy of the queries (zero padded)
+    int dpad;
+    uint2* desc;            // [Q][cap] (start position, cumulative count) of each probe
+    int64_t cap;
+    uint32_t* nprobe;       // [Q]
+    int64_t* ncand;         // [Q]
+    uint32_t* q_cone;       // [Q]
+    uint64_t* q_top;        // [Q]
+};
+hipError_t launch_probe(const ProbeArgs& a, hipStream_t s);
+
+// FP32 candidate scan + arg-min (eq. (1), Algorithm 1).
+struct ScanArgs {
+    const void* planes;
+    int dtype;
+    int64_t N;
+    int D, nch;             // nch = number of 16-byte chunks per row
+    const float* yf;        // [Q][nch*E]
+    int64_t Q;
+    const uint2* desc;
+    int64_t cap;
+    const uint32_t* nprobe;
+    const uint32_t* perm;
+    int64_t* out_idx;
+    float* out_dist;
+    int waves_per_query;    // 1, 2 or 4
+};
+hipError_t launch_scan_fp32(const ScanArgs& a, hipStream_t s);
+
+}  // namespace osann

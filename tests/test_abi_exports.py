@@ -1,0 +1,50 @@
+"""The C-ABI library loads and exports every entry point include/osann.h
+declares, and the Python binding covers exactly those (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "osann.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(os_ann_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_core_calls():
+    names = declared()
+    for core in ("os_ann_build", "os_ann_search", "os_ann_free", "os_ann_build_ex", "os_ann_search_ex",
+                 "os_ann_workspace_bytes", "os_ann_classify", "os_ann_export", "os_ann_info"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1509_03453_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libosann.so is not built (python -m paper_1509_03453_amd.build)")
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for name in declared():
+        assert hasattr(lib, name), name
+    assert sorted(binding.SIGNATURES) == declared()
+
+
+def test_binding_raises_without_library(monkeypatch):
+    from paper_1509_03453_amd import binding
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", "/nonexistent/libosann.so")
+    with pytest.raises(RuntimeError, match="no fallback"):
+        binding.lib()
+
+
+def test_version_and_error_state_without_gpu():
+    from paper_1509_03453_amd import binding
+    assert "gfx950" in binding.os_ann_version()
+    # invalid arguments are rejected on the host before any device call
+    assert binding.lib().os_ann_build(None, 10, 4, 1) is None
+    assert binding.os_ann_last_error() == binding.OS_ANN_EINVAL
+    assert binding.lib().os_ann_workspace_bytes(None, 1, 1, None) == binding.OS_ANN_EINVAL
