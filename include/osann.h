@@ -64,17 +64,30 @@ extern "C" {
 #define OS_ANN_F16 1
 #define OS_ANN_U8  2
 
-/* Search modes. */
-#define OS_ANN_MODE_FP32   0  /* exact FP32 scan of every candidate */
-#define OS_ANN_MODE_TILED  1  /* BF16/FP16 matrix-core screening + FP32 re-rank */
+/* Search modes.
+ *   FP32   every candidate's exact FP32 distance; arg-min on (distance, row).
+ *   TILED  the same candidates are screened on the matrix cores with
+ *          d~ = ||x^||^2 - 2 q^.x^ (x^, q^ rounded to BF16, or kept as FP16
+ *          for FP16 data; FP32 accumulation), the rerank_r smallest (d~, row)
+ *          survive, and their exact FP32 distances (as in FP32 mode) decide
+ *          the result.  out_dist is always the exact FP32 distance of out_idx. */
+#define OS_ANN_MODE_FP32   0
+#define OS_ANN_MODE_TILED  1
 
 /* Search flags. */
 #define OS_ANN_FLAG_TIME_KERNELS 1  /* record HIP events around each kernel launch */
+#define OS_ANN_FLAG_GRAPH        2  /* capture the launch sequence in a hipGraph on the
+                                       first call with these exact arguments (pointers,
+                                       sizes, stream; non-null stream only) and replay it
+                                       on later identical calls */
 
 /* Kernel ids of os_ann_kernel_time. */
-#define OS_ANN_KERNEL_PROBE 0  /* query classification + probe list */
-#define OS_ANN_KERNEL_SCAN  1  /* FP32 candidate scan + arg-min */
-#define OS_ANN_KERNEL_COUNT 2
+#define OS_ANN_KERNEL_PROBE  0  /* query classification + walk state */
+#define OS_ANN_KERNEL_SCAN   1  /* FP32 candidate scan + arg-min */
+#define OS_ANN_KERNEL_SCREEN 2  /* tiled mode: matrix-core screening, per-query top-R */
+#define OS_ANN_KERNEL_FINISH 3  /* tiled mode: merge of top-R lists + FP32 re-rank */
+#define OS_ANN_KERNEL_GRAPH  4  /* a replayed hipGraph, as one unit */
+#define OS_ANN_KERNEL_COUNT  5
 
 typedef struct os_ann_index os_ann_index;
 
@@ -87,7 +100,7 @@ typedef struct os_ann_build_opts {
 
 typedef struct os_ann_search_opts {
     int32_t mode;         /* OS_ANN_MODE_FP32 or OS_ANN_MODE_TILED */
-    int32_t rerank_r;     /* tiled mode: survivors re-ranked in FP32 (1..32, default 8) */
+    int32_t rerank_r;     /* tiled mode: survivors re-ranked in FP32: 4, 8 or 16 (0 = 8) */
     int32_t query_dtype;  /* OS_ANN_F32 / OS_ANN_F16 / OS_ANN_U8 */
     int32_t flags;        /* OS_ANN_FLAG_* bits */
     void *stream;         /* stream the search runs on (NULL = null stream) */
@@ -135,9 +148,14 @@ os_ann_index *os_ann_build_ex(const void *db, int64_t N, int32_t D, int32_t L,
 int os_ann_search(const os_ann_index *idx, const float *queries, int64_t Q,
                   int64_t max_candidates, int64_t *out_idx, float *out_dist);
 
-/* As os_ann_search with options (mode, query dtype, stream, workspace) and
- * the per-query candidate count out_ncand[Q] (int64, may be NULL).
- * opts may be NULL (FP32 mode, FP32 queries, null stream). */
+/* As os_ann_search with options (mode, query dtype, stream, workspace,
+ * flags) and the per-query candidate count out_ncand[Q] (int64, may be
+ * NULL).  opts may be NULL (FP32 mode, FP32 queries, null stream).  The
+ * first tiled search of a new shape (Q, budget, index) times the candidate
+ * work splits and keeps the fastest (in memory, and appended to the file
+ * named by the OSANN_TUNE_FILE environment variable if set); this first call
+ * synchronises the stream.  Results never depend on the split or on the
+ * batch a query arrives in. */
 int os_ann_search_ex(const os_ann_index *idx, const void *queries, int64_t Q,
                      int64_t max_candidates, const os_ann_search_opts *opts,
                      int64_t *out_idx, float *out_dist, int64_t *out_ncand);

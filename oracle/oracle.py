@@ -66,6 +66,13 @@ def lib():
             L.orc_pair_d64.argtypes = [p, i32, i32, p, i32, p, i64, p]
             L.orc_pair_d32.restype = i32
             L.orc_pair_d32.argtypes = [p, i32, i32, p, i32, p, i64, p]
+            L.orc_search_tiled.restype = i32
+            L.orc_search_tiled.argtypes = [p, i32, i64, i32, i32, p, p, p, i32, i64, i64, i32, i32,
+                                           p, p, p, p, p, p, i32]
+            L.orc_pair_dtilde.restype = i32
+            L.orc_pair_dtilde.argtypes = [p, i32, i32, p, i32, p, i64, i32, p]
+            L.orc_round_short.restype = i32
+            L.orc_round_short.argtypes = [p, i64, i32, p]
             _lib = L
     return _lib
 
@@ -215,4 +222,51 @@ def pair_d32(X, Y, rows) -> np.ndarray:
     r, pr = _arr(rows, np.int64)
     out = np.empty(Y.shape[0], dtype=np.float32)
     lib().orc_pair_d32(px, xdt, X.shape[1], py, ydt, pr, Y.shape[0], out.ctypes.data_as(C.c_void_p))
+    return out
+
+
+def search_tiled(X, index, Y, B: int, R: int = 8, use_f16: bool | None = None, nthreads: int = 0):
+    """Screened search (reading R7): ``(idx, d32, d64, ncand, dt_R, top)``.
+
+    ``use_f16`` defaults to True for float16 rows (the rows are kept as
+    stored) and False otherwise (bfloat16 rounding)."""
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    if use_f16 is None:
+        use_f16 = X.dtype == np.float16
+    N, K = X.shape
+    Q = Y.shape[0]
+    off, po = _arr(index["offsets"], np.int64)
+    perm, pp = _arr(index["perm"], np.int64)
+    idx = np.empty(Q, dtype=np.int64)
+    d32 = np.empty(Q, dtype=np.float32)
+    d64 = np.empty(Q, dtype=np.float64)
+    nca = np.empty(Q, dtype=np.int64)
+    dtr = np.empty(Q, dtype=np.float64)
+    top = np.empty((Q, R), dtype=np.int64)
+    rc = lib().orc_search_tiled(px, xdt, N, K, index["G"], po, pp, py, ydt, Q, int(B), int(R), int(use_f16),
+                                idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
+                                d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
+                                dtr.ctypes.data_as(C.c_void_p), top.ctypes.data_as(C.c_void_p), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_search_tiled failed ({rc})")
+    return idx, d32, d64, nca, dtr, top
+
+
+def pair_dtilde(X, Y, rows, use_f16: bool = False) -> np.ndarray:
+    """d~ = ||x^||^2 - 2 q^.x^ of (q, rows[q]) in double on rounded values."""
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    r, pr = _arr(rows, np.int64)
+    out = np.empty(Y.shape[0], dtype=np.float64)
+    lib().orc_pair_dtilde(px, xdt, X.shape[1], py, ydt, pr, Y.shape[0], int(use_f16),
+                          out.ctypes.data_as(C.c_void_p))
+    return out
+
+
+def round_short(x, use_f16: bool = False) -> np.ndarray:
+    """Values rounded to bfloat16 (or binary16), as doubles."""
+    x, px = _arr(np.ravel(x), np.float32)
+    out = np.empty(x.shape[0], dtype=np.float64)
+    lib().orc_round_short(px, x.shape[0], int(use_f16), out.ctypes.data_as(C.c_void_p))
     return out

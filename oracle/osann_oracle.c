@@ -489,3 +489,166 @@ int orc_pair_d32(const void *X, int xdtype, int K, const void *Y, int ydtype,
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Screened search with an exact re-rank (reading R7)                        */
+/* ------------------------------------------------------------------------ */
+/*
+ * Reading R7 (not in the paper; the paper always computes exact distances on
+ * the original vectors, Section 1 and Algorithm 1): candidates are first
+ * ranked by d~ = ||x^||^2 - 2 q^.x^, where x^ and q^ are x and q rounded to
+ * a short format (bfloat16, or binary16 for binary16 data) with round to
+ * nearest, ties to even; the R smallest (d~, row) pairs survive and the
+ * exact FP32 distance of eq. (1) decides among them.  d~ is evaluated in
+ * double on the rounded values.
+ */
+
+/* Round to `bits` significant bits (nearest, ties to even) with the
+ * exponent range of the target format: smallest normal 2^emin, values below
+ * it quantised to 2^(emin - bits + 1); overflow past the largest finite
+ * value gives infinity. */
+static double round_sig(double x, int bits, int emin, double maxfin)
+{
+    if (x == 0.0 || !isfinite(x))
+        return x;
+    int e = ilogb(x);
+    if (e < emin)
+        e = emin;
+    double q = ldexp(1.0, e - bits + 1);   /* spacing of the format at |x| */
+    double r = nearbyint(x / q) * q;       /* default mode: ties to even */
+    if (fabs(r) > maxfin)
+        return copysign(INFINITY, x);
+    return r;
+}
+
+/* bfloat16: 8 significant bits, exponent range of binary32. */
+static double to_bf16(float x)
+{
+    return round_sig((double)x, 8, -126, 3.3895313892515355e38);
+}
+
+/* binary16: 11 significant bits, smallest normal 2^-14, largest 65504. */
+static double to_f16(float x)
+{
+    return round_sig((double)x, 11, -14, 65504.0);
+}
+
+struct cand {
+    double dt;
+    int64_t row;
+};
+
+static int cand_less(const struct cand *a, const struct cand *b)
+{
+    return a->dt < b->dt || (a->dt == b->dt && a->row < b->row);
+}
+
+/* Screened search: same probe walk and candidates as orc_search; out_dt_R
+ * receives the R-th smallest d~ (infinity with fewer than R candidates) and
+ * out_top (Q x R, may be NULL) the surviving rows in (d~, row) order, -1 padded. */
+int orc_search_tiled(const void *X, int xdtype, int64_t N, int K, int G,
+                     const int64_t *offsets, const int64_t *perm,
+                     const void *Y, int ydtype, int64_t Q, int64_t B, int R, int use_f16,
+                     int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
+                     double *out_dt_R, int64_t *out_top, int nthreads)
+{
+    (void)N;
+    if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || R < 1 || R > 64)
+        return -1;
+    int64_t NC = orc_num_cones(K, G);
+    set_threads(nthreads);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < Q; q++) {
+        float y[256], x[256];
+        double yh[256];
+        load_row(Y, ydtype, q, K, y);
+        for (int i = 0; i < K; i++)
+            yh[i] = use_f16 ? to_f16(y[i]) : to_bf16(y[i]);
+        int64_t *probes = (int64_t *)malloc(sizeof(int64_t) * (size_t)NC);
+        if (!probes) {
+#pragma omp atomic write
+            bad = 1;
+            continue;
+        }
+        int64_t ncand = 0;
+        int64_t np = orc_probe(y, K, G, offsets, B, probes, NC, &ncand);
+        struct cand top[64];
+        int kept = 0;
+        for (int64_t k = 0; k < np; k++) {
+            int64_t c = probes[k];
+            for (int64_t pos = offsets[c]; pos < offsets[c + 1]; pos++) {
+                int64_t row = perm[pos];
+                load_row(X, xdtype, row, K, x);
+                double n2 = 0.0, dot = 0.0;
+                for (int i = 0; i < K; i++) {
+                    double xh = use_f16 ? to_f16(x[i]) : to_bf16(x[i]);
+                    n2 += xh * xh;
+                    dot += yh[i] * xh;
+                }
+                struct cand cd = { n2 - 2.0 * dot, row };
+                /* keep the R smallest (d~, row), sorted (insertion) */
+                if (kept < R || cand_less(&cd, &top[kept - 1])) {
+                    int at = kept < R ? kept++ : R - 1;
+                    while (at > 0 && cand_less(&cd, &top[at - 1])) {
+                        top[at] = top[at - 1];
+                        at--;
+                    }
+                    top[at] = cd;
+                }
+            }
+        }
+        float best_d = INFINITY;
+        int64_t best_row = INT64_MAX;
+        double best_d64 = INFINITY;
+        for (int t = 0; t < kept; t++) {
+            float d32;
+            double d64;
+            load_row(X, xdtype, top[t].row, K, x);
+            dist2(x, y, K, &d32, &d64);
+            int64_t before = best_row;
+            argmin_update(d32, top[t].row, &best_d, &best_row);
+            if (best_row != before)
+                best_d64 = d64;
+        }
+        out_idx[q] = best_row;
+        out_d32[q] = best_d;
+        out_d64[q] = best_d64;
+        out_ncand[q] = ncand;
+        if (out_dt_R)
+            out_dt_R[q] = kept == R ? top[R - 1].dt : INFINITY;
+        if (out_top)
+            for (int t = 0; t < R; t++)
+                out_top[q * R + t] = t < kept ? top[t].row : -1;
+        free(probes);
+    }
+    return bad ? -2 : 0;
+}
+
+/* d~ of given (query, row) pairs, as in orc_search_tiled. */
+int orc_pair_dtilde(const void *X, int xdtype, int K, const void *Y, int ydtype,
+                    const int64_t *rows, int64_t Q, int use_f16, double *out)
+{
+    for (int64_t q = 0; q < Q; q++) {
+        float y[256], x[256];
+        load_row(Y, ydtype, q, K, y);
+        load_row(X, xdtype, rows[q], K, x);
+        double n2 = 0.0, dot = 0.0;
+        for (int i = 0; i < K; i++) {
+            double xh = use_f16 ? to_f16(x[i]) : to_bf16(x[i]);
+            double yh = use_f16 ? to_f16(y[i]) : to_bf16(y[i]);
+            n2 += xh * xh;
+            dot += yh * xh;
+        }
+        out[q] = n2 - 2.0 * dot;
+    }
+    return 0;
+}
+
+/* Rounded value of each element (for pinning the rounding). */
+int orc_round_short(const float *x, int64_t n, int use_f16, double *out)
+{
+    for (int64_t i = 0; i < n; i++)
+        out[i] = use_f16 ? to_f16(x[i]) : to_bf16(x[i]);
+    return 0;
+}

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libosann.so
 OS_ANN_OK, OS_ANN_EINVAL, OS_ANN_ENOMEM, OS_ANN_EDEVICE, OS_ANN_ENOTSUP, OS_ANN_ENONFINITE = 0, -1, -2, -3, -4, -5
 OS_ANN_F32, OS_ANN_F16, OS_ANN_U8 = 0, 1, 2
 OS_ANN_MODE_FP32, OS_ANN_MODE_TILED = 0, 1
-OS_ANN_FLAG_TIME_KERNELS = 1
-OS_ANN_KERNEL_PROBE, OS_ANN_KERNEL_SCAN = 0, 1
+OS_ANN_FLAG_TIME_KERNELS, OS_ANN_FLAG_GRAPH = 1, 2
+OS_ANN_KERNEL_PROBE, OS_ANN_KERNEL_SCAN, OS_ANN_KERNEL_SCREEN, OS_ANN_KERNEL_FINISH, OS_ANN_KERNEL_GRAPH = 0, 1, 2, 3, 4
 
 _DTYPE_CODE = {torch.float32: OS_ANN_F32, torch.float16: OS_ANN_F16, torch.uint8: OS_ANN_U8}
 

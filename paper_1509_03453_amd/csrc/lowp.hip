@@ -1,0 +1,145 @@
+// Low-precision copy of an index for the matrix-core screening pass.
+//
+// Buckets are re-laid out with their size rounded up to 16 rows, so that a
+// 16-row MFMA tile never straddles two buckets:
+//   poff[c]        padded start of bucket c (poff[NC] = NP)
+//   xl[p][dk]      row at padded position p, BF16 (round to nearest even) for
+//                  FP32 and uint8 data, FP16 as stored for FP16 data; dk = D
+//                  rounded up to 32 (one MFMA K step); zero padded
+//   nrm[p]         FP32 sum of squares of the rounded row, +inf on padding rows
+//   prow[p]        original row id, 0xFFFFFFFF on padding rows
+//   iperm[row]     sorted position of each original row (exact FP32 re-rank)
+//   ne_id[c]       rank of cone c among the non-empty cones; ne_cone is its inverse
+#include "osann_device.h"
+#include "osann_kernels.h"
+
+namespace osann {
+
+__global__ void binom_table_kernel(uint32_t* __restrict__ tab) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 256 * 8) return;
+    const int n = i / 8, k = i % 8;
+    const uint64_t c = binom_dev(n, k);
+    tab[i] = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
+}
+
+hipError_t launch_binom_table(uint32_t* tab, hipStream_t s) {
+    hipLaunchKernelGGL(binom_table_kernel, dim3(8), dim3(256), 0, s, tab);
+    return hipGetLastError();
+}
+
+__global__ void lowp_sizes_kernel(const uint32_t* __restrict__ off, int64_t nc, uint32_t* __restrict__ psz,
+                                  uint32_t* __restrict__ nef) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const uint32_t len = off[c + 1] - off[c];
+    psz[c] = (len + 15u) & ~15u;
+    nef[c] = len > 0;
+}
+
+__global__ void ne_cone_kernel(const uint32_t* __restrict__ off, int64_t nc, const uint32_t* __restrict__ ne_id,
+                               uint32_t* __restrict__ ne_cone) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nc && off[c + 1] > off[c]) ne_cone[ne_id[c]] = (uint32_t)c;
+}
+
+hipError_t launch_lowp_layout(const uint32_t* offsets, int64_t n_cones, uint32_t* psz_tmp, uint32_t* nef_tmp,
+                              uint32_t* scan_tmp, uint32_t* poff, uint32_t* ne_id, uint32_t* ne_cone,
+                              hipStream_t s) {
+    const dim3 grid((unsigned)((n_cones + 255) / 256));
+    hipLaunchKernelGGL(lowp_sizes_kernel, grid, dim3(256), 0, s, offsets, n_cones, psz_tmp, nef_tmp);
+    hipError_t e = launch_exclusive_scan(psz_tmp, n_cones, poff, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan(nef_tmp, n_cones, ne_id, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ne_cone_kernel, grid, dim3(256), 0, s, offsets, n_cones, ne_id, ne_cone);
+    return hipGetLastError();
+}
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// One thread per (sorted position, 16-byte chunk of the planes).
+template <typename E>
+__global__ void lowp_rows_kernel(const uint4* __restrict__ planes, int64_t N, int D, int nch,
+                                 const uint32_t* __restrict__ sorted_cone, const uint32_t* __restrict__ off,
+                                 const uint32_t* __restrict__ poff, const uint32_t* __restrict__ perm, int dk,
+                                 int to_f16, uint16_t* __restrict__ xl, uint32_t* __restrict__ prow,
+                                 uint32_t* __restrict__ iperm) {
+    constexpr int EPC = Unpack<E>::n;
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= N * nch) return;
+    const int64_t pos = f / nch;
+    const int k = (int)(f % nch);
+    const uint32_t c = sorted_cone[pos];
+    const int64_t p = (int64_t)poff[c] + (pos - (int64_t)off[c]);
+    float x[EPC];
+    Unpack<E>::run(planes[(int64_t)k * N + pos], x);
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+        const int i = k * EPC + e;
+        if (i < D) xl[p * dk + i] = to_f16 ? f16_rne(x[e]) : bf16_rne(x[e]);
+    }
+    if (k == 0) {
+        const uint32_t row = perm[pos];
+        prow[p] = row;
+        iperm[row] = (uint32_t)pos;
+    }
+}
+
+__global__ void lowp_norm_kernel(const uint16_t* __restrict__ xl, int64_t np, int D, int dk, int is_f16,
+                                 const uint32_t* __restrict__ prow, float* __restrict__ nrm) {
+#pragma clang fp contract(off)
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    if (prow[p] == 0xFFFFFFFFu) {
+        nrm[p] = __builtin_huge_valf();
+        return;
+    }
+    float acc = 0.0f;
+    for (int i = 0; i < D; ++i) {
+        const uint16_t b = xl[p * dk + i];
+        const float v = is_f16 ? F16::val(b) : __uint_as_float((uint32_t)b << 16);
+        const float sq = v * v;
+        acc = acc + sq;
+    }
+    nrm[p] = acc;
+}
+
+hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
+                            const uint32_t* offsets, const uint32_t* poff, const uint32_t* perm, int dk,
+                            int to_f16, uint16_t* xl, uint32_t* prow, uint32_t* iperm, float* nrm, int64_t np_total,
+                            hipStream_t s) {
+    const int64_t n = N * nch;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    auto pl = static_cast<const uint4*>(planes);
+    switch (dtype) {
+        case kF32:
+            hipLaunchKernelGGL(lowp_rows_kernel<F32>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
+                               poff, perm, dk, to_f16, xl, prow, iperm);
+            break;
+        case kF16:
+            hipLaunchKernelGGL(lowp_rows_kernel<F16>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
+                               poff, perm, dk, to_f16, xl, prow, iperm);
+            break;
+        case kU8:
+            hipLaunchKernelGGL(lowp_rows_kernel<U8>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
+                               poff, perm, dk, to_f16, xl, prow, iperm);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(lowp_norm_kernel, dim3((unsigned)((np_total + 255) / 256)), dim3(256), 0, s, xl, np_total, D,
+                       dk, to_f16, prow, nrm);
+    return hipGetLastError();
+}
+
+}  // namespace osann

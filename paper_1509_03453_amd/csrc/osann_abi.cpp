@@ -1,14 +1,20 @@
 // Host side of the C ABI declared in include/osann.h: argument checks, device
-// memory of an index, and the launch sequence of the gfx950 kernels.
+// memory of an index, the launch sequences of the gfx950 kernels, the split
+// autotuner of the tiled path and hipGraph replay of repeated searches.
 #include "osann.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "osann_kernels.h"
+#include "osann_tiled.h"
 
 using namespace osann;
 
@@ -31,30 +37,59 @@ int hip_fail(hipError_t e, const char* what) {
                 std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define OSANN_HIP(call, what)                      \
-    do {                                           \
-        hipError_t e_ = (call);                    \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
+#define OSANN_HIP(call, what)                              \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, what);   \
     } while (0)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+int64_t pow2_ceil(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
 
 }  // namespace
+
+// Low-precision, 16-row padded copy used by the tiled path (built on first use).
+struct LowpCopy {
+    bool ready = false;
+    int dk = 0, f16 = 0;
+    int64_t np = 0;  // padded rows
+    uint32_t* poff = nullptr;
+    uint32_t* ne_id = nullptr;
+    uint32_t* ne_cone = nullptr;
+    uint16_t* xl = nullptr;
+    float* nrm = nullptr;
+    uint32_t* prow = nullptr;
+    uint32_t* iperm = nullptr;
+};
+
+struct GraphEntry {
+    std::vector<int64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 struct os_ann_index {
     int64_t N = 0;
     int32_t D = 0, L = 0, dtype = 0;
     int64_t n_cones = 0, n_sub = 0, n_nonempty = 0;
     int nch = 0, epc = 0;
-    int device = 0;
+    int device = 0, num_cu = 256;
     size_t device_bytes = 0;
     uint32_t* row_cone = nullptr;
     uint64_t* row_top = nullptr;
     uint32_t* perm = nullptr;
+    uint32_t* sorted_cone = nullptr;
     uint32_t* offsets = nullptr;
     void* planes = nullptr;
     uint8_t* lexsub = nullptr;
     uint8_t* maskord = nullptr;
+    uint32_t* binom = nullptr;
+    std::mutex lowp_mu;
+    LowpCopy lp;
     // scratch owned by the index, used when the caller brings no workspace
     std::mutex scratch_mu;
     void* scratch = nullptr;
@@ -66,10 +101,16 @@ struct os_ann_index {
     };
     std::mutex time_mu;
     std::vector<Timed> timed;
+    // captured search sequences
+    std::mutex graph_mu;
+    std::vector<GraphEntry> graphs;
 };
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// memory
+// ---------------------------------------------------------------------------
 int dev_alloc(os_ann_index* ix, void** p, size_t bytes, const char* what) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
@@ -83,14 +124,25 @@ int dev_alloc(os_ann_index* ix, void** p, size_t bytes, const char* what) {
     return OS_ANN_OK;
 }
 
+void drop_graphs(os_ann_index* ix) {
+    for (auto& g : ix->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    ix->graphs.clear();
+}
+
 void release(os_ann_index* ix) {
     if (!ix) return;
     for (auto& t : ix->timed) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
     }
-    void* ptrs[] = {ix->row_cone, ix->row_top, ix->perm, ix->offsets, ix->planes,
-                    ix->lexsub,   ix->maskord, ix->scratch};
+    drop_graphs(ix);
+    void* ptrs[] = {ix->row_cone, ix->row_top,  ix->perm,       ix->sorted_cone, ix->offsets,
+                    ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
+                    ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
+                    ix->lp.prow,  ix->lp.iperm};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete ix;
@@ -107,30 +159,101 @@ int check_shape(int64_t N, int32_t D, int32_t L, int64_t* n_cones) {
 }
 
 bool dtype_ok(int32_t t) { return t == kF32 || t == kF16 || t == kU8; }
+bool rerank_ok(int32_t r) { return r == 4 || r == 8 || r == 16; }
 
-// Scratch layout of one search: FP32 query copy, probe descriptors, probe
-// counts, candidate counts.
+// Builds the low-precision copy once per index.
+int ensure_lowp(os_ann_index* ix, hipStream_t s) {
+    std::lock_guard<std::mutex> g(ix->lowp_mu);
+    LowpCopy& lp = ix->lp;
+    if (lp.ready) return OS_ANN_OK;
+    const int64_t nc = ix->n_cones;
+    lp.dk = (int)align_up((size_t)ix->D, 32);
+    lp.f16 = ix->dtype == kF16;
+    uint32_t* tmp = nullptr;
+    const int64_t scan_words = exclusive_scan_tmp_words(nc);
+    int rc = dev_alloc(ix, (void**)&lp.poff, (size_t)(nc + 1) * 4, "poff");
+    if (!rc) rc = dev_alloc(ix, (void**)&lp.ne_id, (size_t)(nc + 1) * 4, "ne_id");
+    if (!rc) rc = dev_alloc(ix, (void**)&lp.ne_cone, (size_t)nc * 4, "ne_cone");
+    if (!rc) rc = dev_alloc(nullptr, (void**)&tmp, (size_t)(2 * nc + scan_words) * 4, "lowp scratch");
+    if (rc) return rc;
+    auto done = [&](int code) {
+        if (tmp) (void)hipFree(tmp);
+        return code;
+    };
+    hipError_t e = launch_lowp_layout(ix->offsets, nc, tmp, tmp + nc, tmp + 2 * nc, lp.poff, lp.ne_id,
+                                      lp.ne_cone, s);
+    uint32_t np32 = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&np32, lp.poff + nc, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(hip_fail(e, "low-precision layout"));
+    lp.np = np32;
+    const int64_t rows = lp.np + 16;  // 16 zero rows past the end
+    rc = dev_alloc(ix, (void**)&lp.xl, (size_t)rows * lp.dk * 2, "xl");
+    if (!rc) rc = dev_alloc(ix, (void**)&lp.nrm, (size_t)rows * 4, "nrm");
+    if (!rc) rc = dev_alloc(ix, (void**)&lp.prow, (size_t)rows * 4, "prow");
+    if (!rc) rc = dev_alloc(ix, (void**)&lp.iperm, (size_t)ix->N * 4, "iperm");
+    if (rc) return done(rc);
+    e = hipMemsetAsync(lp.xl, 0, (size_t)rows * lp.dk * 2, s);
+    if (e == hipSuccess) e = launch_fill_u32(lp.prow, rows, 0xFFFFFFFFu, s);
+    if (e == hipSuccess)
+        e = launch_lowp_rows(ix->planes, ix->dtype, ix->N, ix->D, ix->nch, ix->sorted_cone, ix->offsets, lp.poff,
+                             ix->perm, lp.dk, lp.f16, lp.xl, lp.prow, lp.iperm, lp.nrm, rows, s);
+    if (e == hipSuccess) e = tiled_screen_max_lds(kTabBytesMax + 4096);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(hip_fail(e, "low-precision copy"));
+    lp.ready = true;
+    return done(OS_ANN_OK);
+}
+
+// ---------------------------------------------------------------------------
+// search plans: byte offsets inside one scratch buffer
+// ---------------------------------------------------------------------------
 struct SearchPlan {
-    int64_t Q = 0, cap = 0;
-    int dpad = 0;
-    size_t off_yf = 0, off_desc = 0, off_np = 0, off_nc = 0, bytes = 0;
+    int64_t Q = 0;
+    int dpad = 0, mode = OS_ANN_MODE_FP32, R = 8;
+    size_t off_yf = 0, off_order = 0, off_sbit = 0, off_jstop = 0, off_np = 0, off_nc = 0;
+    // tiled mode
+    int dk = 0, smin = 1, smax = 1;
+    int64_t T = 0;
+    size_t off_ql = 0, off_qcone = 0, off_sort = 0, off_qorder = 0, off_qsorted = 0, off_part = 0,
+           off_counter = 0;
+    size_t bytes = 0;
 };
 
-SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget) {
+SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int mode, int R) {
     SearchPlan p;
     p.Q = Q;
+    p.mode = mode;
+    p.R = R;
     p.dpad = ix->nch * ix->epc;
-    p.cap = budget >= ix->N ? 1 : (budget < ix->n_nonempty ? budget : ix->n_nonempty);
-    if (p.cap < 1) p.cap = 1;
     size_t at = 0;
-    p.off_yf = at;
-    at = align_up(at + (size_t)Q * p.dpad * sizeof(float), 256);
-    p.off_desc = at;
-    at = align_up(at + (size_t)Q * p.cap * sizeof(uint2), 256);
-    p.off_np = at;
-    at = align_up(at + (size_t)Q * sizeof(uint32_t), 256);
-    p.off_nc = at;
-    at = align_up(at + (size_t)Q * sizeof(int64_t), 256);
+    auto take = [&](size_t bytes) {
+        const size_t here = at;
+        at = align_up(at + bytes, 256);
+        return here;
+    };
+    p.off_yf = take((size_t)Q * p.dpad * sizeof(float));
+    p.off_order = take((size_t)Q * ix->D);
+    p.off_sbit = take((size_t)Q * ix->D);
+    p.off_jstop = take((size_t)Q * sizeof(uint32_t));
+    p.off_np = take((size_t)Q * sizeof(uint32_t));
+    p.off_nc = take((size_t)Q * sizeof(int64_t));
+    if (mode == OS_ANN_MODE_TILED) {
+        p.dk = (int)align_up((size_t)ix->D, 32);
+        p.T = (Q + kTileQ - 1) / kTileQ;
+        const int64_t ne = ix->n_nonempty > 0 ? ix->n_nonempty : 1;
+        p.smin = (int)pow2_ceil((ne * 8 + (int64_t)kTabBytesMax - 1) / (int64_t)kTabBytesMax);
+        const int64_t want = (4 * (int64_t)ix->num_cu + p.T - 1) / (p.T > 0 ? p.T : 1);
+        p.smax = (int)std::max<int64_t>(p.smin, std::min<int64_t>(16, pow2_ceil(std::max<int64_t>(want, 1))));
+        while (p.smax > p.smin && p.smax > ne) p.smax >>= 1;
+        p.off_ql = take((size_t)Q * p.dk * 2);
+        p.off_qcone = take((size_t)Q * 4);
+        p.off_sort = take((size_t)(4 * Q + radix_hist_words(Q)) * 4);
+        p.off_qorder = take((size_t)Q * 4);
+        p.off_qsorted = take((size_t)Q * 4);
+        p.off_part = take((size_t)Q * p.smax * R * 8);
+        p.off_counter = take(256);
+    }
     p.bytes = at;
     return p;
 }
@@ -139,13 +262,15 @@ int search_checks(const os_ann_index* ix, const void* queries, int64_t Q, int64_
                   const os_ann_search_opts* o) {
     if (!ix) return fail(OS_ANN_EINVAL, "null index");
     if (Q < 0) return fail(OS_ANN_EINVAL, "Q must be >= 0");
+    if (Q >= (int64_t(1) << 31)) return fail(OS_ANN_EINVAL, "Q must be below 2^31");
     if (budget < 1) return fail(OS_ANN_EINVAL, "max_candidates must be >= 1");
     if (Q > 0 && !queries) return fail(OS_ANN_EINVAL, "null queries");
     if (o) {
         if (!dtype_ok(o->query_dtype)) return fail(OS_ANN_EINVAL, "bad query dtype");
         if (o->mode != OS_ANN_MODE_FP32 && o->mode != OS_ANN_MODE_TILED)
             return fail(OS_ANN_EINVAL, "bad mode");
-        if (o->mode == OS_ANN_MODE_TILED) return fail(OS_ANN_EINVAL, "tiled mode is not available");
+        if (o->mode == OS_ANN_MODE_TILED && !rerank_ok(o->rerank_r ? o->rerank_r : 8))
+            return fail(OS_ANN_EINVAL, "rerank_r must be 4, 8 or 16");
     }
     return OS_ANN_OK;
 }
@@ -166,6 +291,8 @@ int get_scratch(os_ann_index* ix, const os_ann_search_opts* o, size_t bytes, cha
             ix->device_bytes -= ix->scratch_bytes;
             ix->scratch = nullptr;
             ix->scratch_bytes = 0;
+            std::lock_guard<std::mutex> gg(ix->graph_mu);  // graphs captured the old scratch
+            drop_graphs(ix);
         }
         const size_t want = align_up(bytes + bytes / 4, 1 << 20);
         int rc = dev_alloc(ix, &ix->scratch, want, "search scratch");
@@ -196,13 +323,309 @@ hipError_t timed_launch(os_ann_index* ix, bool on, int kernel, hipStream_t s, F&
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// autotuner of the tiled path: number of cone splits per query tile
+// ---------------------------------------------------------------------------
+struct Tuner {
+    std::mutex mu;
+    bool loaded = false;
+    std::map<std::string, int> best;
+
+    static const char* path() { return std::getenv("OSANN_TUNE_FILE"); }
+
+    void load_locked() {
+        if (loaded) return;
+        loaded = true;
+        const char* p = path();
+        if (!p) return;
+        FILE* f = std::fopen(p, "r");
+        if (!f) return;
+        char key[256];
+        int s = 0;
+        double ms = 0;
+        while (std::fscanf(f, "%255s %d %lf", key, &s, &ms) == 3) best[key] = s;
+        std::fclose(f);
+    }
+    int get(const std::string& k) {
+        std::lock_guard<std::mutex> g(mu);
+        load_locked();
+        auto it = best.find(k);
+        return it == best.end() ? 0 : it->second;
+    }
+    void put(const std::string& k, int s, double ms) {
+        std::lock_guard<std::mutex> g(mu);
+        load_locked();
+        best[k] = s;
+        if (const char* p = path()) {
+            if (FILE* f = std::fopen(p, "a")) {
+                std::fprintf(f, "%s %d %.4f\n", k.c_str(), s, ms);
+                std::fclose(f);
+            }
+        }
+    }
+};
+Tuner g_tuner;
+
+std::string tune_key(const os_ann_index* ix, const SearchPlan& p, int64_t budget) {
+    const int64_t qb = pow2_ceil(p.Q);
+    const int64_t bb = pow2_ceil(std::min<int64_t>(budget, ix->N));
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "gfx950:D%d:L%d:t%d:R%d:ne%lld:N%lld:Q%lld:B%lld", ix->D, ix->L, ix->dtype,
+                  p.R, (long long)ix->n_nonempty, (long long)pow2_ceil(ix->N), (long long)qb, (long long)bb);
+    return buf;
+}
+
+// ---------------------------------------------------------------------------
+// launch sequences
+// ---------------------------------------------------------------------------
+struct Call {
+    os_ann_index* ix;
+    const void* queries;
+    int qtype;
+    int64_t Q, budget;
+    int64_t* out_idx;
+    float* out_dist;
+    int64_t* out_ncand;
+    char* base;
+    SearchPlan p;
+    bool timing;
+    hipStream_t s;
+};
+
+ProbeArgs probe_args(const Call& c) {
+    const os_ann_index* ix = c.ix;
+    ProbeArgs pa{};
+    pa.Y = c.queries;
+    pa.qtype = c.qtype;
+    pa.Q = c.Q;
+    pa.D = ix->D;
+    pa.L = ix->L;
+    pa.offsets = ix->offsets;
+    pa.n_cones = ix->n_cones;
+    pa.n_sub = ix->n_sub;
+    pa.N = ix->N;
+    pa.budget = c.budget;
+    pa.lexsub = ix->lexsub;
+    pa.maskord = ix->maskord;
+    pa.binom = ix->binom;
+    pa.yf = reinterpret_cast<float*>(c.base + c.p.off_yf);
+    pa.dpad = c.p.dpad;
+    pa.order = reinterpret_cast<uint8_t*>(c.base + c.p.off_order);
+    pa.sbit = reinterpret_cast<uint8_t*>(c.base + c.p.off_sbit);
+    pa.jstop = reinterpret_cast<uint32_t*>(c.base + c.p.off_jstop);
+    pa.nprobe = reinterpret_cast<uint32_t*>(c.base + c.p.off_np);
+    pa.ncand = c.out_ncand ? c.out_ncand : reinterpret_cast<int64_t*>(c.base + c.p.off_nc);
+    if (c.p.mode == OS_ANN_MODE_TILED) {
+        pa.ql = reinterpret_cast<uint16_t*>(c.base + c.p.off_ql);
+        pa.dk = c.p.dk;
+        pa.ql_f16 = ix->lp.f16;
+        pa.q_cone = reinterpret_cast<uint32_t*>(c.base + c.p.off_qcone);
+    }
+    return pa;
+}
+
+hipError_t enqueue_fp32(const Call& c) {
+    os_ann_index* ix = c.ix;
+    const ProbeArgs pa = probe_args(c);
+    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] { return launch_probe(pa, c.s); });
+    if (e != hipSuccess) return e;
+    ScanArgs sa{};
+    sa.planes = ix->planes;
+    sa.dtype = ix->dtype;
+    sa.N = ix->N;
+    sa.D = ix->D;
+    sa.L = ix->L;
+    sa.nch = ix->nch;
+    sa.yf = pa.yf;
+    sa.Q = c.Q;
+    sa.order = pa.order;
+    sa.sbit = pa.sbit;
+    sa.jstop = pa.jstop;
+    sa.offsets = ix->offsets;
+    sa.n_sub = ix->n_sub;
+    sa.lexsub = ix->lexsub;
+    sa.maskord = ix->maskord;
+    sa.binom = ix->binom;
+    sa.perm = ix->perm;
+    sa.out_idx = c.out_idx;
+    sa.out_dist = c.out_dist;
+    const int64_t expect = std::min<int64_t>(c.budget, ix->N);
+    sa.waves_per_query = expect <= 8192 ? 1 : 4;
+    return timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] { return launch_scan_fp32(sa, c.s); });
+}
+
+hipError_t enqueue_tiled(const Call& c, int S) {
+    os_ann_index* ix = c.ix;
+    const SearchPlan& p = c.p;
+    const ProbeArgs pa = probe_args(c);
+    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] { return launch_probe(pa, c.s); });
+    if (e != hipSuccess) return e;
+    uint32_t* qorder = reinterpret_cast<uint32_t*>(c.base + p.off_qorder);
+    e = launch_sort_by_cone(pa.q_cone, c.Q, ix->n_cones, reinterpret_cast<uint32_t*>(c.base + p.off_sort), qorder,
+                            reinterpret_cast<uint32_t*>(c.base + p.off_qsorted), c.s);
+    if (e != hipSuccess) return e;
+    uint32_t* counter = reinterpret_cast<uint32_t*>(c.base + p.off_counter);
+    e = launch_fill_u32(counter, 1, 0u, c.s);
+    if (e != hipSuccess) return e;
+    TiledArgs ta{};
+    ta.xl = ix->lp.xl;
+    ta.dk = ix->lp.dk;
+    ta.nrm = ix->lp.nrm;
+    ta.prow = ix->lp.prow;
+    ta.poff = ix->lp.poff;
+    ta.offsets = ix->offsets;
+    ta.ne_id = ix->lp.ne_id;
+    ta.ne_cone = ix->lp.ne_cone;
+    ta.n_ne = ix->n_nonempty;
+    ta.lexsub = ix->lexsub;
+    ta.maskord = ix->maskord;
+    ta.binom = ix->binom;
+    ta.n_sub = ix->n_sub;
+    ta.D = ix->D;
+    ta.L = ix->L;
+    ta.ql = pa.ql;
+    ta.Q = c.Q;
+    ta.qorder = qorder;
+    ta.order = pa.order;
+    ta.sbit = pa.sbit;
+    ta.jstop = pa.jstop;
+    ta.T = p.T;
+    ta.S = S;
+    ta.counter = counter;
+    ta.part = reinterpret_cast<uint2*>(c.base + p.off_part);
+    const size_t lds = (size_t)((ix->n_nonempty + S - 1) / S) * 8;
+    int occ = tiled_screen_occupancy(p.R, ix->lp.f16, ix->lp.dk / 32, lds);
+    if (occ < 1) occ = 1;
+    const int64_t items = p.T * S;
+    const int blocks = (int)std::min<int64_t>(items, (int64_t)occ * ix->num_cu);
+    e = timed_launch(ix, c.timing, OS_ANN_KERNEL_SCREEN, c.s,
+                     [&] { return launch_tiled_screen(ta, p.R, ix->lp.f16, blocks, c.s); });
+    if (e != hipSuccess) return e;
+    FinishArgs fa{};
+    fa.part = ta.part;
+    fa.S = S;
+    fa.Q = c.Q;
+    fa.planes = ix->planes;
+    fa.dtype = ix->dtype;
+    fa.N = ix->N;
+    fa.nch = ix->nch;
+    fa.iperm = ix->lp.iperm;
+    fa.yf = pa.yf;
+    fa.dpad = p.dpad;
+    fa.out_idx = c.out_idx;
+    fa.out_dist = c.out_dist;
+    return timed_launch(ix, c.timing, OS_ANN_KERNEL_FINISH, c.s, [&] { return launch_tiled_finish(fa, p.R, c.s); });
+}
+
+// Picks the split count of the tiled path: OSANN_TILED_SPLITS if it names a
+// valid candidate, else the cached choice, else timed over the candidates
+// (every candidate computes the same result, so the outputs of the last run
+// are valid), else (during capture) the smallest candidate.
+int choose_splits(Call& c, bool may_time, hipError_t* err) {
+    const SearchPlan& p = c.p;
+    *err = hipSuccess;
+    if (const char* env = std::getenv("OSANN_TILED_SPLITS")) {  // fixed split count (testing)
+        const int v = std::atoi(env);
+        if (v >= p.smin && v <= p.smax && (v & (v - 1)) == 0) return v;
+    }
+    if (p.smin == p.smax) return p.smin;
+    const std::string key = tune_key(c.ix, p, c.budget);
+    if (int s = g_tuner.get(key)) {
+        if (s >= p.smin && s <= p.smax) return s;
+    }
+    if (!may_time) return p.smin;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    int best_s = p.smin;
+    float best_ms = 1e30f;
+    const bool timing = c.timing;
+    c.timing = false;
+    for (int s = p.smin; s <= p.smax && e == hipSuccess; s <<= 1) {
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first run warms caches
+            e = hipEventRecord(a, c.s);
+            if (e == hipSuccess) e = enqueue_tiled(c, s);
+            if (e == hipSuccess) e = hipEventRecord(b, c.s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e == hipSuccess && rep == 1 && ms < best_ms) {
+                best_ms = ms;
+                best_s = s;
+            }
+        }
+    }
+    c.timing = timing;
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    *err = e;
+    if (e == hipSuccess) g_tuner.put(key, best_s, best_ms);
+    return best_s;
+}
+
+hipError_t enqueue(const Call& c, int S) {
+    return c.p.mode == OS_ANN_MODE_TILED ? enqueue_tiled(c, S) : enqueue_fp32(c);
+}
+
+// Replays (or captures, then replays) the whole launch sequence of a call.
+int run_graph(Call& c, int S) {
+    os_ann_index* ix = c.ix;
+    std::vector<int64_t> key = {c.p.mode,
+                                c.p.R,
+                                S,
+                                c.Q,
+                                c.budget,
+                                c.qtype,
+                                (int64_t)(intptr_t)c.queries,
+                                (int64_t)(intptr_t)c.out_idx,
+                                (int64_t)(intptr_t)c.out_dist,
+                                (int64_t)(intptr_t)c.out_ncand,
+                                (int64_t)(intptr_t)c.base,
+                                (int64_t)(intptr_t)c.s};
+    std::lock_guard<std::mutex> g(ix->graph_mu);
+    GraphEntry* hit = nullptr;
+    for (auto& e : ix->graphs)
+        if (e.key == key) hit = &e;
+    if (!hit) {
+        GraphEntry ne;
+        ne.key = key;
+        Call cc = c;
+        cc.timing = false;
+        OSANN_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal), "graph capture");
+        hipError_t e = enqueue(cc, S);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c.s, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+        }
+        ne.graph = graph;
+        e = hipGraphInstantiate(&ne.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "graph instantiate");
+        }
+        if (ix->graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(ix->graphs.front().exec);
+            (void)hipGraphDestroy(ix->graphs.front().graph);
+            ix->graphs.erase(ix->graphs.begin());
+        }
+        ix->graphs.push_back(ne);
+        hit = &ix->graphs.back();
+    }
+    hipGraphExec_t exec = hit->exec;
+    OSANN_HIP(timed_launch(ix, c.timing, OS_ANN_KERNEL_GRAPH, c.s, [&] { return hipGraphLaunch(exec, c.s); }),
+              "graph launch");
+    return OS_ANN_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 int os_ann_last_error(void) { return g_err; }
 const char* os_ann_last_error_message(void) { return g_msg.c_str(); }
-const char* os_ann_version(void) { return "osann 0.1 gfx950"; }
+const char* os_ann_version(void) { return "osann 0.2 gfx950"; }
 
 os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L,
                               const os_ann_build_opts* opts) {
@@ -230,6 +653,9 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L,
     ix->epc = chunk_elems(dtype);
     ix->nch = (D + ix->epc - 1) / ix->epc;
     (void)hipGetDevice(&ix->device);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ix->device) == hipSuccess && ncu > 0)
+        ix->num_cu = ncu;
 
     uint32_t* tmp = nullptr;
     uint32_t* small = nullptr;  // [0] non-finite flag, [1] non-empty count
@@ -243,11 +669,13 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L,
     if (dev_alloc(ix, (void**)&ix->row_cone, n * 4, "row_cone") ||
         dev_alloc(ix, (void**)&ix->row_top, n * 8, "row_top") ||
         dev_alloc(ix, (void**)&ix->perm, n * 4, "perm") ||
+        dev_alloc(ix, (void**)&ix->sorted_cone, n * 4, "sorted_cone") ||
         dev_alloc(ix, (void**)&ix->offsets, (size_t)(nc + 1) * 4, "offsets") ||
         dev_alloc(ix, &ix->planes, (size_t)ix->nch * n * 16, "planes") ||
         dev_alloc(ix, (void**)&ix->lexsub, (size_t)ix->n_sub * L, "lexsub") ||
         dev_alloc(ix, (void**)&ix->maskord, 128, "maskord") ||
-        dev_alloc(nullptr, (void**)&tmp, (size_t)(5 * N + radix_hist_words(N)) * 4, "sort scratch") ||
+        dev_alloc(ix, (void**)&ix->binom, 256 * 8 * 4, "binom") ||
+        dev_alloc(nullptr, (void**)&tmp, (size_t)(4 * N + radix_hist_words(N)) * 4, "sort scratch") ||
         dev_alloc(nullptr, (void**)&small, 16, "flags"))
         return bail(0);
 
@@ -258,13 +686,13 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L,
         }
         return true;
     };
-    uint32_t* sorted_cone = tmp + 4 * N + radix_hist_words(N);
     if (!step(hipMemsetAsync(small, 0, 16, s), "memset") ||
         !step(launch_row_keys(db, dtype, N, D, L, ix->row_cone, ix->row_top, small, s), "key kernel") ||
-        !step(launch_sort_by_cone(ix->row_cone, N, nc, tmp, ix->perm, sorted_cone, s), "radix sort") ||
-        !step(launch_offsets(sorted_cone, N, nc, ix->offsets, s), "offsets") ||
+        !step(launch_sort_by_cone(ix->row_cone, N, nc, tmp, ix->perm, ix->sorted_cone, s), "radix sort") ||
+        !step(launch_offsets(ix->sorted_cone, N, nc, ix->offsets, s), "offsets") ||
         !step(launch_gather_planes(db, dtype, N, D, ix->perm, ix->planes, s), "gather") ||
         !step(launch_probe_tables(D, L, ix->lexsub, ix->maskord, s), "probe tables") ||
+        !step(launch_binom_table(ix->binom, s), "binomial table") ||
         !step(launch_count_nonempty(ix->offsets, nc, small + 1, s), "count"))
         return bail(0);
     uint32_t host_small[2] = {0, 0};
@@ -278,6 +706,8 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L,
     ix->n_nonempty = host_small[1];
     (void)hipFree(tmp);
     (void)hipFree(small);
+    tmp = small = nullptr;
+    if (opts && opts->want_lowp && ensure_lowp(ix, s)) return bail(0);
     return ix;
 }
 
@@ -290,10 +720,11 @@ void os_ann_free(os_ann_index* idx) { release(idx); }
 int64_t os_ann_workspace_bytes(const os_ann_index* idx, int64_t Q, int64_t max_candidates,
                                const os_ann_search_opts* opts) {
     clear_error();
-    if (!idx) return fail(OS_ANN_EINVAL, "null index");
-    if (Q < 0 || max_candidates < 1) return fail(OS_ANN_EINVAL, "bad Q or max_candidates");
-    if (opts && opts->mode == OS_ANN_MODE_TILED) return fail(OS_ANN_EINVAL, "tiled mode is not available");
-    return (int64_t)plan_search(idx, Q, max_candidates).bytes;
+    int rc = search_checks(idx, idx, Q, max_candidates, opts);
+    if (rc) return rc;
+    const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
+    const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
+    return (int64_t)plan_search(idx, Q, mode, R).bytes;
 }
 
 int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, int64_t max_candidates,
@@ -305,52 +736,33 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     if (Q == 0) return OS_ANN_OK;
     if (!out_idx || !out_dist) return fail(OS_ANN_EINVAL, "null output");
     auto* ix = const_cast<os_ann_index*>(cidx);
-    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
-    const SearchPlan p = plan_search(ix, Q, max_candidates);
-    char* base = nullptr;
-    if ((rc = get_scratch(ix, opts, p.bytes, &base))) return rc;
-
-    ProbeArgs pa{};
-    pa.Y = queries;
-    pa.qtype = opts ? opts->query_dtype : kF32;
-    pa.Q = Q;
-    pa.D = ix->D;
-    pa.L = ix->L;
-    pa.offsets = ix->offsets;
-    pa.n_cones = ix->n_cones;
-    pa.n_sub = ix->n_sub;
-    pa.N = ix->N;
-    pa.budget = max_candidates;
-    pa.lexsub = ix->lexsub;
-    pa.maskord = ix->maskord;
-    pa.yf = reinterpret_cast<float*>(base + p.off_yf);
-    pa.dpad = p.dpad;
-    pa.desc = reinterpret_cast<uint2*>(base + p.off_desc);
-    pa.cap = p.cap;
-    pa.nprobe = reinterpret_cast<uint32_t*>(base + p.off_np);
-    pa.ncand = out_ncand ? out_ncand : reinterpret_cast<int64_t*>(base + p.off_nc);
-    const bool timing = opts && (opts->flags & OS_ANN_FLAG_TIME_KERNELS);
-    OSANN_HIP(timed_launch(ix, timing, OS_ANN_KERNEL_PROBE, s, [&] { return launch_probe(pa, s); }),
-              "probe kernel");
-
-    ScanArgs sa{};
-    sa.planes = ix->planes;
-    sa.dtype = ix->dtype;
-    sa.N = ix->N;
-    sa.D = ix->D;
-    sa.nch = ix->nch;
-    sa.yf = pa.yf;
-    sa.Q = Q;
-    sa.desc = pa.desc;
-    sa.cap = p.cap;
-    sa.nprobe = pa.nprobe;
-    sa.perm = ix->perm;
-    sa.out_idx = out_idx;
-    sa.out_dist = out_dist;
-    const int64_t expect = max_candidates < ix->N ? max_candidates : ix->N;
-    sa.waves_per_query = expect <= 8192 ? 1 : 4;
-    OSANN_HIP(timed_launch(ix, timing, OS_ANN_KERNEL_SCAN, s, [&] { return launch_scan_fp32(sa, s); }),
-              "scan kernel");
+    Call c{};
+    c.ix = ix;
+    c.queries = queries;
+    c.qtype = opts ? opts->query_dtype : kF32;
+    c.Q = Q;
+    c.budget = max_candidates;
+    c.out_idx = out_idx;
+    c.out_dist = out_dist;
+    c.out_ncand = out_ncand;
+    c.s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    c.timing = opts && (opts->flags & OS_ANN_FLAG_TIME_KERNELS);
+    const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
+    const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
+    c.p = plan_search(ix, Q, mode, R);
+    if ((rc = get_scratch(ix, opts, c.p.bytes, &c.base))) return rc;
+    int S = 1;
+    if (mode == OS_ANN_MODE_TILED) {
+        if ((rc = ensure_lowp(ix, c.s))) return rc;
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        if (c.s) (void)hipStreamIsCapturing(c.s, &st);
+        hipError_t e = hipSuccess;
+        S = choose_splits(c, st == hipStreamCaptureStatusNone, &e);
+        if (e != hipSuccess) return hip_fail(e, "split autotune");
+    }
+    const bool graph = opts && (opts->flags & OS_ANN_FLAG_GRAPH) && c.s;
+    if (graph) return run_graph(c, S);
+    OSANN_HIP(enqueue(c, S), mode == OS_ANN_MODE_TILED ? "tiled search" : "fp32 search");
     return OS_ANN_OK;
 }
 
@@ -368,7 +780,7 @@ int os_ann_classify(const os_ann_index* cidx, const void* queries, int32_t query
     int rc = search_checks(cidx, queries, Q, max_candidates, &o);
     if (rc) return rc;
     if (Q == 0) return OS_ANN_OK;
-    auto* ix = const_cast<os_ann_index*>(cidx);
+    const os_ann_index* ix = cidx;
     hipStream_t s = static_cast<hipStream_t>(stream);
     ProbeArgs pa{};
     pa.Y = queries;
@@ -383,10 +795,10 @@ int os_ann_classify(const os_ann_index* cidx, const void* queries, int32_t query
     pa.budget = max_candidates;
     pa.lexsub = ix->lexsub;
     pa.maskord = ix->maskord;
+    pa.binom = ix->binom;
     pa.q_cone = q_cone;
     pa.q_top = q_top;
     pa.ncand = q_ncand;
-    pa.cap = 1;
     OSANN_HIP(launch_probe(pa, s), "probe kernel");
     return OS_ANN_OK;
 }
@@ -410,8 +822,7 @@ int os_ann_export(const os_ann_index* ix, uint32_t* row_cone, uint64_t* row_top,
 int os_ann_export_rows(const os_ann_index* ix, float* rows, void* stream) {
     clear_error();
     if (!ix || !rows) return fail(OS_ANN_EINVAL, "null argument");
-    OSANN_HIP(launch_planes_to_rows(ix->planes, ix->dtype, ix->N, ix->D, rows,
-                                    static_cast<hipStream_t>(stream)),
+    OSANN_HIP(launch_planes_to_rows(ix->planes, ix->dtype, ix->N, ix->D, rows, static_cast<hipStream_t>(stream)),
               "export rows");
     return OS_ANN_OK;
 }

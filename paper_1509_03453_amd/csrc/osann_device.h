@@ -77,6 +77,139 @@ __device__ inline uint32_t cone_of(int (&idx)[L], int (&sg)[L]) {
     return (uint32_t)((rank << L) | bits);
 }
 
+// Same as cone_of for a run-time L <= kMaxL (fixed-size arrays, guarded
+// loops, so the arrays stay in registers); binomials from a table
+// binom[n*8 + k] = C(n, k).
+__device__ inline uint32_t cone_of_rt(int L, int (&idx)[7], int (&sg)[7], const uint32_t* __restrict__ binom) {
+#pragma unroll
+    for (int a = 1; a < 7; ++a)
+#pragma unroll
+        for (int b = 6; b >= a; --b)
+            if (b < L && idx[b - 1] > idx[b]) {
+                int t = idx[b]; idx[b] = idx[b - 1]; idx[b - 1] = t;
+                t = sg[b]; sg[b] = sg[b - 1]; sg[b - 1] = t;
+            }
+    uint64_t rank = 0;
+    uint32_t bits = 0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+        if (j < L) {
+            rank += binom[idx[j] * 8 + j + 1];
+            bits = (bits << 1) | (uint32_t)sg[j];
+        }
+    return (uint32_t)((rank << L) | bits);
+}
+
+// Walk position j of a query -> cone (Section 3.B order).  The walk is laid
+// out in blocks h = 0..L of C(D,L)*C(L,h) positions: block h takes the
+// L-subsets T of rank positions in lexicographic order (lexsub) and, inside
+// each T, the sign-flip masks of popcount h in ascending value (maskord);
+// mask bit L-1-b flips the sign of component order[T_b].  order[] lists the
+// query's components by decreasing magnitude and sbit[] holds the query's
+// sign bits by component.
+__device__ inline uint32_t probe_cone(int64_t j, int L, const uint8_t* order, const uint8_t* sbit,
+                                      int64_t n_sub, const uint8_t* __restrict__ lexsub,
+                                      const uint8_t* __restrict__ maskord, const uint32_t* __restrict__ binom) {
+    int64_t t = j;
+    int mask = 0;
+    if (j >= n_sub) {  // phase B: some signs flipped
+        int64_t base = n_sub;
+        int mstart = 1;
+        uint64_t cl = 1;
+        for (int h = 1; h <= L; ++h) {
+            cl = binom[L * 8 + h];
+            const int64_t sz = n_sub * (int64_t)cl;
+            if (j < base + sz) break;
+            base += sz;
+            mstart += (int)cl;
+        }
+        const int64_t jj = j - base;
+        t = jj / (int64_t)cl;
+        mask = maskord[mstart + (int)(jj % (int64_t)cl)];
+    }
+    int idx[7], sg[7];
+#pragma unroll
+    for (int b = 0; b < 7; ++b) {
+        if (b < L) {
+            idx[b] = order[lexsub[t * L + b]];
+            sg[b] = sbit[idx[b]] ^ ((mask >> (L - 1 - b)) & 1);
+        } else {
+            idx[b] = 0;
+            sg[b] = 0;
+        }
+    }
+    return cone_of_rt(L, idx, sg, binom);
+}
+
+// 16-byte chunk of stored components -> FP32 values (exact).
+template <typename E>
+struct Unpack;
+template <>
+struct Unpack<F32> {
+    static constexpr int n = 4;
+    __device__ static void run(const uint4& v, float (&o)[4]) {
+        o[0] = __uint_as_float(v.x);
+        o[1] = __uint_as_float(v.y);
+        o[2] = __uint_as_float(v.z);
+        o[3] = __uint_as_float(v.w);
+    }
+};
+template <>
+struct Unpack<F16> {
+    static constexpr int n = 8;
+    __device__ static void run(const uint4& v, float (&o)[8]) {
+        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            o[2 * k] = F16::val((uint16_t)(wv[k] & 0xFFFFu));
+            o[2 * k + 1] = F16::val((uint16_t)(wv[k] >> 16));
+        }
+    }
+};
+template <>
+struct Unpack<U8> {
+    static constexpr int n = 16;
+    __device__ static void run(const uint4& v, float (&o)[16]) {
+        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) o[4 * k + b] = (float)((wv[k] >> (8 * b)) & 0xFFu);
+    }
+};
+
+// Squared distance between the row at sorted position `pos` of the
+// chunk-major planes and the FP32 query y (zero padded to nch chunks): in
+// ascending component order, subtraction, product and sum each rounded.
+template <typename E>
+__device__ inline float row_dist_fp32(const uint4* __restrict__ planes, int64_t N, int nch, int64_t pos,
+                                      const float* y) {
+#pragma clang fp contract(off)
+    constexpr int EPC = Unpack<E>::n;
+    float acc = 0.0f;
+    for (int c = 0; c < nch; ++c) {
+        float x[EPC];
+        Unpack<E>::run(planes[(int64_t)c * N + pos], x);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const float d = x[e] - y[c * EPC + e];
+            const float sq = d * d;
+            acc = acc + sq;
+        }
+    }
+    return acc;
+}
+
+// Round-to-nearest-even FP32 -> BF16 bits (finite inputs).
+__device__ inline uint16_t bf16_rne(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+// Round-to-nearest-even FP32 -> FP16 bits.
+__device__ inline uint16_t f16_rne(float f) {
+    return __builtin_bit_cast(uint16_t, (_Float16)f);
+}
+
 // ---------------------------------------------------------------------------
 // wave64 primitives
 // ---------------------------------------------------------------------------

@@ -71,7 +71,19 @@ hipError_t launch_widen_u32(const uint32_t* in, int64_t n, int64_t* out, hipStre
 hipError_t launch_planes_to_rows(const void* planes, int dtype, int64_t N, int D,
                                  float* rows, hipStream_t s);
 
-// Query classification and probe list (Section 3.B walk).
+// Exclusive prefix sum: out[0..n] (out[n] = total); tmp holds
+// exclusive_scan_tmp_words(n) words.
+int64_t exclusive_scan_tmp_words(int64_t n);
+hipError_t launch_exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* tmp,
+                                 hipStream_t s);
+
+// jstop value meaning "every row is a candidate" (budget >= N).
+constexpr uint32_t kWalkAll = 0xFFFFFFFFu;
+
+// Query classification and walk state (Section 3.B).  Per query the kernel
+// stores its decreasing-magnitude order and sign bits and the length of the
+// walk prefix that meets the budget; consumers regenerate the probed cones
+// from that state (probe_cone), so no per-probe list is materialised.
 struct ProbeArgs {
     const void* Y;          // queries [Q][D], dtype qtype
     int qtype;
@@ -83,12 +95,17 @@ struct ProbeArgs {
     int64_t budget;         // max_candidates
     const uint8_t* lexsub;
     const uint8_t* maskord;
-    // outputs (any may be null except where noted)
+    const uint32_t* binom;  // [256*8] C(n, k)
+    // outputs (any may be null)
     float* yf;              // [Q][dpad] FP32 copy of the queries (zero padded)
     int dpad;
-    uint2* desc;            // [Q][cap] (start position, cumulative count) of each probe
-    int64_t cap;
-    uint32_t* nprobe;       // [Q]
+    uint16_t* ql;           // [Q][dk] BF16 (or FP16) copy for the matrix-core path
+    int dk;
+    int ql_f16;             // 1: FP16 rounding, 0: BF16 rounding
+    uint8_t* order;         // [Q][D] components by decreasing magnitude
+    uint8_t* sbit;          // [Q][D] sign bit of each component
+    uint32_t* jstop;        // [Q] walk positions taken (kWalkAll: every row)
+    uint32_t* nprobe;       // [Q] non-empty cones probed
     int64_t* ncand;         // [Q]
     uint32_t* q_cone;       // [Q]
     uint64_t* q_top;        // [Q]
@@ -100,12 +117,17 @@ struct ScanArgs {
     const void* planes;
     int dtype;
     int64_t N;
-    int D, nch;             // nch = number of 16-byte chunks per row
+    int D, L, nch;          // nch = number of 16-byte chunks per row
     const float* yf;        // [Q][nch*E]
     int64_t Q;
-    const uint2* desc;
-    int64_t cap;
-    const uint32_t* nprobe;
+    const uint8_t* order;
+    const uint8_t* sbit;
+    const uint32_t* jstop;
+    const uint32_t* offsets;
+    int64_t n_sub;
+    const uint8_t* lexsub;
+    const uint8_t* maskord;
+    const uint32_t* binom;
     const uint32_t* perm;
     int64_t* out_idx;
     float* out_dist;

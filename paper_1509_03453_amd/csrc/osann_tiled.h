@@ -1,0 +1,74 @@
+// Internal interface of the matrix-core (tiled) search path and of the
+// low-precision index copy it reads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace osann {
+
+constexpr int kTileQ = 64;            // queries per tile: 4 waves x 16
+constexpr size_t kTabBytesMax = 48 * 1024;  // LDS budget of one split's cone table
+
+struct TiledArgs {
+    // low-precision index
+    const uint16_t* xl;
+    int dk;
+    const float* nrm;
+    const uint32_t* prow;
+    const uint32_t* poff;
+    const uint32_t* offsets;
+    const uint32_t* ne_id;
+    const uint32_t* ne_cone;
+    int64_t n_ne;
+    // walk tables
+    const uint8_t* lexsub;
+    const uint8_t* maskord;
+    const uint32_t* binom;
+    int64_t n_sub;
+    int D, L;
+    // queries
+    const uint16_t* ql;     // [Q][dk]
+    int64_t Q;
+    const uint32_t* qorder; // tile slot -> query
+    const uint8_t* order;   // [Q][D]
+    const uint8_t* sbit;    // [Q][D]
+    const uint32_t* jstop;  // [Q]
+    // schedule
+    int64_t T;              // tiles
+    int S;                  // splits of the non-empty cones
+    uint32_t* counter;      // work-queue head, zero before the launch
+    // output
+    uint2* part;            // [Q][S][R] (FP32 bits of d~, row)
+};
+
+struct FinishArgs {
+    const uint2* part;
+    int S;
+    int64_t Q;
+    const void* planes;
+    int dtype;
+    int64_t N;
+    int nch;
+    const uint32_t* iperm;
+    const float* yf;
+    int dpad;
+    int64_t* out_idx;
+    float* out_dist;
+};
+
+hipError_t launch_binom_table(uint32_t* tab, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_lowp_layout(const uint32_t* offsets, int64_t n_cones, uint32_t* psz_tmp, uint32_t* nef_tmp,
+                              uint32_t* scan_tmp, uint32_t* poff, uint32_t* ne_id, uint32_t* ne_cone,
+                              hipStream_t s);
+hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
+                            const uint32_t* offsets, const uint32_t* poff, const uint32_t* perm, int dk,
+                            int to_f16, uint16_t* xl, uint32_t* prow, uint32_t* iperm, float* nrm, int64_t np_total,
+                            hipStream_t s);
+hipError_t launch_tiled_screen(const TiledArgs& a, int R, int f16in, int blocks, hipStream_t s);
+hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s);
+hipError_t tiled_screen_max_lds(size_t bytes);
+int tiled_screen_occupancy(int R, int f16in, int ks, size_t lds);
+
+}  // namespace osann

@@ -4,13 +4,14 @@
 // One wave64 per query.  The wave ranks the query's components by decreasing
 // magnitude (all-pairs integer compares of packed keys, ties to the lower
 // index), derives the query's own cone, then walks the probe sequence 64
-// entries at a time:
-//   probe j -> (number of flipped signs h, lexicographic L-subset T of rank
-//   positions, flip mask) -> profile {order[t] : t in T} with the query's
-//   signs, flipped by the mask -> cone -> bucket (start, size).
-// A wave prefix sum of the bucket sizes finds the first probe at which the
-// running candidate count reaches the budget; the non-empty probes up to it
-// are compacted with a ballot and written as (start, cumulative count).
+// positions at a time:
+//   position j -> (number of flipped signs h, lexicographic L-subset T of
+//   rank positions, flip mask) -> profile {order[t] : t in T} with the
+//   query's signs, flipped by the mask -> cone -> bucket size.
+// A wave prefix sum of the bucket sizes finds the first position at which
+// the running candidate count reaches the budget.  The kernel stores the
+// query's order, sign bits and that walk length; the scans regenerate the
+// probed cones from them, so the probe list costs O(D) bytes per query.
 #include "osann_device.h"
 #include "osann_kernels.h"
 
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
     const int D = a.D;
     auto Y = static_cast<const typename E::raw*>(a.Y);
 
-    // 1. load the query, keep an FP32 copy, stage the component keys
+    // 1. load the query, keep FP32 and low-precision copies, stage the keys
     uint64_t mine[kMaxD / 64];
 #pragma unroll
     for (int m = 0; m < kMaxD / 64; ++m) {
@@ -38,10 +39,13 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
         if (qv && i < D) {
             const typename E::raw b = Y[q * D + i];
             k = comp_key(E::mag(b), i, E::neg(b));
-            if (a.yf) a.yf[q * a.dpad + i] = E::val(b);
+            const float v = E::val(b);
+            if (a.yf) a.yf[q * a.dpad + i] = v;
+            if (a.ql) a.ql[q * a.dk + i] = a.ql_f16 ? f16_rne(v) : bf16_rne(v);
             keys[w][i] = k;
-        } else if (qv && a.yf && i < a.dpad) {
-            a.yf[q * a.dpad + i] = 0.0f;
+        } else if (qv) {
+            if (a.yf && i < a.dpad) a.yf[q * a.dpad + i] = 0.0f;
+            if (a.ql && i < a.dk) a.ql[q * a.dk + i] = 0;
         }
         mine[m] = k;
     }
@@ -61,7 +65,11 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
     __syncthreads();
     if (!qv) return;  // no barrier below this point
 
-    // 3. own cone and packed top-L pairs
+    // 3. walk state, own cone and packed top-L pairs
+    for (int i = l; i < D; i += 64) {
+        if (a.order) a.order[q * D + i] = order[w][i];
+        if (a.sbit) a.sbit[q * D + i] = sbit[w][i];
+    }
     if (l == 0) {
         int idx[L], sg[L];
         uint64_t packed = 0;
@@ -75,63 +83,44 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
         const uint32_t own = cone_of<L>(idx, sg);
         if (a.q_cone) a.q_cone[q] = own;
     }
-    if (!a.desc && !a.ncand && !a.nprobe) return;
+    if (!a.jstop && !a.ncand && !a.nprobe) return;
 
-    // 4. a budget of at least N takes every cone: one descriptor for all rows
+    // 4. a budget of at least N takes every cone
     if (a.budget >= a.N) {
         if (l == 0) {
-            if (a.desc) a.desc[q * a.cap] = make_uint2(0u, (uint32_t)a.N);
-            if (a.nprobe) a.nprobe[q] = 1;
+            if (a.jstop) a.jstop[q] = kWalkAll;
+            if (a.nprobe) a.nprobe[q] = 0xFFFFFFFFu;
             if (a.ncand) a.ncand[q] = a.N;
         }
         return;
     }
 
-    // 5. walk the probe sequence until the budget is met
+    // 5. walk the probe sequence 64 positions at a time until the budget is met
     const uint64_t budget = (uint64_t)a.budget;
     uint64_t carry = 0;
-    uint32_t np = 0;
+    uint32_t np = 0, stop_at = 0;
     for (int64_t j0 = 0; j0 < a.n_cones; j0 += 64) {
         const int64_t j = j0 + l;
-        uint32_t start = 0, len = 0;
+        uint32_t len = 0;
         if (j < a.n_cones) {
-            // block h of the sequence holds C(D,L)*C(L,h) probes with h flips
-            int64_t base = 0;
-            int h = 0, mstart = 0;
-            uint64_t cl = 1;
-            for (; h <= L; ++h) {
-                cl = binom_dev(L, h);
-                const int64_t sz = a.n_sub * (int64_t)cl;
-                if (j < base + sz) break;
-                base += sz;
-                mstart += (int)cl;
-            }
-            const int64_t jj = j - base;
-            const int64_t t = jj / (int64_t)cl;
-            const int mask = a.maskord[mstart + (int)(jj % (int64_t)cl)];
-            int idx[L], sg[L];
-#pragma unroll
-            for (int b = 0; b < L; ++b) {
-                idx[b] = order[w][a.lexsub[t * L + b]];
-                sg[b] = sbit[w][idx[b]] ^ ((mask >> (L - 1 - b)) & 1);
-            }
-            const uint32_t c = cone_of<L>(idx, sg);
-            start = a.offsets[c];
-            len = a.offsets[c + 1] - start;
+            const uint32_t c = probe_cone(j, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
+            len = a.offsets[c + 1] - a.offsets[c];
         }
         const uint32_t incl = wave_incl_scan(len);
         const uint64_t tot = carry + incl;
         const uint64_t reached = __ballot(j < a.n_cones && tot >= budget);
         const int stop = reached ? __ffsll((unsigned long long)reached) - 1 : 63;
-        const bool take = j < a.n_cones && l <= stop && len > 0;
-        const uint64_t tm = __ballot(take);
-        const uint32_t slot = np + (uint32_t)__popcll(tm & lanemask_lt());
-        if (take && a.desc && slot < a.cap) a.desc[q * a.cap + slot] = make_uint2(start, (uint32_t)tot);
+        const uint64_t tm = __ballot(j < a.n_cones && l <= stop && len > 0);
         np += (uint32_t)__popcll(tm);
         carry += shfl_u32(incl, stop);
-        if (reached) break;
+        if (reached) {
+            stop_at = (uint32_t)(j0 + stop + 1);
+            break;
+        }
+        stop_at = (uint32_t)(j0 + 64 < a.n_cones ? j0 + 64 : a.n_cones);
     }
     if (l == 0) {
+        if (a.jstop) a.jstop[q] = stop_at;
         if (a.nprobe) a.nprobe[q] = np;
         if (a.ncand) a.ncand[q] = (int64_t)carry;
     }

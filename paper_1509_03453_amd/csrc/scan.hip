@@ -2,9 +2,11 @@
 // short-list search that Section 3.D names as the critical cost).
 //
 // One to four waves per query.  The query sits in LDS (FP32, zero padded to
-// whole 16-byte chunks).  Lane f of the query's waves takes candidates f,
-// f + 64*w, ... of the query's flattened candidate list; a per-lane cursor
-// over the probe descriptors turns the flat index into a sorted position.
+// whole 16-byte chunks) with its walk state.  Each wave regenerates the
+// query's probed cones 64 walk positions at a time (probe_cone), keeps the
+// buckets' starts and running candidate counts in LDS, and lane f of the
+// query's waves takes candidates f, f + 64*w, ... of that chunk; a per-lane
+// cursor over the running counts turns the flat index into a sorted position.
 // Each lane then reads its row chunk by chunk from the chunk-major planes:
 // for a fixed chunk, 64 lanes on consecutive positions read 1 KiB of
 // contiguous memory, and each lane accumulates its own row's squared
@@ -18,49 +20,52 @@
 
 namespace osann {
 
-template <typename E>
-struct Unpack;
-template <>
-struct Unpack<F32> {
-    static constexpr int n = 4;
-    __device__ static void run(const uint4& v, float (&o)[4]) {
-        o[0] = __uint_as_float(v.x);
-        o[1] = __uint_as_float(v.y);
-        o[2] = __uint_as_float(v.z);
-        o[3] = __uint_as_float(v.w);
-    }
-};
-template <>
-struct Unpack<F16> {
-    static constexpr int n = 8;
-    __device__ static void run(const uint4& v, float (&o)[8]) {
-        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+// Distance of the candidate at sorted position pos, then the running
+// arg-min on (distance, original row).
+template <typename E, int NCH>
+__device__ inline void visit(const ScanArgs& a, const uint4* __restrict__ planes, const float* y, int64_t pos,
+                             float& best, uint32_t& brow) {
+#pragma clang fp contract(off)
+    constexpr int EPC = Unpack<E>::n;
+    float acc;
+    if (NCH) {
+        acc = 0.0f;
+        uint4 v[NCH ? NCH : 1];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            o[2 * k] = F16::val((uint16_t)(wv[k] & 0xFFFFu));
-            o[2 * k + 1] = F16::val((uint16_t)(wv[k] >> 16));
+        for (int c = 0; c < NCH; ++c) v[c] = planes[(int64_t)c * a.N + pos];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            float x[EPC];
+            Unpack<E>::run(v[c], x);
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const float d = x[e] - y[c * EPC + e];
+                const float sq = d * d;
+                acc = acc + sq;
+            }
         }
+    } else {
+        acc = row_dist_fp32<E>(planes, a.N, a.nch, pos, y);
     }
-};
-template <>
-struct Unpack<U8> {
-    static constexpr int n = 16;
-    __device__ static void run(const uint4& v, float (&o)[16]) {
-        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) o[4 * k + b] = (float)((wv[k] >> (8 * b)) & 0xFFu);
+    if (acc < best) {
+        best = acc;
+        brow = a.perm[pos];
+    } else if (acc == best) {
+        const uint32_t r = a.perm[pos];
+        brow = r < brow ? r : brow;
     }
-};
+}
 
 template <typename E, int NCH>
 __global__ __launch_bounds__(256) void scan_fp32_kernel(ScanArgs a) {
-#pragma clang fp contract(off)
-    constexpr int EPC = Unpack<E>::n;
     __shared__ float ys[4][kMaxD];
+    __shared__ uint8_t s_order[4][kMaxD];
+    __shared__ uint8_t s_sbit[4][kMaxD];
+    __shared__ uint32_t s_start[4][64];
+    __shared__ uint32_t s_incl[4][64];
     __shared__ float red_d[4];
     __shared__ uint32_t red_r[4];
+    constexpr int EPC = Unpack<E>::n;
     const int nch = NCH ? NCH : a.nch;
     const int wpq = a.waves_per_query;
     const int qpb = 4 / wpq;
@@ -71,59 +76,49 @@ __global__ __launch_bounds__(256) void scan_fp32_kernel(ScanArgs a) {
     const int dp = nch * EPC;
 
     for (int i = sub * 64 + l; i < dp; i += wpq * 64) ys[slot][i] = qv ? a.yf[q * dp + i] : 0.0f;
+    for (int i = sub * 64 + l; i < a.D; i += wpq * 64) {
+        s_order[slot][i] = qv ? a.order[q * a.D + i] : 0;
+        s_sbit[slot][i] = qv ? a.sbit[q * a.D + i] : 0;
+    }
     __syncthreads();
 
     float best = __builtin_huge_valf();
     uint32_t brow = 0xFFFFFFFFu;
-    if (qv) {
-        const uint2* dq = a.desc + q * a.cap;
-        const uint32_t np = a.nprobe[q];
-        const uint32_t total = np ? dq[np - 1].y : 0u;
-        const uint4* planes = static_cast<const uint4*>(a.planes);
-        const float* y = ys[slot];
-        uint32_t k = 0, prev = 0;
-        uint2 cur = np ? dq[0] : make_uint2(0u, 0u);
-        for (uint32_t f = sub * 64 + l; f < total; f += wpq * 64) {
-            while (cur.y <= f) {
-                prev = cur.y;
-                cur = dq[++k];
+    const uint4* planes = static_cast<const uint4*>(a.planes);
+    const float* y = ys[slot];
+    const uint32_t jstop = qv ? a.jstop[q] : 0u;
+    if (jstop == kWalkAll) {
+        for (int64_t f = sub * 64 + l; f < a.N; f += wpq * 64) visit<E, NCH>(a, planes, y, f, best, brow);
+    } else {
+        uint32_t* st = s_start[w];
+        uint32_t* in = s_incl[w];
+        for (uint32_t j0 = 0; j0 < jstop; j0 += 64) {
+            // this wave's copy of the chunk's bucket starts and running counts
+            const uint32_t j = j0 + l;
+            uint32_t start = 0, len = 0;
+            if (j < jstop) {
+                const uint32_t c = probe_cone(j, a.L, s_order[slot], s_sbit[slot], a.n_sub, a.lexsub, a.maskord, a.binom);
+                start = a.offsets[c];
+                len = a.offsets[c + 1] - start;
             }
-            const int64_t pos = (int64_t)cur.x + (f - prev);
-            float acc = 0.0f;
-            if (NCH) {
-                uint4 v[NCH ? NCH : 1];
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) v[c] = planes[(int64_t)c * a.N + pos];
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    float x[EPC];
-                    Unpack<E>::run(v[c], x);
-#pragma unroll
-                    for (int e = 0; e < EPC; ++e) {
-                        const float d = x[e] - y[c * EPC + e];
-                        const float sq = d * d;
-                        acc = acc + sq;
-                    }
-                }
-            } else {
-                for (int c = 0; c < nch; ++c) {
-                    float x[EPC];
-                    Unpack<E>::run(planes[(int64_t)c * a.N + pos], x);
-#pragma unroll
-                    for (int e = 0; e < EPC; ++e) {
-                        const float d = x[e] - y[c * EPC + e];
-                        const float sq = d * d;
-                        acc = acc + sq;
-                    }
-                }
+            const uint32_t incl = wave_incl_scan(len);
+            st[l] = start;
+            in[l] = incl;
+            const uint32_t total = shfl_u32(incl, 63);
+            // make the wave's LDS writes visible to its other lanes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            uint32_t k = 0;
+            for (uint32_t f = sub * 64 + l; f < total; f += wpq * 64) {
+                while (in[k] <= f) ++k;
+                const uint32_t before = k ? in[k - 1] : 0u;
+                visit<E, NCH>(a, planes, y, (int64_t)st[k] + (f - before), best, brow);
             }
-            if (acc < best) {
-                best = acc;
-                brow = a.perm[pos];
-            } else if (acc == best) {
-                const uint32_t r = a.perm[pos];
-                brow = r < brow ? r : brow;
-            }
+            // every lane is done reading before the next chunk overwrites
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
     }
     wave_argmin(best, brow);

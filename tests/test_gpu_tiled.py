@@ -1,0 +1,173 @@
+"""GPU parity of the tiled (matrix-core screening + FP32 re-rank) mode
+against the oracle's screened search on the same seeded inputs.
+
+Bit-exact: candidate counts; the returned distance equals the exact FP32
+distance of the returned row.  The screening values d~ are accumulated in
+FP32 on the GPU and in double in the oracle, so the R-th survivor may
+differ where two d~ are within rounding of the R-th one; a result row that
+differs from the oracle's must be explained by exactly such a near-tie
+(checked per query), and such queries must be rare."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1509_03453_amd import binding as B
+from paper_1509_03453_amd import workloads as W
+from tests.gpu_util import dev, gpu_search, say
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B.lib()
+
+
+def check_tiled(orc, X, Y, L, budgets, R=8, tag="", max_mismatch=0.02):
+    say(f"[tiled] {tag} N={X.shape[0]} D={X.shape[1]} L={L} Q={Y.shape[0]} R={R} dtype={X.dtype}")
+    h = B.os_ann_build_ex(dev(X), L)
+    o = orc.build_index(X, L)
+    f16 = X.dtype == np.float16
+    D = X.shape[1]
+    try:
+        for budget in budgets:
+            say(f"[tiled] {tag} budget={budget}")
+            gi, gd, gn = B.os_ann_search_ex(h, dev(Y), budget, mode=B.OS_ANN_MODE_TILED, rerank_r=R)
+            torch.cuda.synchronize()
+            gi, gd, gn = gi.cpu().numpy(), gd.cpu().numpy(), gn.cpu().numpy()
+            oi, od32, od64, on, dtr, top = orc.search_tiled(X, o, Y, budget, R=R)
+            assert np.array_equal(gn, on), tag
+            assert (gi >= 0).all() and (gi < X.shape[0]).all()
+            # the reported distance is the exact FP32 distance of the reported row
+            assert np.array_equal(gd.view(np.uint32), orc.pair_d32(X, Y, gi).view(np.uint32)), tag
+            bad = np.flatnonzero(gi != oi)
+            for q in bad:
+                xs = orc.round_short(X[[gi[q], oi[q], top[q][-1]]].astype(np.float32), f16).reshape(3, D)
+                ys = orc.round_short(Y[q].astype(np.float32), f16)
+                scale = ((xs ** 2).sum(1) + 2 * np.abs(xs * ys).sum(1)).max()
+                tol = 4 * (D + 2) * U * scale
+                t = dtr[q]
+                dg = orc.pair_dtilde(X, Y[q:q + 1], [gi[q]], f16)[0]
+                do = orc.pair_dtilde(X, Y[q:q + 1], [oi[q]], f16)[0]
+                if gi[q] in top[q]:
+                    assert do >= t - tol, (tag, q, "oracle's pick dropped without a near tie")
+                else:
+                    assert dg <= t + tol, (tag, q, "GPU kept a row beyond the R-th d~")
+            assert len(bad) <= max_mismatch * len(gi) + 1, (tag, len(bad))
+            say(f"[tiled] {tag} budget={budget} mismatches={len(bad)}/{len(gi)}")
+    finally:
+        B.os_ann_free(h)
+
+
+def test_tiled_gaussian_small_dims(orc):
+    X = W.gaussian_db(16384, 16, seed=W.SEEDS["gauss16_db"])
+    Y = W.gaussian_queries(600, 16, seed=W.SEEDS["gauss16_q"])
+    check_tiled(orc, X, Y, 1, (1, 512, 4000, 16384), tag="gauss16 L1")
+
+
+def test_tiled_gaussian_d64(orc):
+    X = W.gaussian_db(60000, 64, seed=2101)
+    Y = W.gaussian_queries(700, 64, seed=2102)
+    check_tiled(orc, X, Y, 2, (256, 1024, 8192), tag="gauss64 L2")
+
+
+@pytest.mark.parametrize("R", [4, 16])
+def test_tiled_rerank_sizes(orc, R):
+    X = W.gaussian_db(20000, 32, seed=2201)
+    Y = W.gaussian_queries(300, 32, seed=2202)
+    check_tiled(orc, X, Y, 2, (700,), R=R, tag=f"gauss32 R{R}")
+
+
+def test_tiled_descriptor_uint8(orc):
+    X = W.descriptor_db(30000, 128, seed=W.SEEDS["desc_db"])
+    Y, _ = W.descriptor_queries(X, 400)
+    check_tiled(orc, X, Y, 2, (256, 2048), tag="descriptor u8")
+
+
+def test_tiled_patches_fp16(orc):
+    img = W.patch_field(256)
+    X = W.patch_rows(img)
+    Yimg = np.roll(img, (3, 5), axis=(0, 1)) + np.random.default_rng(9).normal(0, 0.05, img.shape)
+    Y = W.patch_rows(Yimg)[::83]
+    check_tiled(orc, X, Y, 2, (64, 1024), tag="patches f16")
+
+
+def test_tiled_edges(orc):
+    X = W.gaussian_db(3000, 8, seed=2301)
+    check_tiled(orc, X, W.gaussian_queries(1, 8, seed=2302), 3, (1, 50, 3000), tag="Q=1 L3")
+    check_tiled(orc, X, W.gaussian_queries(65, 8, seed=2303), 3, (20, 2999), tag="Q=65 L3")
+    Xw = W.gaussian_db(4000, 256, seed=2304)
+    check_tiled(orc, Xw, W.gaussian_queries(70, 256, seed=2305), 1, (100, 4000), tag="D=256 L1")
+    Xr = W.gaussian_db(5000, 40, seed=2306)
+    check_tiled(orc, Xr, W.gaussian_queries(90, 40, seed=2307), 2, (300,), tag="D=40 ragged")
+    h = B.os_ann_build_ex(dev(X), 2)
+    with pytest.raises(B.OsAnnError) as e:
+        B.os_ann_search_ex(h, dev(W.gaussian_queries(3, 8, seed=1)), 10, mode=B.OS_ANN_MODE_TILED,
+                           rerank_r=5)
+    assert e.value.code == B.OS_ANN_EINVAL
+    B.os_ann_free(h)
+
+
+def test_tiled_split_and_batch_invariance(orc, monkeypatch):
+    X = W.gaussian_db(50000, 64, seed=2401)
+    Y = W.gaussian_queries(900, 64, seed=2402)
+    h = B.os_ann_build_ex(dev(X), 2)
+    yd = dev(Y)
+    outs = []
+    for splits in ("1", "2", "4", "16"):
+        monkeypatch.setenv("OSANN_TILED_SPLITS", splits)
+        say(f"[tiled] splits={splits}")
+        i, d, n = B.os_ann_search_ex(h, yd, 2000, mode=B.OS_ANN_MODE_TILED)
+        torch.cuda.synchronize()
+        outs.append((i.cpu().numpy(), d.cpu().numpy(), n.cpu().numpy()))
+    monkeypatch.delenv("OSANN_TILED_SPLITS")
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    perm = np.random.default_rng(3).permutation(900)
+    for sl in (slice(0, 1), slice(5, 69), slice(100, 900)):
+        sub = np.ascontiguousarray(Y[perm[sl]])
+        i, d, n = B.os_ann_search_ex(h, dev(sub), 2000, mode=B.OS_ANN_MODE_TILED)
+        torch.cuda.synchronize()
+        assert np.array_equal(i.cpu().numpy(), outs[0][0][perm[sl]])
+        assert np.array_equal(d.cpu().numpy(), outs[0][1][perm[sl]])
+    B.os_ann_free(h)
+
+
+@pytest.mark.parametrize("mode", [B.OS_ANN_MODE_FP32, B.OS_ANN_MODE_TILED])
+def test_graph_replay_matches_eager(orc, mode):
+    X = W.gaussian_db(40000, 64, seed=2501)
+    Y = W.gaussian_queries(500, 64, seed=2502)
+    h = B.os_ann_build_ex(dev(X), 2)
+    yd = dev(Y)
+    eager = B.os_ann_search_ex(h, yd, 1500, mode=mode)
+    torch.cuda.synchronize()
+    eager = [t.cpu().numpy() for t in eager]
+    s = torch.cuda.Stream()
+    nb = B.os_ann_workspace_bytes(h, 500, 1500, mode=mode)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    oi = torch.empty(500, dtype=torch.int64, device="cuda")
+    od = torch.empty(500, dtype=torch.float32, device="cuda")
+    on = torch.empty(500, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    for rep in range(4):
+        say(f"[graph] mode={mode} replay {rep}")
+        oi.fill_(-7)
+        od.fill_(-1.0)
+        on.fill_(-1)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            B.os_ann_search_ex(h, yd, 1500, mode=mode, stream=s, workspace=ws, out_idx=oi, out_dist=od,
+                               out_ncand=on, flags=B.OS_ANN_FLAG_GRAPH)
+        s.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(oi.cpu().numpy(), eager[0])
+        assert np.array_equal(od.cpu().numpy(), eager[1])
+        assert np.array_equal(on.cpu().numpy(), eager[2])
+        del junk
+    B.os_ann_free(h)
