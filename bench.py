@@ -3,13 +3,16 @@
 Workload: 1,000,000 database rows and 10,000 queries, D=64, i.i.d. N(0,1)
 FP32 (seeded), hashed on the L=2 largest components (8064 cones).  One step
 is the whole hot path over one batch: hash + bucket the resident database
-(index build), then classify the queries, walk their probe lists and scan
-the candidates with the FP32 arg-min.  The search budget is the smallest
-budget of a sweep whose recall@1 reaches 0.9 (exact NN from an independent
-torch GEMM + float64 refinement on the GPU).
+(index build, including the BF16 copy in tiled mode), then classify the
+queries, walk their probe lists and scan the candidates.  Both search modes
+run: plain FP32 (exact distance of every candidate) and BF16-tiled (matrix-
+core screening + exact FP32 re-rank of the top 8).  Each mode runs at the
+smallest budget of a sweep whose recall@1 reaches 0.9, with the exact NN
+from an independent torch GEMM + float64 refinement on the GPU.
 
-Prints ONE JSON line (rank 0).  Usage:
+Prints ONE JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                    [--mode fp32|tiled|both] [--budget B]
 """
 from __future__ import annotations
 
@@ -27,6 +30,8 @@ sys.path.insert(0, ROOT)
 N_DB, N_Q, DIM, L_HASH = 1_000_000, 10_000, 64, 2
 SWEEP = (256, 1024, 4096, 65536, 262144, 327680, 393216)
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
+RERANK = 8
 
 
 def log(*a):
@@ -56,26 +61,25 @@ def pair_d64_torch(db, q, rows):
     return ((db[rows].double() - q.double()) ** 2).sum(1)
 
 
-def cpu_baseline(X, Y, budget, qps_units, target_s=15.0):
+def cpu_baseline(X, Y, budget, target_s=15.0):
     """The oracle as it stands, on the host cores, on a bounded sample."""
     from oracle import oracle as O
     threads = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
     idx = O.build_index(X, L_HASH)
     t_build = time.perf_counter() - t0
-    # probe the per-query cost on a few queries, then size the sample
-    n = 8
+    n = 4 * threads
     t0 = time.perf_counter()
     O.search(X, idx, Y[:n], budget, nthreads=threads)
     per = (time.perf_counter() - t0) / n
-    n = int(max(16, min(len(Y), (target_s - t_build) / max(per, 1e-6))))
+    n = int(max(n, min(len(Y), (target_s - t_build) / max(per, 1e-6))))
     t0 = time.perf_counter()
     O.search(X, idx, Y[:n], budget, nthreads=threads)
     t_search = time.perf_counter() - t0
     t_step = t_build + t_search / n * N_Q
-    return {"value": round(N_Q / t_step, 3), "unit": qps_units, "cores": threads, "kind": "oracle",
-            "sample": f"index build over all {N_DB} rows ({t_build:.2f} s, single thread) + search of "
-                      f"the first {n} of {N_Q} queries at budget {budget} ({t_search:.2f} s, "
+    return {"value": round(N_Q / t_step, 3), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"index build over all {N_DB} rows ({t_build:.2f} s, single thread) + plain search "
+                      f"of the first {n} of {N_Q} queries at budget {budget} ({t_search:.2f} s, "
                       f"{threads} threads), scaled to one {N_Q}-query step"}
 
 
@@ -85,6 +89,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--mode", choices=("fp32", "tiled", "both"), default="both")
     ap.add_argument("--budget", type=int, default=0, help="fixed budget instead of the recall sweep")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -107,108 +112,161 @@ def main():
     log("[bench] exact NN (torch GEMM + float64 refinement)")
     _, nn_d64 = exact_nn_torch(db, q)
 
-    log("[bench] index build")
-    h = B.os_ann_build_ex(db, L_HASH)
-    info = B.os_ann_info(h)
+    modes = ("fp32", "tiled") if args.mode == "both" else (args.mode,)
+    mcode = {"fp32": B.OS_ANN_MODE_FP32, "tiled": B.OS_ANN_MODE_TILED}
+    kern = {"fp32": B.OS_ANN_KERNEL_SCAN, "tiled": B.OS_ANN_KERNEL_SCREEN}
     flags = B.OS_ANN_FLAG_TIME_KERNELS
 
-    def run(budget, timed=False):
-        i, d, n = B.os_ann_search_ex(h, q, budget, flags=flags if timed else 0)
-        return i, d, n
+    log("[bench] index build")
+    h = B.os_ann_build_ex(db, L_HASH, want_lowp="tiled" in modes)
+    info = B.os_ann_info(h)
 
-    sweep = []
-    chosen = args.budget
-    for budget in ([args.budget] if args.budget else SWEEP):
-        i, d, n = run(budget)
+    def clear_times(hh):
+        for k in range(5):
+            B.os_ann_kernel_time(hh, k)
+
+    results = {}
+    for m in modes:
+        sweep, chosen = [], args.budget
+        for budget in ([args.budget] if args.budget else SWEEP):
+            B.os_ann_search_ex(h, q, budget, mode=mcode[m], rerank_r=RERANK)  # warm (and tune)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            i, d, n = B.os_ann_search_ex(h, q, budget, mode=mcode[m], rerank_r=RERANK)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            d64 = pair_d64_torch(db, q, i)
+            recall = float((d64 == nn_d64).double().mean())
+            rel = (d.double() - d64).abs() / d64.clamp_min(1e-300)
+            sweep.append({"budget": budget, "recall_at_1": round(recall, 4),
+                          "mean_ncand": round(float(n.double().mean()), 1),
+                          "speedup_vs_linear": round(N_DB / float(n.double().mean()), 2),
+                          "search_ms": round(ms, 3), "search_qps": round(N_Q / ms * 1e3, 1),
+                          "max_rel_err_vs_fp64": float(rel.max())})
+            log(f"[bench] {m} sweep {sweep[-1]}")
+            if not chosen and recall >= 0.9:
+                chosen = budget
+                break
+        results[m] = {"sweep": sweep, "budget": chosen or SWEEP[-1]}
+    clear_times(h)
+
+    # search-only time with hipGraph replay on a side stream
+    side = torch.cuda.Stream()
+    for m in modes:
+        budget = results[m]["budget"]
+        nb = B.os_ann_workspace_bytes(h, N_Q, budget, mode=mcode[m], rerank_r=RERANK)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        oi = torch.empty(N_Q, dtype=torch.int64, device="cuda")
+        od = torch.empty(N_Q, dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        i, d, n = run(budget)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
-        d64 = pair_d64_torch(db, q, i)
-        recall = float((d64 == nn_d64).double().mean())
-        rel = ((d.double() - d64).abs() / d64.clamp_min(1e-300))
-        sweep.append({"budget": budget, "recall_at_1": round(recall, 4),
-                      "mean_ncand": round(float(n.double().mean()), 1),
-                      "speedup_vs_linear": round(N_DB / float(n.double().mean()), 2),
-                      "search_ms": round(ms, 3), "search_qps": round(N_Q / ms * 1e3, 1),
-                      "max_rel_err_vs_fp64": float(rel.max())})
-        log(f"[bench] sweep {sweep[-1]}")
-        if not chosen and recall >= 0.9:
-            chosen = budget
-            break
-    if not chosen:
-        chosen = SWEEP[-1]
-    pick = [s for s in sweep if s["budget"] == chosen][0]
-    B.os_ann_kernel_time(h, B.OS_ANN_KERNEL_SCAN)  # drop any earlier records
-    B.os_ann_kernel_time(h, B.OS_ANN_KERNEL_PROBE)
+        reps = 5
+        for r in range(reps + 1):
+            if r == 1:
+                side.synchronize()
+                t0 = time.perf_counter()
+            with torch.cuda.stream(side):
+                B.os_ann_search_ex(h, q, budget, mode=mcode[m], rerank_r=RERANK, stream=side, workspace=ws,
+                                   out_idx=oi, out_dist=od, want_ncand=False, flags=B.OS_ANN_FLAG_GRAPH)
+        side.synchronize()
+        results[m]["search_graph_ms"] = round((time.perf_counter() - t0) * 1e3 / reps, 3)
+        del ws
     B.os_ann_free(h)
 
     # ---- timed steps: build + search of the whole batch ----
-    def step(timed):
-        hh = B.os_ann_build_ex(db, L_HASH)
-        i, d, n = B.os_ann_search_ex(hh, q, chosen, flags=flags if timed else 0)
-        return hh, n
+    for m in modes:
+        budget = results[m]["budget"]
 
-    log(f"[bench] warmup {args.warmup} steps, budget {chosen}")
-    for _ in range(args.warmup):
-        hh, _ = step(False)
-        torch.cuda.synchronize()
-        B.os_ann_free(hh)
-    step_ms, scan_ms, probe_ms, scan_bytes = [], [], [], []
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        hh, n = step(True)
-        torch.cuda.synchronize()
-        step_ms.append((time.perf_counter() - t0) * 1e3)
-        ns, ms_s = B.os_ann_kernel_time(hh, B.OS_ANN_KERNEL_SCAN)
-        npb, ms_p = B.os_ann_kernel_time(hh, B.OS_ANN_KERNEL_PROBE)
-        scan_ms.append(ms_s / max(ns, 1))
-        probe_ms.append(ms_p / max(npb, 1))
-        # algorithmic bytes of the scan: candidate rows + query + result + winner's row id
-        scan_bytes.append(float(n.double().sum()) * DIM * 4 + N_Q * (DIM * 4 + 12 + 8))
-        B.os_ann_free(hh)
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - t_all
-    ms_per_step = total_s * 1e3 / args.steps
-    value = N_Q / (ms_per_step / 1e3)
-    scan_avg_ms = float(np.mean(scan_ms))
-    achieved = float(np.mean(scan_bytes)) / (scan_avg_ms / 1e3) / 1e9
+        def step(timed):
+            hh = B.os_ann_build_ex(db, L_HASH, want_lowp=(m == "tiled"))
+            i, d, n = B.os_ann_search_ex(hh, q, budget, mode=mcode[m], rerank_r=RERANK,
+                                         flags=flags if timed else 0)
+            return hh, n
 
+        log(f"[bench] {m}: warmup {args.warmup} steps, budget {budget}")
+        for _ in range(args.warmup):
+            hh, _ = step(False)
+            torch.cuda.synchronize()
+            B.os_ann_free(hh)
+        step_ms, kern_ms, probe_ms, ncand_sum = [], [], [], []
+        extra_ms = []
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            hh, n = step(True)
+            torch.cuda.synchronize()
+            step_ms.append((time.perf_counter() - t0) * 1e3)
+            nk, msk = B.os_ann_kernel_time(hh, kern[m])
+            npb, msp = B.os_ann_kernel_time(hh, B.OS_ANN_KERNEL_PROBE)
+            nf, msf = B.os_ann_kernel_time(hh, B.OS_ANN_KERNEL_FINISH)
+            kern_ms.append(msk / max(nk, 1))
+            probe_ms.append(msp / max(npb, 1))
+            extra_ms.append(msf / max(nf, 1) if nf else 0.0)
+            ncand_sum.append(float(n.double().sum()))
+            B.os_ann_free(hh)
+        torch.cuda.synchronize()
+        total_s = time.perf_counter() - t_all
+        ms_per_step = total_s * 1e3 / args.steps
+        kavg = float(np.mean(kern_ms))
+        nsum = float(np.mean(ncand_sum))
+        if m == "fp32":
+            # candidate rows + query + result + winner's row id, per launch
+            bytes_ = nsum * DIM * 4 + N_Q * (DIM * 4 + 12 + 8)
+            ach = bytes_ / (kavg / 1e3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "scan_fp32_kernel",
+                    "algorithmic_bytes_per_launch": bytes_}
+        else:
+            # one D-long dot product (2*D flops) per (query, candidate) pair
+            flops = nsum * 2 * DIM
+            ach = flops / (kavg / 1e3) / 1e12
+            roof = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / PEAK_BF16_TFLOPS, 4), "traffic": None, "kernel": "tiled_screen_kernel",
+                    "algorithmic_flops_per_launch": flops}
+        pick = [s for s in results[m]["sweep"] if s["budget"] == budget][0]
+        results[m].update({
+            "value": round(N_Q / (ms_per_step / 1e3), 2), "ms_per_step": round(ms_per_step, 3),
+            "p50_ms": round(float(np.percentile(step_ms, 50)), 3),
+            "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
+            "recall_at_1": pick["recall_at_1"], "mean_ncand": pick["mean_ncand"],
+            "max_rel_err_vs_fp64": pick["max_rel_err_vs_fp64"],
+            "kernel_ms": {"main": round(kavg, 4), "probe": round(float(np.mean(probe_ms)), 4),
+                          "finish": round(float(np.mean(extra_ms)), 4)},
+            "roofline": roof,
+        })
+        log(f"[bench] {m}: {results[m]['value']} q/s, {ms_per_step:.3f} ms/step")
+
+    best = max(modes, key=lambda m: results[m]["value"])
+    r = results[best]
     out = {
-        "metric": "queries/sec at recall@1>=0.9 (plain FP32 scan), HBM GB/s; p50/p99 step latency",
-        "value": round(value, 2),
+        "metric": "queries/sec at recall@1>=0.9 (plain FP32 vs BF16-tiled), HBM GB/s; p50/p99 step latency",
+        "value": r["value"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if best == "tiled" else "f32",
         "data": "synthetic (seeded i.i.d. N(0,1))",
         "config": {"workload": "gaussian-1M-d64-L2: N=1000000 db rows, Q=10000 queries, D=64, "
-                               "FP32, L=2 (8064 cones), one basis",
-                   "budget": chosen, "mode": "fp32", "recall_at_1": pick["recall_at_1"],
-                   "mean_ncand": pick["mean_ncand"], "max_rel_err_vs_fp64": pick["max_rel_err_vs_fp64"],
-                   "step": "index build (key + radix bucket + permuted copy) + classify/probe + FP32 scan"},
-        "p50_ms": round(float(np.percentile(step_ms, 50)), 3),
-        "p99_ms": round(float(np.percentile(step_ms, 99)), 3),
-        "search_only_qps": pick["search_qps"],
-        "kernel_ms": {"scan_fp32": round(scan_avg_ms, 4), "probe": round(float(np.mean(probe_ms)), 4)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": "scan_fp32_kernel", "bytes_per_launch": float(np.mean(scan_bytes))},
-        "sweep": sweep,
+                               "FP32 rows, L=2 (8064 cones), one basis",
+                   "mode": best, "budget": r["budget"], "recall_at_1": r["recall_at_1"],
+                   "rerank_r": RERANK if best == "tiled" else None,
+                   "step": "index build + classify/probe + candidate scan (tiled: + BF16 copy, "
+                           "MFMA screening, FP32 re-rank)"},
+        "p50_ms": r["p50_ms"],
+        "p99_ms": r["p99_ms"],
+        "roofline": r["roofline"],
+        "modes": results,
         "index": {"n_cones": info["n_cones"], "n_nonempty": info["n_nonempty"],
                   "device_bytes": info["device_bytes"]},
     }
     if not args.no_cpu:
         log("[bench] oracle CPU baseline")
-        out["cpu_baseline"] = cpu_baseline(X, Y, chosen, "queries/s")
+        out["cpu_baseline"] = cpu_baseline(X, Y, r["budget"])
     print(json.dumps(out), flush=True)
 
 

@@ -21,7 +21,10 @@ constexpr int kRadixThreads = 256;
 constexpr int kRadixChunk = 2048;  // elements per block (8 tiles of 256)
 
 static inline int64_t radix_blocks(int64_t N) { return (N + kRadixChunk - 1) / kRadixChunk; }
-int64_t radix_hist_words(int64_t N) { return 256 * radix_blocks(N); }
+int64_t radix_hist_words(int64_t N) {
+    const int64_t h = 256 * radix_blocks(N);
+    return 2 * h + 1 + exclusive_scan_tmp_words(h);  // counts, scanned counts, scan scratch
+}
 
 __global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                                    int64_t N, int shift,
@@ -37,30 +40,6 @@ __global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint32_
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
-}
-
-// Exclusive scan of `n` words in place, one block of 1024 threads, each
-// thread owning a contiguous segment.
-__global__ __launch_bounds__(1024) void exclusive_scan_kernel(uint32_t* __restrict__ v, int64_t n) {
-    __shared__ uint32_t part[1024];
-    const int64_t seg = (n + 1023) / 1024;
-    const int64_t b = threadIdx.x * seg, e = b + seg < n ? b + seg : n;
-    uint32_t sum = 0;
-    for (int64_t i = b; i < e; ++i) sum += v[i];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {  // Hillis-Steele on the partials
-        uint32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += t;
-        __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - sum;
-    for (int64_t i = b; i < e; ++i) {
-        uint32_t x = v[i];
-        v[i] = run;
-        run += x;
-    }
 }
 
 __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
@@ -117,7 +96,10 @@ hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_co
     uint32_t* va = tmp + N;
     uint32_t* kb = tmp + 2 * N;
     uint32_t* vb = tmp + 3 * N;
-    uint32_t* hist = tmp + 4 * N;
+    const int64_t hw = 256 * nb;
+    uint32_t* hist = tmp + 4 * N;        // per (digit, block) counts
+    uint32_t* hscan = hist + hw;         // their exclusive scan (hw + 1 words)
+    uint32_t* stmp = hscan + hw + 1;     // scan scratch
     const uint32_t* kin = row_cone;
     const uint32_t* vin = nullptr;  // identity on the first pass
     for (int p = 0; p < passes; ++p) {
@@ -126,9 +108,10 @@ hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_co
         uint32_t* vout = last ? perm_out : ((p & 1) ? vb : va);
         hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin, N,
                            8 * p, hist, nb);
-        hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(1024), 0, s, hist, 256 * nb);
+        hipError_t e = launch_exclusive_scan(hist, hw, hscan, stmp, s);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin,
-                           vin, N, 8 * p, hist, nb, kout, vout);
+                           vin, N, 8 * p, hscan, nb, kout, vout);
         kin = kout;
         vin = vout;
     }

@@ -47,7 +47,8 @@ hipError_t launch_row_keys(const void* X, int dtype, int64_t N, int D, int L,
                            hipStream_t s);
 
 // Stable LSD radix sort of (cone, row) by cone; writes perm and sorted cones.
-// tmp must hold 4 arrays of N u32 plus radix_hist_words(N) u32.
+// tmp must hold 4 arrays of N u32 plus radix_hist_words(N) u32.  The scan of
+// the per-block digit counts uses launch_exclusive_scan.
 int64_t radix_hist_words(int64_t N);
 hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_cones,
                                uint32_t* tmp, uint32_t* perm_out, uint32_t* sorted_cone_out,
