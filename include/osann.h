@@ -56,7 +56,8 @@ extern "C" {
                                  bad dtype or mode; workspace too small */
 #define OS_ANN_ENOMEM     -2  /* device allocation failed */
 #define OS_ANN_EDEVICE    -3  /* a HIP runtime call or kernel launch failed */
-#define OS_ANN_ENOTSUP    -4  /* N_C = C(D,L) * 2^L above 2^24 */
+#define OS_ANN_ENOTSUP    -4  /* N_C = C(D,L) * 2^L above 2^24; tiled mode with more
+                                 non-empty cones than its LDS cone list holds */
 #define OS_ANN_ENONFINITE -5  /* NaN or infinity in the database (build only) */
 
 /* Storage types of database rows and queries. */

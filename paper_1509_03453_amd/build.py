@@ -20,8 +20,10 @@ OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libosann.so")
 ARCH = "gfx950"
 
-# Packed FP32 ops are kept off: plain scalar FP32 code only.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 ops are kept off: plain scalar FP32 code only.  MFMA results
+# go straight to VGPRs (no accumulator-register read-backs in the epilogues).
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-mfma-vgpr-form"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-command-line-argument", "-I", INCLUDE, "-I", CSRC]
 

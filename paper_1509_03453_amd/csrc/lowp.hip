@@ -7,8 +7,8 @@
 //                  FP32 and uint8 data, FP16 as stored for FP16 data; dk = D
 //                  rounded up to 32 (one MFMA K step); zero padded
 //   nrm[p]         FP32 sum of squares of the rounded row, +inf on padding rows
-//   prow[p]        original row id, 0xFFFFFFFF on padding rows
-//   iperm[row]     sorted position of each original row (exact FP32 re-rank)
+//   ppos[p]        sorted position of the row (exact FP32 re-rank from the
+//                  planes; original id via perm), 0xFFFFFFFF on padding rows
 //   ne_id[c]       rank of cone c among the non-empty cones; ne_cone is its inverse
 #include "osann_device.h"
 #include "osann_kernels.h"
@@ -71,9 +71,8 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
 template <typename E>
 __global__ void lowp_rows_kernel(const uint4* __restrict__ planes, int64_t N, int D, int nch,
                                  const uint32_t* __restrict__ sorted_cone, const uint32_t* __restrict__ off,
-                                 const uint32_t* __restrict__ poff, const uint32_t* __restrict__ perm, int dk,
-                                 int to_f16, uint16_t* __restrict__ xl, uint32_t* __restrict__ prow,
-                                 uint32_t* __restrict__ iperm) {
+                                 const uint32_t* __restrict__ poff, int dk, int to_f16,
+                                 uint16_t* __restrict__ xl, uint32_t* __restrict__ ppos) {
     constexpr int EPC = Unpack<E>::n;
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= N * nch) return;
@@ -88,19 +87,15 @@ __global__ void lowp_rows_kernel(const uint4* __restrict__ planes, int64_t N, in
         const int i = k * EPC + e;
         if (i < D) xl[p * dk + i] = to_f16 ? f16_rne(x[e]) : bf16_rne(x[e]);
     }
-    if (k == 0) {
-        const uint32_t row = perm[pos];
-        prow[p] = row;
-        iperm[row] = (uint32_t)pos;
-    }
+    if (k == 0) ppos[p] = (uint32_t)pos;
 }
 
 __global__ void lowp_norm_kernel(const uint16_t* __restrict__ xl, int64_t np, int D, int dk, int is_f16,
-                                 const uint32_t* __restrict__ prow, float* __restrict__ nrm) {
+                                 const uint32_t* __restrict__ ppos, float* __restrict__ nrm) {
 #pragma clang fp contract(off)
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    if (prow[p] == 0xFFFFFFFFu) {
+    if (ppos[p] == 0xFFFFFFFFu) {
         nrm[p] = __builtin_huge_valf();
         return;
     }
@@ -115,30 +110,29 @@ __global__ void lowp_norm_kernel(const uint16_t* __restrict__ xl, int64_t np, in
 }
 
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
-                            const uint32_t* offsets, const uint32_t* poff, const uint32_t* perm, int dk,
-                            int to_f16, uint16_t* xl, uint32_t* prow, uint32_t* iperm, float* nrm, int64_t np_total,
-                            hipStream_t s) {
+                            const uint32_t* offsets, const uint32_t* poff, int dk, int to_f16, uint16_t* xl,
+                            uint32_t* ppos, float* nrm, int64_t np_total, hipStream_t s) {
     const int64_t n = N * nch;
     const dim3 grid((unsigned)((n + 255) / 256));
     auto pl = static_cast<const uint4*>(planes);
     switch (dtype) {
         case kF32:
             hipLaunchKernelGGL(lowp_rows_kernel<F32>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
-                               poff, perm, dk, to_f16, xl, prow, iperm);
+                               poff, dk, to_f16, xl, ppos);
             break;
         case kF16:
             hipLaunchKernelGGL(lowp_rows_kernel<F16>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
-                               poff, perm, dk, to_f16, xl, prow, iperm);
+                               poff, dk, to_f16, xl, ppos);
             break;
         case kU8:
             hipLaunchKernelGGL(lowp_rows_kernel<U8>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
-                               poff, perm, dk, to_f16, xl, prow, iperm);
+                               poff, dk, to_f16, xl, ppos);
             break;
         default:
             return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(lowp_norm_kernel, dim3((unsigned)((np_total + 255) / 256)), dim3(256), 0, s, xl, np_total, D,
-                       dk, to_f16, prow, nrm);
+                       dk, to_f16, ppos, nrm);
     return hipGetLastError();
 }
 

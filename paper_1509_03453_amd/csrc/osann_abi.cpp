@@ -62,8 +62,7 @@ struct LowpCopy {
     uint32_t* ne_cone = nullptr;
     uint16_t* xl = nullptr;
     float* nrm = nullptr;
-    uint32_t* prow = nullptr;
-    uint32_t* iperm = nullptr;
+    uint32_t* ppos = nullptr;
 };
 
 struct GraphEntry {
@@ -142,7 +141,7 @@ void release(os_ann_index* ix) {
     void* ptrs[] = {ix->row_cone, ix->row_top,  ix->perm,       ix->sorted_cone, ix->offsets,
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
-                    ix->lp.prow,  ix->lp.iperm};
+                    ix->lp.ppos};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete ix;
@@ -190,15 +189,14 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
     const int64_t rows = lp.np + 16;  // 16 zero rows past the end
     rc = dev_alloc(ix, (void**)&lp.xl, (size_t)rows * lp.dk * 2, "xl");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.nrm, (size_t)rows * 4, "nrm");
-    if (!rc) rc = dev_alloc(ix, (void**)&lp.prow, (size_t)rows * 4, "prow");
-    if (!rc) rc = dev_alloc(ix, (void**)&lp.iperm, (size_t)ix->N * 4, "iperm");
+    if (!rc) rc = dev_alloc(ix, (void**)&lp.ppos, (size_t)rows * 4, "ppos");
     if (rc) return done(rc);
     e = hipMemsetAsync(lp.xl, 0, (size_t)rows * lp.dk * 2, s);
-    if (e == hipSuccess) e = launch_fill_u32(lp.prow, rows, 0xFFFFFFFFu, s);
+    if (e == hipSuccess) e = launch_fill_u32(lp.ppos, rows, 0xFFFFFFFFu, s);
     if (e == hipSuccess)
         e = launch_lowp_rows(ix->planes, ix->dtype, ix->N, ix->D, ix->nch, ix->sorted_cone, ix->offsets, lp.poff,
-                             ix->perm, lp.dk, lp.f16, lp.xl, lp.prow, lp.iperm, lp.nrm, rows, s);
-    if (e == hipSuccess) e = tiled_screen_max_lds(kTabBytesMax + 4096);
+                             lp.dk, lp.f16, lp.xl, lp.ppos, lp.nrm, rows, s);
+    if (e == hipSuccess) e = tiled_screen_max_lds(kScreenLdsMax);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return done(hip_fail(e, "low-precision copy"));
     lp.ready = true;
@@ -213,14 +211,21 @@ struct SearchPlan {
     int dpad = 0, mode = OS_ANN_MODE_FP32, R = 8;
     size_t off_yf = 0, off_order = 0, off_sbit = 0, off_jstop = 0, off_np = 0, off_nc = 0;
     // tiled mode
-    int dk = 0, smin = 1, smax = 1;
-    int64_t T = 0;
+    int dk = 0, smin = 1, smax = 1, mq = 0;
+    int64_t T = 0, nw = 0;
+    bool bitmap = false, fits = true;
     size_t off_ql = 0, off_qcone = 0, off_sort = 0, off_qorder = 0, off_qsorted = 0, off_part = 0,
-           off_counter = 0;
+           off_counter = 0, off_qbits = 0;
     size_t bytes = 0;
 };
 
-SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int mode, int R) {
+// Non-empty cones per split for S splits: a multiple of 64 (whole bitmap words).
+int64_t split_span(int64_t n_ne, int S) {
+    const int64_t per = (n_ne + S - 1) / S;
+    return (per + 63) / 64 * 64;
+}
+
+SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mode, int R) {
     SearchPlan p;
     p.Q = Q;
     p.mode = mode;
@@ -239,13 +244,24 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int mode, int R) {
     p.off_np = take((size_t)Q * sizeof(uint32_t));
     p.off_nc = take((size_t)Q * sizeof(int64_t));
     if (mode == OS_ANN_MODE_TILED) {
-        p.dk = (int)align_up((size_t)ix->D, 32);
-        p.T = (Q + kTileQ - 1) / kTileQ;
         const int64_t ne = ix->n_nonempty > 0 ? ix->n_nonempty : 1;
-        p.smin = (int)pow2_ceil((ne * 8 + (int64_t)kTabBytesMax - 1) / (int64_t)kTabBytesMax);
+        p.dk = (int)align_up((size_t)ix->D, 32);
+        p.mq = tile_queries(R);
+        p.T = (Q + p.mq - 1) / p.mq;
+        p.nw = (ne + 63) / 64;
+        // smallest split count whose cone list and row batches fit in LDS
+        p.smin = 1;
+        while (p.smin < 16 && (split_span(ne, p.smin) * 48 > (int64_t)kTabBytesMax ||
+                               tiled_screen_lds(split_span(ne, p.smin), p.dk) > kScreenLdsMax))
+            p.smin <<= 1;
+        p.fits = tiled_screen_lds(split_span(ne, p.smin), p.dk) <= kScreenLdsMax;
         const int64_t want = (4 * (int64_t)ix->num_cu + p.T - 1) / (p.T > 0 ? p.T : 1);
         p.smax = (int)std::max<int64_t>(p.smin, std::min<int64_t>(16, pow2_ceil(std::max<int64_t>(want, 1))));
-        while (p.smax > p.smin && p.smax > ne) p.smax >>= 1;
+        while (p.smax > p.smin && split_span(ne, p.smax) < 64 * 2) p.smax >>= 1;
+        // probed-cone bitmaps pay off once a query probes many cones and stay small
+        const int64_t mean_bucket = std::max<int64_t>(1, ix->N / ne);
+        const int64_t probes = std::min<int64_t>(budget, ix->N) / mean_bucket + 1;
+        p.bitmap = probes >= 32 && p.nw <= 512 && (size_t)Q * p.nw * 8 <= ((size_t)1 << 30);
         p.off_ql = take((size_t)Q * p.dk * 2);
         p.off_qcone = take((size_t)Q * 4);
         p.off_sort = take((size_t)(4 * Q + radix_hist_words(Q)) * 4);
@@ -253,6 +269,7 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int mode, int R) {
         p.off_qsorted = take((size_t)Q * 4);
         p.off_part = take((size_t)Q * p.smax * R * 8);
         p.off_counter = take(256);
+        if (p.bitmap) p.off_qbits = take((size_t)Q * p.nw * 8);
     }
     p.bytes = at;
     return p;
@@ -420,6 +437,12 @@ ProbeArgs probe_args(const Call& c) {
         pa.dk = c.p.dk;
         pa.ql_f16 = ix->lp.f16;
         pa.q_cone = reinterpret_cast<uint32_t*>(c.base + c.p.off_qcone);
+        if (c.p.bitmap) {
+            pa.qbits = reinterpret_cast<uint64_t*>(c.base + c.p.off_qbits);
+            pa.nw = c.p.nw;
+            pa.ne_id = ix->lp.ne_id;
+            pa.n_ne = ix->n_nonempty;
+        }
     }
     return pa;
 }
@@ -471,7 +494,7 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     ta.xl = ix->lp.xl;
     ta.dk = ix->lp.dk;
     ta.nrm = ix->lp.nrm;
-    ta.prow = ix->lp.prow;
+    ta.ppos = ix->lp.ppos;
     ta.poff = ix->lp.poff;
     ta.offsets = ix->offsets;
     ta.ne_id = ix->lp.ne_id;
@@ -489,15 +512,21 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     ta.order = pa.order;
     ta.sbit = pa.sbit;
     ta.jstop = pa.jstop;
+    ta.qbits = pa.qbits;
+    ta.nw = p.nw;
     ta.T = p.T;
     ta.S = S;
+    ta.span = split_span(ix->n_nonempty > 0 ? ix->n_nonempty : 1, S);
     ta.counter = counter;
     ta.part = reinterpret_cast<uint2*>(c.base + p.off_part);
-    const size_t lds = (size_t)((ix->n_nonempty + S - 1) / S) * 8;
+    const size_t lds = tiled_screen_lds(ta.span, ta.dk);
     int occ = tiled_screen_occupancy(p.R, ix->lp.f16, ix->lp.dk / 32, lds);
     if (occ < 1) occ = 1;
     const int64_t items = p.T * S;
     const int blocks = (int)std::min<int64_t>(items, (int64_t)occ * ix->num_cu);
+    if (std::getenv("OSANN_VERBOSE"))
+        std::fprintf(stderr, "[osann] tiled Q=%lld T=%lld S=%d span=%lld lds=%zu occ=%d blocks=%d bitmap=%d R=%d\n",
+                     (long long)c.Q, (long long)p.T, S, (long long)ta.span, lds, occ, blocks, (int)p.bitmap, p.R);
     e = timed_launch(ix, c.timing, OS_ANN_KERNEL_SCREEN, c.s,
                      [&] { return launch_tiled_screen(ta, p.R, ix->lp.f16, blocks, c.s); });
     if (e != hipSuccess) return e;
@@ -509,7 +538,8 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     fa.dtype = ix->dtype;
     fa.N = ix->N;
     fa.nch = ix->nch;
-    fa.iperm = ix->lp.iperm;
+    fa.ppos = ix->lp.ppos;
+    fa.perm = ix->perm;
     fa.yf = pa.yf;
     fa.dpad = p.dpad;
     fa.out_idx = c.out_idx;
@@ -724,7 +754,7 @@ int64_t os_ann_workspace_bytes(const os_ann_index* idx, int64_t Q, int64_t max_c
     if (rc) return rc;
     const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
-    return (int64_t)plan_search(idx, Q, mode, R).bytes;
+    return (int64_t)plan_search(idx, Q, max_candidates, mode, R).bytes;
 }
 
 int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, int64_t max_candidates,
@@ -749,7 +779,9 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     c.timing = opts && (opts->flags & OS_ANN_FLAG_TIME_KERNELS);
     const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
-    c.p = plan_search(ix, Q, mode, R);
+    c.p = plan_search(ix, Q, max_candidates, mode, R);
+    if (!c.p.fits)
+        return fail(OS_ANN_ENOTSUP, "tiled mode: too many non-empty cones for the LDS cone list at this D");
     if ((rc = get_scratch(ix, opts, c.p.bytes, &c.base))) return rc;
     int S = 1;
     if (mode == OS_ANN_MODE_TILED) {

@@ -110,6 +110,11 @@ struct ProbeArgs {
     int64_t* ncand;         // [Q]
     uint32_t* q_cone;       // [Q]
     uint64_t* q_top;        // [Q]
+    // optional bitmap of the probed non-empty cones, [Q][nw] words
+    uint64_t* qbits;
+    int64_t nw;
+    const uint32_t* ne_id;  // cone -> rank among the non-empty cones
+    int64_t n_ne;
 };
 hipError_t launch_probe(const ProbeArgs& a, hipStream_t s);
 

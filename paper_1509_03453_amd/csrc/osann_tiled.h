@@ -7,15 +7,19 @@
 
 namespace osann {
 
-constexpr int kTileQ = 64;            // queries per tile: 4 waves x 16
-constexpr size_t kTabBytesMax = 48 * 1024;  // LDS budget of one split's cone table
+// A tile holds 4 waves x 16*G queries (G MFMA B operand groups per wave);
+// G = 4 for R <= 8, G = 2 for R = 16 (register budget of the top-R lists).
+inline int tile_groups(int R) { return R <= 8 ? 4 : 2; }
+inline int tile_queries(int R) { return 64 * tile_groups(R); }
+constexpr size_t kTabBytesMax = 40 * 1024;  // LDS budget of one split's marked-cone list (48 B per cone)
+constexpr size_t kScreenLdsMax = 156 * 1024;  // dynamic LDS of one screen block (160 KB minus static)
 
 struct TiledArgs {
     // low-precision index
     const uint16_t* xl;
     int dk;
     const float* nrm;
-    const uint32_t* prow;
+    const uint32_t* ppos;   // sorted position of each padded row (0xFFFFFFFF: padding)
     const uint32_t* poff;
     const uint32_t* offsets;
     const uint32_t* ne_id;
@@ -34,12 +38,17 @@ struct TiledArgs {
     const uint8_t* order;   // [Q][D]
     const uint8_t* sbit;    // [Q][D]
     const uint32_t* jstop;  // [Q]
+    // probed cones: per-query bitmap over the non-empty cones (or null:
+    // the kernel regenerates each query's walk)
+    const uint64_t* qbits;  // [Q][nw]
+    int64_t nw;
     // schedule
     int64_t T;              // tiles
     int S;                  // splits of the non-empty cones
+    int64_t span;           // non-empty cones per split (multiple of 64)
     uint32_t* counter;      // work-queue head, zero before the launch
     // output
-    uint2* part;            // [Q][S][R] (FP32 bits of d~, row)
+    uint2* part;            // [Q][S][R] (FP32 bits of d~, padded position)
 };
 
 struct FinishArgs {
@@ -50,7 +59,8 @@ struct FinishArgs {
     int dtype;
     int64_t N;
     int nch;
-    const uint32_t* iperm;
+    const uint32_t* ppos;
+    const uint32_t* perm;
     const float* yf;
     int dpad;
     int64_t* out_idx;
@@ -63,10 +73,10 @@ hipError_t launch_lowp_layout(const uint32_t* offsets, int64_t n_cones, uint32_t
                               uint32_t* scan_tmp, uint32_t* poff, uint32_t* ne_id, uint32_t* ne_cone,
                               hipStream_t s);
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
-                            const uint32_t* offsets, const uint32_t* poff, const uint32_t* perm, int dk,
-                            int to_f16, uint16_t* xl, uint32_t* prow, uint32_t* iperm, float* nrm, int64_t np_total,
-                            hipStream_t s);
+                            const uint32_t* offsets, const uint32_t* poff, int dk, int to_f16, uint16_t* xl,
+                            uint32_t* ppos, float* nrm, int64_t np_total, hipStream_t s);
 hipError_t launch_tiled_screen(const TiledArgs& a, int R, int f16in, int blocks, hipStream_t s);
+size_t tiled_screen_lds(int64_t span, int dk);
 hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s);
 hipError_t tiled_screen_max_lds(size_t bytes);
 int tiled_screen_occupancy(int R, int f16in, int ks, size_t lds);

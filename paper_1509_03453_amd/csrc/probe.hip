@@ -21,6 +21,7 @@ constexpr int kProbeWaves = 4;
 
 template <typename E, int L>
 __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
+    extern __shared__ unsigned long long qb_all[];  // [kProbeWaves][nw] when a.qbits
     __shared__ uint64_t keys[kProbeWaves][kMaxD];
     __shared__ uint8_t order[kProbeWaves][kMaxD];
     __shared__ uint8_t sbit[kProbeWaves][kMaxD];
@@ -92,7 +93,19 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
             if (a.nprobe) a.nprobe[q] = 0xFFFFFFFFu;
             if (a.ncand) a.ncand[q] = a.N;
         }
+        if (a.qbits)
+            for (int64_t k = l; k < a.nw; k += 64) {
+                const int64_t rem = a.n_ne - 64 * k;
+                a.qbits[q * a.nw + k] = rem >= 64 ? ~0ull : ((1ull << rem) - 1);
+            }
         return;
+    }
+    unsigned long long* qb = qb_all + (int64_t)w * a.nw;
+    if (a.qbits) {
+        for (int64_t k = l; k < a.nw; k += 64) qb[k] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
 
     // 5. walk the probe sequence 64 positions at a time until the budget is met
@@ -101,16 +114,21 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
     uint32_t np = 0, stop_at = 0;
     for (int64_t j0 = 0; j0 < a.n_cones; j0 += 64) {
         const int64_t j = j0 + l;
-        uint32_t len = 0;
+        uint32_t len = 0, c = 0;
         if (j < a.n_cones) {
-            const uint32_t c = probe_cone(j, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
+            c = probe_cone(j, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
             len = a.offsets[c + 1] - a.offsets[c];
         }
         const uint32_t incl = wave_incl_scan(len);
         const uint64_t tot = carry + incl;
         const uint64_t reached = __ballot(j < a.n_cones && tot >= budget);
         const int stop = reached ? __ffsll((unsigned long long)reached) - 1 : 63;
-        const uint64_t tm = __ballot(j < a.n_cones && l <= stop && len > 0);
+        const bool taken = j < a.n_cones && l <= stop && len > 0;
+        const uint64_t tm = __ballot(taken);
+        if (a.qbits && taken) {
+            const uint32_t e = a.ne_id[c];
+            atomicOr(&qb[e >> 6], 1ull << (e & 63));
+        }
         np += (uint32_t)__popcll(tm);
         carry += shfl_u32(incl, stop);
         if (reached) {
@@ -124,15 +142,22 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
         if (a.nprobe) a.nprobe[q] = np;
         if (a.ncand) a.ncand[q] = (int64_t)carry;
     }
+    if (a.qbits) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        for (int64_t k = l; k < a.nw; k += 64) a.qbits[q * a.nw + k] = qb[k];
+    }
 }
 
 template <typename E>
 static hipError_t dispatch_probe(const ProbeArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.Q + kProbeWaves - 1) / kProbeWaves)), block(64 * kProbeWaves);
+    const size_t lds = a.qbits ? (size_t)kProbeWaves * a.nw * 8 : 0;
     switch (a.L) {
 #define OSANN_PROBE_CASE(LL)                                                  \
     case LL:                                                                  \
-        hipLaunchKernelGGL((probe_kernel<E, LL>), grid, block, 0, s, a);      \
+        hipLaunchKernelGGL((probe_kernel<E, LL>), grid, block, lds, s, a);    \
         break;
         OSANN_PROBE_CASE(1) OSANN_PROBE_CASE(2) OSANN_PROBE_CASE(3) OSANN_PROBE_CASE(4)
         OSANN_PROBE_CASE(5) OSANN_PROBE_CASE(6) OSANN_PROBE_CASE(7)

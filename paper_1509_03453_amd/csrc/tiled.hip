@@ -8,7 +8,7 @@
 // cone's rows in 16-row MFMA tiles (bucket sizes are padded to 16 rows in
 // the low-precision copy).  With the rows as the MFMA A operand and the
 // wave's 16 queries as B, lane l holds the dot products of query l%16 with 4
-// rows, so each lane keeps a private top-R list of (d~, row) for one query,
+// rows, so each lane keeps a private top-R list of (d~, position) for one query,
 // where d~ = ||x^||^2 - 2 q^.x^ ranks candidates like the squared distance
 // of the rounded vectors.  The four lanes of a query merge their lists with
 // shuffles (bitonic), and the split's list goes to a per-query slot.  A
@@ -82,15 +82,79 @@ __device__ inline void list_insert(float (&d)[R], uint32_t (&r)[R], float nd, ui
     }
 }
 
-template <bool F16IN, int KS, int R>
+template <bool F16IN>
+__device__ inline f32x4_t mfma16(const uint4& a, const uint4& b, f32x4_t acc) {
+    if (F16IN)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, b),
+                                                      acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                   acc, 0, 0, 0);
+}
+
+constexpr int kBatchRows = 128;  // rows staged in LDS per batch (8 MFMA row tiles)
+
+// Exclusive prefix sum of one value per thread over the 256-thread block.
+__device__ inline uint32_t block_scan256(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const int w = threadIdx.x / 64, l = lane_id();
+    const uint32_t incl = wave_incl_scan(v);
+    if (l == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        before += k < w ? wsum[k] : 0u;
+        all += wsum[k];
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+// LDS slot (16-byte unit) of unit c of row r: XOR swizzle inside each row so
+// that the 16 rows an MFMA A-fragment read touches fall in different banks.
+template <int CPR>
+__device__ inline int swz(int r, int c) {
+    constexpr int M = CPR < 8 ? CPR - 1 : 7;
+    return r * CPR + (c ^ (r & M));
+}
+
+// Marked cone of a split: padded rows [p0, p1) and, per wave, which of its
+// queries probe the cone.
+struct ListEntry {
+    uint32_t p0, p1, pad0, pad1;
+    uint64_t m[4];
+};
+
+template <bool F16IN, int KS, int R, int G>
 __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
-    extern __shared__ uint64_t tab[];
+    constexpr int QW = 16 * G;              // queries per wave
+    constexpr int MQ = 4 * QW;              // queries per tile
+    constexpr int CPR = KS * 4;             // 16-byte units per row (dk = 32*KS)
+    constexpr int KU = kBatchRows * CPR / 256;  // units each thread stages per batch
+    extern __shared__ uint64_t dyn[];
+    // dyn: list[span] | scratch: first the cone table tab[span][4], then
+    //      (once the list is built) rows[2][128*CPR] (uint4) and nrm[2][128]
     __shared__ uint8_t s_order[4][kMaxD];
     __shared__ uint8_t s_sbit[4][kMaxD];
-    __shared__ uint32_t s_item;
+    __shared__ uint32_t s_item, s_nlist, s_wsum[4];
     const int w = threadIdx.x / 64, l = lane_id();
     const int64_t total = a.T * a.S;
-    const int64_t span = (a.n_ne + a.S - 1) / a.S;
+    ListEntry* list = reinterpret_cast<ListEntry*>(dyn);
+    uint64_t* tab = dyn + 6 * a.span;
+    uint4* rows = reinterpret_cast<uint4*>(tab);
+    float* nrmb = reinterpret_cast<float*>(rows + 2 * kBatchRows * CPR);
+    // this thread's staging units: global element offset inside a batch and LDS slot
+    int goff[KU], gslot[KU], grow[KU];
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+        const int u = threadIdx.x + 256 * k;
+        grow[k] = u / CPR;
+        goff[k] = grow[k] * a.dk + 8 * (u % CPR);
+        gslot[k] = swz<CPR>(grow[k], u % CPR);
+    }
+    int aslot[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) aslot[ks] = swz<CPR>(l % 16, l / 16 + 4 * ks);
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1u);
         __syncthreads();
@@ -99,117 +163,248 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
         if (item >= total) break;
         const int64_t t = item / a.S;
         const int s = (int)(item % a.S);
-        const int64_t n0 = s * span;
-        const int64_t n1 = n0 + span < a.n_ne ? n0 + span : a.n_ne;
+        const int64_t n0 = s * a.span;
+        const int64_t n1 = n0 + a.span < a.n_ne ? n0 + a.span : a.n_ne;
         const int nspan = n1 > n0 ? (int)(n1 - n0) : 0;
+        const int64_t wslot0 = t * MQ + (int64_t)w * QW;  // first tile slot of this wave
 
-        // 1. which of the tile's queries probe each cone of the split
-        for (int i = threadIdx.x; i < nspan; i += blockDim.x) tab[i] = 0;
-        __syncthreads();
-        for (int c = 0; c < 16; ++c) {
-            const int slot = 16 * w + c;
-            const int64_t qs = t * kTileQ + slot;
-            if (qs >= a.Q) break;
-            const uint32_t q = a.qorder[qs];
-            const uint32_t js = a.jstop[q];
-            const unsigned long long bit = 1ull << slot;
-            if (js == kWalkAll) {
-                for (int i = l; i < nspan; i += 64) atomicOr((unsigned long long*)&tab[i], bit);
-                continue;
+        // 1. per cone of the split: which of this wave's queries probe it
+        if (a.qbits) {
+            // transpose the queries' probed-cone bitmaps with ballots
+            const bool mine = l < QW && wslot0 + l < a.Q;
+            const uint32_t q = mine ? a.qorder[wslot0 + l] : 0u;
+            for (int64_t k = n0 >> 6; k * 64 < n1; ++k) {
+                const uint64_t word = mine ? a.qbits[(int64_t)q * a.nw + k] : 0ull;
+                uint64_t col = 0;
+#pragma unroll 8
+                for (int c = 0; c < 64; ++c) {
+                    const uint64_t m = __ballot((word >> c) & 1ull);
+                    col = c == l ? m : col;
+                }
+                const int64_t e = k * 64 + l;
+                if (e >= n0 && e < n1) tab[(e - n0) * 4 + w] = col;
             }
-            for (int i = l; i < a.D; i += 64) {
-                s_order[w][i] = a.order[(int64_t)q * a.D + i];
-                s_sbit[w][i] = a.sbit[(int64_t)q * a.D + i];
-            }
+        } else {
+            for (int i = l; i < nspan; i += 64) tab[i * 4 + w] = 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            for (uint32_t j0 = 0; j0 < js; j0 += 64) {
-                const uint32_t j = j0 + l;
-                if (j < js) {
-                    const uint32_t cone =
-                        probe_cone(j, a.L, s_order[w], s_sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
-                    if (a.offsets[cone + 1] > a.offsets[cone]) {
-                        const int64_t e = a.ne_id[cone];
-                        if (e >= n0 && e < n1) atomicOr((unsigned long long*)&tab[e - n0], bit);
+            for (int c = 0; c < QW; ++c) {
+                if (wslot0 + c >= a.Q) break;
+                const uint32_t q = a.qorder[wslot0 + c];
+                const uint32_t js = a.jstop[q];
+                const unsigned long long bit = 1ull << c;
+                if (js == kWalkAll) {
+                    for (int i = l; i < nspan; i += 64) atomicOr((unsigned long long*)&tab[i * 4 + w], bit);
+                    continue;
+                }
+                for (int i = l; i < a.D; i += 64) {
+                    s_order[w][i] = a.order[(int64_t)q * a.D + i];
+                    s_sbit[w][i] = a.sbit[(int64_t)q * a.D + i];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                for (uint32_t j0 = 0; j0 < js; j0 += 64) {
+                    const uint32_t j = j0 + l;
+                    if (j < js) {
+                        const uint32_t cone =
+                            probe_cone(j, a.L, s_order[w], s_sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
+                        if (a.offsets[cone + 1] > a.offsets[cone]) {
+                            const int64_t e = a.ne_id[cone];
+                            if (e >= n0 && e < n1) atomicOr((unsigned long long*)&tab[(e - n0) * 4 + w], bit);
+                        }
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
         __syncthreads();
 
-        // 2. this wave's 16 queries as the MFMA B operand
-        const int64_t myslot = t * kTileQ + 16 * w + (l % 16);
-        const bool qok = myslot < a.Q;
-        const uint32_t myq = qok ? a.qorder[myslot] : 0u;
-        uint4 bq[KS];
+        // 2. compact list of the cones some query of the tile probes
+        if (threadIdx.x == 0) s_nlist = 0;
+        __syncthreads();
+        for (int base = 0; base < nspan; base += 256) {
+            const int i = base + threadIdx.x;
+            uint64_t m[4] = {0, 0, 0, 0};
+            if (i < nspan)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-            bq[ks] = qok ? *reinterpret_cast<const uint4*>(a.ql + (int64_t)myq * a.dk + ks * 32 + 8 * (l / 16))
-                         : make_uint4(0, 0, 0, 0);
-
-        float ld[R];
-        uint32_t lr[R];
+                for (int k = 0; k < 4; ++k) m[k] = tab[i * 4 + k];
+            const bool hit = (m[0] | m[1] | m[2] | m[3]) != 0;
+            uint32_t cnt;
+            const uint32_t at = block_scan256(hit ? 1u : 0u, s_wsum, &cnt);
+            if (hit) {
+                const uint32_t cone = a.ne_cone[n0 + i];
+                ListEntry e;
+                e.p0 = a.poff[cone];
+                e.p1 = a.poff[cone + 1];
+                e.pad0 = e.pad1 = 0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            ld[k] = __builtin_huge_valf();
-            lr[k] = 0xFFFFFFFFu;
+                for (int k = 0; k < 4; ++k) e.m[k] = m[k];
+                list[s_nlist + at] = e;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) s_nlist += cnt;
+            __syncthreads();
         }
+        const int nlist = (int)s_nlist;  // the table is dead from here on: its space holds the row batches
 
-        // 3. stream the marked cones' rows through the matrix cores
-        for (int i = 0; i < nspan; ++i) {
-            const uint64_t m = tab[i];
-            const uint32_t wm = (uint32_t)(m >> (16 * w)) & 0xFFFFu;
-            if (wm == 0) continue;
-            const bool probed = (wm >> (l % 16)) & 1u;
-            const uint32_t cone = a.ne_cone[n0 + i];
-            const uint32_t p1 = a.poff[cone + 1];
-            for (uint32_t p = a.poff[cone]; p < p1; p += 16) {
-                f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                const uint16_t* arow = a.xl + (int64_t)(p + (l % 16)) * a.dk + 8 * (l / 16);
+        // 3. B operands: group g of this wave = queries 16g .. 16g+15 of the wave
+        uint4 bq[G][KS];
+        bool qok[G];
+        uint32_t myq[G];
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    const uint4 av = *reinterpret_cast<const uint4*>(arow + ks * 32);
-                    if (F16IN)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8_t, av),
-                                                                    __builtin_bit_cast(f16x8_t, bq[ks]), acc, 0,
-                                                                    0, 0);
-                    else
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av),
-                                                                     __builtin_bit_cast(bf16x8_t, bq[ks]), acc, 0,
-                                                                     0, 0);
+        for (int g = 0; g < G; ++g) {
+            const int64_t slot = wslot0 + 16 * g + (l % 16);
+            qok[g] = slot < a.Q;
+            myq[g] = qok[g] ? a.qorder[slot] : 0u;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                bq[g][ks] = qok[g] ? *reinterpret_cast<const uint4*>(a.ql + (int64_t)myq[g] * a.dk + ks * 32 +
+                                                                     8 * (l / 16))
+                                   : make_uint4(0, 0, 0, 0);
+        }
+        float ld[G][R];
+        uint32_t lr[G][R];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                ld[g][k] = __builtin_huge_valf();
+                lr[g][k] = 0xFFFFFFFFu;
+            }
+        // the query operands have landed before the batch loop starts, so no
+        // wait inside the loop has to drain the batch prefetch for them
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+
+        // 4. batches of up to 128 rows staged in LDS; the next batch is loaded
+        //    into registers while the current one is on the matrix cores.
+        //    qthr[g]: the smallest R-th value among the four lanes of the
+        //    lane's query (a bound on the query's R-th best, refreshed every
+        //    batch); a candidate above it can never reach the final top R.
+        float qthr[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) qthr[g] = __builtin_huge_valf();
+        uint4 stage[KU];
+        float nst = 0.0f;
+        auto issue = [&](uint32_t p, uint32_t n) {
+            const uint16_t* src = a.xl + (int64_t)p * a.dk;
+#pragma unroll
+            for (int k = 0; k < KU; ++k)
+                stage[k] = (uint32_t)grow[k] < n ? *reinterpret_cast<const uint4*>(src + goff[k])
+                                                 : make_uint4(0, 0, 0, 0);
+            nst = threadIdx.x < n ? a.nrm[(int64_t)p + threadIdx.x] : __builtin_huge_valf();
+        };
+        auto park = [&](int buf) {
+            uint4* dst = rows + buf * kBatchRows * CPR;
+#pragma unroll
+            for (int k = 0; k < KU; ++k) dst[gslot[k]] = stage[k];
+            if (threadIdx.x < kBatchRows) nrmb[buf * kBatchRows + threadIdx.x] = nst;
+        };
+        int li = 0;          // list entry of the staged batch
+        uint32_t bp = 0;     // its first padded row
+        uint32_t bn = 0;     // its rows
+        if (nlist > 0) {
+            bp = list[0].p0;
+            bn = list[0].p1 - bp < kBatchRows ? list[0].p1 - bp : kBatchRows;
+            issue(bp, bn);
+            park(0);
+        }
+        __syncthreads();
+        int buf = 0;
+        while (li < nlist) {
+            // next batch: rest of this cone, else the next listed cone
+            const uint32_t cur_p1 = list[li].p1;
+            const uint64_t mk = list[li].m[w];
+            int nli = li;
+            uint32_t np = bp + bn, nn = 0;
+            if (np >= cur_p1) {
+                nli = li + 1;
+                if (nli < nlist) np = list[nli].p0;
+            }
+            if (nli < nlist) {
+                const uint32_t end = list[nli].p1;
+                nn = end - np < kBatchRows ? end - np : kBatchRows;
+                issue(np, nn);
+            }
+            // screen the staged batch
+            if (mk != 0) {
+                const uint4* rb = rows + buf * kBatchRows * CPR;
+                const float* nb = nrmb + buf * kBatchRows + 4 * (l / 16);
+                float thr[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const bool probed = (mk >> (16 * g + (l % 16))) & 1ull;
+                    thr[g] = probed ? fminf(qthr[g], ld[g][R - 1]) : -__builtin_huge_valf();
                 }
-                const int64_t rb = (int64_t)p + 4 * (l / 16);
-                const float4 nv = *reinterpret_cast<const float4*>(a.nrm + rb);
-                const float nn[4] = {nv.x, nv.y, nv.z, nv.w};
+                for (uint32_t r0 = 0; r0 < bn; r0 += 16) {
+                    uint4 av[KS];
 #pragma unroll
-                for (int ii = 0; ii < 4; ++ii) {
-                    const float d = nn[ii] - 2.0f * acc[ii];
-                    if (probed && d <= ld[R - 1]) {
-                        const uint32_t row = a.prow[rb + ii];
-                        if (d < ld[R - 1] || row < lr[R - 1]) list_insert<R>(ld, lr, d, row);
+                    for (int ks = 0; ks < KS; ++ks) av[ks] = rb[aslot[ks] + r0 * CPR];
+                    const float4 nv4 = *reinterpret_cast<const float4*>(nb + r0);
+                    f32x4_t acc[G];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        acc[g] = mfma16<F16IN>(av[0], bq[g][0], f32x4_t{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+                        for (int ks = 1; ks < KS; ++ks) acc[g] = mfma16<F16IN>(av[ks], bq[g][ks], acc[g]);
+                    }
+                    const float nv[4] = {nv4.x, nv4.y, nv4.z, nv4.w};
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        float d[4];
+#pragma unroll
+                        for (int ii = 0; ii < 4; ++ii) d[ii] = nv[ii] - 2.0f * acc[g][ii];
+                        if (fminf(fminf(d[0], d[1]), fminf(d[2], d[3])) <= thr[g]) {
+#pragma unroll
+                            for (int ii = 0; ii < 4; ++ii) {
+                                // key (d~, padded position): a total order, no memory access
+                                const uint32_t pp = bp + r0 + 4 * (l / 16) + ii;
+                                if (d[ii] <= thr[g] && pair_less(d[ii], pp, ld[g][R - 1], lr[g][R - 1]) &&
+                                    nv[ii] < __builtin_huge_valf())
+                                    list_insert<R>(ld[g], lr[g], d[ii], pp);
+                            }
+                            thr[g] = fminf(thr[g], ld[g][R - 1]);
+                        }
                     }
                 }
             }
+            // refresh the per-query bound from the four lanes of each query
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                float k = fminf(qthr[g], ld[g][R - 1]);
+                k = fminf(k, __shfl_xor(k, 16, 64));
+                k = fminf(k, __shfl_xor(k, 32, 64));
+                qthr[g] = k;
+            }
+            if (nli < nlist) park(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+            li = nli;
+            bp = np;
+            bn = nn;
         }
 
-        // 4. merge the four lanes of each query, store the split's list
-        merge_with<R>(ld, lr, 16);
-        merge_with<R>(ld, lr, 32);
-        if (l < 16 && qok) {
-            uint2* dst = a.part + ((int64_t)myq * a.S + s) * R;
+        // 5. merge the four lanes of each query, store the split's lists
 #pragma unroll
-            for (int k = 0; k < R; ++k) dst[k] = make_uint2(__float_as_uint(ld[k]), lr[k]);
+        for (int g = 0; g < G; ++g) {
+            merge_with<R>(ld[g], lr[g], 16);
+            merge_with<R>(ld[g], lr[g], 32);
+            if (l < 16 && qok[g]) {
+                uint2* dst = a.part + ((int64_t)myq[g] * a.S + s) * R;
+#pragma unroll
+                for (int k = 0; k < R; ++k) dst[k] = make_uint2(__float_as_uint(ld[g][k]), lr[g][k]);
+            }
         }
         __syncthreads();
     }
 }
 
-// One group of G lanes per query: merge the S split lists, re-rank the R
-// survivors with the exact FP32 distance, arg-min on (distance, row).
+// One group of G lanes per query: merge the S split lists (ordered by
+// (d~, padded position)), re-rank the R survivors with the exact FP32
+// distance, arg-min on (distance, original row).
 template <typename E, int R, int G>
 __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -230,13 +425,17 @@ __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
     }
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) merge_with<R>(ld, lr, m);
-    uint32_t cr = 0xFFFFFFFFu;
+    uint32_t cp = 0xFFFFFFFFu;
 #pragma unroll
     for (int k = 0; k < R; ++k)
-        if (k == g) cr = lr[k];
+        if (k == g) cp = lr[k];
     float cd = __builtin_huge_valf();
-    if (qv && cr != 0xFFFFFFFFu)
-        cd = row_dist_fp32<E>(static_cast<const uint4*>(f.planes), f.N, f.nch, f.iperm[cr], f.yf + q * f.dpad);
+    uint32_t cr = 0xFFFFFFFFu;
+    if (qv && cp != 0xFFFFFFFFu) {
+        const uint32_t pos = f.ppos[cp];
+        cr = f.perm[pos];
+        cd = row_dist_fp32<E>(static_cast<const uint4*>(f.planes), f.N, f.nch, pos, f.yf + q * f.dpad);
+    }
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) {
         const float od = __shfl_xor(cd, m, 64);
@@ -254,20 +453,29 @@ __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
 
 template <bool F16IN, int R>
 static hipError_t screen_ks(const TiledArgs& a, int ks, dim3 grid, size_t lds, hipStream_t s) {
+    constexpr int G = R <= 8 ? 4 : 2;
     switch (ks) {
-        case 1: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 1, R>), grid, dim3(256), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 2, R>), grid, dim3(256), lds, s, a); break;
-        case 4: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 4, R>), grid, dim3(256), lds, s, a); break;
-        case 8: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 8, R>), grid, dim3(256), lds, s, a); break;
+        case 1: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 1, R, G>), grid, dim3(256), lds, s, a); break;
+        case 2: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 2, R, G>), grid, dim3(256), lds, s, a); break;
+        case 4: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 4, R, G>), grid, dim3(256), lds, s, a); break;
+        case 8: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 8, R, G>), grid, dim3(256), lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+// Dynamic LDS of the screen kernel: marked-cone list (48 B per cone), then
+// the larger of the cone table (32 B per cone) and the two staged row
+// batches with their norms.
+size_t tiled_screen_lds(int64_t span, int dk) {
+    const size_t sp = (size_t)(span > 0 ? span : 1);
+    const size_t batches = (size_t)2 * kBatchRows * dk * 2 + 2 * kBatchRows * 4;
+    return sp * 48 + (sp * 32 > batches ? sp * 32 : batches);
+}
+
 hipError_t launch_tiled_screen(const TiledArgs& a, int R, int f16in, int blocks, hipStream_t s) {
     const int ks = a.dk / 32;
-    const int64_t span = (a.n_ne + a.S - 1) / a.S;
-    const size_t lds = (size_t)(span > 0 ? span : 1) * sizeof(uint64_t);
+    const size_t lds = tiled_screen_lds(a.span, a.dk);
     const dim3 grid((unsigned)blocks);
     if (f16in) {
         if (R == 4) return screen_ks<true, 4>(a, ks, grid, lds, s);
@@ -313,19 +521,20 @@ hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+#define OSANN_EACH_SCREEN(X)                                                                        \
+    X(true, 1, 4, 4) X(true, 2, 4, 4) X(true, 4, 4, 4) X(true, 8, 4, 4) X(true, 1, 8, 4) X(true, 2, 8, 4)    \
+    X(true, 4, 8, 4) X(true, 8, 8, 4) X(true, 1, 16, 2) X(true, 2, 16, 2) X(true, 4, 16, 2)                  \
+    X(true, 8, 16, 2) X(false, 1, 4, 4) X(false, 2, 4, 4) X(false, 4, 4, 4) X(false, 8, 4, 4)               \
+    X(false, 1, 8, 4) X(false, 2, 8, 4) X(false, 4, 8, 4) X(false, 8, 8, 4) X(false, 1, 16, 2)              \
+    X(false, 2, 16, 2) X(false, 4, 16, 2) X(false, 8, 16, 2)
+
 hipError_t tiled_screen_max_lds(size_t bytes) {
     hipError_t e = hipSuccess;
-#define OSANN_SET_LDS(F16IN, KS, R)                                                                        \
+#define OSANN_SET_LDS(F16IN, KS, R, G)                                                                     \
     if (e == hipSuccess)                                                                                   \
-        e = hipFuncSetAttribute((const void*)tiled_screen_kernel<F16IN, KS, R>,                            \
+        e = hipFuncSetAttribute((const void*)tiled_screen_kernel<F16IN, KS, R, G>,                         \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-#define OSANN_SET_LDS_R(F16IN, KS) OSANN_SET_LDS(F16IN, KS, 4) OSANN_SET_LDS(F16IN, KS, 8) OSANN_SET_LDS(F16IN, KS, 16)
-#define OSANN_SET_LDS_KS(F16IN) \
-    OSANN_SET_LDS_R(F16IN, 1) OSANN_SET_LDS_R(F16IN, 2) OSANN_SET_LDS_R(F16IN, 4) OSANN_SET_LDS_R(F16IN, 8)
-    OSANN_SET_LDS_KS(true)
-    OSANN_SET_LDS_KS(false)
-#undef OSANN_SET_LDS_KS
-#undef OSANN_SET_LDS_R
+    OSANN_EACH_SCREEN(OSANN_SET_LDS)
 #undef OSANN_SET_LDS
     return e;
 }
@@ -333,14 +542,9 @@ hipError_t tiled_screen_max_lds(size_t bytes) {
 int tiled_screen_occupancy(int R, int f16in, int ks, size_t lds) {
     int nb = 0;
     const void* fn = nullptr;
-#define OSANN_PICK(F16IN, KS, RR) \
-    if (f16in == (int)F16IN && ks == KS && R == RR) fn = (const void*)tiled_screen_kernel<F16IN, KS, RR>;
-#define OSANN_PICK_R(F16IN, KS) OSANN_PICK(F16IN, KS, 4) OSANN_PICK(F16IN, KS, 8) OSANN_PICK(F16IN, KS, 16)
-#define OSANN_PICK_KS(F16IN) OSANN_PICK_R(F16IN, 1) OSANN_PICK_R(F16IN, 2) OSANN_PICK_R(F16IN, 4) OSANN_PICK_R(F16IN, 8)
-    OSANN_PICK_KS(true)
-    OSANN_PICK_KS(false)
-#undef OSANN_PICK_KS
-#undef OSANN_PICK_R
+#define OSANN_PICK(F16IN, KS, RR, G) \
+    if (f16in == (int)F16IN && ks == KS && R == RR) fn = (const void*)tiled_screen_kernel<F16IN, KS, RR, G>;
+    OSANN_EACH_SCREEN(OSANN_PICK)
 #undef OSANN_PICK
     if (!fn) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds) != hipSuccess) return 0;
