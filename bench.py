@@ -83,6 +83,73 @@ def cpu_baseline(X, Y, budget, target_s=15.0):
                       f"{threads} threads), scaled to one {N_Q}-query step"}
 
 
+def recall_budget(idx, queries, nn_d64, db, sweep, mode, pair):
+    """Smallest budget of ``sweep`` whose recall@1 (distance equal to the exact NN's) reaches 0.9."""
+    import torch
+    from paper_1509_03453_amd import binding as B
+    rec = None
+    for budget in sweep:
+        i, _, _ = B.os_ann_search_ex(idx, queries, budget, mode=mode, rerank_r=RERANK)
+        d = pair(db, queries, i)
+        rec = float((d <= nn_d64).double().mean())
+        if rec >= 0.9:
+            return budget, rec
+    return sweep[-1], rec
+
+
+def serving_leg(X2, db2, budget2, n_req=600, rate=400.0):
+    """Continuous batching over three resident indexes: 16384x16 Gaussian (L=1), the
+    1e6x64 Gaussian database (L=2) and 1e6x128 descriptor-like uint8 rows (L=2);
+    Poisson arrivals of 1..4096-query requests, tiled search at each index's
+    recall-0.9 budget; QPS and p50/p99 latency from arrival to completion."""
+    import torch
+    from paper_1509_03453_amd import binding as B
+    from paper_1509_03453_amd import serving as S
+    from paper_1509_03453_amd import workloads as W
+    T = B.OS_ANN_MODE_TILED
+    X1 = W.gaussian_db(16384, 16, W.SEEDS["gauss16_db"])
+    X3 = W.descriptor_db(1_000_000, 128)
+    db1, db3 = torch.from_numpy(X1).cuda(), torch.from_numpy(X3).cuda()
+    db3f = db3.float()
+    gen = {"gauss16": lambda n, s: W.gaussian_queries(n, 16, s),
+           "gauss64": lambda n, s: W.gaussian_queries(n, 64, s),
+           "desc128": lambda n, s: W.descriptor_queries(X3, n, pick_seed=s, noise_seed=s + 1)[0]}
+    dbf = {"gauss16": db1, "gauss64": db2, "desc128": db3f}
+    ix = {"gauss16": B.Index(db1, 1, want_lowp=True), "gauss64": B.Index(db2, 2, want_lowp=True),
+          "desc128": B.Index(db3, 2, want_lowp=True)}
+    budgets = {"gauss64": budget2}
+    cal = {}
+    for name in ("gauss16", "desc128"):
+        qc = torch.from_numpy(gen[name](4096, 7000 + len(name))).cuda()
+        _, nn = exact_nn_torch(dbf[name], qc)
+        budgets[name], cal[name] = recall_budget(ix[name].handle, qc, nn, dbf[name],
+                                                 (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384),
+                                                 T, pair_d64_torch)
+    log(f"[bench] serving budgets {budgets} (calibration recall {cal})")
+    res = [S.ResidentIndex(n, ix[n], budgets[n], mode=T, rerank_r=RERANK) for n in ("gauss16", "gauss64", "desc128")]
+    names = [r.name for r in res]
+    arrivals = W.serving_requests(n_req, rate, 3, max_q=4096)
+    reqs = [S.Request(i, names[w], torch.from_numpy(gen[names[w]](n, sd)).cuda(), a)
+            for i, (a, w, n, sd) in enumerate(arrivals)]
+    srv = S.Server(res, slots=4, max_batch=8192, pool_cap_bytes=8 << 30, reserve_bytes=2 << 30)
+    srv.warmup({n: torch.from_numpy(gen[n](8192, 6000 + k)).cuda() for k, n in enumerate(names)})
+    log(f"[bench] serving {n_req} requests at {rate}/s")
+    st = srv.run(reqs, max_seconds=300)
+    recall = {}
+    for name in names:  # recall@1 of what the server returned, on up to 4096 of its queries
+        rr = [r for r in reqs if r.index == name]
+        qs = torch.cat([r.queries for r in rr])[:4096]
+        got = torch.cat([r.out_idx for r in rr])[:4096]
+        _, nn = exact_nn_torch(dbf[name], qs)
+        recall[name] = round(float((pair_d64_torch(dbf[name], qs, got) <= nn).double().mean()), 4)
+    for r in res:
+        r.index.close()
+    st.update({"offered_rate_req_s": rate, "slots": 4, "max_batch": 8192, "budgets": budgets,
+               "recall_at_1": recall, "mode": "tiled", "rerank_r": RERANK,
+               "indexes": "gauss16 16384x16 L=1; gauss64 1e6x64 L=2; desc128 1e6x128 u8 L=2"})
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +158,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--mode", choices=("fp32", "tiled", "both"), default="both")
     ap.add_argument("--budget", type=int, default=0, help="fixed budget instead of the recall sweep")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -264,6 +332,8 @@ def main():
         "index": {"n_cones": info["n_cones"], "n_nonempty": info["n_nonempty"],
                   "device_bytes": info["device_bytes"]},
     }
+    if not args.no_serving and "tiled" in modes:
+        out["serving"] = serving_leg(X, db, results["tiled"]["budget"])
     if not args.no_cpu:
         log("[bench] oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(X, Y, r["budget"])

@@ -215,7 +215,7 @@ struct SearchPlan {
     int64_t T = 0, nw = 0;
     bool bitmap = false, fits = true;
     size_t off_ql = 0, off_qcone = 0, off_sort = 0, off_qorder = 0, off_qsorted = 0, off_part = 0,
-           off_counter = 0, off_qbits = 0;
+           off_counter = 0, off_qbits = 0, off_cmin = 0;
     size_t bytes = 0;
 };
 
@@ -269,6 +269,7 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         p.off_qsorted = take((size_t)Q * 4);
         p.off_part = take((size_t)Q * p.smax * R * 8);
         p.off_counter = take(256);
+        p.off_cmin = take((size_t)Q * R * 4);
         if (p.bitmap) p.off_qbits = take((size_t)Q * p.nw * 8);
     }
     p.bytes = at;
@@ -490,6 +491,9 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     uint32_t* counter = reinterpret_cast<uint32_t*>(c.base + p.off_counter);
     e = launch_fill_u32(counter, 1, 0u, c.s);
     if (e != hipSuccess) return e;
+    uint32_t* cmin = reinterpret_cast<uint32_t*>(c.base + p.off_cmin);
+    e = launch_fill_u32(cmin, c.Q * p.R, 0xFFFFFFFFu, c.s);
+    if (e != hipSuccess) return e;
     TiledArgs ta{};
     ta.xl = ix->lp.xl;
     ta.dk = ix->lp.dk;
@@ -519,6 +523,7 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     ta.span = split_span(ix->n_nonempty > 0 ? ix->n_nonempty : 1, S);
     ta.counter = counter;
     ta.part = reinterpret_cast<uint2*>(c.base + p.off_part);
+    ta.cmin = cmin;
     const size_t lds = tiled_screen_lds(ta.span, ta.dk);
     int occ = tiled_screen_occupancy(p.R, ix->lp.f16, ix->lp.dk / 32, lds);
     if (occ < 1) occ = 1;

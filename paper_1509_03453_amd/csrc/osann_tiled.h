@@ -49,6 +49,8 @@ struct TiledArgs {
     uint32_t* counter;      // work-queue head, zero before the launch
     // output
     uint2* part;            // [Q][S][R] (FP32 bits of d~, padded position)
+    uint32_t* cmin;         // [Q][R] smallest order-preserving d~ bits kept per class
+                            // (padded position mod R), 0xFFFFFFFF before the launch
 };
 
 struct FinishArgs {

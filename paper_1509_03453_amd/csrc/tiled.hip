@@ -1,20 +1,31 @@
 // Matrix-core screening of the candidates with an exact FP32 re-rank.
 //
-// Queries are sorted by their own cone and cut into tiles of 64 (four waves
-// of 16).  A work item is (tile, split): split s owns a contiguous range of
+// Queries are sorted by their own cone and cut into tiles of 4 waves x 16G
+// queries.  A work item is (tile, split): split s owns a contiguous range of
 // the non-empty cones.  The block first marks, in an LDS table over that
-// range, which of its 64 queries probe each cone (each wave regenerates its
-// queries' walks, Section 3.B); then for every marked cone it streams the
-// cone's rows in 16-row MFMA tiles (bucket sizes are padded to 16 rows in
-// the low-precision copy).  With the rows as the MFMA A operand and the
-// wave's 16 queries as B, lane l holds the dot products of query l%16 with 4
-// rows, so each lane keeps a private top-R list of (d~, position) for one query,
-// where d~ = ||x^||^2 - 2 q^.x^ ranks candidates like the squared distance
-// of the rounded vectors.  The four lanes of a query merge their lists with
-// shuffles (bitonic), and the split's list goes to a per-query slot.  A
-// finishing pass merges the splits, recomputes the exact FP32 distance of
-// the R survivors and keeps the arg-min on (distance, row).  The order in
-// which candidates are met never matters: lists are kept in the total order
+// range, which of its queries probe each cone (from the probe pass's bitmaps,
+// or by regenerating the walks of Section 3.B); then for every marked cone it
+// streams the cone's rows through LDS in batches of up to 128 and screens
+// them in 16-row MFMA tiles (bucket sizes are padded to 16 rows in the
+// low-precision copy).  With the rows as the MFMA A operand and 16 queries
+// as B, lane l holds the products of query l%16 with 4 rows, so each lane
+// keeps a private top-R list of (d~, position) for one query, where
+// d~ = ||x^||^2 - 2 q^.x^ ranks candidates like the squared distance of the
+// rounded vectors.
+//
+// Pruning: a candidate whose d~ exceeds an upper bound of the query's final
+// R-th value can never be kept.  Two bounds are used: the R-th entry of the
+// lane lists (smallest over the four lanes of the query), and a bound shared
+// by all splits: every kept candidate lowers the minimum of its class
+// (padded position mod R) in a per-query array, and R distinct candidates
+// lie at or below the largest class minimum, so that value bounds the R-th.
+// Both only ever discard candidates outside the final top R, so the result
+// is the same whatever the timing of the splits.
+//
+// The four lanes of a query merge their lists with shuffles (bitonic), and
+// the split's list goes to a per-query slot.  A finishing pass merges the
+// splits, recomputes the exact FP32 distance of the R survivors and keeps
+// the arg-min on (distance, row).  Lists are kept in the total order
 // (d~, row), so results do not depend on the batch or the split.
 #include "osann_device.h"
 #include "osann_kernels.h"
@@ -80,6 +91,17 @@ __device__ inline void list_insert(float (&d)[R], uint32_t (&r)[R], float nd, ui
         d[0] = nd;
         r[0] = nr;
     }
+}
+
+// Order-preserving map of a non-NaN float to 32 bits (and back); 0xFFFFFFFF
+// (above every float) stands for "no candidate yet".
+__device__ inline uint32_t ord_bits(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline float ord_float(uint32_t u) {
+    if (u == 0xFFFFFFFFu) return __builtin_huge_valf();
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
 }
 
 template <bool F16IN>
@@ -329,6 +351,18 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
                 nn = end - np < kBatchRows ? end - np : kBatchRows;
                 issue(np, nn);
             }
+            // this lane's share (R/4 classes) of its queries' shared class minima
+            uint32_t cm[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const uint32_t* cp = a.cmin + (int64_t)myq[g] * R + (l / 16) * (R / 4);
+                cm[g] = 0;
+#pragma unroll
+                for (int k = 0; k < R / 4; ++k) {
+                    const uint32_t v = __hip_atomic_load(cp + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    cm[g] = v > cm[g] ? v : cm[g];
+                }
+            }
             // screen the staged batch
             if (mk != 0) {
                 const uint4* rb = rows + buf * kBatchRows * CPR;
@@ -363,21 +397,31 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
                                 // key (d~, padded position): a total order, no memory access
                                 const uint32_t pp = bp + r0 + 4 * (l / 16) + ii;
                                 if (d[ii] <= thr[g] && pair_less(d[ii], pp, ld[g][R - 1], lr[g][R - 1]) &&
-                                    nv[ii] < __builtin_huge_valf())
+                                    nv[ii] < __builtin_huge_valf()) {
                                     list_insert<R>(ld[g], lr[g], d[ii], pp);
+                                    __hip_atomic_fetch_min(a.cmin + (int64_t)myq[g] * R + (pp & (R - 1)),
+                                                           ord_bits(d[ii]), __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                                }
                             }
                             thr[g] = fminf(thr[g], ld[g][R - 1]);
                         }
                     }
                 }
             }
-            // refresh the per-query bound from the four lanes of each query
+            // refresh the per-query bound: the four lanes' R-th entries and the
+            // largest shared class minimum (read at the start of the batch)
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 float k = fminf(qthr[g], ld[g][R - 1]);
                 k = fminf(k, __shfl_xor(k, 16, 64));
                 k = fminf(k, __shfl_xor(k, 32, 64));
-                qthr[g] = k;
+                uint32_t c = cm[g];
+                const uint32_t c16 = (uint32_t)__shfl_xor((int)c, 16, 64);
+                c = c16 > c ? c16 : c;
+                const uint32_t c32 = (uint32_t)__shfl_xor((int)c, 32, 64);
+                c = c32 > c ? c32 : c;
+                qthr[g] = fminf(k, ord_float(c));
             }
             if (nli < nlist) park(buf ^ 1);
             __syncthreads();

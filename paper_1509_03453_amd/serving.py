@@ -1,0 +1,259 @@
+"""Continuous-batching search server over several resident indexes.
+
+Requests (a batch of 1..4096 queries against one named index) arrive over
+time.  The server keeps every index resident on the device and runs a host
+loop that
+
+* moves requests whose arrival time has come into a per-index queue;
+* retires launches whose completion event has fired, releasing their slot
+  and their device memory;
+* admits queued work while a slot is free AND the device memory it needs
+  (the library's workspace for that batch, staging for the queries and the
+  outputs) fits both in the free HBM above a reserve and in the pool cap;
+* packs the oldest queued requests of one index into a micro-batch of at most
+  ``max_batch`` queries (whole requests only; one request larger than the cap
+  goes alone) and launches one ``os_ann_search_ex`` on that slot's stream.
+
+So requests arriving while others are on the GPU start as soon as a slot and
+memory free up, and their kernels overlap on the device.  Latency is measured
+on the device clock: completion event time minus the request's arrival time,
+both relative to a start event recorded when the run begins.
+
+The search itself (hash, probe, screen, re-rank) is entirely in the HIP
+library: this module only schedules calls to it.  A query's result does not
+depend on which other queries share its launch (every accumulation order is
+fixed per (query, candidate) pair and the candidate lists are ordered by a
+total order), so a request gets the same answer alone and in the mix.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Sequence
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+__all__ = ["Request", "ResidentIndex", "Server", "pack_batch", "admissible", "latency_stats"]
+
+
+@dataclasses.dataclass
+class Request:
+    """One client request: ``queries`` (device, rows of the index's query type) for index ``index``."""
+    rid: int
+    index: str
+    queries: torch.Tensor
+    arrival: float                       # seconds after the run starts
+    out_idx: torch.Tensor | None = None  # filled on completion (device views)
+    out_dist: torch.Tensor | None = None
+    launched: float | None = None        # host seconds when its batch was launched
+    done: float | None = None            # device seconds of its batch's completion event
+    batch_id: int | None = None
+
+    @property
+    def n(self) -> int:
+        return int(self.queries.shape[0])
+
+    @property
+    def latency(self) -> float | None:
+        return None if self.done is None else self.done - self.arrival
+
+
+@dataclasses.dataclass
+class ResidentIndex:
+    """A built index kept on the device with its serving parameters."""
+    name: str
+    index: B.Index
+    budget: int
+    mode: int = B.OS_ANN_MODE_TILED
+    rerank_r: int = 8
+
+    def workspace(self, q: int) -> int:
+        return self.index.workspace_bytes(q, self.budget, self.mode, self.rerank_r)
+
+
+# ---------------------------------------------------------------------------
+# scheduling policy (pure functions, host only)
+# ---------------------------------------------------------------------------
+def pack_batch(queue: Sequence[int], max_batch: int) -> int:
+    """How many requests, from the head of ``queue`` (their query counts), go into one launch.
+
+    Whole requests are taken in arrival order while the total stays within
+    ``max_batch``; the head request is always taken, even when it alone is
+    larger than the cap."""
+    total, k = 0, 0
+    for n in queue:
+        if k > 0 and total + n > max_batch:
+            break
+        total += n
+        k += 1
+    return k
+
+
+def admissible(need: int, free_hbm: int, reserve: int, in_flight: int, pool_cap: int) -> bool:
+    """A launch needing ``need`` device bytes may start: it fits above the reserve and under the cap."""
+    return need <= free_hbm - reserve and in_flight + need <= pool_cap
+
+
+def latency_stats(lat: Sequence[float]) -> dict:
+    """p50 / p99 / mean / max of latencies in seconds, reported in milliseconds."""
+    a = np.asarray(lat, dtype=np.float64) * 1e3
+    if a.size == 0:
+        return {"p50_ms": None, "p99_ms": None, "mean_ms": None, "max_ms": None}
+    return {"p50_ms": float(np.percentile(a, 50)), "p99_ms": float(np.percentile(a, 99)),
+            "mean_ms": float(a.mean()), "max_ms": float(a.max())}
+
+
+def pick_index(queues: dict[str, collections.deque]) -> str | None:
+    """The index whose oldest queued request arrived first (first come, first served)."""
+    best, t = None, None
+    for name, q in queues.items():
+        if q and (t is None or q[0].arrival < t):
+            best, t = name, q[0].arrival
+    return best
+
+
+# ---------------------------------------------------------------------------
+# the server
+# ---------------------------------------------------------------------------
+class _Slot:
+    def __init__(self, device):
+        self.stream = torch.cuda.Stream(device=device)  # default priority
+        self.event = torch.cuda.Event(enable_timing=True)
+        self.reqs: list[Request] = []
+        self.hold: tuple = ()
+        self.bytes = 0
+        self.busy = False
+
+
+class Server:
+    """Serve requests against resident indexes with continuous batching on ``slots`` streams.
+
+    ``pool_cap_bytes`` bounds the device memory held by launches in flight;
+    ``reserve_bytes`` is the free HBM left untouched for everything else."""
+
+    def __init__(self, indexes: Sequence[ResidentIndex], slots: int = 4, max_batch: int = 8192,
+                 pool_cap_bytes: int = 4 << 30, reserve_bytes: int = 1 << 30,
+                 device: torch.device | str = "cuda:0",
+                 free_hbm: Callable[[], int] | None = None):
+        if slots < 1 or max_batch < 1:
+            raise ValueError("slots and max_batch must be positive")
+        self.indexes = {r.name: r for r in indexes}
+        self.device = torch.device(device)
+        self.max_batch = int(max_batch)
+        self.pool_cap = int(pool_cap_bytes)
+        self.reserve = int(reserve_bytes)
+        self.slots = [_Slot(self.device) for _ in range(slots)]
+        self._free_hbm = free_hbm or self._device_free
+        self.in_flight = 0
+        self.n_batches = 0
+        self.peak_in_flight = 0
+        self.max_concurrent = 0
+
+    def _device_free(self) -> int:
+        free, _ = torch.cuda.mem_get_info(self.device)
+        # blocks the caching allocator holds but does not use are free to us too
+        cached = torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
+        return int(free + cached)
+
+    def need_bytes(self, ix: ResidentIndex, q: int, qbytes_per_row: int) -> int:
+        return ix.workspace(q) + q * (qbytes_per_row + 8 + 4)
+
+    def warmup(self, samples: dict[str, torch.Tensor]) -> None:
+        """Runs every index once per power-of-two batch size up to ``max_batch``, on queries drawn
+        from its own distribution (``samples[name]``, at least ``max_batch`` rows), so that the
+        library's per-size choices are made and cached before requests are timed."""
+        for name, ix in self.indexes.items():
+            x = samples[name]
+            q = 1
+            while True:
+                q = min(q, self.max_batch, x.shape[0])
+                ix.index.search(x[:q], ix.budget, mode=ix.mode, rerank_r=ix.rerank_r)
+                if q >= min(self.max_batch, x.shape[0]):
+                    break
+                q *= 2
+        torch.cuda.synchronize(self.device)
+
+    def _launch(self, slot: _Slot, ix: ResidentIndex, reqs: list[Request], need: int, now: float) -> None:
+        q_total = sum(r.n for r in reqs)
+        with torch.cuda.stream(slot.stream):
+            qs = reqs[0].queries if len(reqs) == 1 else torch.cat([r.queries for r in reqs])
+            ws = torch.empty(ix.workspace(q_total), dtype=torch.uint8, device=self.device)
+            oi = torch.empty(q_total, dtype=torch.int64, device=self.device)
+            od = torch.empty(q_total, dtype=torch.float32, device=self.device)
+            B.os_ann_search_ex(ix.index.handle, qs, ix.budget, mode=ix.mode, stream=slot.stream,
+                               workspace=ws, rerank_r=ix.rerank_r, out_idx=oi, out_dist=od,
+                               want_ncand=False)
+            slot.event.record(slot.stream)
+        off = 0
+        for r in reqs:
+            r.out_idx, r.out_dist = oi[off:off + r.n], od[off:off + r.n]
+            r.launched, r.batch_id = now, self.n_batches
+            off += r.n
+        slot.reqs, slot.hold, slot.bytes, slot.busy = reqs, (qs, ws, oi, od), need, True
+        self.in_flight += need
+        self.n_batches += 1
+        self.peak_in_flight = max(self.peak_in_flight, self.in_flight)
+        self.max_concurrent = max(self.max_concurrent, sum(s.busy for s in self.slots))
+
+    def run(self, requests: Sequence[Request], max_seconds: float = 600.0) -> dict:
+        """Serves ``requests`` (arrival times relative to the start) and returns throughput and latency."""
+        for r in requests:
+            if r.index not in self.indexes:
+                raise KeyError(f"request {r.rid} names unknown index {r.index!r}")
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        queues = {name: collections.deque() for name in self.indexes}
+        base = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(self.device)
+        base.record(torch.cuda.current_stream(self.device))
+        base.synchronize()
+        t0 = time.perf_counter()
+        finished: list[Request] = []
+        while pending or any(queues.values()) or any(s.busy for s in self.slots):
+            now = time.perf_counter() - t0
+            if now > max_seconds:
+                raise TimeoutError(f"serving run exceeded {max_seconds} s")
+            while pending and pending[0].arrival <= now:
+                r = pending.popleft()
+                queues[r.index].append(r)
+            for s in self.slots:  # retire
+                if s.busy and s.event.query():
+                    t_done = base.elapsed_time(s.event) * 1e-3
+                    for r in s.reqs:
+                        r.done = t_done
+                    finished.extend(s.reqs)
+                    self.in_flight -= s.bytes
+                    s.reqs, s.hold, s.bytes, s.busy = [], (), 0, False
+            progressed = False
+            for s in self.slots:  # admit
+                if s.busy:
+                    continue
+                name = pick_index(queues)
+                if name is None:
+                    break
+                ix, q = self.indexes[name], queues[name]
+                k = pack_batch([r.n for r in q], self.max_batch)
+                reqs = [q[i] for i in range(k)]
+                row_bytes = reqs[0].queries.element_size() * reqs[0].queries.shape[1]
+                need = self.need_bytes(ix, sum(r.n for r in reqs), row_bytes)
+                if not admissible(need, self._free_hbm(), self.reserve, self.in_flight, self.pool_cap):
+                    if self.in_flight == 0:
+                        raise MemoryError(f"request {reqs[0].rid} needs {need} B; pool cap or free HBM too small")
+                    break
+                for _ in range(k):
+                    q.popleft()
+                self._launch(s, ix, reqs, need, now)
+                progressed = True
+            if not progressed:
+                time.sleep(5e-5)
+        wall = time.perf_counter() - t0
+        n_q = sum(r.n for r in finished)
+        span = max(r.done for r in finished) - min(r.arrival for r in finished) if finished else 0.0
+        out = {"requests": len(finished), "queries": n_q, "batches": self.n_batches,
+               "qps": n_q / span if span > 0 else None, "span_s": span, "wall_s": wall,
+               "max_concurrent_launches": self.max_concurrent, "peak_in_flight_bytes": self.peak_in_flight}
+        out.update(latency_stats([r.latency for r in finished]))
+        return out

@@ -1,0 +1,126 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (the whole query batch in one call), on sampled queries the
+oracle recomputes one by one.
+
+* 1e6 x 64 i.i.d. Gaussian FP32, L=2, 1e4 queries: budgets 256/1024/4096 and
+  327680 (the smallest swept budget at which recall@1 reaches 0.9), both modes.
+* 1e6 x 128 descriptor-like uint8 rows, L=2, 1e4 noisy queries, both modes.
+* ~4.2e6 mean-removed 8x8 FP16 patches of a 2048x2048 1/f field, L=2, queries
+  are all patches of the shifted noisy field (~4.2e6), tiled mode.
+
+The index itself (every key, bucket offset and permutation entry) is compared
+in full; searches are compared on a spread sample of queries."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1509_03453_amd import binding as B
+from paper_1509_03453_amd import workloads as W
+from tests.gpu_util import dev, say, unpack_top
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+RTOL = 1e-5
+U = 2.0 ** -24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B.lib()
+
+
+def full_index(orc, X, L, tag):
+    say(f"[full] {tag}: building N={X.shape[0]} D={X.shape[1]} L={L} dtype={X.dtype}")
+    h = B.os_ann_build_ex(dev(X), L, want_lowp=True)
+    ex = B.os_ann_export(h)
+    torch.cuda.synchronize()
+    o = orc.build_index(X, L)
+    cone = ex["cone"].cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(cone, o["cone"]), tag
+    ti, ts = unpack_top(ex["top"].cpu().numpy().view(np.uint64), L)
+    assert np.array_equal(ti, o["top"]) and np.array_equal(ts, o["sign"]), tag
+    assert np.array_equal(ex["offsets"].cpu().numpy(), o["offsets"]), tag
+    assert np.array_equal(ex["perm"].cpu().numpy(), o["perm"]), tag
+    del ex
+    return h, o
+
+
+def sample_ids(Q, n):
+    return np.unique(np.linspace(0, Q - 1, n).astype(np.int64))
+
+
+def fp32_sampled(orc, X, o, h, Y, yq, budget, sample, tag):
+    say(f"[full] {tag}: fp32 Q={Y.shape[0]} B={budget}")
+    gi, gd, gn = B.os_ann_search_ex(h, yq, budget, mode=B.OS_ANN_MODE_FP32)
+    torch.cuda.synchronize()
+    gi, gd, gn = gi.cpu().numpy()[sample], gd.cpu().numpy()[sample], gn.cpu().numpy()[sample]
+    oi, od32, od64, on = orc.search(X, o, Y[sample], budget)
+    assert np.array_equal(gn, on), tag
+    assert np.array_equal(gi, oi), tag
+    assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), tag
+    assert (np.abs(gd - od64) <= RTOL * np.maximum(od64, 1e-300)).all(), tag
+
+
+def tiled_sampled(orc, X, o, h, Y, yq, budget, sample, tag, R=8, max_mismatch=0.02):
+    say(f"[full] {tag}: tiled Q={Y.shape[0]} B={budget}")
+    gi, gd, gn = B.os_ann_search_ex(h, yq, budget, mode=B.OS_ANN_MODE_TILED, rerank_r=R)
+    torch.cuda.synchronize()
+    gi, gd, gn = gi.cpu().numpy()[sample], gd.cpu().numpy()[sample], gn.cpu().numpy()[sample]
+    Ys = Y[sample]
+    oi, od32, od64, on, dtr, top = orc.search_tiled(X, o, Ys, budget, R=R)
+    assert np.array_equal(gn, on), tag
+    assert np.array_equal(gd.view(np.uint32), orc.pair_d32(X, Ys, gi).view(np.uint32)), tag
+    f16 = X.dtype == np.float16
+    D = X.shape[1]
+    bad = np.flatnonzero(gi != oi)
+    for q in bad:  # a differing row must be explained by a near tie at the R-th screening value
+        xs = orc.round_short(X[[gi[q], oi[q], top[q][-1]]].astype(np.float32), f16).reshape(3, D)
+        ys = orc.round_short(Ys[q].astype(np.float32), f16)
+        tol = 4 * (D + 2) * U * ((xs ** 2).sum(1) + 2 * np.abs(xs * ys).sum(1)).max()
+        dg = orc.pair_dtilde(X, Ys[q:q + 1], [gi[q]], f16)[0]
+        do = orc.pair_dtilde(X, Ys[q:q + 1], [oi[q]], f16)[0]
+        if gi[q] in top[q]:
+            assert do >= dtr[q] - tol, (tag, q)
+        else:
+            assert dg <= dtr[q] + tol, (tag, q)
+    assert len(bad) <= max_mismatch * len(sample) + 1, (tag, len(bad))
+
+
+def test_gaussian_1m_d64(orc):
+    X = W.gaussian_db(1_000_000, 64, W.SEEDS["gauss64_db"])
+    Y = W.gaussian_queries(10_000, 64, W.SEEDS["gauss64_q"])
+    h, o = full_index(orc, X, 2, "gauss 1e6x64")
+    yq = dev(Y)
+    try:
+        for budget, n in ((256, 400), (1024, 400), (4096, 200), (327680, 48)):
+            s = sample_ids(len(Y), n)
+            fp32_sampled(orc, X, o, h, Y, yq, budget, s, "gauss 1e6x64")
+            tiled_sampled(orc, X, o, h, Y, yq, budget, s, "gauss 1e6x64")
+    finally:
+        B.os_ann_free(h)
+
+
+def test_descriptor_1m_d128_u8(orc):
+    X = W.descriptor_db(1_000_000, 128)
+    Y, _ = W.descriptor_queries(X, 10_000)
+    h, o = full_index(orc, X, 2, "desc 1e6x128 u8")
+    yq = dev(Y)
+    try:
+        for budget, n in ((256, 300), (1024, 300), (4096, 150)):
+            s = sample_ids(len(Y), n)
+            fp32_sampled(orc, X, o, h, Y, yq, budget, s, "desc 1e6x128 u8")
+            tiled_sampled(orc, X, o, h, Y, yq, budget, s, "desc 1e6x128 u8")
+    finally:
+        B.os_ann_free(h)
+
+
+def test_patches_4m_fp16(orc):
+    X, Y = W.patch_pair(2048)
+    h, o = full_index(orc, X, 2, "patches 2048^2 f16")
+    yq = dev(Y)
+    try:
+        for budget, n in ((64, 300), (1024, 200)):
+            tiled_sampled(orc, X, o, h, Y, yq, budget, sample_ids(len(Y), n), "patches 2048^2 f16")
+        fp32_sampled(orc, X, o, h, Y, yq, 1024, sample_ids(len(Y), 200), "patches 2048^2 f16")
+    finally:
+        B.os_ann_free(h)
