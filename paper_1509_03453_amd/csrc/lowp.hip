@@ -6,7 +6,8 @@
 //   xl[p][dk]      row at padded position p, BF16 (round to nearest even) for
 //                  FP32 and uint8 data, FP16 as stored for FP16 data; dk = D
 //                  rounded up to 32 (one MFMA K step); zero padded
-//   nrm[p]         FP32 sum of squares of the rounded row, +inf on padding rows
+//   nrm[p]         FP32 sum of squares of the rounded row (ascending component
+//                  order), +inf on padding rows
 //   ppos[p]        sorted position of the row (exact FP32 re-rank from the
 //                  planes; original id via perm), 0xFFFFFFFF on padding rows
 //   ne_id[c]       rank of cone c among the non-empty cones; ne_cone is its inverse
@@ -67,72 +68,99 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-// One thread per (sorted position, 16-byte chunk of the planes).
+// Rounded value of one component and its 16-bit code.
+__device__ inline uint16_t lowp_code(float x, int to_f16, float* v) {
+    const uint16_t b = to_f16 ? f16_rne(x) : bf16_rne(x);
+    *v = to_f16 ? F16::val(b) : __uint_as_float((uint32_t)b << 16);
+    return b;
+}
+
+// One thread per sorted position (coalesced reads of the chunk-major
+// planes): rounds the row, writes it to its padded position in 16-byte
+// units of 8 components, and stores the FP32 sum of squares of the rounded
+// values taken in ascending component order, and the position map.
 template <typename E>
 __global__ void lowp_rows_kernel(const uint4* __restrict__ planes, int64_t N, int D, int nch,
                                  const uint32_t* __restrict__ sorted_cone, const uint32_t* __restrict__ off,
                                  const uint32_t* __restrict__ poff, int dk, int to_f16,
-                                 uint16_t* __restrict__ xl, uint32_t* __restrict__ ppos) {
-    constexpr int EPC = Unpack<E>::n;
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= N * nch) return;
-    const int64_t pos = f / nch;
-    const int k = (int)(f % nch);
+                                 uint16_t* __restrict__ xl, uint32_t* __restrict__ ppos, float* __restrict__ nrm) {
+#pragma clang fp contract(off)
+    constexpr int EPC = Unpack<E>::n;             // components per 16-byte chunk of the planes
+    constexpr int CPU = EPC >= 8 ? 1 : 8 / EPC;   // chunks per step (at least one output unit)
+    constexpr int NU = CPU * EPC / 8;             // output units per step
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= N) return;
     const uint32_t c = sorted_cone[pos];
     const int64_t p = (int64_t)poff[c] + (pos - (int64_t)off[c]);
-    float x[EPC];
-    Unpack<E>::run(planes[(int64_t)k * N + pos], x);
-#pragma unroll
-    for (int e = 0; e < EPC; ++e) {
-        const int i = k * EPC + e;
-        if (i < D) xl[p * dk + i] = to_f16 ? f16_rne(x[e]) : bf16_rne(x[e]);
-    }
-    if (k == 0) ppos[p] = (uint32_t)pos;
-}
-
-__global__ void lowp_norm_kernel(const uint16_t* __restrict__ xl, int64_t np, int D, int dk, int is_f16,
-                                 const uint32_t* __restrict__ ppos, float* __restrict__ nrm) {
-#pragma clang fp contract(off)
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    if (ppos[p] == 0xFFFFFFFFu) {
-        nrm[p] = __builtin_huge_valf();
-        return;
-    }
+    uint4* dst = reinterpret_cast<uint4*>(xl + p * dk);
     float acc = 0.0f;
-    for (int i = 0; i < D; ++i) {
-        const uint16_t b = xl[p * dk + i];
-        const float v = is_f16 ? F16::val(b) : __uint_as_float((uint32_t)b << 16);
-        const float sq = v * v;
-        acc = acc + sq;
+    for (int k0 = 0; k0 < nch; k0 += CPU) {
+        float x[CPU * EPC];
+#pragma unroll
+        for (int j = 0; j < CPU; ++j) {
+            float t[EPC];
+            if (k0 + j < nch) {
+                Unpack<E>::run(planes[(int64_t)(k0 + j) * N + pos], t);
+            } else {
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) t[e] = 0.0f;
+            }
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) x[j * EPC + e] = t[e];
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            uint32_t w[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                uint16_t code[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int e = u * 8 + 2 * h + q;
+                    const int i = k0 * EPC + e;
+                    code[q] = 0;
+                    if (i < D) {
+                        float v;
+                        code[q] = lowp_code(x[e], to_f16, &v);
+                        const float sq = v * v;
+                        acc = acc + sq;
+                    }
+                }
+                w[h] = (uint32_t)code[0] | ((uint32_t)code[1] << 16);
+            }
+            dst[(k0 * EPC) / 8 + u] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
     }
+    ppos[p] = (uint32_t)pos;
     nrm[p] = acc;
 }
 
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
                             const uint32_t* offsets, const uint32_t* poff, int dk, int to_f16, uint16_t* xl,
                             uint32_t* ppos, float* nrm, int64_t np_total, hipStream_t s) {
-    const int64_t n = N * nch;
-    const dim3 grid((unsigned)((n + 255) / 256));
+    // padding rows: zero components, no position, +inf norm (never kept)
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(xl), np_total * dk / 2, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(ppos, np_total, 0xFFFFFFFFu, s);
+    if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(nrm), np_total, 0x7F800000u, s);
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)((N + 255) / 256));
     auto pl = static_cast<const uint4*>(planes);
     switch (dtype) {
         case kF32:
             hipLaunchKernelGGL(lowp_rows_kernel<F32>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
-                               poff, dk, to_f16, xl, ppos);
+                               poff, dk, to_f16, xl, ppos, nrm);
             break;
         case kF16:
             hipLaunchKernelGGL(lowp_rows_kernel<F16>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
-                               poff, dk, to_f16, xl, ppos);
+                               poff, dk, to_f16, xl, ppos, nrm);
             break;
         case kU8:
             hipLaunchKernelGGL(lowp_rows_kernel<U8>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
-                               poff, dk, to_f16, xl, ppos);
+                               poff, dk, to_f16, xl, ppos, nrm);
             break;
         default:
             return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(lowp_norm_kernel, dim3((unsigned)((np_total + 255) / 256)), dim3(256), 0, s, xl, np_total, D,
-                       dk, to_f16, ppos, nrm);
     return hipGetLastError();
 }
 

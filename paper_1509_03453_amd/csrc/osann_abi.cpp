@@ -191,10 +191,7 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
     if (!rc) rc = dev_alloc(ix, (void**)&lp.nrm, (size_t)rows * 4, "nrm");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.ppos, (size_t)rows * 4, "ppos");
     if (rc) return done(rc);
-    e = hipMemsetAsync(lp.xl, 0, (size_t)rows * lp.dk * 2, s);
-    if (e == hipSuccess) e = launch_fill_u32(lp.ppos, rows, 0xFFFFFFFFu, s);
-    if (e == hipSuccess)
-        e = launch_lowp_rows(ix->planes, ix->dtype, ix->N, ix->D, ix->nch, ix->sorted_cone, ix->offsets, lp.poff,
+    e = launch_lowp_rows(ix->planes, ix->dtype, ix->N, ix->D, ix->nch, ix->sorted_cone, ix->offsets, lp.poff,
                              lp.dk, lp.f16, lp.xl, lp.ppos, lp.nrm, rows, s);
     if (e == hipSuccess) e = tiled_screen_max_lds(kScreenLdsMax);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
