@@ -7,7 +7,7 @@
 //                  FP32 and uint8 data, FP16 as stored for FP16 data; dk = D
 //                  rounded up to 32 (one MFMA K step); zero padded
 //   nrm[p]         FP32 sum of squares of the rounded row (ascending component
-//                  order), +inf on padding rows
+//                  order), NaN on padding rows
 //   ppos[p]        sorted position of the row (exact FP32 re-rank from the
 //                  planes; original id via perm), 0xFFFFFFFF on padding rows
 //   ne_id[c]       rank of cone c among the non-empty cones; ne_cone is its inverse
@@ -138,10 +138,10 @@ __global__ void lowp_rows_kernel(const uint4* __restrict__ planes, int64_t N, in
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
                             const uint32_t* offsets, const uint32_t* poff, int dk, int to_f16, uint16_t* xl,
                             uint32_t* ppos, float* nrm, int64_t np_total, hipStream_t s) {
-    // padding rows: zero components, no position, +inf norm (never kept)
+    // padding rows: zero components, no position, NaN norm (fails every comparison)
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(xl), np_total * dk / 2, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32(ppos, np_total, 0xFFFFFFFFu, s);
-    if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(nrm), np_total, 0x7F800000u, s);
+    if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(nrm), np_total, 0x7FC00000u, s);
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((N + 255) / 256));
     auto pl = static_cast<const uint4*>(planes);

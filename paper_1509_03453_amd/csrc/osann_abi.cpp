@@ -193,7 +193,7 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
     if (rc) return done(rc);
     e = launch_lowp_rows(ix->planes, ix->dtype, ix->N, ix->D, ix->nch, ix->sorted_cone, ix->offsets, lp.poff,
                              lp.dk, lp.f16, lp.xl, lp.ppos, lp.nrm, rows, s);
-    if (e == hipSuccess) e = tiled_screen_max_lds(kScreenLdsMax);
+    if (e == hipSuccess) e = tiled_screen_max_lds();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return done(hip_fail(e, "low-precision copy"));
     lp.ready = true;
@@ -249,9 +249,10 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         // smallest split count whose cone list and row batches fit in LDS
         p.smin = 1;
         while (p.smin < 16 && (split_span(ne, p.smin) * 48 > (int64_t)kTabBytesMax ||
-                               tiled_screen_lds(split_span(ne, p.smin), p.dk) > kScreenLdsMax))
+                               tiled_screen_lds(split_span(ne, p.smin), p.dk) + tiled_screen_static_lds(R) >
+                                   kLdsPerBlock))
             p.smin <<= 1;
-        p.fits = tiled_screen_lds(split_span(ne, p.smin), p.dk) <= kScreenLdsMax;
+        p.fits = tiled_screen_lds(split_span(ne, p.smin), p.dk) + tiled_screen_static_lds(R) <= kLdsPerBlock;
         const int64_t want = (4 * (int64_t)ix->num_cu + p.T - 1) / (p.T > 0 ? p.T : 1);
         p.smax = (int)std::max<int64_t>(p.smin, std::min<int64_t>(16, pow2_ceil(std::max<int64_t>(want, 1))));
         while (p.smax > p.smin && split_span(ne, p.smax) < 64 * 2) p.smax >>= 1;
@@ -490,6 +491,17 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     if (e != hipSuccess) return e;
     uint32_t* cmin = reinterpret_cast<uint32_t*>(c.base + p.off_cmin);
     e = launch_fill_u32(cmin, c.Q * p.R, 0xFFFFFFFFu, c.s);
+    if (e != hipSuccess) return e;
+    SeedArgs sd{};
+    sd.xl = ix->lp.xl;
+    sd.nrm = ix->lp.nrm;
+    sd.poff = ix->lp.poff;
+    sd.dk = ix->lp.dk;
+    sd.ql = pa.ql;
+    sd.q_cone = pa.q_cone;
+    sd.Q = c.Q;
+    sd.cmin = cmin;
+    e = launch_tiled_seed(sd, p.R, ix->lp.f16, c.s);
     if (e != hipSuccess) return e;
     TiledArgs ta{};
     ta.xl = ix->lp.xl;

@@ -12,7 +12,7 @@ namespace osann {
 inline int tile_groups(int R) { return R <= 8 ? 4 : 2; }
 inline int tile_queries(int R) { return 64 * tile_groups(R); }
 constexpr size_t kTabBytesMax = 40 * 1024;  // LDS budget of one split's marked-cone list (48 B per cone)
-constexpr size_t kScreenLdsMax = 156 * 1024;  // dynamic LDS of one screen block (160 KB minus static)
+constexpr size_t kLdsPerBlock = 160 * 1024;  // LDS of one compute unit, all usable by one block
 
 struct TiledArgs {
     // low-precision index
@@ -53,6 +53,19 @@ struct TiledArgs {
                             // (padded position mod R), 0xFFFFFFFF before the launch
 };
 
+// Bound seeding before the screen: d~ of (part of) each query's own cone on
+// the vector units, raised by an accumulation-order error bound.
+struct SeedArgs {
+    const uint16_t* xl;
+    const float* nrm;
+    const uint32_t* poff;
+    int dk;
+    const uint16_t* ql;      // [Q][dk]
+    const uint32_t* q_cone;  // [Q] own cone
+    int64_t Q;
+    uint32_t* cmin;          // [Q][2R]
+};
+
 struct FinishArgs {
     const uint2* part;
     int S;
@@ -78,9 +91,11 @@ hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int
                             const uint32_t* offsets, const uint32_t* poff, int dk, int to_f16, uint16_t* xl,
                             uint32_t* ppos, float* nrm, int64_t np_total, hipStream_t s);
 hipError_t launch_tiled_screen(const TiledArgs& a, int R, int f16in, int blocks, hipStream_t s);
-size_t tiled_screen_lds(int64_t span, int dk);
+size_t tiled_screen_lds(int64_t span, int dk);  // dynamic LDS bytes of one screen block
+size_t tiled_screen_static_lds(int R);          // static LDS bytes (upper bound) of one screen block
 hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s);
-hipError_t tiled_screen_max_lds(size_t bytes);
+hipError_t launch_tiled_seed(const SeedArgs& a, int R, int f16in, hipStream_t s);
+hipError_t tiled_screen_max_lds();
 int tiled_screen_occupancy(int R, int f16in, int ks, size_t lds);
 
 }  // namespace osann

@@ -8,25 +8,29 @@
 // streams the cone's rows through LDS in batches of up to 128 and screens
 // them in 16-row MFMA tiles (bucket sizes are padded to 16 rows in the
 // low-precision copy).  With the rows as the MFMA A operand and 16 queries
-// as B, lane l holds the products of query l%16 with 4 rows, so each lane
-// keeps a private top-R list of (d~, position) for one query, where
-// d~ = ||x^||^2 - 2 q^.x^ ranks candidates like the squared distance of the
-// rounded vectors.
+// as B, lane l holds the products of query l%16 with 4 rows, from which it
+// forms d~ = ||x^||^2 - 2 q^.x^, which ranks candidates like the squared
+// distance of the rounded vectors.
+//
+// Each query keeps, per split, a top-R list of (d~, padded position) in
+// LDS.  The tile loop only compares d~ with a per-query bound; the few
+// candidates at or below it go to a per-wave hit buffer, which is merged
+// into the lists (one lane per query) when it fills and after every batch.
 //
 // Pruning: a candidate whose d~ exceeds an upper bound of the query's final
 // R-th value can never be kept.  Two bounds are used: the R-th entry of the
-// lane lists (smallest over the four lanes of the query), and a bound shared
-// by all splits: every kept candidate lowers the minimum of its class
-// (padded position mod R) in a per-query array, and R distinct candidates
-// lie at or below the largest class minimum, so that value bounds the R-th.
-// Both only ever discard candidates outside the final top R, so the result
-// is the same whatever the timing of the splits.
+// split's list of the query, and a bound shared by all splits: every kept
+// candidate lowers the minimum of its class (padded position mod R) in a
+// per-query array, and R distinct candidates lie at or below the largest
+// class minimum, so that value bounds the R-th.  A pass before the screen
+// seeds the class minima from the query's own cone.  Bounds only ever
+// discard candidates outside the final top R, so the result is the same
+// whatever the timing of the splits.
 //
-// The four lanes of a query merge their lists with shuffles (bitonic), and
-// the split's list goes to a per-query slot.  A finishing pass merges the
-// splits, recomputes the exact FP32 distance of the R survivors and keeps
-// the arg-min on (distance, row).  Lists are kept in the total order
-// (d~, row), so results do not depend on the batch or the split.
+// A finishing pass merges the S split lists, recomputes the exact FP32
+// distance of the R survivors and keeps the arg-min on (distance, row).
+// Lists are kept in the total order (d~, position), so results do not
+// depend on the batch or the split.
 #include "osann_device.h"
 #include "osann_kernels.h"
 #include "osann_tiled.h"
@@ -114,6 +118,7 @@ __device__ inline f32x4_t mfma16(const uint4& a, const uint4& b, f32x4_t acc) {
 }
 
 constexpr int kBatchRows = 128;  // rows staged in LDS per batch (8 MFMA row tiles)
+constexpr int kHitCap = 64;      // hit buffer entries per wave (one full ballot)
 
 // Exclusive prefix sum of one value per thread over the 256-thread block.
 __device__ inline uint32_t block_scan256(uint32_t v, uint32_t* wsum, uint32_t* total) {
@@ -159,6 +164,8 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
     __shared__ uint8_t s_order[4][kMaxD];
     __shared__ uint8_t s_sbit[4][kMaxD];
     __shared__ uint32_t s_item, s_nlist, s_wsum[4];
+    __shared__ uint2 s_list[4][QW * R];     // per wave: top-R list of each query slot
+    __shared__ uint4 s_hit[4][kHitCap];     // per wave: (d~ bits, padded position, slot) hits
     const int w = threadIdx.x / 64, l = lane_id();
     const int64_t total = a.T * a.S;
     ListEntry* list = reinterpret_cast<ListEntry*>(dyn);
@@ -273,7 +280,8 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
         }
         const int nlist = (int)s_nlist;  // the table is dead from here on: its space holds the row batches
 
-        // 3. B operands: group g of this wave = queries 16g .. 16g+15 of the wave
+        // 3. B operands: group g of this wave = query slots 16g .. 16g+15 of the
+        //    wave; lane l works on slot 16g + l%16 of every group
         uint4 bq[G][KS];
         bool qok[G];
         uint32_t myq[G];
@@ -288,27 +296,78 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
                                                                      8 * (l / 16))
                                    : make_uint4(0, 0, 0, 0);
         }
-        float ld[G][R];
-        uint32_t lr[G][R];
-#pragma unroll
-        for (int g = 0; g < G; ++g)
+        // The split's top-R list of every query of the wave lives in LDS
+        // (wlist[slot][k], ascending (d~, padded position)); lane l owns slot l
+        // when lists are updated.  Candidates that pass the bound go to a hit
+        // buffer first and are merged in bulk, which keeps the tile loop free
+        // of list code.
+        uint2* wl = s_list[w];
+        for (int k = l; k < QW * R; k += 64) wl[k] = make_uint2(0x7F800000u, 0xFFFFFFFFu);
+        uint32_t nhit = 0;
+        // shared bound of slot l's query (owner view) and of slot 16g + l%16
+        const uint32_t own_q = l < QW && wslot0 + l < a.Q ? a.qorder[wslot0 + l] : 0u;
+        const bool own_ok = l < QW && wslot0 + l < a.Q;
+        auto class_bound = [&](uint32_t q) {
+            uint32_t c = 0;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                ld[g][k] = __builtin_huge_valf();
-                lr[g][k] = 0xFFFFFFFFu;
+                const uint32_t v =
+                    __hip_atomic_load(a.cmin + (int64_t)q * R + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                c = v > c ? v : c;
             }
-        // the query operands have landed before the batch loop starts, so no
-        // wait inside the loop has to drain the batch prefetch for them
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+            return c;
+        };
+        // thr[g]: no candidate of slot 16g + l%16 above it can enter the final
+        // top R: the minimum of the slot's list R-th entry and the shared bound
+        float thr[G];
+        uint32_t ownb = own_ok ? class_bound(own_q) : 0xFFFFFFFFu;
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): operands and bounds landed
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        auto refresh_thr = [&]() {
+            // owner lane l: bound of slot l; everyone: bound of its 4 slots
+            const float ob = fminf(ord_float(ownb), __uint_as_float(wl[l % QW * R + R - 1].x));
+#pragma unroll
+            for (int g = 0; g < G; ++g) thr[g] = __shfl(ob, 16 * g + (l % 16), 64);
+        };
+        refresh_thr();
+        // merge the hit buffer into the lists: lane l takes the hits of slot l
+        auto flush = [&]() {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            float ld[R];
+            uint32_t lr[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const uint2 e = wl[(l % QW) * R + k];
+                ld[k] = __uint_as_float(e.x);
+                lr[k] = e.y;
+            }
+            bool changed = false;
+            for (uint32_t h = 0; h < nhit; ++h) {
+                const uint4 e = s_hit[w][h];
+                const float d = __uint_as_float(e.x);
+                if (e.z == (uint32_t)l && pair_less(d, e.y, ld[R - 1], lr[R - 1])) {
+                    list_insert<R>(ld, lr, d, e.y);
+                    changed = true;
+                    __hip_atomic_fetch_min(a.cmin + (int64_t)own_q * R + (e.y & (R - 1)), ord_bits(d),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            if (changed && l < QW)
+#pragma unroll
+                for (int k = 0; k < R; ++k) wl[l * R + k] = make_uint2(__float_as_uint(ld[k]), lr[k]);
+            nhit = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            refresh_thr();
+        };
 
         // 4. batches of up to 128 rows staged in LDS; the next batch is loaded
         //    into registers while the current one is on the matrix cores.
-        //    qthr[g]: the smallest R-th value among the four lanes of the
-        //    lane's query (a bound on the query's R-th best, refreshed every
-        //    batch); a candidate above it can never reach the final top R.
-        float qthr[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) qthr[g] = __builtin_huge_valf();
         uint4 stage[KU];
         float nst = 0.0f;
         auto issue = [&](uint32_t p, uint32_t n) {
@@ -317,7 +376,7 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
             for (int k = 0; k < KU; ++k)
                 stage[k] = (uint32_t)grow[k] < n ? *reinterpret_cast<const uint4*>(src + goff[k])
                                                  : make_uint4(0, 0, 0, 0);
-            nst = threadIdx.x < n ? a.nrm[(int64_t)p + threadIdx.x] : __builtin_huge_valf();
+            nst = a.nrm[(int64_t)p + (threadIdx.x < n ? threadIdx.x : n - 1)];
         };
         auto park = [&](int buf) {
             uint4* dst = rows + buf * kBatchRows * CPR;
@@ -351,28 +410,27 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
                 nn = end - np < kBatchRows ? end - np : kBatchRows;
                 issue(np, nn);
             }
-            // this lane's share (R/4 classes) of its queries' shared class minima
-            uint32_t cm[G];
+            // the shared class minima of slot l's query, read now and folded
+            // into the bound after the batch.  Plain loads: a cached copy may
+            // be stale, but every value ever stored there is a valid bound
+            // (the words only decrease), and cached reads keep the batch
+            // pipeline short.
+            uint32_t cmv[R];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const uint32_t* cp = a.cmin + (int64_t)myq[g] * R + (l / 16) * (R / 4);
-                cm[g] = 0;
-#pragma unroll
-                for (int k = 0; k < R / 4; ++k) {
-                    const uint32_t v = __hip_atomic_load(cp + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    cm[g] = v > cm[g] ? v : cm[g];
-                }
-            }
+            for (int k = 0; k < R; ++k) cmv[k] = a.cmin[(int64_t)own_q * R + k];
             // screen the staged batch
             if (mk != 0) {
                 const uint4* rb = rows + buf * kBatchRows * CPR;
                 const float* nb = nrmb + buf * kBatchRows + 4 * (l / 16);
-                float thr[G];
+                float pthr[G];  // thr, or -inf for slots that do not probe this cone
+                auto set_pthr = [&]() {
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const bool probed = (mk >> (16 * g + (l % 16))) & 1ull;
-                    thr[g] = probed ? fminf(qthr[g], ld[g][R - 1]) : -__builtin_huge_valf();
-                }
+                    for (int g = 0; g < G; ++g) {
+                        const bool probed = (mk >> (16 * g + (l % 16))) & 1ull;
+                        pthr[g] = probed ? thr[g] : -__builtin_huge_valf();
+                    }
+                };
+                set_pthr();
                 for (uint32_t r0 = 0; r0 < bn; r0 += 16) {
                     uint4 av[KS];
 #pragma unroll
@@ -386,43 +444,45 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
                         for (int ks = 1; ks < KS; ++ks) acc[g] = mfma16<F16IN>(av[ks], bq[g][ks], acc[g]);
                     }
                     const float nv[4] = {nv4.x, nv4.y, nv4.z, nv4.w};
+                    // d~ of the lane's 4 rows for each group; a NaN norm marks
+                    // a padding row and never passes
+                    float d[G][4];
+                    bool hit = false;
 #pragma unroll
-                    for (int g = 0; g < G; ++g) {
-                        float d[4];
+                    for (int g = 0; g < G; ++g)
 #pragma unroll
-                        for (int ii = 0; ii < 4; ++ii) d[ii] = nv[ii] - 2.0f * acc[g][ii];
-                        if (fminf(fminf(d[0], d[1]), fminf(d[2], d[3])) <= thr[g]) {
+                        for (int ii = 0; ii < 4; ++ii) {
+                            d[g][ii] = nv[ii] - 2.0f * acc[g][ii];
+                            hit = hit || d[g][ii] <= pthr[g];
+                        }
+                    if (__ballot(hit) != 0) {  // rare once the bounds have settled
+#pragma unroll
+                        for (int g = 0; g < G; ++g)
 #pragma unroll
                             for (int ii = 0; ii < 4; ++ii) {
-                                // key (d~, padded position): a total order, no memory access
-                                const uint32_t pp = bp + r0 + 4 * (l / 16) + ii;
-                                if (d[ii] <= thr[g] && pair_less(d[ii], pp, ld[g][R - 1], lr[g][R - 1]) &&
-                                    nv[ii] < __builtin_huge_valf()) {
-                                    list_insert<R>(ld[g], lr[g], d[ii], pp);
-                                    __hip_atomic_fetch_min(a.cmin + (int64_t)myq[g] * R + (pp & (R - 1)),
-                                                           ord_bits(d[ii]), __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
+                                const bool pass = d[g][ii] <= pthr[g];
+                                const uint64_t m = __ballot(pass);
+                                if (m == 0) continue;
+                                if (nhit + (uint32_t)__popcll(m) > (uint32_t)kHitCap) flush();
+                                if (pass) {
+                                    const uint32_t at = nhit + (uint32_t)__popcll(m & lanemask_lt());
+                                    s_hit[w][at] = make_uint4(__float_as_uint(d[g][ii]), bp + r0 + 4 * (l / 16) + ii,
+                                                              16 * g + (l % 16), 0u);
                                 }
+                                nhit += (uint32_t)__popcll(m);
                             }
-                            thr[g] = fminf(thr[g], ld[g][R - 1]);
-                        }
+                        set_pthr();
                     }
                 }
             }
-            // refresh the per-query bound: the four lanes' R-th entries and the
-            // largest shared class minimum (read at the start of the batch)
+            if (nhit > 0) flush();
+            if (own_ok) {
+                uint32_t c = 0;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                float k = fminf(qthr[g], ld[g][R - 1]);
-                k = fminf(k, __shfl_xor(k, 16, 64));
-                k = fminf(k, __shfl_xor(k, 32, 64));
-                uint32_t c = cm[g];
-                const uint32_t c16 = (uint32_t)__shfl_xor((int)c, 16, 64);
-                c = c16 > c ? c16 : c;
-                const uint32_t c32 = (uint32_t)__shfl_xor((int)c, 32, 64);
-                c = c32 > c ? c32 : c;
-                qthr[g] = fminf(k, ord_float(c));
+                for (int k = 0; k < R; ++k) c = cmv[k] > c ? cmv[k] : c;
+                ownb = c;
             }
+            refresh_thr();
             if (nli < nlist) park(buf ^ 1);
             __syncthreads();
             buf ^= 1;
@@ -431,19 +491,81 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
             bn = nn;
         }
 
-        // 5. merge the four lanes of each query, store the split's lists
+        // 5. store the split's lists
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (own_ok) {
+            uint2* dst = a.part + ((int64_t)own_q * a.S + s) * R;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            merge_with<R>(ld[g], lr[g], 16);
-            merge_with<R>(ld[g], lr[g], 32);
-            if (l < 16 && qok[g]) {
-                uint2* dst = a.part + ((int64_t)myq[g] * a.S + s) * R;
-#pragma unroll
-                for (int k = 0; k < R; ++k) dst[k] = make_uint2(__float_as_uint(ld[g][k]), lr[g][k]);
-            }
+            for (int k = 0; k < R; ++k) dst[k] = wl[l * R + k];
         }
         __syncthreads();
     }
+}
+
+// Seeds the shared class minima before the screen, so that no split starts
+// without a bound.  One wave per query; each lane takes one row of the
+// query's own cone (the first kSeedRows rows at most), computes d~ on the
+// vector units and raises it by a bound on the difference to any FP32
+// accumulation of the same products (the matrix cores add them in another
+// order): each of the two sums is off by at most dk*u*S with S the sum of
+// |products|, and the final subtraction by u*(|n| + 2|q.x|), so
+// (4dk + 8)*u*(n + 2S) covers both (u = 2^-24), with a margin.  The raised
+// value is at least the screen's d~ of a real candidate of its class, so the
+// largest-class-minimum rule stays a valid bound.
+constexpr int kSeedRows = 256;
+
+template <bool F16IN, int R>
+__global__ __launch_bounds__(256) void tiled_seed_kernel(SeedArgs a) {
+#pragma clang fp contract(off)
+    const int64_t q = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const int l = lane_id();
+    if (q >= a.Q) return;
+    const uint32_t c = a.q_cone[q];
+    const uint32_t p0 = a.poff[c], p1 = a.poff[c + 1];
+    const uint32_t pend = p1 - p0 > (uint32_t)kSeedRows ? p0 + kSeedRows : p1;
+    const float gamma = (float)(4 * a.dk + 8) * 5.9604645e-08f * 1.01f;
+    for (uint32_t p = p0 + l; p < pend; p += 64) {
+        const float n = a.nrm[p];
+        if (!(n < __builtin_huge_valf())) continue;  // padding row (NaN norm)
+        const uint4* xr = reinterpret_cast<const uint4*>(a.xl + (int64_t)p * a.dk);
+        const uint4* qr = reinterpret_cast<const uint4*>(a.ql + q * a.dk);
+        float dot = 0.0f, sabs = 0.0f;
+        for (int k = 0; k < a.dk / 8; ++k) {
+            const uint4 xv = xr[k], qv = qr[k];
+            const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w}, qw[4] = {qv.x, qv.y, qv.z, qv.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const uint16_t xb = (uint16_t)(xw[h] >> (16 * e)), qb = (uint16_t)(qw[h] >> (16 * e));
+                    const float xf = F16IN ? F16::val(xb) : __uint_as_float((uint32_t)xb << 16);
+                    const float qf = F16IN ? F16::val(qb) : __uint_as_float((uint32_t)qb << 16);
+                    const float pr = xf * qf;
+                    dot = dot + pr;
+                    sabs = sabs + fabsf(pr);
+                }
+        }
+        const float d = n - 2.0f * dot;
+        const float tol = gamma * (n + 2.0f * sabs);
+        __hip_atomic_fetch_min(a.cmin + q * R + (p & (R - 1)), ord_bits(d + tol), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+hipError_t launch_tiled_seed(const SeedArgs& a, int R, int f16in, hipStream_t s) {
+    if (a.Q <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.Q + 3) / 4));
+#define OSANN_SEED(F, RR)                                                                     \
+    if ((f16in != 0) == F && R == RR) {                                                       \
+        hipLaunchKernelGGL((tiled_seed_kernel<F, RR>), grid, dim3(256), 0, s, a);             \
+        return hipGetLastError();                                                             \
+    }
+    OSANN_SEED(true, 4) OSANN_SEED(true, 8) OSANN_SEED(true, 16)
+    OSANN_SEED(false, 4) OSANN_SEED(false, 8) OSANN_SEED(false, 16)
+#undef OSANN_SEED
+    return hipErrorInvalidValue;
 }
 
 // One group of G lanes per query: merge the S split lists (ordered by
@@ -477,8 +599,10 @@ __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
     uint32_t cr = 0xFFFFFFFFu;
     if (qv && cp != 0xFFFFFFFFu) {
         const uint32_t pos = f.ppos[cp];
-        cr = f.perm[pos];
-        cd = row_dist_fp32<E>(static_cast<const uint4*>(f.planes), f.N, f.nch, pos, f.yf + q * f.dpad);
+        if (pos != 0xFFFFFFFFu) {  // a padding row never enters a list; checked anyway
+            cr = f.perm[pos];
+            cd = row_dist_fp32<E>(static_cast<const uint4*>(f.planes), f.N, f.nch, pos, f.yf + q * f.dpad);
+        }
     }
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) {
@@ -572,12 +696,23 @@ hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s) {
     X(false, 1, 8, 4) X(false, 2, 8, 4) X(false, 4, 8, 4) X(false, 8, 8, 4) X(false, 1, 16, 2)              \
     X(false, 2, 16, 2) X(false, 4, 16, 2) X(false, 8, 16, 2)
 
-hipError_t tiled_screen_max_lds(size_t bytes) {
+size_t tiled_screen_static_lds(int R) {
+    const size_t qw = 16 * (size_t)tile_groups(R);
+    return 4 * qw * R * 8 + 4 * (size_t)kHitCap * 16 + 2 * 4 * kMaxD + 512;
+}
+
+// Lets every screen kernel take all the LDS its static arrays leave free.
+hipError_t tiled_screen_max_lds() {
     hipError_t e = hipSuccess;
 #define OSANN_SET_LDS(F16IN, KS, R, G)                                                                     \
-    if (e == hipSuccess)                                                                                   \
-        e = hipFuncSetAttribute((const void*)tiled_screen_kernel<F16IN, KS, R, G>,                         \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) {                                                                                 \
+        hipFuncAttributes fa{};                                                                            \
+        e = hipFuncGetAttributes(&fa, (const void*)tiled_screen_kernel<F16IN, KS, R, G>);                  \
+        if (e == hipSuccess)                                                                               \
+            e = hipFuncSetAttribute((const void*)tiled_screen_kernel<F16IN, KS, R, G>,                     \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,                            \
+                                    (int)(kLdsPerBlock - fa.sharedSizeBytes));                             \
+    }
     OSANN_EACH_SCREEN(OSANN_SET_LDS)
 #undef OSANN_SET_LDS
     return e;
