@@ -73,6 +73,11 @@ def lib():
             L.orc_pair_dtilde.argtypes = [p, i32, i32, p, i32, p, i64, i32, p]
             L.orc_round_short.restype = i32
             L.orc_round_short.argtypes = [p, i64, i32, p]
+            L.orc_rotate.restype = i32
+            L.orc_rotate.argtypes = [p, i32, i64, i32, p, p]
+            L.orc_search_rot.restype = i32
+            L.orc_search_rot.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, p, i32, i64, i64,
+                                         p, p, p, p, i32]
             _lib = L
     return _lib
 
@@ -270,3 +275,46 @@ def round_short(x, use_f16: bool = False) -> np.ndarray:
     out = np.empty(x.shape[0], dtype=np.float64)
     lib().orc_round_short(px, x.shape[0], int(use_f16), out.ctypes.data_as(C.c_void_p))
     return out
+
+
+def rotate(X, M):
+    """Coordinates of the rows of ``X`` in the basis ``M`` (K x K), FP32 (reading R9)."""
+    X, px, dt = _rows(X)
+    N, K = X.shape
+    M, pm = _arr(M, np.float32)
+    out = np.empty((N, K), dtype=np.float32)
+    rc = lib().orc_rotate(px, dt, N, K, pm, out.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise ValueError(f"orc_rotate failed ({rc})")
+    return out
+
+
+def build_index_rot(X, G: int, rots):
+    """One table per basis (Section 3.A): the rows' coordinates in basis r
+    are hashed and bucketed; every table refers to the original rows."""
+    rots = np.ascontiguousarray(rots, dtype=np.float32)
+    tabs = [build_index(rotate(X, rots[r]), G) for r in range(rots.shape[0])]
+    return {"tables": tabs, "rots": rots, "G": G, "K": X.shape[1], "n_cones": tabs[0]["n_cones"]}
+
+
+def search_rot(X, index, Y, B: int, nthreads: int = 0):
+    """Algorithm 1 with several bases: ``(idx, d32, d64, ncand)`` per query."""
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    N, K = X.shape
+    Q = Y.shape[0]
+    R = len(index["tables"])
+    off, po = _arr(np.concatenate([t["offsets"] for t in index["tables"]]), np.int64)
+    perm, pp = _arr(np.concatenate([t["perm"] for t in index["tables"]]), np.int64)
+    rots, pr = _arr(index["rots"], np.float32)
+    idx = np.empty(Q, dtype=np.int64)
+    d32 = np.empty(Q, dtype=np.float32)
+    d64 = np.empty(Q, dtype=np.float64)
+    nca = np.empty(Q, dtype=np.int64)
+    rc = lib().orc_search_rot(px, xdt, N, K, index["G"], R, pr, po, pp, py, ydt, Q, int(B),
+                              idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
+                              d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
+                              int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_search_rot failed ({rc})")
+    return idx, d32, d64, nca

@@ -29,6 +29,12 @@
  *   R5  the search budget B is met with whole cones: probing stops after the
  *       first cone at which the running candidate count reaches B.
  *   R6  arg-min over (FP32 distance, original row) in lexicographic order.
+ *   R9  several bases: coordinates in basis r are M_r times the vector, in
+ *       FP32 term by term (ascending j); distances stay on the original
+ *       vectors (a rotation preserves them).
+ *   R10 several bases: the l-th cone of every basis (empty cones included)
+ *       forms level l; the budget counts the rows of visited cones, rows seen
+ *       again in another basis included; ncand counts distinct rows.
  *
  * Precision: distances are produced both in double (the definition, eq. (1))
  * and in FP32 evaluated term by term in ascending component order with each
@@ -651,4 +657,109 @@ int orc_round_short(const float *x, int64_t n, int use_f16, double *out)
     for (int64_t i = 0; i < n; i++)
         out[i] = use_f16 ? to_f16(x[i]) : to_bf16(x[i]);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Several bases (Section 3.A, Algorithm 1)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Coordinates of rows in another basis (reading R9): out[n][i] =
+ * sum_j M[i][j] x[n][j] with M a K x K row-major matrix, evaluated in FP32
+ * in ascending j with each product and sum rounded separately. */
+int orc_rotate(const void *X, int dtype, int64_t N, int K, const float *M, float *out)
+{
+    if (K < 1 || K > 256)
+        return -1;
+    for (int64_t n = 0; n < N; n++) {
+        float x[256];
+        load_row(X, dtype, n, K, x);
+        for (int i = 0; i < K; i++) {
+            float acc = 0.0f;
+            for (int j = 0; j < K; j++) {
+                float pr = M[(int64_t)i * K + j] * x[j];
+                acc = acc + pr;
+            }
+            out[n * K + i] = acc;
+        }
+    }
+    return 0;
+}
+
+/* Algorithm 1 with R bases.  Basis r has its own table (offsets_r, perm_r
+ * built from the rows' coordinates in that basis by orc_hash/orc_bucket);
+ * rot holds the R matrices.  For each query: its coordinates in every basis
+ * and each basis's full probe order (Section 3.B); then, for l = 0, 1, ...
+ * (the l-th cone of every basis's order, empty cones included) and for
+ * r = 0..R-1, every row of cone l of basis r that is not yet marked analyzed
+ * gets its distance computed (on the original vectors), updates the arg-min
+ * and is marked.  Reading R10: the budget counts the rows of the visited
+ * cones, a row met again in another basis counting again, and the search
+ * stops after the cone at which that count reaches B.  ncand is the number
+ * of distinct rows whose distance was computed. */
+int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, const float *rot,
+                   const int64_t *offsets, const int64_t *perms,
+                   const void *Y, int ydtype, int64_t Q, int64_t B,
+                   int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
+                   int nthreads)
+{
+    if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || R < 1)
+        return -1;
+    int64_t NC = orc_num_cones(K, G);
+    set_threads(nthreads);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 2)
+    for (int64_t q = 0; q < Q; q++) {
+        float y[256], yr[256], x[256];
+        load_row(Y, ydtype, q, K, y);
+        int64_t *walks = (int64_t *)malloc(sizeof(int64_t) * (size_t)(NC * R));
+        unsigned char *analyzed = (unsigned char *)calloc((size_t)N, 1);
+        if (!walks || !analyzed) {
+            free(walks);
+            free(analyzed);
+#pragma omp atomic write
+            bad = 1;
+            continue;
+        }
+        for (int r = 0; r < R; r++) {
+            orc_rotate(y, ORC_F32, 1, K, rot + (int64_t)r * K * K, yr);
+            orc_walk(yr, K, G, walks + (int64_t)r * NC, NC);
+        }
+        float best_d = INFINITY;
+        int64_t best_row = INT64_MAX;
+        double best_d64 = INFINITY;
+        int64_t visited = 0, ncand = 0;
+        int done = 0;
+        for (int64_t l = 0; l < NC && !done; l++) {
+            for (int r = 0; r < R && !done; r++) {
+                const int64_t *off = offsets + (int64_t)r * (NC + 1);
+                const int64_t *perm = perms + (int64_t)r * N;
+                int64_t c = walks[(int64_t)r * NC + l];
+                for (int64_t pos = off[c]; pos < off[c + 1]; pos++) {
+                    int64_t row = perm[pos];
+                    if (analyzed[row])
+                        continue;
+                    float d32;
+                    double d64;
+                    load_row(X, xdtype, row, K, x);
+                    dist2(x, y, K, &d32, &d64);
+                    int64_t before = best_row;
+                    argmin_update(d32, row, &best_d, &best_row);
+                    if (best_row != before)
+                        best_d64 = d64;
+                    analyzed[row] = 1;
+                    ncand++;
+                }
+                visited += off[c + 1] - off[c];
+                if (visited >= B)
+                    done = 1;
+            }
+        }
+        out_idx[q] = best_row;
+        out_d32[q] = best_d;
+        out_d64[q] = best_d64;
+        out_ncand[q] = ncand;
+        free(walks);
+        free(analyzed);
+    }
+    return bad ? -2 : 0;
 }

@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "gaussian_db", "gaussian_queries", "descriptor_db", "descriptor_queries",
     "patch_field", "patch_rows", "patch_pair", "serving_requests",
-    "tie_heavy", "SEEDS",
+    "tie_heavy", "random_bases", "SEEDS",
 ]
 
 # One seed per array, 1000*workload + k.
@@ -38,6 +38,7 @@ SEEDS = {
     "desc_db": 3001, "desc_pick": 3002, "desc_noise": 3003,
     "patch_field": 4001, "patch_noise": 4002, "patch_sample": 4003,
     "serve_arrivals": 5001,
+    "bases": 6001,
 }
 
 
@@ -145,3 +146,21 @@ def serving_requests(n_req: int, rate: float, n_indexes: int, max_q: int = 4096,
     sizes = r.integers(1, int(max_q) + 1, size=int(n_req))
     qseeds = r.integers(1 << 20, 1 << 30, size=int(n_req))
     return [(float(a), int(b), int(c), int(s)) for a, b, c, s in zip(t, which, sizes, qseeds)]
+
+
+def random_bases(n: int, d: int, seed: int = SEEDS["bases"], identity_first: bool = True) -> np.ndarray:
+    """``n`` orthonormal ``d x d`` FP32 matrices, row-major, for the
+    several-bases search: the Q factor of a Gaussian matrix with the signs of
+    R's diagonal folded in (Haar-distributed), in float64 then rounded.  The
+    first one is the identity when ``identity_first`` (the original basis)."""
+    r = _rng(seed)
+    out = np.empty((int(n), int(d), int(d)), dtype=np.float32)
+    for k in range(int(n)):
+        if k == 0 and identity_first:
+            out[k] = np.eye(d, dtype=np.float32)
+            continue
+        a = r.standard_normal((d, d))
+        q, rr = np.linalg.qr(a)
+        q = q * np.sign(np.diag(rr))[None, :]
+        out[k] = q.astype(np.float32)
+    return out
