@@ -129,6 +129,23 @@ os_ann_index *os_ann_build_ex(const void *db, int64_t N, int32_t D, int32_t L,
                               const os_ann_build_opts *opts);
 
 /*
+ * Build an index with several bases (Section 3.A; Algorithm 1 with R
+ * rotations).  rot holds n_rot (1..16) D x D FP32 matrices, row-major, device
+ * memory: the coordinates of a vector y in basis r are rot[r] y, evaluated in
+ * FP32 term by term (ascending j, each product and sum rounded).  Every basis
+ * gets its own table (hashing and bucketing of the rows' coordinates in that
+ * basis) holding the original rows; distances are always taken on the
+ * original rows.  Passing the identity as rot[0] keeps the original basis.
+ * The matrices need not be orthonormal (the result is then still the arg-min
+ * over the visited rows, but the cones no longer describe rotated space).
+ * Searches on such an index run in OS_ANN_MODE_FP32 only (tiled: ENOTSUP);
+ * opts->want_lowp must be 0.  Synchronous; the library copies db and rot.
+ * Errors: EINVAL, ENOMEM, EDEVICE, ENOTSUP, ENONFINITE (returns NULL).
+ */
+os_ann_index *os_ann_build_rot(const void *db, int64_t N, int32_t D, int32_t L, const float *rot,
+                               int32_t n_rot, const os_ann_build_opts *opts);
+
+/*
  * Approximate NN of Q FP32 queries (row-major queries[Q][D]), Algorithm 1
  * with one basis: each query's cones are visited in the Section 3.B order
  * (own cone first; then the other profiles that share the query's signs, in
@@ -189,6 +206,11 @@ int os_ann_classify(const os_ann_index *idx, const void *queries, int32_t query_
  */
 int os_ann_export(const os_ann_index *idx, uint32_t *row_cone, uint64_t *row_top,
                   int64_t *offsets, int64_t *perm, void *stream);
+
+/* As os_ann_export for basis r (0 <= r < n_rot) of an index built with
+ * os_ann_build_rot; r = 0 for any other index. */
+int os_ann_export_basis(const os_ann_index *idx, int32_t r, uint32_t *row_cone, uint64_t *row_top,
+                        int64_t *offsets, int64_t *perm, void *stream);
 
 /* Copy out the permuted rows, converted exactly to FP32: rows[N][D] with
  * rows[pos] = db[perm[pos]].  Asynchronous on `stream`. */

@@ -48,6 +48,8 @@ SIGNATURES = {
     "os_ann_build": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32]),
     "os_ann_build_ex": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
                                      C.POINTER(os_ann_build_opts)]),
+    "os_ann_build_rot": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                      C.POINTER(os_ann_build_opts)]),
     "os_ann_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
     "os_ann_search_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                    C.POINTER(os_ann_search_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -55,6 +57,8 @@ SIGNATURES = {
     "os_ann_classify": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int64,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "os_ann_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "os_ann_export_basis": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
     "os_ann_export_rows": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "os_ann_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "os_ann_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -127,6 +131,19 @@ def os_ann_build(db: torch.Tensor, L: int) -> int:
 def os_ann_build_ex(db: torch.Tensor, L: int, stream=None, want_lowp: bool = False) -> int:
     o = os_ann_build_opts(_check_rows(db, "db"), int(bool(want_lowp)), _stream_ptr(stream))
     h = lib().os_ann_build_ex(_ptr(db), db.shape[0], db.shape[1], int(L), C.byref(o))
+    if not h:
+        _raise()
+    return h
+
+
+def os_ann_build_rot(db: torch.Tensor, L: int, rot: torch.Tensor, stream=None) -> int:
+    """Index with several bases; ``rot`` is a device FP32 tensor [n_rot, D, D]."""
+    if rot.dtype != torch.float32 or rot.dim() != 3 or not rot.is_contiguous() or rot.device != db.device:
+        raise ValueError("rot must be a contiguous FP32 [n_rot, D, D] tensor on the db's device")
+    if rot.shape[1] != db.shape[1] or rot.shape[2] != db.shape[1]:
+        raise ValueError("rot must hold D x D matrices")
+    o = os_ann_build_opts(_check_rows(db, "db"), 0, _stream_ptr(stream))
+    h = lib().os_ann_build_rot(_ptr(db), db.shape[0], db.shape[1], int(L), _ptr(rot), rot.shape[0], C.byref(o))
     if not h:
         _raise()
     return h
@@ -229,6 +246,22 @@ def os_ann_export(index: int, stream=None) -> dict:
     off = torch.empty(nc + 1, dtype=torch.int64, device=dev)
     perm = torch.empty(N, dtype=torch.int64, device=dev)
     rc = lib().os_ann_export(index, _ptr(cone), _ptr(top), _ptr(off), _ptr(perm), _stream_ptr(stream))
+    if rc:
+        _raise(rc)
+    return {"cone": cone, "top": top, "offsets": off, "perm": perm}
+
+
+def os_ann_export_basis(index: int, r: int, stream=None) -> dict:
+    """As os_ann_export, for basis ``r`` of a several-bases index."""
+    info = os_ann_info(index)
+    N, nc = info["N"], info["n_cones"]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    cone = torch.empty(N, dtype=torch.int32, device=dev)
+    top = torch.empty(N, dtype=torch.int64, device=dev)
+    off = torch.empty(nc + 1, dtype=torch.int64, device=dev)
+    perm = torch.empty(N, dtype=torch.int64, device=dev)
+    rc = lib().os_ann_export_basis(index, int(r), _ptr(cone), _ptr(top), _ptr(off), _ptr(perm),
+                                   _stream_ptr(stream))
     if rc:
         _raise(rc)
     return {"cone": cone, "top": top, "offsets": off, "perm": perm}

@@ -103,6 +103,14 @@ struct os_ann_index {
     // captured search sequences
     std::mutex graph_mu;
     std::vector<GraphEntry> graphs;
+    // several bases (Section 3.A): one table per basis; this index then owns
+    // the tables, the bases and their gathered copies
+    int n_rot = 0;
+    std::vector<os_ann_index*> sub;
+    float* rot = nullptr;            // [R][D][D]
+    uint32_t* rot_offsets = nullptr;  // [R][n_cones+1]
+    uint32_t* rot_perm = nullptr;     // [R][N]
+    uint64_t* xtop = nullptr;         // [R][R][N]
 };
 
 namespace {
@@ -138,10 +146,11 @@ void release(os_ann_index* ix) {
         (void)hipEventDestroy(t.stop);
     }
     drop_graphs(ix);
+    for (auto* t : ix->sub) release(t);
     void* ptrs[] = {ix->row_cone, ix->row_top,  ix->perm,       ix->sorted_cone, ix->offsets,
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
-                    ix->lp.ppos};
+                    ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete ix;
@@ -213,6 +222,7 @@ struct SearchPlan {
     bool bitmap = false, fits = true;
     size_t off_ql = 0, off_qcone = 0, off_sort = 0, off_qorder = 0, off_qsorted = 0, off_part = 0,
            off_counter = 0, off_qbits = 0, off_cmin = 0;
+    size_t off_yr = 0;  // several bases: query coordinates [R][Q][D]
     size_t bytes = 0;
 };
 
@@ -235,6 +245,17 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         return here;
     };
     p.off_yf = take((size_t)Q * p.dpad * sizeof(float));
+    if (ix->n_rot > 0) {  // several bases: FP32 scan with per-basis walk state
+        const size_t R = (size_t)ix->n_rot;
+        p.mode = OS_ANN_MODE_FP32;
+        p.off_yr = take(R * (size_t)Q * ix->D * sizeof(float));
+        p.off_order = take(R * (size_t)Q * ix->D);
+        p.off_sbit = take(R * (size_t)Q * ix->D);
+        p.off_jstop = take((size_t)Q * sizeof(uint32_t));
+        p.off_nc = take((size_t)Q * sizeof(int64_t));
+        p.bytes = at;
+        return p;
+    }
     p.off_order = take((size_t)Q * ix->D);
     p.off_sbit = take((size_t)Q * ix->D);
     p.off_jstop = take((size_t)Q * sizeof(uint32_t));
@@ -287,6 +308,8 @@ int search_checks(const os_ann_index* ix, const void* queries, int64_t Q, int64_
             return fail(OS_ANN_EINVAL, "bad mode");
         if (o->mode == OS_ANN_MODE_TILED && !rerank_ok(o->rerank_r ? o->rerank_r : 8))
             return fail(OS_ANN_EINVAL, "rerank_r must be 4, 8 or 16");
+        if (o->mode == OS_ANN_MODE_TILED && ix->n_rot > 0)
+            return fail(OS_ANN_ENOTSUP, "several bases: FP32 mode only");
     }
     return OS_ANN_OK;
 }
@@ -607,7 +630,64 @@ int choose_splits(Call& c, bool may_time, hipError_t* err) {
     return best_s;
 }
 
+// Several bases: FP32 queries, coordinates in every basis, interleaved walk
+// length, then the scan that analyzes each row once.
+hipError_t enqueue_rot(const Call& c) {
+    os_ann_index* ix = c.ix;
+    const SearchPlan& p = c.p;
+    const int R = ix->n_rot;
+    ProbeArgs pa{};
+    pa.Y = c.queries;
+    pa.qtype = c.qtype;
+    pa.Q = c.Q;
+    pa.D = ix->D;
+    pa.L = ix->L;
+    pa.yf = reinterpret_cast<float*>(c.base + p.off_yf);
+    pa.dpad = p.dpad;
+    float* yr = reinterpret_cast<float*>(c.base + p.off_yr);
+    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] {
+        hipError_t r = launch_probe(pa, c.s);
+        for (int b = 0; b < R && r == hipSuccess; ++b)
+            r = launch_rotate(c.queries, c.qtype, c.Q, ix->D, ix->rot + (size_t)b * ix->D * ix->D,
+                              yr + (size_t)b * c.Q * ix->D, c.s);
+        return r;
+    });
+    if (e != hipSuccess) return e;
+    RotArgs ra{};
+    ra.N = ix->N;
+    ra.D = ix->D;
+    ra.L = ix->L;
+    ra.R = R;
+    ra.nch = ix->nch;
+    ra.dtype = ix->dtype;
+    ra.dpad = p.dpad;
+    ra.n_cones = ix->n_cones;
+    ra.n_sub = ix->n_sub;
+    ra.offsets = ix->rot_offsets;
+    ra.perm = ix->rot_perm;
+    ra.xtop = ix->xtop;
+    for (int b = 0; b < R; ++b) ra.planes[b] = ix->sub[b]->planes;
+    ra.lexsub = ix->sub[0]->lexsub;
+    ra.maskord = ix->sub[0]->maskord;
+    ra.binom = ix->sub[0]->binom;
+    ra.Q = c.Q;
+    ra.budget = c.budget;
+    ra.yr = yr;
+    ra.yf = pa.yf;
+    ra.order = reinterpret_cast<uint8_t*>(c.base + p.off_order);
+    ra.sbit = reinterpret_cast<uint8_t*>(c.base + p.off_sbit);
+    ra.kstop = reinterpret_cast<uint32_t*>(c.base + p.off_jstop);
+    ra.visited = reinterpret_cast<int64_t*>(c.base + p.off_nc);
+    ra.out_idx = c.out_idx;
+    ra.out_dist = c.out_dist;
+    ra.out_ncand = c.out_ncand;
+    e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] { return launch_probe_rot(ra, c.s); });
+    if (e != hipSuccess) return e;
+    return timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] { return launch_scan_rot(ra, c.s); });
+}
+
 hipError_t enqueue(const Call& c, int S) {
+    if (c.ix->n_rot > 0) return enqueue_rot(c);
     return c.p.mode == OS_ANN_MODE_TILED ? enqueue_tiled(c, S) : enqueue_fp32(c);
 }
 
@@ -671,21 +751,15 @@ int os_ann_last_error(void) { return g_err; }
 const char* os_ann_last_error_message(void) { return g_msg.c_str(); }
 const char* os_ann_version(void) { return "osann 0.2 gfx950"; }
 
-os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L,
-                              const os_ann_build_opts* opts) {
-    clear_error();
-    const int32_t dtype = opts ? opts->dtype : kF32;
-    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
-    int64_t nc = 0;
-    if (!db) {
-        fail(OS_ANN_EINVAL, "null db");
-        return nullptr;
-    }
-    if (!dtype_ok(dtype)) {
-        fail(OS_ANN_EINVAL, "bad db dtype");
-        return nullptr;
-    }
-    if (check_shape(N, D, L, &nc)) return nullptr;
+}  // extern "C"
+
+namespace {
+// One table: the rows `keys` (type key_dtype) are hashed and bucketed; the
+// table stores the rows `db` (type dtype) in that bucket order.  For one
+// basis both are the database; for basis r of several, keys holds the
+// database's coordinates in that basis.
+os_ann_index* build_table(const void* keys, int32_t key_dtype, const void* db, int32_t dtype, int64_t N, int32_t D,
+                          int32_t L, int64_t nc, hipStream_t s) {
 
     auto* ix = new os_ann_index();
     ix->N = N;
@@ -731,7 +805,7 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L,
         return true;
     };
     if (!step(hipMemsetAsync(small, 0, 16, s), "memset") ||
-        !step(launch_row_keys(db, dtype, N, D, L, ix->row_cone, ix->row_top, small, s), "key kernel") ||
+        !step(launch_row_keys(keys, key_dtype, N, D, L, ix->row_cone, ix->row_top, small, s), "key kernel") ||
         !step(launch_sort_by_cone(ix->row_cone, N, nc, tmp, ix->perm, ix->sorted_cone, s), "radix sort") ||
         !step(launch_offsets(ix->sorted_cone, N, nc, ix->offsets, s), "offsets") ||
         !step(launch_gather_planes(db, dtype, N, D, ix->perm, ix->planes, s), "gather") ||
@@ -751,9 +825,122 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L,
     (void)hipFree(tmp);
     (void)hipFree(small);
     tmp = small = nullptr;
-    if (opts && opts->want_lowp && ensure_lowp(ix, s)) return bail(0);
     return ix;
 }
+}  // namespace
+
+extern "C" {
+
+os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L, const os_ann_build_opts* opts) {
+    clear_error();
+    const int32_t dtype = opts ? opts->dtype : kF32;
+    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    int64_t nc = 0;
+    if (!db) {
+        fail(OS_ANN_EINVAL, "null db");
+        return nullptr;
+    }
+    if (!dtype_ok(dtype)) {
+        fail(OS_ANN_EINVAL, "bad db dtype");
+        return nullptr;
+    }
+    if (check_shape(N, D, L, &nc)) return nullptr;
+    os_ann_index* ix = build_table(db, dtype, db, dtype, N, D, L, nc, s);
+    if (ix && opts && opts->want_lowp && ensure_lowp(ix, s)) {
+        release(ix);
+        return nullptr;
+    }
+    return ix;
+}
+
+os_ann_index* os_ann_build_rot(const void* db, int64_t N, int32_t D, int32_t L, const float* rot, int32_t n_rot,
+                               const os_ann_build_opts* opts) {
+    clear_error();
+    const int32_t dtype = opts ? opts->dtype : kF32;
+    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    int64_t nc = 0;
+    if (!db || !rot) {
+        fail(OS_ANN_EINVAL, "null db or bases");
+        return nullptr;
+    }
+    if (!dtype_ok(dtype)) {
+        fail(OS_ANN_EINVAL, "bad db dtype");
+        return nullptr;
+    }
+    if (n_rot < 1 || n_rot > kMaxRot) {
+        fail(OS_ANN_EINVAL, "n_rot must be in [1, 16]");
+        return nullptr;
+    }
+    if (opts && opts->want_lowp) {
+        fail(OS_ANN_ENOTSUP, "several bases: FP32 mode only");
+        return nullptr;
+    }
+    if (check_shape(N, D, L, &nc)) return nullptr;
+    auto* ix = new os_ann_index();
+    ix->N = N;
+    ix->D = D;
+    ix->L = L;
+    ix->dtype = dtype;
+    ix->n_cones = nc;
+    ix->n_sub = binom_host(D, L);
+    ix->epc = chunk_elems(dtype);
+    ix->nch = (D + ix->epc - 1) / ix->epc;
+    ix->n_rot = n_rot;
+    (void)hipGetDevice(&ix->device);
+    float* coords = nullptr;
+    auto bail = [&]() -> os_ann_index* {
+        if (coords) (void)hipFree(coords);
+        release(ix);
+        return nullptr;
+    };
+    const size_t n = (size_t)N, R = (size_t)n_rot;
+    if (dev_alloc(ix, (void**)&ix->rot, R * D * D * 4, "bases") ||
+        dev_alloc(ix, (void**)&ix->rot_offsets, R * (size_t)(nc + 1) * 4, "basis offsets") ||
+        dev_alloc(ix, (void**)&ix->rot_perm, R * n * 4, "basis perms") ||
+        dev_alloc(ix, (void**)&ix->xtop, R * R * n * 8, "cross tops") ||
+        dev_alloc(nullptr, (void**)&coords, n * D * 4, "coordinates"))
+        return bail();
+    hipError_t e = hipMemcpyAsync(ix->rot, rot, R * D * D * 4, hipMemcpyDeviceToDevice, s);
+    for (int r = 0; r < n_rot && e == hipSuccess; ++r) {
+        e = launch_rotate(db, dtype, N, D, ix->rot + (size_t)r * D * D, coords, s);
+        if (e != hipSuccess) break;
+        os_ann_index* t = build_table(coords, kF32, db, dtype, N, D, L, nc, s);
+        if (!t) return bail();
+        ix->sub.push_back(t);
+        ix->device_bytes += t->device_bytes;
+        e = hipMemcpyAsync(ix->rot_offsets + (size_t)r * (nc + 1), t->offsets, (size_t)(nc + 1) * 4,
+                           hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ix->rot_perm + (size_t)r * n, t->perm, n * 4, hipMemcpyDeviceToDevice, s);
+    }
+    for (int r = 0; r < n_rot && e == hipSuccess; ++r)
+        for (int r2 = 0; r2 < n_rot && e == hipSuccess; ++r2)
+            if (r2 != r)
+                e = launch_gather_top(ix->sub[r]->perm, N, ix->sub[r2]->row_top,
+                                      ix->xtop + ((size_t)r * R + r2) * n, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hip_fail(e, "several-bases build");
+        return bail();
+    }
+    (void)hipFree(coords);
+    ix->n_nonempty = ix->sub[0]->n_nonempty;
+    return ix;
+}
+
+int os_ann_export_basis(const os_ann_index* ix, int32_t r, uint32_t* row_cone, uint64_t* row_top,
+                        int64_t* offsets, int64_t* perm, void* stream) {
+    clear_error();
+    if (!ix) return fail(OS_ANN_EINVAL, "null index");
+    if (ix->n_rot == 0) {
+        if (r != 0) return fail(OS_ANN_EINVAL, "basis out of range");
+        return os_ann_export(ix, row_cone, row_top, offsets, perm, stream);
+    }
+    if (r < 0 || r >= ix->n_rot) return fail(OS_ANN_EINVAL, "basis out of range");
+    return os_ann_export(ix->sub[r], row_cone, row_top, offsets, perm, stream);
+}
+
+
 
 os_ann_index* os_ann_build(const float* db, int64_t N, int32_t D, int32_t L) {
     return os_ann_build_ex(db, N, D, L, nullptr);
@@ -821,6 +1008,7 @@ int os_ann_classify(const os_ann_index* cidx, const void* queries, int32_t query
                     int64_t max_candidates, uint32_t* q_cone, uint64_t* q_top, int64_t* q_ncand,
                     void* stream) {
     clear_error();
+    if (cidx && cidx->n_rot > 0) return fail(OS_ANN_ENOTSUP, "classify: one basis only");
     os_ann_search_opts o{};
     o.query_dtype = query_dtype;
     int rc = search_checks(cidx, queries, Q, max_candidates, &o);
@@ -853,6 +1041,7 @@ int os_ann_export(const os_ann_index* ix, uint32_t* row_cone, uint64_t* row_top,
                   int64_t* perm, void* stream) {
     clear_error();
     if (!ix) return fail(OS_ANN_EINVAL, "null index");
+    if (ix->n_rot > 0) ix = ix->sub[0];  // basis 0
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (row_cone)
         OSANN_HIP(hipMemcpyAsync(row_cone, ix->row_cone, (size_t)ix->N * 4, hipMemcpyDeviceToDevice, s),
@@ -868,6 +1057,7 @@ int os_ann_export(const os_ann_index* ix, uint32_t* row_cone, uint64_t* row_top,
 int os_ann_export_rows(const os_ann_index* ix, float* rows, void* stream) {
     clear_error();
     if (!ix || !rows) return fail(OS_ANN_EINVAL, "null argument");
+    if (ix->n_rot > 0) ix = ix->sub[0];  // basis 0's order
     OSANN_HIP(launch_planes_to_rows(ix->planes, ix->dtype, ix->N, ix->D, rows, static_cast<hipStream_t>(stream)),
               "export rows");
     return OS_ANN_OK;

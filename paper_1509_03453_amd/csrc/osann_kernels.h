@@ -141,4 +141,33 @@ struct ScanArgs {
 };
 hipError_t launch_scan_fp32(const ScanArgs& a, hipStream_t s);
 
+// Several bases: one table per basis over the same original rows.
+constexpr int kMaxRot = 16;
+struct RotArgs {
+    int64_t N;
+    int D, L, R, nch, dtype, dpad;
+    int64_t n_cones, n_sub;
+    const uint32_t* offsets;          // [R][n_cones+1]
+    const uint32_t* perm;             // [R][N] original row at each position of basis r's table
+    const uint64_t* xtop;             // [R][R][N] packed top-L pairs, in basis r2, of basis r's rows
+    const void* planes[kMaxRot];      // basis r's table: original rows, chunk-major
+    const uint8_t* lexsub;
+    const uint8_t* maskord;
+    const uint32_t* binom;
+    int64_t Q, budget;
+    const float* yr;                  // [R][Q][D] query coordinates in each basis
+    const float* yf;                  // [Q][dpad] FP32 queries
+    uint8_t* order;                   // [Q][R][D] walk state per basis
+    uint8_t* sbit;                    // [Q][R][D]
+    uint32_t* kstop;                  // [Q] schedule slots visited
+    int64_t* visited;                 // [Q] rows of the visited cones (repeats counted), may be null
+    int64_t* out_idx;
+    float* out_dist;
+    int64_t* out_ncand;               // distinct rows analyzed, may be null
+};
+hipError_t launch_rotate(const void* X, int dtype, int64_t N, int D, const float* M, float* out, hipStream_t s);
+hipError_t launch_probe_rot(const RotArgs& a, hipStream_t s);
+hipError_t launch_scan_rot(const RotArgs& a, hipStream_t s);
+hipError_t launch_gather_top(const uint32_t* perm, int64_t N, const uint64_t* top2, uint64_t* xt, hipStream_t s);
+
 }  // namespace osann

@@ -1,0 +1,303 @@
+// Several bases (Section 3.A; Algorithm 1 with R rotations).
+//
+// Every basis r has its own table, built from the rows' coordinates in that
+// basis (row_keys + radix sort + offsets), holding the original rows in its
+// bucket order.  A search visits, for l = 0, 1, ... and r = 0..R-1, the l-th
+// cone of basis r in the query's Section 3.B order (empty cones included),
+// and stops after the cone at which the rows of the visited cones, a row met
+// again counting again, reach the budget.  A row is analyzed once: at the
+// first (l, r) of that schedule whose cone holds it.  Instead of a per-query
+// mark per row, the scan tells that first visit from the row's cones in the
+// other bases: the position of a cone in the query's probe order of basis r'
+// has a closed form (the inverse of the walk), so the row is skipped when
+// some basis r' reaches it at an earlier level, or at the same level with
+// r' < r.  Skipping duplicates never changes the arg-min; it saves their
+// distances.
+#include "osann_device.h"
+#include "osann_kernels.h"
+
+namespace osann {
+
+// out[n][i] = sum_j M[i][j] x[n][j] in FP32, ascending j, each product and
+// sum rounded separately; one thread per (row, output component).
+template <typename E>
+__global__ void rotate_kernel(const void* __restrict__ X, int64_t N, int D, const float* __restrict__ M,
+                              float* __restrict__ out) {
+#pragma clang fp contract(off)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * D) return;
+    const int64_t n = t / D;
+    const int i = (int)(t % D);
+    auto x = static_cast<const typename E::raw*>(X) + n * D;
+    const float* m = M + (int64_t)i * D;
+    float acc = 0.0f;
+    for (int j = 0; j < D; ++j) {
+        const float pr = m[j] * E::val(x[j]);
+        acc = acc + pr;
+    }
+    out[t] = acc;
+}
+
+hipError_t launch_rotate(const void* X, int dtype, int64_t N, int D, const float* M, float* out, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    const int64_t n = N * D;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    switch (dtype) {
+        case kF32: hipLaunchKernelGGL(rotate_kernel<F32>, grid, dim3(256), 0, s, X, N, D, M, out); break;
+        case kF16: hipLaunchKernelGGL(rotate_kernel<F16>, grid, dim3(256), 0, s, X, N, D, M, out); break;
+        case kU8: hipLaunchKernelGGL(rotate_kernel<U8>, grid, dim3(256), 0, s, X, N, D, M, out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+constexpr int kRotWaves = 4;
+
+// Ranks the D components of one FP32 vector (decreasing magnitude, ties to
+// the lower index) into order[rank] = component, sbit[component] = sign bit
+// and rank_of[component] = rank.  Called by a whole wave.
+__device__ inline void rank_vector(const float* __restrict__ y, int D, uint64_t* keys, uint8_t* order,
+                                   uint8_t* sbit, uint8_t* rank_of) {
+    const int l = lane_id();
+    for (int i = l; i < D; i += 64) {
+        const uint32_t b = __float_as_uint(y[i]);
+        keys[i] = comp_key(F32::mag(b), i, F32::neg(b));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int i = l; i < D; i += 64) {
+        const uint64_t k = keys[i];
+        int rank = 0;
+        for (int j = 0; j < D; ++j) rank += keys[j] > k;
+        order[rank] = (uint8_t)i;
+        sbit[i] = (uint8_t)key_sign(k);
+        if (rank_of) rank_of[i] = (uint8_t)rank;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One wave per query: rank the query in every basis (walk state to
+// a.order/a.sbit, [Q][R][D]) and find the schedule length: the first slot
+// k = l*R + r at which the visited rows reach the budget, plus one.
+__global__ __launch_bounds__(64 * kRotWaves) void probe_rot_kernel(RotArgs a) {
+    __shared__ uint64_t keys[kRotWaves][kMaxD];
+    __shared__ uint8_t order[kRotWaves][kMaxRot][kMaxD];
+    __shared__ uint8_t sbit[kRotWaves][kMaxRot][kMaxD];
+    const int w = threadIdx.x / 64, l = lane_id();
+    const int64_t q = (int64_t)blockIdx.x * kRotWaves + w;
+    if (q >= a.Q) return;  // no block barrier in this kernel
+    const int D = a.D, R = a.R;
+    for (int r = 0; r < R; ++r) {
+        rank_vector(a.yr + ((int64_t)r * a.Q + q) * D, D, keys[w], order[w][r], sbit[w][r], nullptr);
+        for (int i = l; i < D; i += 64) {
+            a.order[(q * R + r) * D + i] = order[w][r][i];
+            a.sbit[(q * R + r) * D + i] = sbit[w][r][i];
+        }
+    }
+    const int64_t nslots = (int64_t)R * a.n_cones;
+    const uint64_t budget = (uint64_t)a.budget;
+    uint64_t carry = 0;
+    uint32_t stop_at = (uint32_t)nslots;
+    for (int64_t k0 = 0; k0 < nslots; k0 += 64) {
+        const int64_t k = k0 + l;
+        uint32_t len = 0;
+        if (k < nslots) {
+            const int r = (int)(k % R);
+            const int64_t lv = k / R;
+            const uint32_t c = probe_cone(lv, a.L, order[w][r], sbit[w][r], a.n_sub, a.lexsub, a.maskord, a.binom);
+            const uint32_t* off = a.offsets + (int64_t)r * (a.n_cones + 1);
+            len = off[c + 1] - off[c];
+        }
+        const uint32_t incl = wave_incl_scan(len);
+        const uint64_t reached = __ballot(k < nslots && carry + incl >= budget);
+        if (reached) {
+            stop_at = (uint32_t)(k0 + __ffsll((unsigned long long)reached));
+            carry += shfl_u32(incl, __ffsll((unsigned long long)reached) - 1);
+            break;
+        }
+        carry += shfl_u32(incl, 63);
+    }
+    if (l == 0) {
+        a.kstop[q] = stop_at;
+        if (a.visited) a.visited[q] = (int64_t)carry;
+    }
+}
+
+// Position of a row's cone in the query's probe order of one basis (the
+// inverse of probe_cone): top = the row's L largest components in that basis
+// (packed 9-bit (index, sign bit) pairs), rank_of/sbit = the query's ranks
+// and sign bits by component in that basis.  With T = the row's components'
+// query ranks in ascending order and the mask of signs that differ from the
+// query's (bit L-1-b for T_b): block h = popcount(mask) starts at
+// C(D,L) * (C(L,0) + .. + C(L,h-1)); inside it, T's lexicographic rank times
+// C(L,h) plus the mask's rank among the masks of popcount h.
+__device__ inline int64_t walk_position(uint64_t top, int L, int D, const uint8_t* rank_of, const uint8_t* sbit,
+                                        int64_t n_sub, const uint32_t* __restrict__ binom, const uint8_t* mrank,
+                                        const uint32_t* hstart) {
+    int t[7], f[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        t[j] = 0x7FFF;
+        f[j] = 0;
+        if (j < L) {
+            const uint32_t pr = (uint32_t)(top >> (9 * j)) & 0x1FFu;
+            const int idx = (int)(pr & 0xFFu);
+            t[j] = rank_of[idx];
+            f[j] = (int)(pr >> 8) ^ (int)sbit[idx];
+        }
+    }
+#pragma unroll
+    for (int x = 1; x < 7; ++x)
+#pragma unroll
+        for (int y = 6; y >= x; --y)
+            if (t[y - 1] > t[y]) {
+                int u = t[y]; t[y] = t[y - 1]; t[y - 1] = u;
+                u = f[y]; f[y] = f[y - 1]; f[y - 1] = u;
+            }
+    int mask = 0;
+    int64_t colex = 0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+        if (j < L) {
+            mask |= f[j] << (L - 1 - j);
+            // lexicographic rank of T = C(D,L) - 1 - colex rank of {D-1-T}
+            colex += binom[(D - 1 - t[L - 1 - j]) * 8 + j + 1];
+        }
+    const int h = __popc(mask);
+    const int64_t lex = n_sub - 1 - colex;
+    return n_sub * (int64_t)hstart[h] + lex * (int64_t)binom[L * 8 + h] + mrank[mask];
+}
+
+// One wave per query: the schedule's slots 64 at a time (cones and their
+// sizes in LDS), then each cone's rows, a row per lane: skip it if another
+// basis reaches it first, else its FP32 distance (term by term, ascending
+// components) and the arg-min on (distance, original row).
+template <typename E>
+__global__ __launch_bounds__(64 * kRotWaves) void scan_rot_kernel(RotArgs a) {
+    __shared__ uint8_t order[kRotWaves][kMaxRot][kMaxD];
+    __shared__ uint8_t sbit[kRotWaves][kMaxRot][kMaxD];
+    __shared__ uint8_t rank_of[kRotWaves][kMaxRot][kMaxD];
+    __shared__ uint32_t slot_c[kRotWaves][64];
+    __shared__ uint8_t mrank[128];
+    __shared__ uint32_t hstart[8];
+    const int w = threadIdx.x / 64, l = lane_id();
+    if (threadIdx.x < 128) {  // rank of each mask among the masks of its popcount
+        const int m = threadIdx.x;
+        int c = 0;
+        for (int v = 0; v < m; ++v) c += __popc(v) == __popc(m);
+        mrank[m] = (uint8_t)c;
+    }
+    if (threadIdx.x < 8) {
+        uint32_t s = 0;
+        for (int h = 0; h < (int)threadIdx.x; ++h) s += a.binom[a.L * 8 + h];
+        hstart[threadIdx.x] = s;
+    }
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * kRotWaves + w;
+    if (q >= a.Q) return;  // no block barrier below
+    const int D = a.D, R = a.R, L = a.L;
+    for (int r = 0; r < R; ++r)
+        for (int i = l; i < D; i += 64) {
+            const uint8_t o = a.order[(q * R + r) * D + i];
+            order[w][r][i] = o;
+            rank_of[w][r][o] = (uint8_t)i;
+            sbit[w][r][i] = a.sbit[(q * R + r) * D + i];
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const float* y = a.yf + q * a.dpad;
+    const int64_t kstop = a.kstop[q];
+    float best = __builtin_huge_valf();
+    uint32_t best_row = 0xFFFFFFFFu;
+    uint32_t analyzed = 0;
+    for (int64_t k0 = 0; k0 < kstop; k0 += 64) {
+        if (k0 + l < kstop) {
+            const int64_t k = k0 + l;
+            const int r = (int)(k % R);
+            slot_c[w][l] = probe_cone(k / R, L, order[w][r], sbit[w][r], a.n_sub, a.lexsub, a.maskord, a.binom);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const int nk = kstop - k0 < 64 ? (int)(kstop - k0) : 64;
+        for (int s = 0; s < nk; ++s) {
+            const int64_t k = k0 + s;
+            const int r = (int)(k % R);
+            const int64_t lv = k / R;
+            const uint32_t c = slot_c[w][s];
+            const uint32_t* off = a.offsets + (int64_t)r * (a.n_cones + 1);
+            const uint32_t p0 = off[c], p1 = off[c + 1];
+            const uint4* planes = static_cast<const uint4*>(a.planes[r]);
+            for (uint32_t p = p0 + l; p < p1; p += 64) {
+                bool first = true;
+                for (int r2 = 0; r2 < R && first; ++r2) {
+                    if (r2 == r) continue;
+                    const uint64_t top = a.xtop[((int64_t)r * R + r2) * a.N + p];
+                    const int64_t pos2 = walk_position(top, L, D, rank_of[w][r2], sbit[w][r2], a.n_sub, a.binom,
+                                                       mrank, hstart);
+                    first = !(pos2 < lv || (pos2 == lv && r2 < r));
+                }
+                if (!first) continue;
+                ++analyzed;
+                const float d = row_dist_fp32<E>(planes, a.N, a.nch, p, y);
+                if (d <= best) {
+                    const uint32_t row = a.perm[(int64_t)r * a.N + p];
+                    if (d < best || row < best_row) {
+                        best = d;
+                        best_row = row;
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    wave_argmin(best, best_row);
+    uint32_t tot = analyzed;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) tot += (uint32_t)__shfl_xor((int)tot, o, 64);
+    if (l == 0) {
+        a.out_idx[q] = best_row == 0xFFFFFFFFu ? -1 : (int64_t)best_row;
+        a.out_dist[q] = best;
+        if (a.out_ncand) a.out_ncand[q] = tot;
+    }
+}
+
+hipError_t launch_probe_rot(const RotArgs& a, hipStream_t s) {
+    if (a.Q <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.Q + kRotWaves - 1) / kRotWaves));
+    hipLaunchKernelGGL(probe_rot_kernel, grid, dim3(64 * kRotWaves), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_rot(const RotArgs& a, hipStream_t s) {
+    if (a.Q <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.Q + kRotWaves - 1) / kRotWaves));
+    switch (a.dtype) {
+        case kF32: hipLaunchKernelGGL(scan_rot_kernel<F32>, grid, dim3(64 * kRotWaves), 0, s, a); break;
+        case kF16: hipLaunchKernelGGL(scan_rot_kernel<F16>, grid, dim3(64 * kRotWaves), 0, s, a); break;
+        case kU8: hipLaunchKernelGGL(scan_rot_kernel<U8>, grid, dim3(64 * kRotWaves), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Gathers, for the rows of basis r's table in its order, their packed top-L
+// pairs in basis r2: xt[p] = top2[perm[p]].
+__global__ void gather_top_kernel(const uint32_t* __restrict__ perm, int64_t N, const uint64_t* __restrict__ top2,
+                                  uint64_t* __restrict__ xt) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) xt[p] = top2[perm[p]];
+}
+
+hipError_t launch_gather_top(const uint32_t* perm, int64_t N, const uint64_t* top2, uint64_t* xt, hipStream_t s) {
+    hipLaunchKernelGGL(gather_top_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, perm, N, top2, xt);
+    return hipGetLastError();
+}
+
+}  // namespace osann
