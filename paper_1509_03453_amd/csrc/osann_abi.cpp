@@ -111,6 +111,7 @@ struct os_ann_index {
     uint32_t* rot_offsets = nullptr;  // [R][n_cones+1]
     uint32_t* rot_perm = nullptr;     // [R][N]
     uint64_t* xtop = nullptr;         // [R][R][N]
+    void** planes_tab = nullptr;      // [R] device copies of the tables' plane pointers
 };
 
 namespace {
@@ -150,7 +151,8 @@ void release(os_ann_index* ix) {
     void* ptrs[] = {ix->row_cone, ix->row_top,  ix->perm,       ix->sorted_cone, ix->offsets,
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
-                    ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop};
+                    ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
+                    ix->planes_tab};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete ix;
@@ -666,7 +668,8 @@ hipError_t enqueue_rot(const Call& c) {
     ra.offsets = ix->rot_offsets;
     ra.perm = ix->rot_perm;
     ra.xtop = ix->xtop;
-    for (int b = 0; b < R; ++b) ra.planes[b] = ix->sub[b]->planes;
+    ra.planes_tab = reinterpret_cast<const uint4* const*>(ix->planes_tab);
+    ra.waves_per_query = std::min<int64_t>(c.budget, ix->N) <= 8192 ? 1 : 4;
     ra.lexsub = ix->sub[0]->lexsub;
     ra.maskord = ix->sub[0]->maskord;
     ra.binom = ix->sub[0]->binom;
@@ -898,6 +901,7 @@ os_ann_index* os_ann_build_rot(const void* db, int64_t N, int32_t D, int32_t L, 
         dev_alloc(ix, (void**)&ix->rot_offsets, R * (size_t)(nc + 1) * 4, "basis offsets") ||
         dev_alloc(ix, (void**)&ix->rot_perm, R * n * 4, "basis perms") ||
         dev_alloc(ix, (void**)&ix->xtop, R * R * n * 8, "cross tops") ||
+        dev_alloc(ix, (void**)&ix->planes_tab, R * sizeof(void*), "plane table") ||
         dev_alloc(nullptr, (void**)&coords, n * D * 4, "coordinates"))
         return bail();
     hipError_t e = hipMemcpyAsync(ix->rot, rot, R * D * D * 4, hipMemcpyDeviceToDevice, s);
@@ -918,6 +922,10 @@ os_ann_index* os_ann_build_rot(const void* db, int64_t N, int32_t D, int32_t L, 
             if (r2 != r)
                 e = launch_gather_top(ix->sub[r]->perm, N, ix->sub[r2]->row_top,
                                       ix->xtop + ((size_t)r * R + r2) * n, s);
+    std::vector<void*> tab_host;
+    for (auto* t : ix->sub) tab_host.push_back(t->planes);
+    if (e == hipSuccess && (int)tab_host.size() == n_rot)
+        e = hipMemcpyAsync(ix->planes_tab, tab_host.data(), R * sizeof(void*), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         hip_fail(e, "several-bases build");

@@ -150,7 +150,7 @@ struct RotArgs {
     const uint32_t* offsets;          // [R][n_cones+1]
     const uint32_t* perm;             // [R][N] original row at each position of basis r's table
     const uint64_t* xtop;             // [R][R][N] packed top-L pairs, in basis r2, of basis r's rows
-    const void* planes[kMaxRot];      // basis r's table: original rows, chunk-major
+    const uint4* const* planes_tab;   // [R] device pointers: basis r's table, original rows, chunk-major
     const uint8_t* lexsub;
     const uint8_t* maskord;
     const uint32_t* binom;
@@ -164,6 +164,7 @@ struct RotArgs {
     int64_t* out_idx;
     float* out_dist;
     int64_t* out_ncand;               // distinct rows analyzed, may be null
+    int waves_per_query;              // 1, 2 or 4
 };
 hipError_t launch_rotate(const void* X, int dtype, int64_t N, int D, const float* M, float* out, hipStream_t s);
 hipError_t launch_probe_rot(const RotArgs& a, hipStream_t s);

@@ -171,19 +171,56 @@ __device__ inline int64_t walk_position(uint64_t top, int L, int D, const uint8_
     return n_sub * (int64_t)hstart[h] + lex * (int64_t)binom[L * 8 + h] + mrank[mask];
 }
 
-// One wave per query: the schedule's slots 64 at a time (cones and their
-// sizes in LDS), then each cone's rows, a row per lane: skip it if another
-// basis reaches it first, else its FP32 distance (term by term, ascending
-// components) and the arg-min on (distance, original row).
-template <typename E>
-__global__ __launch_bounds__(64 * kRotWaves) void scan_rot_kernel(RotArgs a) {
-    __shared__ uint8_t order[kRotWaves][kMaxRot][kMaxD];
-    __shared__ uint8_t sbit[kRotWaves][kMaxRot][kMaxD];
-    __shared__ uint8_t rank_of[kRotWaves][kMaxRot][kMaxD];
-    __shared__ uint32_t slot_c[kRotWaves][64];
+// Squared FP32 distance of the row at position pos of a chunk-major table
+// (term by term, ascending components); NCH > 0 issues all chunk loads first.
+template <typename E, int NCH>
+__device__ inline float rot_row_dist(const uint4* __restrict__ planes, int64_t N, int nch, int64_t pos,
+                                     const float* y) {
+#pragma clang fp contract(off)
+    constexpr int EPC = Unpack<E>::n;
+    if (!NCH) return row_dist_fp32<E>(planes, N, nch, pos, y);
+    uint4 v[NCH ? NCH : 1];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) v[c] = planes[(int64_t)c * N + pos];
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        float x[EPC];
+        Unpack<E>::run(v[c], x);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+            const float d = x[e] - y[c * EPC + e];
+            const float sq = d * d;
+            acc = acc + sq;
+        }
+    }
+    return acc;
+}
+
+// One to four waves per query.  The schedule's slots are taken 64 at a time
+// (cone starts and running row counts in LDS); lane f of the query's waves
+// takes rows f, f + 64*wpq, ... of that chunk through a cursor over the
+// running counts.  A row is skipped if another basis reaches it first, else
+// its FP32 distance feeds the arg-min on (distance, original row).
+template <typename E, int NCH>
+__global__ __launch_bounds__(256) void scan_rot_kernel(RotArgs a) {
+    __shared__ uint8_t order[4][kMaxRot][kMaxD];
+    __shared__ uint8_t sbit[4][kMaxRot][kMaxD];
+    __shared__ uint8_t rank_of[4][kMaxRot][kMaxD];
+    __shared__ float ys[4][kMaxD];
+    __shared__ uint32_t s_start[4][64];
+    __shared__ uint32_t s_incl[4][64];
     __shared__ uint8_t mrank[128];
     __shared__ uint32_t hstart[8];
+    __shared__ float red_d[4];
+    __shared__ uint32_t red_r[4], red_n[4];
+    const int wpq = a.waves_per_query;
+    const int qpb = 4 / wpq;
     const int w = threadIdx.x / 64, l = lane_id();
+    const int slot = w / wpq, sub = w % wpq;
+    const int64_t q = (int64_t)blockIdx.x * qpb + slot;
+    const bool qv = q < a.Q;
+    const int D = a.D, R = a.R, L = a.L;
     if (threadIdx.x < 128) {  // rank of each mask among the masks of its popcount
         const int m = threadIdx.x;
         int c = 0;
@@ -192,64 +229,67 @@ __global__ __launch_bounds__(64 * kRotWaves) void scan_rot_kernel(RotArgs a) {
     }
     if (threadIdx.x < 8) {
         uint32_t s = 0;
-        for (int h = 0; h < (int)threadIdx.x; ++h) s += a.binom[a.L * 8 + h];
+        for (int h = 0; h < (int)threadIdx.x; ++h) s += a.binom[L * 8 + h];
         hstart[threadIdx.x] = s;
     }
-    __syncthreads();
-    const int64_t q = (int64_t)blockIdx.x * kRotWaves + w;
-    if (q >= a.Q) return;  // no block barrier below
-    const int D = a.D, R = a.R, L = a.L;
+    for (int i = sub * 64 + l; i < a.dpad; i += wpq * 64) ys[slot][i] = qv ? a.yf[q * a.dpad + i] : 0.0f;
     for (int r = 0; r < R; ++r)
-        for (int i = l; i < D; i += 64) {
-            const uint8_t o = a.order[(q * R + r) * D + i];
-            order[w][r][i] = o;
-            rank_of[w][r][o] = (uint8_t)i;
-            sbit[w][r][i] = a.sbit[(q * R + r) * D + i];
+        for (int i = sub * 64 + l; i < D; i += wpq * 64) {
+            const uint8_t o = qv ? a.order[(q * R + r) * D + i] : (uint8_t)i;
+            order[slot][r][i] = o;
+            rank_of[slot][r][o] = (uint8_t)i;
+            sbit[slot][r][i] = qv ? a.sbit[(q * R + r) * D + i] : 0;
         }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const float* y = a.yf + q * a.dpad;
-    const int64_t kstop = a.kstop[q];
+    __syncthreads();
+    const float* y = ys[slot];
+    const int64_t kstop = qv ? a.kstop[q] : 0;
     float best = __builtin_huge_valf();
-    uint32_t best_row = 0xFFFFFFFFu;
+    uint32_t brow = 0xFFFFFFFFu;
     uint32_t analyzed = 0;
+    uint32_t* st = s_start[w];
+    uint32_t* in = s_incl[w];
     for (int64_t k0 = 0; k0 < kstop; k0 += 64) {
-        if (k0 + l < kstop) {
-            const int64_t k = k0 + l;
-            const int r = (int)(k % R);
-            slot_c[w][l] = probe_cone(k / R, L, order[w][r], sbit[w][r], a.n_sub, a.lexsub, a.maskord, a.binom);
+        const int64_t kl = k0 + l;
+        uint32_t start = 0, len = 0;
+        if (kl < kstop) {
+            const int r = (int)(kl % R);
+            const uint32_t c = probe_cone(kl / R, L, order[slot][r], sbit[slot][r], a.n_sub, a.lexsub, a.maskord,
+                                          a.binom);
+            const uint32_t* off = a.offsets + (int64_t)r * (a.n_cones + 1);
+            start = off[c];
+            len = off[c + 1] - start;
         }
+        const uint32_t incl = wave_incl_scan(len);
+        st[l] = start;
+        in[l] = incl;
+        const uint32_t total = shfl_u32(incl, 63);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const int nk = kstop - k0 < 64 ? (int)(kstop - k0) : 64;
-        for (int s = 0; s < nk; ++s) {
-            const int64_t k = k0 + s;
-            const int r = (int)(k % R);
-            const int64_t lv = k / R;
-            const uint32_t c = slot_c[w][s];
-            const uint32_t* off = a.offsets + (int64_t)r * (a.n_cones + 1);
-            const uint32_t p0 = off[c], p1 = off[c + 1];
-            const uint4* planes = static_cast<const uint4*>(a.planes[r]);
-            for (uint32_t p = p0 + l; p < p1; p += 64) {
-                bool first = true;
-                for (int r2 = 0; r2 < R && first; ++r2) {
-                    if (r2 == r) continue;
-                    const uint64_t top = a.xtop[((int64_t)r * R + r2) * a.N + p];
-                    const int64_t pos2 = walk_position(top, L, D, rank_of[w][r2], sbit[w][r2], a.n_sub, a.binom,
-                                                       mrank, hstart);
-                    first = !(pos2 < lv || (pos2 == lv && r2 < r));
-                }
-                if (!first) continue;
-                ++analyzed;
-                const float d = row_dist_fp32<E>(planes, a.N, a.nch, p, y);
-                if (d <= best) {
-                    const uint32_t row = a.perm[(int64_t)r * a.N + p];
-                    if (d < best || row < best_row) {
-                        best = d;
-                        best_row = row;
-                    }
+        uint32_t k = 0;
+        for (uint32_t f = sub * 64 + l; f < total; f += wpq * 64) {
+            while (in[k] <= f) ++k;
+            const uint32_t before = k ? in[k - 1] : 0u;
+            const int64_t kk = k0 + k;
+            const int r = (int)(kk % R);
+            const int64_t lv = kk / R;
+            const int64_t p = (int64_t)st[k] + (f - before);
+            bool first = true;
+            for (int r2 = 0; r2 < R && first; ++r2) {
+                if (r2 == r) continue;
+                const uint64_t top = a.xtop[((int64_t)r * R + r2) * a.N + p];
+                const int64_t pos2 = walk_position(top, L, D, rank_of[slot][r2], sbit[slot][r2], a.n_sub, a.binom,
+                                                   mrank, hstart);
+                first = !(pos2 < lv || (pos2 == lv && r2 < r));
+            }
+            if (!first) continue;
+            ++analyzed;
+            const float d = rot_row_dist<E, NCH>(a.planes_tab[r], a.N, a.nch, p, y);
+            if (d <= best) {
+                const uint32_t row = a.perm[(int64_t)r * a.N + p];
+                if (d < best || row < brow) {
+                    best = d;
+                    brow = row;
                 }
             }
         }
@@ -257,12 +297,30 @@ __global__ __launch_bounds__(64 * kRotWaves) void scan_rot_kernel(RotArgs a) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-    wave_argmin(best, best_row);
+    wave_argmin(best, brow);
     uint32_t tot = analyzed;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) tot += (uint32_t)__shfl_xor((int)tot, o, 64);
-    if (l == 0) {
-        a.out_idx[q] = best_row == 0xFFFFFFFFu ? -1 : (int64_t)best_row;
+    if (wpq > 1) {
+        if (l == 0) {
+            red_d[w] = best;
+            red_r[w] = brow;
+            red_n[w] = tot;
+        }
+        __syncthreads();
+        if (sub == 0 && l == 0)
+            for (int o = 1; o < wpq; ++o) {
+                const float od = red_d[w + o];
+                const uint32_t orow = red_r[w + o];
+                tot += red_n[w + o];
+                if (od < best || (od == best && orow < brow)) {
+                    best = od;
+                    brow = orow;
+                }
+            }
+    }
+    if (qv && sub == 0 && l == 0) {
+        a.out_idx[q] = brow == 0xFFFFFFFFu ? -1 : (int64_t)brow;
         a.out_dist[q] = best;
         if (a.out_ncand) a.out_ncand[q] = tot;
     }
@@ -275,16 +333,32 @@ hipError_t launch_probe_rot(const RotArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_scan_rot(const RotArgs& a, hipStream_t s) {
-    if (a.Q <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.Q + kRotWaves - 1) / kRotWaves));
-    switch (a.dtype) {
-        case kF32: hipLaunchKernelGGL(scan_rot_kernel<F32>, grid, dim3(64 * kRotWaves), 0, s, a); break;
-        case kF16: hipLaunchKernelGGL(scan_rot_kernel<F16>, grid, dim3(64 * kRotWaves), 0, s, a); break;
-        case kU8: hipLaunchKernelGGL(scan_rot_kernel<U8>, grid, dim3(64 * kRotWaves), 0, s, a); break;
-        default: return hipErrorInvalidValue;
+template <typename E>
+static hipError_t dispatch_scan_rot(const RotArgs& a, hipStream_t s) {
+    const int qpb = 4 / a.waves_per_query;
+    const dim3 grid((unsigned)((a.Q + qpb - 1) / qpb)), block(256);
+    switch (a.nch) {
+#define OSANN_ROT_CASE(C)                                                   \
+    case C:                                                                 \
+        hipLaunchKernelGGL((scan_rot_kernel<E, C>), grid, block, 0, s, a);  \
+        break;
+        OSANN_ROT_CASE(1) OSANN_ROT_CASE(2) OSANN_ROT_CASE(4) OSANN_ROT_CASE(8) OSANN_ROT_CASE(16)
+#undef OSANN_ROT_CASE
+        default:
+            hipLaunchKernelGGL((scan_rot_kernel<E, 0>), grid, block, 0, s, a);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_scan_rot(const RotArgs& a, hipStream_t s) {
+    if (a.Q <= 0) return hipSuccess;
+    if (a.waves_per_query != 1 && a.waves_per_query != 2 && a.waves_per_query != 4) return hipErrorInvalidValue;
+    switch (a.dtype) {
+        case kF32: return dispatch_scan_rot<F32>(a, s);
+        case kF16: return dispatch_scan_rot<F16>(a, s);
+        case kU8: return dispatch_scan_rot<U8>(a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 // Gathers, for the rows of basis r's table in its order, their packed top-L

@@ -7,6 +7,7 @@ oracle recomputes one by one.
 * 1e6 x 128 descriptor-like uint8 rows, L=2, 1e4 noisy queries, both modes.
 * ~4.2e6 mean-removed 8x8 FP16 patches of a 2048x2048 1/f field, L=2, queries
   are all patches of the shifted noisy field (~4.2e6), tiled mode.
+* the 1e6 x 64 Gaussian workload with four bases (Section 3.A).
 
 The index itself (every key, bucket offset and permutation entry) is compared
 in full; searches are compared on a spread sample of queries."""
@@ -122,5 +123,35 @@ def test_patches_4m_fp16(orc):
         for budget, n in ((64, 300), (1024, 200)):
             tiled_sampled(orc, X, o, h, Y, yq, budget, sample_ids(len(Y), n), "patches 2048^2 f16")
         fp32_sampled(orc, X, o, h, Y, yq, 1024, sample_ids(len(Y), 200), "patches 2048^2 f16")
+    finally:
+        B.os_ann_free(h)
+
+
+def test_several_bases_1m_d64(orc):
+    # four bases (the first the identity) on the full 1e6 x 64 workload, at the
+    # budget where recall@1 reaches 0.9, in the benchmark's launch shape
+    X = W.gaussian_db(1_000_000, 64, W.SEEDS["gauss64_db"])
+    Y = W.gaussian_queries(10_000, 64, W.SEEDS["gauss64_q"])
+    rots = W.random_bases(4, 64)
+    say("[full] several bases: building 4 tables")
+    h = B.os_ann_build_rot(dev(X), 2, dev(rots))
+    o = orc.build_index_rot(X, 2, rots)
+    try:
+        for r in range(4):
+            ex = B.os_ann_export_basis(h, r)
+            torch.cuda.synchronize()
+            assert np.array_equal(ex["offsets"].cpu().numpy(), o["tables"][r]["offsets"]), r
+            assert np.array_equal(ex["perm"].cpu().numpy(), o["tables"][r]["perm"]), r
+            del ex
+        yq = dev(Y)
+        for budget, n in ((4096, 200), (131072, 40)):
+            s = sample_ids(len(Y), n)
+            say(f"[full] several bases: budget {budget}")
+            gi, gd, gn = B.os_ann_search_ex(h, yq, budget)
+            torch.cuda.synchronize()
+            gi, gd, gn = gi.cpu().numpy()[s], gd.cpu().numpy()[s], gn.cpu().numpy()[s]
+            oi, od32, od64, on = orc.search_rot(X, o, Y[s], budget)
+            assert np.array_equal(gn, on) and np.array_equal(gi, oi), budget
+            assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), budget
     finally:
         B.os_ann_free(h)
