@@ -153,7 +153,7 @@ struct ListEntry {
 };
 
 template <bool F16IN, int KS, int R, int G>
-__global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
+__global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
     constexpr int QW = 16 * G;              // queries per wave
     constexpr int MQ = 4 * QW;              // queries per tile
     constexpr int CPR = KS * 4;             // 16-byte units per row (dk = 32*KS)
@@ -431,31 +431,51 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
                     }
                 };
                 set_pthr();
-                for (uint32_t r0 = 0; r0 < bn; r0 += 16) {
-                    uint4 av[KS];
+                // software pipeline: tile r0's products are on the matrix
+                // cores while tile r0-16's d~ are formed and compared, and
+                // tile r0+16's fragments are read from LDS
+                auto frag = [&](uint32_t r0, uint4 (&av)[KS], float4& nv4) {
 #pragma unroll
                     for (int ks = 0; ks < KS; ++ks) av[ks] = rb[aslot[ks] + r0 * CPR];
-                    const float4 nv4 = *reinterpret_cast<const float4*>(nb + r0);
-                    f32x4_t acc[G];
+                    nv4 = *reinterpret_cast<const float4*>(nb + r0);
+                };
+                auto products = [&](const uint4 (&av)[KS], f32x4_t (&acc)[G]) {
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
                         acc[g] = mfma16<F16IN>(av[0], bq[g][0], f32x4_t{0.0f, 0.0f, 0.0f, 0.0f});
 #pragma unroll
                         for (int ks = 1; ks < KS; ++ks) acc[g] = mfma16<F16IN>(av[ks], bq[g][ks], acc[g]);
                     }
-                    const float nv[4] = {nv4.x, nv4.y, nv4.z, nv4.w};
+                };
+                uint4 av[KS];
+                float4 nv4;
+                f32x4_t acc[G];
+                frag(0, av, nv4);
+                products(av, acc);
+                float4 nv_cur = nv4;
+                for (uint32_t r0 = 0; r0 < bn; r0 += 16) {
+                    const bool more = r0 + 16 < bn;
+                    f32x4_t acc_next[G];
+                    float4 nv_next = nv_cur;
+                    if (more) {
+                        frag(r0 + 16, av, nv_next);
+                        products(av, acc_next);
+                    }
+                    const float nv[4] = {nv_cur.x, nv_cur.y, nv_cur.z, nv_cur.w};
                     // d~ of the lane's 4 rows for each group; a NaN norm marks
                     // a padding row and never passes
+                    // (fminf drops NaN operands, so padding rows fall out of
+                    // the minimum; a -inf threshold makes the margin +inf)
                     float d[G][4];
-                    bool hit = false;
+                    float margin = __builtin_huge_valf();
 #pragma unroll
-                    for (int g = 0; g < G; ++g)
+                    for (int g = 0; g < G; ++g) {
 #pragma unroll
-                        for (int ii = 0; ii < 4; ++ii) {
-                            d[g][ii] = nv[ii] - 2.0f * acc[g][ii];
-                            hit = hit || d[g][ii] <= pthr[g];
-                        }
-                    if (__ballot(hit) != 0) {  // rare once the bounds have settled
+                        for (int ii = 0; ii < 4; ++ii) d[g][ii] = nv[ii] - 2.0f * acc[g][ii];
+                        const float m4 = fminf(fminf(d[g][0], d[g][1]), fminf(d[g][2], d[g][3]));
+                        margin = fminf(margin, m4 - pthr[g]);
+                    }
+                    if (__ballot(margin <= 0.0f) != 0) {  // rare once the bounds have settled
 #pragma unroll
                         for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -472,6 +492,11 @@ __global__ __launch_bounds__(256) void tiled_screen_kernel(TiledArgs a) {
                                 nhit += (uint32_t)__popcll(m);
                             }
                         set_pthr();
+                    }
+                    if (more) {
+#pragma unroll
+                        for (int g = 0; g < G; ++g) acc[g] = acc_next[g];
+                        nv_cur = nv_next;
                     }
                 }
             }
