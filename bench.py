@@ -124,8 +124,10 @@ def recall_budget(idx, queries, nn_d64, db, sweep, mode, pair):
 def serving_leg(X2, db2, budget2, n_req=600, rate=400.0):
     """Continuous batching over three resident indexes: 16384x16 Gaussian (L=1), the
     1e6x64 Gaussian database (L=2) and 1e6x128 descriptor-like uint8 rows (L=2);
-    Poisson arrivals of 1..4096-query requests, tiled search at each index's
-    recall-0.9 budget; QPS and p50/p99 latency from arrival to completion."""
+    Poisson arrivals of 1..4096-query requests, search at each index's
+    recall-0.9 budget, each index in the faster of the two search modes
+    (timed on a calibration batch); QPS and p50/p99 latency from arrival to
+    completion."""
     import torch
     from paper_1509_03453_amd import binding as B
     from paper_1509_03453_amd import serving as S
@@ -150,8 +152,11 @@ def serving_leg(X2, db2, budget2, n_req=600, rate=400.0):
                                                  (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384),
                                                  T, pair_d64_torch)
     log(f"[bench] serving budgets {budgets} (calibration recall {cal})")
-    res = [S.ResidentIndex(n, ix[n], budgets[n], mode=T, rerank_r=RERANK) for n in ("gauss16", "gauss64", "desc128")]
-    names = [r.name for r in res]
+    names = ["gauss16", "gauss64", "desc128"]
+    modes = {n: S.choose_mode(ix[n], torch.from_numpy(gen[n](2048, 5000 + k)).cuda(), budgets[n], RERANK)
+             for k, n in enumerate(names)}
+    log(f"[bench] serving modes {modes} (0 = FP32 scan, 1 = tiled)")
+    res = [S.ResidentIndex(n, ix[n], budgets[n], mode=modes[n], rerank_r=RERANK) for n in names]
     arrivals = W.serving_requests(n_req, rate, 3, max_q=4096)
     reqs = [S.Request(i, names[w], torch.from_numpy(gen[names[w]](n, sd)).cuda(), a)
             for i, (a, w, n, sd) in enumerate(arrivals)]
@@ -169,7 +174,8 @@ def serving_leg(X2, db2, budget2, n_req=600, rate=400.0):
     for r in res:
         r.index.close()
     st.update({"offered_rate_req_s": rate, "slots": 4, "max_batch": 8192, "budgets": budgets,
-               "recall_at_1": recall, "mode": "tiled", "rerank_r": RERANK,
+               "recall_at_1": recall,
+               "modes": {n: ("tiled" if modes[n] == T else "fp32") for n in names}, "rerank_r": RERANK,
                "indexes": "gauss16 16384x16 L=1; gauss64 1e6x64 L=2; desc128 1e6x128 u8 L=2"})
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
 
@@ -234,6 +240,46 @@ def bases_leg(X, db, q, nn_d64, R=4, sweep=(65536, 98304, 131072, 196608, 262144
                     "in every basis + scan analyzing each row once"}
 
 
+def patches_leg(budgets=(64, 256, 1024, 4096), n_sample=10_000):
+    """Batching at scale: every 8x8 patch of a 2048x2048 1/f field (FP16,
+    ~4.2e6 rows) against every patch of the shifted noisy field (~4.2e6
+    queries) in one call per mode; budget = smallest swept one whose recall@1
+    on a spread sample of queries reaches 0.9 (exact NN of the sample by torch)."""
+    import torch
+    from paper_1509_03453_amd import binding as B
+    from paper_1509_03453_amd import workloads as W
+    Xp, Yp = W.patch_pair(2048)
+    db = torch.from_numpy(Xp).cuda()
+    q = torch.from_numpy(Yp).cuda()
+    samp = torch.from_numpy(np.unique(np.linspace(0, len(Yp) - 1, n_sample).astype(np.int64))).cuda()
+    dbf = db.float()
+    _, nn = exact_nn_torch(dbf, q[samp].float(), chunk=500)
+    h = B.os_ann_build_ex(db, L_HASH, want_lowp=True)
+    out = {"N": int(len(Xp)), "Q": int(len(Yp)), "D": DIM, "dtype": "f16", "sweep": []}
+    chosen = None
+    for budget in budgets:
+        rec = {}
+        for m, code in (("fp32", B.OS_ANN_MODE_FP32), ("tiled", B.OS_ANN_MODE_TILED)):
+            B.os_ann_search_ex(h, q, budget, mode=code, want_ncand=False)  # warm-up, split choice
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            i, d, n = B.os_ann_search_ex(h, q, budget, mode=code)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            r = float((pair_d64_torch(dbf, q[samp].float(), i[samp]) <= nn).double().mean())
+            rec[m] = {"search_ms": round(ms, 2), "queries_per_s": round(len(Yp) / ms * 1e3, 1),
+                      "recall_at_1": round(r, 4)}
+            mean_n = float(n.double().mean())
+        out["sweep"].append({"budget": budget, "mean_ncand": round(mean_n, 1), **rec})
+        log(f"[bench] patches {out['sweep'][-1]}")
+        if chosen is None and min(rec["fp32"]["recall_at_1"], rec["tiled"]["recall_at_1"]) >= 0.9:
+            chosen = budget
+            break
+    B.os_ann_free(h)
+    out["budget"] = chosen
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +290,7 @@ def main():
     ap.add_argument("--budget", type=int, default=0, help="fixed budget instead of the recall sweep")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
     ap.add_argument("--no-bases", action="store_true", help="skip the several-bases leg")
+    ap.add_argument("--no-patches", action="store_true", help="skip the 4.2e6-patch batching leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -424,6 +471,9 @@ def main():
         out["several_bases"] = bases_leg(X, db, q, nn_d64)
     if not args.no_serving and "tiled" in modes:
         out["serving"] = serving_leg(X, db, results["tiled"]["budget"])
+    if not args.no_patches and "tiled" in modes:
+        log("[bench] patches")
+        out["patches"] = patches_leg()
     if not args.no_cpu:
         log("[bench] oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(X, Y, r["budget"])

@@ -37,7 +37,7 @@ import torch
 
 from . import binding as B
 
-__all__ = ["Request", "ResidentIndex", "Server", "pack_batch", "admissible", "latency_stats"]
+__all__ = ["Request", "ResidentIndex", "Server", "pack_batch", "admissible", "latency_stats", "choose_mode"]
 
 
 @dataclasses.dataclass
@@ -73,6 +73,28 @@ class ResidentIndex:
 
     def workspace(self, q: int) -> int:
         return self.index.workspace_bytes(q, self.budget, self.mode, self.rerank_r)
+
+
+def choose_mode(index: B.Index, queries: torch.Tensor, budget: int, rerank_r: int = 8, reps: int = 3) -> int:
+    """The faster search mode for this index and budget, timed on ``queries``.
+
+    Both modes visit the same candidates; the matrix-core screening pays off
+    when queries probe many cones, the plain scan when they probe few."""
+    best, best_ms = B.OS_ANN_MODE_FP32, None
+    for mode in (B.OS_ANN_MODE_FP32, B.OS_ANN_MODE_TILED):
+        index.search(queries, budget, mode=mode, rerank_r=rerank_r)  # warm-up (and split choice)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            index.search(queries, budget, mode=mode, rerank_r=rerank_r)
+        t1.record()
+        t1.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        if best_ms is None or ms < best_ms:
+            best, best_ms = mode, ms
+    return best
 
 
 # ---------------------------------------------------------------------------

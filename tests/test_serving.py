@@ -143,3 +143,23 @@ def test_serving_pool_cap_serialises_and_rejects():
         tiny.run([S.Request(0, "gauss64", reqs[0].queries, 0.0)], max_seconds=30)
     for ix in ixs:
         ix.index.close()
+
+
+@pytest.mark.gpu
+def test_choose_mode_returns_the_faster_valid_mode():
+    import torch
+    from paper_1509_03453_amd import binding as B
+    from gpu_util import dev
+
+    X = W.gaussian_db(50000, 64, seed=5101)
+    Y = dev(W.gaussian_queries(2048, 64, seed=5102))
+    ix = B.Index(dev(X), 2, want_lowp=True)
+    try:
+        for budget in (64, 20000):
+            m = S.choose_mode(ix, Y, budget)
+            assert m in (B.OS_ANN_MODE_FP32, B.OS_ANN_MODE_TILED)
+            i, d, n = ix.search(Y, budget, mode=m)
+            torch.cuda.synchronize()
+            assert (i >= 0).all() and (i < 50000).all()
+    finally:
+        ix.close()
