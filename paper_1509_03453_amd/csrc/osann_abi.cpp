@@ -269,16 +269,13 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         p.mq = tile_queries(R);
         p.T = (Q + p.mq - 1) / p.mq;
         p.nw = (ne + 63) / 64;
-        // smallest split count whose cone list and row batches fit in LDS
+        // splits only add parallelism (up to about four wave items for each
+        // of the 8 waves a compute unit holds); the tuner picks the count
         p.smin = 1;
-        while (p.smin < 16 && (split_span(ne, p.smin) * 48 > (int64_t)kTabBytesMax ||
-                               tiled_screen_lds(split_span(ne, p.smin), p.dk) + tiled_screen_static_lds(R) >
-                                   kLdsPerBlock))
-            p.smin <<= 1;
-        p.fits = tiled_screen_lds(split_span(ne, p.smin), p.dk) + tiled_screen_static_lds(R) <= kLdsPerBlock;
-        const int64_t want = (4 * (int64_t)ix->num_cu + p.T - 1) / (p.T > 0 ? p.T : 1);
-        p.smax = (int)std::max<int64_t>(p.smin, std::min<int64_t>(16, pow2_ceil(std::max<int64_t>(want, 1))));
-        while (p.smax > p.smin && split_span(ne, p.smax) < 64 * 2) p.smax >>= 1;
+        p.fits = tiled_screen_lds() + tiled_screen_static_lds(R) <= kLdsPerBlock;
+        const int64_t want = (32 * (int64_t)ix->num_cu + p.T - 1) / (p.T > 0 ? p.T : 1);
+        p.smax = (int)std::min<int64_t>(64, pow2_ceil(std::max<int64_t>(want, 1)));
+        while (p.smax > 1 && split_span(ne, p.smax) < 64 * 2) p.smax >>= 1;
         // probed-cone bitmaps pay off once a query probes many cones and stay small
         const int64_t mean_bucket = std::max<int64_t>(1, ix->N / ne);
         const int64_t probes = std::min<int64_t>(budget, ix->N) / mean_bucket + 1;
@@ -512,7 +509,7 @@ hipError_t enqueue_tiled(const Call& c, int S) {
                             reinterpret_cast<uint32_t*>(c.base + p.off_qsorted), c.s);
     if (e != hipSuccess) return e;
     uint32_t* counter = reinterpret_cast<uint32_t*>(c.base + p.off_counter);
-    e = launch_fill_u32(counter, 1, 0u, c.s);
+    e = launch_fill_u32(counter, kXcd, 0u, c.s);
     if (e != hipSuccess) return e;
     uint32_t* cmin = reinterpret_cast<uint32_t*>(c.base + p.off_cmin);
     e = launch_fill_u32(cmin, c.Q * p.R, 0xFFFFFFFFu, c.s);
@@ -558,11 +555,13 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     ta.counter = counter;
     ta.part = reinterpret_cast<uint2*>(c.base + p.off_part);
     ta.cmin = cmin;
-    const size_t lds = tiled_screen_lds(ta.span, ta.dk);
+    const size_t lds = tiled_screen_lds();
     int occ = tiled_screen_occupancy(p.R, ix->lp.f16, ix->lp.dk / 32, lds);
     if (occ < 1) occ = 1;
-    const int64_t items = p.T * S;
-    const int blocks = (int)std::min<int64_t>(items, (int64_t)occ * ix->num_cu);
+    const int64_t items = p.T * S;  // one wave each, 4 waves per block
+    // a multiple of kXcd blocks, so that every chiplet queue has blocks
+    const int64_t cap = std::max<int64_t>(kXcd, (int64_t)occ * ix->num_cu / kXcd * kXcd);
+    const int blocks = (int)std::min<int64_t>(cap, ((items + 3) / 4 + kXcd - 1) / kXcd * kXcd);
     if (std::getenv("OSANN_VERBOSE"))
         std::fprintf(stderr, "[osann] tiled Q=%lld T=%lld S=%d span=%lld lds=%zu occ=%d blocks=%d bitmap=%d R=%d\n",
                      (long long)c.Q, (long long)p.T, S, (long long)ta.span, lds, occ, blocks, (int)p.bitmap, p.R);

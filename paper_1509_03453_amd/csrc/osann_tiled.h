@@ -7,11 +7,12 @@
 
 namespace osann {
 
-// A tile holds 4 waves x 16*G queries (G MFMA B operand groups per wave);
-// G = 4 for R <= 8, G = 2 for R = 16 (register budget of the top-R lists).
+// A wave tile holds 16*G queries (G MFMA B operand groups); G = 4 for
+// R <= 8, G = 2 for R = 16 (LDS and register budget of the top-R lists).
 inline int tile_groups(int R) { return R <= 8 ? 4 : 2; }
-inline int tile_queries(int R) { return 64 * tile_groups(R); }
-constexpr size_t kTabBytesMax = 40 * 1024;  // LDS budget of one split's marked-cone list (48 B per cone)
+inline int tile_queries(int R) { return 16 * tile_groups(R); }
+constexpr int kChunk = 512;  // cones a screen wave lists at a time (a multiple of 64)
+constexpr int kXcd = 8;      // chiplets (each with its own L2) the blocks of a launch are dealt to in turn
 constexpr size_t kLdsPerBlock = 160 * 1024;  // LDS of one compute unit, all usable by one block
 
 struct TiledArgs {
@@ -43,10 +44,10 @@ struct TiledArgs {
     const uint64_t* qbits;  // [Q][nw]
     int64_t nw;
     // schedule
-    int64_t T;              // tiles
+    int64_t T;              // wave tiles
     int S;                  // splits of the non-empty cones
     int64_t span;           // non-empty cones per split (multiple of 64)
-    uint32_t* counter;      // work-queue head, zero before the launch
+    uint32_t* counter;      // [kXcd] work-queue heads, zero before the launch
     // output
     uint2* part;            // [Q][S][R] (FP32 bits of d~, padded position)
     uint32_t* cmin;         // [Q][R] smallest order-preserving d~ bits kept per class
@@ -91,7 +92,7 @@ hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int
                             const uint32_t* offsets, const uint32_t* poff, int dk, int to_f16, uint16_t* xl,
                             uint32_t* ppos, float* nrm, int64_t np_total, hipStream_t s);
 hipError_t launch_tiled_screen(const TiledArgs& a, int R, int f16in, int blocks, hipStream_t s);
-size_t tiled_screen_lds(int64_t span, int dk);  // dynamic LDS bytes of one screen block
+size_t tiled_screen_lds();                      // dynamic LDS bytes of one screen block
 size_t tiled_screen_static_lds(int R);          // static LDS bytes (upper bound) of one screen block
 hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s);
 hipError_t launch_tiled_seed(const SeedArgs& a, int R, int f16in, hipStream_t s);

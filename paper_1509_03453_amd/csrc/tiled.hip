@@ -1,21 +1,24 @@
 // Matrix-core screening of the candidates with an exact FP32 re-rank.
 //
-// Queries are sorted by their own cone and cut into tiles of 4 waves x 16G
-// queries.  A work item is (tile, split): split s owns a contiguous range of
-// the non-empty cones.  The block first marks, in an LDS table over that
-// range, which of its queries probe each cone (from the probe pass's bitmaps,
-// or by regenerating the walks of Section 3.B); then for every marked cone it
-// streams the cone's rows through LDS in batches of up to 128 and screens
-// them in 16-row MFMA tiles (bucket sizes are padded to 16 rows in the
+// Queries are sorted by their own cone and cut into wave tiles of 16G
+// queries.  A work item is (wave tile, split): split s owns a contiguous
+// range of the non-empty cones, and one wave takes the item alone.  It
+// first lists the cones of its range that some query of the tile probes,
+// with the mask of those queries (from the probe pass's bitmaps, or by
+// regenerating the walks of Section 3.B, one lane per query); then it
+// streams every listed cone's rows, 16 at a time, straight from memory into
+// the MFMA A operand (bucket sizes are padded to 16 rows in the
 // low-precision copy).  With the rows as the MFMA A operand and 16 queries
 // as B, lane l holds the products of query l%16 with 4 rows, from which it
 // forms d~ = ||x^||^2 - 2 q^.x^, which ranks candidates like the squared
-// distance of the rounded vectors.
+// distance of the rounded vectors.  No wave waits for another: a wave only
+// reads the cones its own queries probe.
 //
 // Each query keeps, per split, a top-R list of (d~, padded position) in
 // LDS.  The tile loop only compares d~ with a per-query bound; the few
 // candidates at or below it go to a per-wave hit buffer, which is merged
-// into the lists (one lane per query) when it fills and after every batch.
+// into the lists (one lane per query) when it fills and at the end of the
+// item.
 //
 // Pruning: a candidate whose d~ exceeds an upper bound of the query's final
 // R-th value can never be kept.  Two bounds are used: the R-th entry of the
@@ -30,7 +33,7 @@
 // A finishing pass merges the S split lists, recomputes the exact FP32
 // distance of the R survivors and keeps the arg-min on (distance, row).
 // Lists are kept in the total order (d~, position), so results do not
-// depend on the batch or the split.
+// depend on the order of the tiles or on the split.
 #include "osann_device.h"
 #include "osann_kernels.h"
 #include "osann_tiled.h"
@@ -108,6 +111,12 @@ __device__ inline float ord_float(uint32_t u) {
     return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
 }
 
+// A value every lane of the wave holds alike, moved to scalar registers.
+__device__ inline uint4 uni4(uint4 v) {
+    return make_uint4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
+                      __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+}
+
 template <bool F16IN>
 __device__ inline f32x4_t mfma16(const uint4& a, const uint4& b, f32x4_t acc) {
     if (F16IN)
@@ -117,216 +126,89 @@ __device__ inline f32x4_t mfma16(const uint4& a, const uint4& b, f32x4_t acc) {
                                                    acc, 0, 0, 0);
 }
 
-constexpr int kBatchRows = 128;  // rows staged in LDS per batch (8 MFMA row tiles)
-constexpr int kHitCap = 64;      // hit buffer entries per wave (one full ballot)
+constexpr int kHitCap = 64;   // hit buffer entries per wave (one full ballot)
 
-// Exclusive prefix sum of one value per thread over the 256-thread block.
-__device__ inline uint32_t block_scan256(uint32_t v, uint32_t* wsum, uint32_t* total) {
-    const int w = threadIdx.x / 64, l = lane_id();
-    const uint32_t incl = wave_incl_scan(v);
-    if (l == 63) wsum[w] = incl;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        before += k < w ? wsum[k] : 0u;
-        all += wsum[k];
-    }
-    __syncthreads();
-    *total = all;
-    return before + incl - v;
-}
-
-// LDS slot (16-byte unit) of unit c of row r: XOR swizzle inside each row so
-// that the 16 rows an MFMA A-fragment read touches fall in different banks.
-template <int CPR>
-__device__ inline int swz(int r, int c) {
-    constexpr int M = CPR < 8 ? CPR - 1 : 7;
-    return r * CPR + (c ^ (r & M));
-}
-
-// Marked cone of a split: padded rows [p0, p1) and, per wave, which of its
-// queries probe the cone.
-struct ListEntry {
-    uint32_t p0, p1, pad0, pad1;
-    uint64_t m[4];
-};
-
+// One wave works on one item at a time: (wave tile of 16G queries, split),
+// taking the split's cones kChunk at a time.  Dynamic LDS holds, per wave,
+// the marked-cone list of one chunk: (p0, p1, probe mask lo, hi) over the
+// padded rows [p0, p1) of each listed cone.  While the walks are
+// regenerated, a cone table (one probe mask per cone of the chunk) sits in
+// the list's upper half and is compacted into the list in place (entry i is
+// written at 16i bytes, table word j is read at 8*kChunk + 8j bytes, j >= i,
+// and a chunk of 64 table words is read before its entries are written).
 template <bool F16IN, int KS, int R, int G>
 __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
-    constexpr int QW = 16 * G;              // queries per wave
-    constexpr int MQ = 4 * QW;              // queries per tile
-    constexpr int CPR = KS * 4;             // 16-byte units per row (dk = 32*KS)
-    constexpr int KU = kBatchRows * CPR / 256;  // units each thread stages per batch
+    constexpr int QW = 16 * G;              // queries per wave tile
     extern __shared__ uint64_t dyn[];
-    // dyn: list[span] | scratch: first the cone table tab[span][4], then
-    //      (once the list is built) rows[2][128*CPR] (uint4) and nrm[2][128]
-    __shared__ uint8_t s_order[4][kMaxD];
-    __shared__ uint8_t s_sbit[4][kMaxD];
-    __shared__ uint32_t s_item, s_nlist, s_wsum[4];
     __shared__ uint2 s_list[4][QW * R];     // per wave: top-R list of each query slot
     __shared__ uint4 s_hit[4][kHitCap];     // per wave: (d~ bits, padded position, slot) hits
     const int w = threadIdx.x / 64, l = lane_id();
-    const int64_t total = a.T * a.S;
-    ListEntry* list = reinterpret_cast<ListEntry*>(dyn);
-    uint64_t* tab = dyn + 6 * a.span;
-    uint4* rows = reinterpret_cast<uint4*>(tab);
-    float* nrmb = reinterpret_cast<float*>(rows + 2 * kBatchRows * CPR);
-    // this thread's staging units: global element offset inside a batch and LDS slot
-    int goff[KU], gslot[KU], grow[KU];
-#pragma unroll
-    for (int k = 0; k < KU; ++k) {
-        const int u = threadIdx.x + 256 * k;
-        grow[k] = u / CPR;
-        goff[k] = grow[k] * a.dk + 8 * (u % CPR);
-        gslot[k] = swz<CPR>(grow[k], u % CPR);
-    }
-    int aslot[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) aslot[ks] = swz<CPR>(l % 16, l / 16 + 4 * ks);
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1u);
-        __syncthreads();
-        const int64_t item = s_item;
-        __syncthreads();
-        if (item >= total) break;
-        const int64_t t = item / a.S;
-        const int s = (int)(item % a.S);
-        const int64_t n0 = s * a.span;
-        const int64_t n1 = n0 + a.span < a.n_ne ? n0 + a.span : a.n_ne;
-        const int nspan = n1 > n0 ? (int)(n1 - n0) : 0;
-        const int64_t wslot0 = t * MQ + (int64_t)w * QW;  // first tile slot of this wave
-
-        // 1. per cone of the split: which of this wave's queries probe it
-        if (a.qbits) {
-            // transpose the queries' probed-cone bitmaps with ballots
-            const bool mine = l < QW && wslot0 + l < a.Q;
-            const uint32_t q = mine ? a.qorder[wslot0 + l] : 0u;
-            for (int64_t k = n0 >> 6; k * 64 < n1; ++k) {
-                const uint64_t word = mine ? a.qbits[(int64_t)q * a.nw + k] : 0ull;
-                uint64_t col = 0;
-#pragma unroll 8
-                for (int c = 0; c < 64; ++c) {
-                    const uint64_t m = __ballot((word >> c) & 1ull);
-                    col = c == l ? m : col;
-                }
-                const int64_t e = k * 64 + l;
-                if (e >= n0 && e < n1) tab[(e - n0) * 4 + w] = col;
-            }
-        } else {
-            for (int i = l; i < nspan; i += 64) tab[i * 4 + w] = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            for (int c = 0; c < QW; ++c) {
-                if (wslot0 + c >= a.Q) break;
-                const uint32_t q = a.qorder[wslot0 + c];
-                const uint32_t js = a.jstop[q];
-                const unsigned long long bit = 1ull << c;
-                if (js == kWalkAll) {
-                    for (int i = l; i < nspan; i += 64) atomicOr((unsigned long long*)&tab[i * 4 + w], bit);
-                    continue;
-                }
-                for (int i = l; i < a.D; i += 64) {
-                    s_order[w][i] = a.order[(int64_t)q * a.D + i];
-                    s_sbit[w][i] = a.sbit[(int64_t)q * a.D + i];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                for (uint32_t j0 = 0; j0 < js; j0 += 64) {
-                    const uint32_t j = j0 + l;
-                    if (j < js) {
-                        const uint32_t cone =
-                            probe_cone(j, a.L, s_order[w], s_sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
-                        if (a.offsets[cone + 1] > a.offsets[cone]) {
-                            const int64_t e = a.ne_id[cone];
-                            if (e >= n0 && e < n1) atomicOr((unsigned long long*)&tab[(e - n0) * 4 + w], bit);
-                        }
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            }
-        }
-        __syncthreads();
-
-        // 2. compact list of the cones some query of the tile probes
-        if (threadIdx.x == 0) s_nlist = 0;
-        __syncthreads();
-        for (int base = 0; base < nspan; base += 256) {
-            const int i = base + threadIdx.x;
-            uint64_t m[4] = {0, 0, 0, 0};
-            if (i < nspan)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) m[k] = tab[i * 4 + k];
-            const bool hit = (m[0] | m[1] | m[2] | m[3]) != 0;
-            uint32_t cnt;
-            const uint32_t at = block_scan256(hit ? 1u : 0u, s_wsum, &cnt);
-            if (hit) {
-                const uint32_t cone = a.ne_cone[n0 + i];
-                ListEntry e;
-                e.p0 = a.poff[cone];
-                e.p1 = a.poff[cone + 1];
-                e.pad0 = e.pad1 = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) e.m[k] = m[k];
-                list[s_nlist + at] = e;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) s_nlist += cnt;
-            __syncthreads();
-        }
-        const int nlist = (int)s_nlist;  // the table is dead from here on: its space holds the row batches
-
-        // 3. B operands: group g of this wave = query slots 16g .. 16g+15 of the
-        //    wave; lane l works on slot 16g + l%16 of every group
-        uint4 bq[G][KS];
-        bool qok[G];
-        uint32_t myq[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t slot = wslot0 + 16 * g + (l % 16);
-            qok[g] = slot < a.Q;
-            myq[g] = qok[g] ? a.qorder[slot] : 0u;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-                bq[g][ks] = qok[g] ? *reinterpret_cast<const uint4*>(a.ql + (int64_t)myq[g] * a.dk + ks * 32 +
-                                                                     8 * (l / 16))
-                                   : make_uint4(0, 0, 0, 0);
-        }
-        // The split's top-R list of every query of the wave lives in LDS
-        // (wlist[slot][k], ascending (d~, padded position)); lane l owns slot l
-        // when lists are updated.  Candidates that pass the bound go to a hit
-        // buffer first and are merged in bulk, which keeps the tile loop free
-        // of list code.
-        uint2* wl = s_list[w];
-        for (int k = l; k < QW * R; k += 64) wl[k] = make_uint2(0x7F800000u, 0xFFFFFFFFu);
-        uint32_t nhit = 0;
-        // shared bound of slot l's query (owner view) and of slot 16g + l%16
-        const uint32_t own_q = l < QW && wslot0 + l < a.Q ? a.qorder[wslot0 + l] : 0u;
-        const bool own_ok = l < QW && wslot0 + l < a.Q;
-        auto class_bound = [&](uint32_t q) {
-            uint32_t c = 0;
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                const uint32_t v =
-                    __hip_atomic_load(a.cmin + (int64_t)q * R + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                c = v > c ? v : c;
-            }
-            return c;
-        };
-        // thr[g]: no candidate of slot 16g + l%16 above it can enter the final
-        // top R: the minimum of the slot's list R-th entry and the shared bound
-        float thr[G];
-        uint32_t ownb = own_ok ? class_bound(own_q) : 0xFFFFFFFFu;
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): operands and bounds landed
+    // Work queue of this block's chiplet (blocks are dealt to the kXcd chiplets
+    // in turn, and each has its own L2): with 8 splits or more, chiplet x
+    // takes the splits x, x + kXcd, ... one after the other, so the waves
+    // of a chiplet stream the same cones at about the same time; else it
+    // takes the tiles x, x + kXcd, ... (tiles in order of their queries'
+    // cones, so all chiplets work on neighbouring cones and balance).  The
+    // mapping only steers locality: every item belongs to exactly one
+    // queue, and every queue is drained by the blocks with that index mod
+    // kXcd.
+    const int xq = (int)(blockIdx.x % kXcd);
+    const bool by_split = a.S >= kXcd;
+    const int64_t total = by_split ? (int64_t)(a.S / kXcd) * a.T
+                                   : (a.T > xq ? (a.T - xq + kXcd - 1) / kXcd : 0) * a.S;
+    uint4* wlist = reinterpret_cast<uint4*>(dyn) + (size_t)w * kChunk;
+    uint64_t* tab = reinterpret_cast<uint64_t*>(wlist) + kChunk;
+    uint2* wl = s_list[w];
+    auto wave_sync = [] {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    };
+    for (;;) {
+        uint32_t got = 0;
+        if (l == 0) got = atomicAdd(a.counter + xq, 1u);
+        const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane(__shfl((int)got, 0, 64)) & 0xFFFFFFFFll;
+        if (item >= total) break;
+        const int64_t t = by_split ? item % a.T : xq + kXcd * (item / a.S);
+        const int s = by_split ? xq + kXcd * (int)(item / a.T) : (int)(item % a.S);
+        const int64_t n0 = s * a.span;
+        const int64_t n1 = n0 + a.span < a.n_ne ? n0 + a.span : a.n_ne;
+        const int64_t slot0 = t * QW;  // first query slot of the wave tile
+        const bool own_ok = l < QW && slot0 + l < a.Q;
+        const uint32_t own_q = own_ok ? a.qorder[slot0 + l] : 0u;
+
+        // 1. B operands: group g = query slots 16g .. 16g+15 of the tile;
+        //    lane l works on slot 16g + l%16 of every group
+        uint4 bq[G][KS];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t slot = slot0 + 16 * g + (l % 16);
+            const uint32_t q = slot < a.Q ? a.qorder[slot] : 0u;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                bq[g][ks] = slot < a.Q ? *reinterpret_cast<const uint4*>(a.ql + (int64_t)q * a.dk + ks * 32 + 8 * (l / 16))
+                                       : make_uint4(0, 0, 0, 0);
+        }
+        // The split's top-R list of every query of the tile lives in LDS
+        // (wl[slot][k], ascending (d~, padded position)); lane l owns slot l
+        // when lists are updated.  Candidates that pass the bound go to a hit
+        // buffer first and are merged in bulk, which keeps the tile loop free
+        // of list code.
+        for (int k = l; k < QW * R; k += 64) wl[k] = make_uint2(0x7F800000u, 0xFFFFFFFFu);
+        uint32_t nhit = 0;
+        uint32_t ownb = 0xFFFFFFFFu;  // shared bound of slot l's query (owner view)
+        if (own_ok)
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const uint32_t v = __hip_atomic_load(a.cmin + (int64_t)own_q * R + k, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                ownb = k == 0 || v > ownb ? v : ownb;
+            }
+        wave_sync();
+        // thr[g]: no candidate of slot 16g + l%16 above it can enter the final
+        // top R: the minimum of the slot's list R-th entry and the shared bound
+        float thr[G];
         auto refresh_thr = [&]() {
-            // owner lane l: bound of slot l; everyone: bound of its 4 slots
             const float ob = fminf(ord_float(ownb), __uint_as_float(wl[l % QW * R + R - 1].x));
 #pragma unroll
             for (int g = 0; g < G; ++g) thr[g] = __shfl(ob, 16 * g + (l % 16), 64);
@@ -334,9 +216,7 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
         refresh_thr();
         // merge the hit buffer into the lists: lane l takes the hits of slot l
         auto flush = [&]() {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            wave_sync();
             float ld[R];
             uint32_t lr[R];
 #pragma unroll
@@ -360,70 +240,89 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
 #pragma unroll
                 for (int k = 0; k < R; ++k) wl[l * R + k] = make_uint2(__float_as_uint(ld[k]), lr[k]);
             nhit = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            wave_sync();
             refresh_thr();
         };
 
-        // 4. batches of up to 128 rows staged in LDS; the next batch is loaded
-        //    into registers while the current one is on the matrix cores.
-        uint4 stage[KU];
-        float nst = 0.0f;
-        auto issue = [&](uint32_t p, uint32_t n) {
-            const uint16_t* src = a.xl + (int64_t)p * a.dk;
+        // 3. the listed cones' rows, 16 at a time, straight from memory into
+        //    the MFMA A operand (lane l: row l%16, columns 8(l/16)+32ks ..);
+        //    the next tile's loads are in flight while the current one is
+        //    screened.  One word of the query's class minima is read per
+        //    tile; the largest of R consecutive reads (one per class) is a
+        //    valid shared bound (the words only decrease), so it replaces
+        //    the owner's bound every R tiles.  Plain loads: a cached copy may
+        //    be stale, which only makes the bound looser.
+        const int lane_off = (l % 16) * a.dk + 8 * (l / 16);
+        auto load = [&](uint32_t pp, uint4 (&av)[KS], float4& nv) {  // pp: uniform
+            const uint16_t* src = a.xl + (int64_t)pp * a.dk;
 #pragma unroll
-            for (int k = 0; k < KU; ++k)
-                stage[k] = (uint32_t)grow[k] < n ? *reinterpret_cast<const uint4*>(src + goff[k])
-                                                 : make_uint4(0, 0, 0, 0);
-            nst = a.nrm[(int64_t)p + (threadIdx.x < n ? threadIdx.x : n - 1)];
+            for (int ks = 0; ks < KS; ++ks) av[ks] = *reinterpret_cast<const uint4*>(src + lane_off + 32 * ks);
+            nv = *reinterpret_cast<const float4*>(a.nrm + pp + 4 * (l / 16));
         };
-        auto park = [&](int buf) {
-            uint4* dst = rows + buf * kBatchRows * CPR;
-#pragma unroll
-            for (int k = 0; k < KU; ++k) dst[gslot[k]] = stage[k];
-            if (threadIdx.x < kBatchRows) nrmb[buf * kBatchRows + threadIdx.x] = nst;
-        };
-        int li = 0;          // list entry of the staged batch
-        uint32_t bp = 0;     // its first padded row
-        uint32_t bn = 0;     // its rows
-        if (nlist > 0) {
-            bp = list[0].p0;
-            bn = list[0].p1 - bp < kBatchRows ? list[0].p1 - bp : kBatchRows;
-            issue(bp, bn);
-            park(0);
-        }
-        __syncthreads();
-        int buf = 0;
-        while (li < nlist) {
-            // next batch: rest of this cone, else the next listed cone
-            const uint32_t cur_p1 = list[li].p1;
-            const uint64_t mk = list[li].m[w];
-            int nli = li;
-            uint32_t np = bp + bn, nn = 0;
-            if (np >= cur_p1) {
-                nli = li + 1;
-                if (nli < nlist) np = list[nli].p0;
+        uint32_t it = 0, run = 0;  // tiles screened in the item, largest class minimum read in the window
+        for (int64_t c0 = n0; c0 < n1; c0 += kChunk) {
+            const int64_t c1 = c0 + kChunk < n1 ? c0 + kChunk : n1;
+            const int nchunk = (int)(c1 - c0);
+            // 2. the chunk's cones that some query of the tile probes, with
+            //    the mask of those queries
+            uint32_t nlist = 0;
+            auto append = [&](int64_t e, uint64_t m) {  // e: non-empty cone rank, m: its mask (this lane)
+                const bool hit = m != 0;
+                const uint64_t b = __ballot(hit);
+                if (hit) {
+                    const uint32_t cone = a.ne_cone[e];
+                    wlist[nlist + (uint32_t)__popcll(b & lanemask_lt())] =
+                        make_uint4(a.poff[cone], a.poff[cone + 1], (uint32_t)m, (uint32_t)(m >> 32));
+                }
+                nlist += (uint32_t)__popcll(b);
+            };
+            if (a.qbits) {
+                // transpose the queries' probed-cone bitmaps with ballots
+                for (int64_t k = c0 >> 6; k * 64 < c1; ++k) {
+                    const uint64_t word = own_ok ? a.qbits[(int64_t)own_q * a.nw + k] : 0ull;
+                    uint64_t col = 0;
+#pragma unroll 8
+                    for (int c = 0; c < 64; ++c) {
+                        const uint64_t m = __ballot((word >> c) & 1ull);
+                        col = c == l ? m : col;
+                    }
+                    const int64_t e = k * 64 + l;
+                    append(e, e >= c0 && e < c1 ? col : 0ull);
+                }
+            } else {
+                // one lane per query regenerates its walk; a query that probes
+                // every cone sets its bit everywhere
+                const uint32_t js = own_ok ? a.jstop[own_q] : 0u;
+                const uint64_t all = __ballot(own_ok && js == kWalkAll);
+                for (int i = l; i < nchunk; i += 64) tab[i] = all;
+                wave_sync();
+                if (own_ok && js != kWalkAll) {
+                    const uint8_t* qo = a.order + (int64_t)own_q * a.D;
+                    const uint8_t* qs = a.sbit + (int64_t)own_q * a.D;
+                    const unsigned long long bit = 1ull << l;
+                    for (uint32_t j = 0; j < js; ++j) {
+                        const uint32_t cone = probe_cone(j, a.L, qo, qs, a.n_sub, a.lexsub, a.maskord, a.binom);
+                        const int64_t e = a.ne_id[cone];
+                        if (e >= c0 && e < c1 && a.offsets[cone + 1] > a.offsets[cone])
+                            atomicOr((unsigned long long*)&tab[e - c0], bit);
+                    }
+                }
+                wave_sync();
+                for (int base = 0; base < nchunk; base += 64) {
+                    const int i = base + l;
+                    const uint64_t m = i < nchunk ? tab[i] : 0ull;
+                    append(c0 + i, m);
+                }
             }
-            if (nli < nlist) {
-                const uint32_t end = list[nli].p1;
-                nn = end - np < kBatchRows ? end - np : kBatchRows;
-                issue(np, nn);
-            }
-            // the shared class minima of slot l's query, read now and folded
-            // into the bound after the batch.  Plain loads: a cached copy may
-            // be stale, but every value ever stored there is a valid bound
-            // (the words only decrease), and cached reads keep the batch
-            // pipeline short.
-            uint32_t cmv[R];
-#pragma unroll
-            for (int k = 0; k < R; ++k) cmv[k] = a.cmin[(int64_t)own_q * R + k];
-            // screen the staged batch
-            if (mk != 0) {
-                const uint4* rb = rows + buf * kBatchRows * CPR;
-                const float* nb = nrmb + buf * kBatchRows + 4 * (l / 16);
-                float pthr[G];  // thr, or -inf for slots that do not probe this cone
+            wave_sync();
+
+            if (nlist > 0) {
+                uint32_t li = 0;
+                uint4 ent = uni4(wlist[0]);
+                uint32_t p = ent.x;
+                float pthr[G];  // thr, or -inf for slots that do not probe the current cone
                 auto set_pthr = [&]() {
+                    const uint64_t mk = ((uint64_t)ent.w << 32) | ent.z;
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
                         const bool probed = (mk >> (16 * g + (l % 16))) & 1ull;
@@ -431,41 +330,37 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                     }
                 };
                 set_pthr();
-                // software pipeline: tile r0's products are on the matrix
-                // cores while tile r0-16's d~ are formed and compared, and
-                // tile r0+16's fragments are read from LDS
-                auto frag = [&](uint32_t r0, uint4 (&av)[KS], float4& nv4) {
-#pragma unroll
-                    for (int ks = 0; ks < KS; ++ks) av[ks] = rb[aslot[ks] + r0 * CPR];
-                    nv4 = *reinterpret_cast<const float4*>(nb + r0);
-                };
-                auto products = [&](const uint4 (&av)[KS], f32x4_t (&acc)[G]) {
+                // One tile: issue the next tile's loads into the other buffer
+                // (the last tile reloads itself), screen this one.  The loop
+                // below alternates two register buffers by name, so no
+                // register with a load in flight is ever copied.
+                auto tile = [&](const uint4 (&av)[KS], const float4& nv4, uint32_t cw, uint4 (&avn)[KS], float4& nvn,
+                                uint32_t& cwn) __attribute__((always_inline)) -> bool {
+                    uint32_t pn = p + 16, lin = li;
+                    uint4 entn = ent;
+                    if (pn >= ent.y) {
+                        lin = li + 1;
+                        if (lin < nlist) {
+                            entn = uni4(wlist[lin]);
+                            pn = entn.x;
+                        }
+                    }
+                    const bool more = lin < nlist;
+                    load(more ? pn : p, avn, nvn);
+                    cwn = a.cmin[(int64_t)own_q * R + (it & (R - 1))];
+                    f32x4_t acc[G];
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
                         acc[g] = mfma16<F16IN>(av[0], bq[g][0], f32x4_t{0.0f, 0.0f, 0.0f, 0.0f});
 #pragma unroll
                         for (int ks = 1; ks < KS; ++ks) acc[g] = mfma16<F16IN>(av[ks], bq[g][ks], acc[g]);
                     }
-                };
-                uint4 av[KS];
-                float4 nv4;
-                f32x4_t acc[G];
-                frag(0, av, nv4);
-                products(av, acc);
-                float4 nv_cur = nv4;
-                for (uint32_t r0 = 0; r0 < bn; r0 += 16) {
-                    const bool more = r0 + 16 < bn;
-                    f32x4_t acc_next[G];
-                    float4 nv_next = nv_cur;
-                    if (more) {
-                        frag(r0 + 16, av, nv_next);
-                        products(av, acc_next);
-                    }
-                    const float nv[4] = {nv_cur.x, nv_cur.y, nv_cur.z, nv_cur.w};
-                    // d~ of the lane's 4 rows for each group; a NaN norm marks
-                    // a padding row and never passes
-                    // (fminf drops NaN operands, so padding rows fall out of
-                    // the minimum; a -inf threshold makes the margin +inf)
+                    // fold the class read one tile earlier; a window of R reads starts with class 0
+                    run = ((it - 1) & (R - 1)) == 0 ? cw : (cw > run ? cw : run);
+                    const float nv[4] = {nv4.x, nv4.y, nv4.z, nv4.w};
+                    // d~ of the lane's 4 rows for each group; a NaN norm marks a
+                    // padding row: fminf drops it from the minimum and it never
+                    // passes; a -inf threshold makes the margin +inf
                     float d[G][4];
                     float margin = __builtin_huge_valf();
 #pragma unroll
@@ -486,46 +381,47 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                                 if (nhit + (uint32_t)__popcll(m) > (uint32_t)kHitCap) flush();
                                 if (pass) {
                                     const uint32_t at = nhit + (uint32_t)__popcll(m & lanemask_lt());
-                                    s_hit[w][at] = make_uint4(__float_as_uint(d[g][ii]), bp + r0 + 4 * (l / 16) + ii,
+                                    s_hit[w][at] = make_uint4(__float_as_uint(d[g][ii]), p + 4 * (l / 16) + ii,
                                                               16 * g + (l % 16), 0u);
                                 }
                                 nhit += (uint32_t)__popcll(m);
                             }
                         set_pthr();
                     }
-                    if (more) {
-#pragma unroll
-                        for (int g = 0; g < G; ++g) acc[g] = acc_next[g];
-                        nv_cur = nv_next;
+                    if (!more) return false;
+                    // reads of classes 0 .. R-1 folded by now: a fresh shared bound
+                    if ((it & (R - 1)) == 0 && it > 0) {
+                        if (own_ok) ownb = run < ownb ? run : ownb;
+                        refresh_thr();
+                        set_pthr();
                     }
+                    ++it;
+                    p = pn;
+                    if (lin != li) {
+                        li = lin;
+                        ent = entn;
+                        set_pthr();
+                    }
+                    return true;
+                };
+                uint4 avA[KS], avB[KS];
+                float4 nvA, nvB;
+                uint32_t cwA = 0xFFFFFFFFu, cwB;
+                load(p, avA, nvA);
+                while (tile(avA, nvA, cwA, avB, nvB, cwB) && tile(avB, nvB, cwB, avA, nvA, cwA)) {
                 }
             }
-            if (nhit > 0) flush();
-            if (own_ok) {
-                uint32_t c = 0;
-#pragma unroll
-                for (int k = 0; k < R; ++k) c = cmv[k] > c ? cmv[k] : c;
-                ownb = c;
-            }
-            refresh_thr();
-            if (nli < nlist) park(buf ^ 1);
-            __syncthreads();
-            buf ^= 1;
-            li = nli;
-            bp = np;
-            bn = nn;
         }
+        if (nhit > 0) flush();
 
-        // 5. store the split's lists
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // 4. store the split's lists
+        wave_sync();
         if (own_ok) {
             uint2* dst = a.part + ((int64_t)own_q * a.S + s) * R;
 #pragma unroll
             for (int k = 0; k < R; ++k) dst[k] = wl[l * R + k];
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -608,10 +504,15 @@ __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
     for (int k = 0; k < R; ++k) {
         ld[k] = __builtin_huge_valf();
         lr[k] = 0xFFFFFFFFu;
-        if (qv && g < f.S) {
-            const uint2 e = f.part[(q * f.S + g) * R + k];
-            ld[k] = __uint_as_float(e.x);
-            lr[k] = e.y;
+    }
+    // lane g takes the split lists g, g + G, ... into its own list
+    for (int sp = g; qv && sp < f.S; sp += G) {
+        const uint2* src = f.part + (q * f.S + sp) * R;
+        for (int k = 0; k < R; ++k) {
+            const uint2 e = src[k];
+            const float d = __uint_as_float(e.x);
+            if (!pair_less(d, e.y, ld[R - 1], lr[R - 1])) break;  // the list is sorted
+            list_insert<R>(ld, lr, d, e.y);
         }
     }
 #pragma unroll
@@ -657,18 +558,13 @@ static hipError_t screen_ks(const TiledArgs& a, int ks, dim3 grid, size_t lds, h
     return hipGetLastError();
 }
 
-// Dynamic LDS of the screen kernel: marked-cone list (48 B per cone), then
-// the larger of the cone table (32 B per cone) and the two staged row
-// batches with their norms.
-size_t tiled_screen_lds(int64_t span, int dk) {
-    const size_t sp = (size_t)(span > 0 ? span : 1);
-    const size_t batches = (size_t)2 * kBatchRows * dk * 2 + 2 * kBatchRows * 4;
-    return sp * 48 + (sp * 32 > batches ? sp * 32 : batches);
-}
+// Dynamic LDS of the screen kernel: per wave, the marked-cone list of one
+// chunk of cones (16 B per cone).
+size_t tiled_screen_lds() { return (size_t)4 * kChunk * 16; }
 
 hipError_t launch_tiled_screen(const TiledArgs& a, int R, int f16in, int blocks, hipStream_t s) {
     const int ks = a.dk / 32;
-    const size_t lds = tiled_screen_lds(a.span, a.dk);
+    const size_t lds = tiled_screen_lds();
     const dim3 grid((unsigned)blocks);
     if (f16in) {
         if (R == 4) return screen_ks<true, 4>(a, ks, grid, lds, s);
@@ -684,7 +580,7 @@ hipError_t launch_tiled_screen(const TiledArgs& a, int R, int f16in, int blocks,
 
 template <typename E, int R>
 static hipError_t finish_g(const FinishArgs& f, hipStream_t s) {
-    const int G = f.S > R ? f.S : R;
+    const int G = f.S > R ? (f.S < 16 ? f.S : 16) : R;
     const int64_t threads = f.Q * G;
     const dim3 grid((unsigned)((threads + 255) / 256));
     switch (G) {
@@ -723,7 +619,7 @@ hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s) {
 
 size_t tiled_screen_static_lds(int R) {
     const size_t qw = 16 * (size_t)tile_groups(R);
-    return 4 * qw * R * 8 + 4 * (size_t)kHitCap * 16 + 2 * 4 * kMaxD + 512;
+    return 4 * qw * R * 8 + 4 * (size_t)kHitCap * 16 + 512;
 }
 
 // Lets every screen kernel take all the LDS its static arrays leave free.
