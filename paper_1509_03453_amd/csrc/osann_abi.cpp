@@ -521,6 +521,7 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     sd.dk = ix->lp.dk;
     sd.ql = pa.ql;
     sd.q_cone = pa.q_cone;
+    sd.qorder = qorder;
     sd.Q = c.Q;
     sd.cmin = cmin;
     e = launch_tiled_seed(sd, p.R, ix->lp.f16, c.s);

@@ -50,7 +50,7 @@ struct TiledArgs {
     uint32_t* counter;      // [kXcd] work-queue heads, zero before the launch
     // output
     uint2* part;            // [Q][S][R] (FP32 bits of d~, padded position)
-    uint32_t* cmin;         // [Q][R] smallest order-preserving d~ bits kept per class
+    uint32_t* cmin;         // [R][Q] by tile slot: smallest order-preserving d~ bits kept per class
                             // (padded position mod R), 0xFFFFFFFF before the launch
 };
 
@@ -63,8 +63,9 @@ struct SeedArgs {
     int dk;
     const uint16_t* ql;      // [Q][dk]
     const uint32_t* q_cone;  // [Q] own cone
+    const uint32_t* qorder;  // tile slot -> query
     int64_t Q;
-    uint32_t* cmin;          // [Q][2R]
+    uint32_t* cmin;          // [R][Q] by tile slot, as in the screen
 };
 
 struct FinishArgs {

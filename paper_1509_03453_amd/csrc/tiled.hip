@@ -176,6 +176,7 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
         const int64_t slot0 = t * QW;  // first query slot of the wave tile
         const bool own_ok = l < QW && slot0 + l < a.Q;
         const uint32_t own_q = own_ok ? a.qorder[slot0 + l] : 0u;
+        const int64_t own_slot = own_ok ? slot0 + l : 0;  // class minima are stored by tile slot
 
         // 1. B operands: group g = query slots 16g .. 16g+15 of the tile;
         //    lane l works on slot 16g + l%16 of every group
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
         if (own_ok)
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const uint32_t v = __hip_atomic_load(a.cmin + (int64_t)own_q * R + k, __ATOMIC_RELAXED,
+                const uint32_t v = __hip_atomic_load(a.cmin + (int64_t)k * a.Q + own_slot, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
                 ownb = k == 0 || v > ownb ? v : ownb;
             }
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                 if (e.z == (uint32_t)l && pair_less(d, e.y, ld[R - 1], lr[R - 1])) {
                     list_insert<R>(ld, lr, d, e.y);
                     changed = true;
-                    __hip_atomic_fetch_min(a.cmin + (int64_t)own_q * R + (e.y & (R - 1)), ord_bits(d),
+                    __hip_atomic_fetch_min(a.cmin + (int64_t)(e.y & (R - 1)) * a.Q + own_slot, ord_bits(d),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                     }
                     const bool more = lin < nlist;
                     load(more ? pn : p, avn, nvn);
-                    cwn = a.cmin[(int64_t)own_q * R + (it & (R - 1))];
+                    cwn = a.cmin[(int64_t)(it & (R - 1)) * a.Q + own_slot];
                     f32x4_t acc[G];
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
@@ -440,9 +441,10 @@ constexpr int kSeedRows = 256;
 template <bool F16IN, int R>
 __global__ __launch_bounds__(256) void tiled_seed_kernel(SeedArgs a) {
 #pragma clang fp contract(off)
-    const int64_t q = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const int64_t slot = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
     const int l = lane_id();
-    if (q >= a.Q) return;
+    if (slot >= a.Q) return;
+    const int64_t q = a.qorder[slot];
     const uint32_t c = a.q_cone[q];
     const uint32_t p0 = a.poff[c], p1 = a.poff[c + 1];
     const uint32_t pend = p1 - p0 > (uint32_t)kSeedRows ? p0 + kSeedRows : p1;
@@ -470,7 +472,7 @@ __global__ __launch_bounds__(256) void tiled_seed_kernel(SeedArgs a) {
         }
         const float d = n - 2.0f * dot;
         const float tol = gamma * (n + 2.0f * sabs);
-        __hip_atomic_fetch_min(a.cmin + q * R + (p & (R - 1)), ord_bits(d + tol), __ATOMIC_RELAXED,
+        __hip_atomic_fetch_min(a.cmin + (int64_t)(p & (R - 1)) * a.Q + slot, ord_bits(d + tol), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
 }
