@@ -139,6 +139,7 @@ constexpr int kHitCap = 64;   // hit buffer entries per wave (one full ballot)
 template <bool F16IN, int KS, int R, int G>
 __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
     constexpr int QW = 16 * G;              // queries per wave tile
+    constexpr int U = KS <= 2 ? 2 : 1;      // row tiles per load group
     extern __shared__ uint64_t dyn[];
     __shared__ uint2 s_list[4][QW * R];     // per wave: top-R list of each query slot
     __shared__ uint4 s_hit[4][kHitCap];     // per wave: (d~ bits, padded position, slot) hits
@@ -318,78 +319,111 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
             wave_sync();
 
             if (nlist > 0) {
-                uint32_t li = 0;
-                uint4 ent = uni4(wlist[0]);
-                uint32_t p = ent.x;
-                float pthr[G];  // thr, or -inf for slots that do not probe the current cone
+                // load cursor: the next tile to load (lli == nlist: past the end)
+                uint32_t lli = 0;
+                uint4 lent = uni4(wlist[0]);
+                uint32_t lp = lent.x;
+                const uint32_t p_any = lp;  // a valid tile, reloaded by a cursor past the end
+                auto advance = [&]() {
+                    if (lli >= nlist) return;
+                    lp += 16;
+                    if (lp >= lent.y) {
+                        ++lli;
+                        if (lli < nlist) {
+                            lent = uni4(wlist[lli]);
+                            lp = lent.x;
+                        }
+                    }
+                };
+                // a group: up to U consecutive tiles of the list, with their
+                // padded positions and probe masks; n valid (a prefix)
+                struct Group {
+                    uint32_t pos[U], mlo[U], mhi[U];
+                    uint32_t n;
+                };
+                auto fill = [&](Group& gr, uint4 (&av)[U][KS], float4 (&nv)[U]) __attribute__((always_inline)) {
+                    gr.n = 0;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const bool v = lli < nlist;
+                        gr.pos[u] = v ? lp : p_any;
+                        gr.mlo[u] = lent.z;
+                        gr.mhi[u] = lent.w;
+                        gr.n += v ? 1u : 0u;
+                        load(gr.pos[u], av[u], nv[u]);
+                        advance();
+                    }
+                };
+                float pthr[G];  // thr, or -inf for slots that do not probe the tile's cone
+                uint32_t cmlo = 0, cmhi = 0;  // the probe mask pthr was set for
                 auto set_pthr = [&]() {
-                    const uint64_t mk = ((uint64_t)ent.w << 32) | ent.z;
+                    const uint64_t mk = ((uint64_t)cmhi << 32) | cmlo;
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
                         const bool probed = (mk >> (16 * g + (l % 16))) & 1ull;
                         pthr[g] = probed ? thr[g] : -__builtin_huge_valf();
                     }
                 };
-                set_pthr();
-                // One tile: issue the next tile's loads into the other buffer
-                // (the last tile reloads itself), screen this one.  The loop
-                // below alternates two register buffers by name, so no
-                // register with a load in flight is ever copied.
-                auto tile = [&](const uint4 (&av)[KS], const float4& nv4, uint32_t cw, uint4 (&avn)[KS], float4& nvn,
-                                uint32_t& cwn) __attribute__((always_inline)) -> bool {
-                    uint32_t pn = p + 16, lin = li;
-                    uint4 entn = ent;
-                    if (pn >= ent.y) {
-                        lin = li + 1;
-                        if (lin < nlist) {
-                            entn = uni4(wlist[lin]);
-                            pn = entn.x;
+                // One group step: issue the next group's loads into the other
+                // buffer (and one word of the class minima), then screen this
+                // group.  The loop below alternates two register buffers by
+                // name, so no register with a load in flight is ever copied,
+                // and U tiles share each wait for memory.
+                auto group = [&](const Group& gr, const uint4 (&av)[U][KS], const float4 (&nv)[U], uint32_t cw,
+                                 Group& grn, uint4 (&avn)[U][KS], float4 (&nvn)[U],
+                                 uint32_t& cwn) __attribute__((always_inline)) -> bool {
+                    fill(grn, avn, nvn);
+                    cwn = a.cmin[(int64_t)(it & (R - 1)) * a.Q + own_slot];
+                    // fold the class read one group earlier; a window of R reads starts with class 0
+                    run = ((it - 1) & (R - 1)) == 0 ? cw : (cw > run ? cw : run);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if ((uint32_t)u >= gr.n) break;
+                        const uint32_t p = gr.pos[u];
+                        if (gr.mlo[u] != cmlo || gr.mhi[u] != cmhi) {
+                            cmlo = gr.mlo[u];
+                            cmhi = gr.mhi[u];
+                            set_pthr();
+                        }
+                        f32x4_t acc[G];
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            acc[g] = mfma16<F16IN>(av[u][0], bq[g][0], f32x4_t{0.0f, 0.0f, 0.0f, 0.0f});
+#pragma unroll
+                            for (int ks = 1; ks < KS; ++ks) acc[g] = mfma16<F16IN>(av[u][ks], bq[g][ks], acc[g]);
+                        }
+                        const float nvv[4] = {nv[u].x, nv[u].y, nv[u].z, nv[u].w};
+                        // d~ of the lane's 4 rows for each group; a NaN norm marks a
+                        // padding row: fminf drops it from the minimum and it never
+                        // passes; a -inf threshold makes the margin +inf
+                        float d[G][4];
+                        float margin = __builtin_huge_valf();
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+#pragma unroll
+                            for (int ii = 0; ii < 4; ++ii) d[g][ii] = nvv[ii] - 2.0f * acc[g][ii];
+                            const float m4 = fminf(fminf(d[g][0], d[g][1]), fminf(d[g][2], d[g][3]));
+                            margin = fminf(margin, m4 - pthr[g]);
+                        }
+                        if (__ballot(margin <= 0.0f) != 0) {  // rare once the bounds have settled
+#pragma unroll
+                            for (int g = 0; g < G; ++g)
+#pragma unroll
+                                for (int ii = 0; ii < 4; ++ii) {
+                                    const bool pass = d[g][ii] <= pthr[g];
+                                    const uint64_t m = __ballot(pass);
+                                    if (m == 0) continue;
+                                    if (nhit + (uint32_t)__popcll(m) > (uint32_t)kHitCap) flush();
+                                    if (pass) {
+                                        const uint32_t at = nhit + (uint32_t)__popcll(m & lanemask_lt());
+                                        s_hit[w][at] = make_uint4(__float_as_uint(d[g][ii]), p + 4 * (l / 16) + ii,
+                                                                  16 * g + (l % 16), 0u);
+                                    }
+                                    nhit += (uint32_t)__popcll(m);
+                                }
+                            set_pthr();
                         }
                     }
-                    const bool more = lin < nlist;
-                    load(more ? pn : p, avn, nvn);
-                    cwn = a.cmin[(int64_t)(it & (R - 1)) * a.Q + own_slot];
-                    f32x4_t acc[G];
-#pragma unroll
-                    for (int g = 0; g < G; ++g) {
-                        acc[g] = mfma16<F16IN>(av[0], bq[g][0], f32x4_t{0.0f, 0.0f, 0.0f, 0.0f});
-#pragma unroll
-                        for (int ks = 1; ks < KS; ++ks) acc[g] = mfma16<F16IN>(av[ks], bq[g][ks], acc[g]);
-                    }
-                    // fold the class read one tile earlier; a window of R reads starts with class 0
-                    run = ((it - 1) & (R - 1)) == 0 ? cw : (cw > run ? cw : run);
-                    const float nv[4] = {nv4.x, nv4.y, nv4.z, nv4.w};
-                    // d~ of the lane's 4 rows for each group; a NaN norm marks a
-                    // padding row: fminf drops it from the minimum and it never
-                    // passes; a -inf threshold makes the margin +inf
-                    float d[G][4];
-                    float margin = __builtin_huge_valf();
-#pragma unroll
-                    for (int g = 0; g < G; ++g) {
-#pragma unroll
-                        for (int ii = 0; ii < 4; ++ii) d[g][ii] = nv[ii] - 2.0f * acc[g][ii];
-                        const float m4 = fminf(fminf(d[g][0], d[g][1]), fminf(d[g][2], d[g][3]));
-                        margin = fminf(margin, m4 - pthr[g]);
-                    }
-                    if (__ballot(margin <= 0.0f) != 0) {  // rare once the bounds have settled
-#pragma unroll
-                        for (int g = 0; g < G; ++g)
-#pragma unroll
-                            for (int ii = 0; ii < 4; ++ii) {
-                                const bool pass = d[g][ii] <= pthr[g];
-                                const uint64_t m = __ballot(pass);
-                                if (m == 0) continue;
-                                if (nhit + (uint32_t)__popcll(m) > (uint32_t)kHitCap) flush();
-                                if (pass) {
-                                    const uint32_t at = nhit + (uint32_t)__popcll(m & lanemask_lt());
-                                    s_hit[w][at] = make_uint4(__float_as_uint(d[g][ii]), p + 4 * (l / 16) + ii,
-                                                              16 * g + (l % 16), 0u);
-                                }
-                                nhit += (uint32_t)__popcll(m);
-                            }
-                        set_pthr();
-                    }
-                    if (!more) return false;
                     // reads of classes 0 .. R-1 folded by now: a fresh shared bound
                     if ((it & (R - 1)) == 0 && it > 0) {
                         if (own_ok) ownb = run < ownb ? run : ownb;
@@ -397,19 +431,17 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                         set_pthr();
                     }
                     ++it;
-                    p = pn;
-                    if (lin != li) {
-                        li = lin;
-                        ent = entn;
-                        set_pthr();
-                    }
-                    return true;
+                    return grn.n > 0;
                 };
-                uint4 avA[KS], avB[KS];
-                float4 nvA, nvB;
+                Group gA, gB;
+                uint4 avA[U][KS], avB[U][KS];
+                float4 nvA[U], nvB[U];
                 uint32_t cwA = 0xFFFFFFFFu, cwB;
-                load(p, avA, nvA);
-                while (tile(avA, nvA, cwA, avB, nvB, cwB) && tile(avB, nvB, cwB, avA, nvA, cwA)) {
+                fill(gA, avA, nvA);
+                cmlo = gA.mlo[0];
+                cmhi = gA.mhi[0];
+                set_pthr();
+                while (group(gA, avA, nvA, cwA, gB, avB, nvB, cwB) && group(gB, avB, nvB, cwB, gA, avA, nvA, cwA)) {
                 }
             }
         }
