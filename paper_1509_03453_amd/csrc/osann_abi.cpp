@@ -524,6 +524,10 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     sd.qorder = qorder;
     sd.Q = c.Q;
     sd.cmin = cmin;
+    // The seed reads up to sd.rows rows of each query's own cone; keep that
+    // near a sixteenth of the budget (16 .. 256 rows), a small share of what
+    // the screen then reads per query.
+    sd.rows = (int)std::min<int64_t>(256, std::max<int64_t>(16, pow2_ceil(std::max<int64_t>(c.budget / 16, 1))));
     e = launch_tiled_seed(sd, p.R, ix->lp.f16, c.s);
     if (e != hipSuccess) return e;
     TiledArgs ta{};

@@ -66,6 +66,7 @@ struct SeedArgs {
     const uint32_t* qorder;  // tile slot -> query
     int64_t Q;
     uint32_t* cmin;          // [R][Q] by tile slot, as in the screen
+    int rows;                // rows of the own cone seeded per query (at most)
 };
 
 struct FinishArgs {

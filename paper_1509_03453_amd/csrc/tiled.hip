@@ -460,7 +460,7 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
 
 // Seeds the shared class minima before the screen, so that no split starts
 // without a bound.  One wave per query; each lane takes one row of the
-// query's own cone (the first kSeedRows rows at most), computes d~ on the
+// query's own cone (the first a.rows rows at most), computes d~ on the
 // vector units and raises it by a bound on the difference to any FP32
 // accumulation of the same products (the matrix cores add them in another
 // order): each of the two sums is off by at most dk*u*S with S the sum of
@@ -468,7 +468,6 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
 // (4dk + 8)*u*(n + 2S) covers both (u = 2^-24), with a margin.  The raised
 // value is at least the screen's d~ of a real candidate of its class, so the
 // largest-class-minimum rule stays a valid bound.
-constexpr int kSeedRows = 256;
 
 template <bool F16IN, int R>
 __global__ __launch_bounds__(256) void tiled_seed_kernel(SeedArgs a) {
@@ -479,7 +478,7 @@ __global__ __launch_bounds__(256) void tiled_seed_kernel(SeedArgs a) {
     const int64_t q = a.qorder[slot];
     const uint32_t c = a.q_cone[q];
     const uint32_t p0 = a.poff[c], p1 = a.poff[c + 1];
-    const uint32_t pend = p1 - p0 > (uint32_t)kSeedRows ? p0 + kSeedRows : p1;
+    const uint32_t pend = p1 - p0 > (uint32_t)a.rows ? p0 + (uint32_t)a.rows : p1;
     const float gamma = (float)(4 * a.dk + 8) * 5.9604645e-08f * 1.01f;
     for (uint32_t p = p0 + l; p < pend; p += 64) {
         const float n = a.nrm[p];
