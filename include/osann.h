@@ -231,8 +231,16 @@ int os_ann_kernel_time(const os_ann_index *idx, int32_t kernel, int64_t *launche
 int os_ann_info(const os_ann_index *idx, int64_t *N, int32_t *D, int32_t *L,
                 int64_t *n_cones, int64_t *n_nonempty, int64_t *device_bytes);
 
-/* Release the index.  The caller makes sure no search on it is in flight. */
+/* Release the index.  The caller makes sure no search on it is in flight.
+ * Waits for the device to finish its work (as hipFree does); the index's
+ * device blocks then stay with the library, idle, for later builds and
+ * searches of the same sizes (at most 8 GiB of idle blocks in all). */
 void os_ann_free(os_ann_index *idx);
+
+/* Return every idle device block kept by the library to the HIP runtime
+ * (for a caller that needs the memory elsewhere).  Blocks of live indexes
+ * are not touched.  Never fails: returns OS_ANN_OK. */
+int os_ann_trim(void);
 
 /* Last error code / message of the calling thread (OS_ANN_OK / "" if none). */
 int os_ann_last_error(void);

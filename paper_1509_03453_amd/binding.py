@@ -64,6 +64,7 @@ SIGNATURES = {
     "os_ann_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                               C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "os_ann_free": (None, [C.c_void_p]),
+    "os_ann_trim": (C.c_int, []),
     "os_ann_last_error": (C.c_int, []),
     "os_ann_last_error_message": (C.c_char_p, []),
     "os_ann_version": (C.c_char_p, []),
@@ -280,6 +281,11 @@ def os_ann_export_rows(index: int, stream=None) -> torch.Tensor:
 def os_ann_free(index: int) -> None:
     if index:
         lib().os_ann_free(index)
+
+
+def os_ann_trim() -> None:
+    """Hand the library's idle device blocks back to the HIP runtime."""
+    lib().os_ann_trim()
 
 
 def os_ann_last_error() -> int:

@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "osann_kernels.h"
@@ -119,10 +120,87 @@ namespace {
 // ---------------------------------------------------------------------------
 // memory
 // ---------------------------------------------------------------------------
+// Freed device blocks are kept per (device, rounded size) and handed out
+// again, so that indexes and scratch built and released over and over do
+// not pay hipMalloc / hipFree (which waits for the whole device) each time.
+// A block enters the cache only once the device has finished with it: every
+// caller of dev_free has synchronized first, as hipFree itself would.
+struct BlockCache {
+    std::mutex mu;
+    std::multimap<std::pair<int, size_t>, void*> idle;             // (device, size) -> block
+    std::unordered_map<void*, std::pair<int, size_t>> owned;        // block -> (device, size)
+    size_t idle_bytes = 0;
+};
+BlockCache& block_cache() {
+    static BlockCache* c = new BlockCache;  // never destroyed: blocks live until the process ends
+    return *c;
+}
+constexpr size_t kIdleMax = size_t(8) << 30;  // idle bytes kept at most (all devices)
+
+size_t block_size(size_t bytes) { return bytes > (size_t(1) << 20) ? align_up(bytes, size_t(2) << 20) : align_up(bytes, 256); }
+
+// Returns the idle blocks of every device to the runtime.
+void trim_blocks() {
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    for (auto& kv : c.idle) (void)hipFree(kv.second);
+    c.idle.clear();
+    c.idle_bytes = 0;
+}
+
+hipError_t cached_malloc(void** p, size_t bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const size_t sz = block_size(bytes);
+    BlockCache& c = block_cache();
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        auto it = c.idle.find({dev, sz});
+        if (it != c.idle.end()) {
+            *p = it->second;
+            c.idle.erase(it);
+            c.idle_bytes -= sz;
+            c.owned[*p] = {dev, sz};
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(p, sz);
+    if (e == hipErrorOutOfMemory) {  // idle blocks of other sizes may be what is missing
+        (void)hipGetLastError();
+        trim_blocks();
+        e = hipMalloc(p, sz);
+    }
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(c.mu);
+    c.owned[*p] = {dev, sz};
+    return hipSuccess;
+}
+
+// The caller has synchronized the device (no kernel still uses p).
+void dev_free(void* p) {
+    if (!p) return;
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.owned.find(p);
+    if (it == c.owned.end()) {
+        (void)hipFree(p);
+        return;
+    }
+    const auto key = it->second;
+    c.owned.erase(it);
+    if (c.idle_bytes + key.second <= kIdleMax) {
+        c.idle.emplace(key, p);
+        c.idle_bytes += key.second;
+    } else {
+        (void)hipFree(p);
+    }
+}
+
 int dev_alloc(os_ann_index* ix, void** p, size_t bytes, const char* what) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = cached_malloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
@@ -140,21 +218,21 @@ void drop_graphs(os_ann_index* ix) {
     ix->graphs.clear();
 }
 
-void release(os_ann_index* ix) {
+void release(os_ann_index* ix, bool synced = false) {
     if (!ix) return;
+    if (!synced) (void)hipDeviceSynchronize();  // the blocks go back to the cache idle
     for (auto& t : ix->timed) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
     }
     drop_graphs(ix);
-    for (auto* t : ix->sub) release(t);
+    for (auto* t : ix->sub) release(t, true);
     void* ptrs[] = {ix->row_cone, ix->row_top,  ix->perm,       ix->sorted_cone, ix->offsets,
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
                     ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
                     ix->planes_tab};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    for (void* p : ptrs) dev_free(p);
     delete ix;
 }
 
@@ -187,7 +265,8 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
     if (!rc) rc = dev_alloc(nullptr, (void**)&tmp, (size_t)(2 * nc + scan_words) * 4, "lowp scratch");
     if (rc) return rc;
     auto done = [&](int code) {
-        if (tmp) (void)hipFree(tmp);
+        if (code != OS_ANN_OK) (void)hipDeviceSynchronize();
+        dev_free(tmp);
         return code;
     };
     hipError_t e = launch_lowp_layout(ix->offsets, nc, tmp, tmp + nc, tmp + 2 * nc, lp.poff, lp.ne_id,
@@ -325,7 +404,7 @@ int get_scratch(os_ann_index* ix, const os_ann_search_opts* o, size_t bytes, cha
     if (ix->scratch_bytes < bytes) {
         if (ix->scratch) {
             OSANN_HIP(hipDeviceSynchronize(), "scratch resize");
-            (void)hipFree(ix->scratch);
+            dev_free(ix->scratch);
             ix->device_bytes -= ix->scratch_bytes;
             ix->scratch = nullptr;
             ix->scratch_bytes = 0;
@@ -785,8 +864,9 @@ os_ann_index* build_table(const void* keys, int32_t key_dtype, const void* db, i
     uint32_t* tmp = nullptr;
     uint32_t* small = nullptr;  // [0] non-finite flag, [1] non-empty count
     auto bail = [&](int) -> os_ann_index* {
-        if (tmp) (void)hipFree(tmp);
-        if (small) (void)hipFree(small);
+        (void)hipDeviceSynchronize();
+        dev_free(tmp);
+        dev_free(small);
         release(ix);
         return nullptr;
     };
@@ -829,8 +909,8 @@ os_ann_index* build_table(const void* keys, int32_t key_dtype, const void* db, i
         return bail(0);
     }
     ix->n_nonempty = host_small[1];
-    (void)hipFree(tmp);
-    (void)hipFree(small);
+    dev_free(tmp);
+    dev_free(small);
     tmp = small = nullptr;
     return ix;
 }
@@ -896,7 +976,8 @@ os_ann_index* os_ann_build_rot(const void* db, int64_t N, int32_t D, int32_t L, 
     (void)hipGetDevice(&ix->device);
     float* coords = nullptr;
     auto bail = [&]() -> os_ann_index* {
-        if (coords) (void)hipFree(coords);
+        (void)hipDeviceSynchronize();
+        dev_free(coords);
         release(ix);
         return nullptr;
     };
@@ -935,7 +1016,7 @@ os_ann_index* os_ann_build_rot(const void* db, int64_t N, int32_t D, int32_t L, 
         hip_fail(e, "several-bases build");
         return bail();
     }
-    (void)hipFree(coords);
+    dev_free(coords);
     ix->n_nonempty = ix->sub[0]->n_nonempty;
     return ix;
 }
@@ -959,6 +1040,12 @@ os_ann_index* os_ann_build(const float* db, int64_t N, int32_t D, int32_t L) {
 }
 
 void os_ann_free(os_ann_index* idx) { release(idx); }
+
+int os_ann_trim(void) {
+    clear_error();
+    trim_blocks();
+    return OS_ANN_OK;
+}
 
 int64_t os_ann_workspace_bytes(const os_ann_index* idx, int64_t Q, int64_t max_candidates,
                                const os_ann_search_opts* opts) {
