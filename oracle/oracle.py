@@ -78,6 +78,11 @@ def lib():
             L.orc_search_rot.restype = i32
             L.orc_search_rot.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, p, i32, i64, i64,
                                          p, p, p, p, i32]
+            L.orc_search_keyed.restype = i32
+            L.orc_search_keyed.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, i32, p, i64, i64,
+                                           p, p, p, p, i32]
+            L.orc_project.restype = i32
+            L.orc_project.argtypes = [p, i32, i64, i32, p, p, i32, p]
             _lib = L
     return _lib
 
@@ -317,4 +322,85 @@ def search_rot(X, index, Y, B: int, nthreads: int = 0):
                               int(nthreads))
     if rc != 0:
         raise RuntimeError(f"orc_search_rot failed ({rc})")
+    return idx, d32, d64, nca
+
+
+# ---------------------------------------------------------------------------
+# PCA front-end (Section 4.B; reading R11)
+# ---------------------------------------------------------------------------
+
+def pca_basis(X, k: int):
+    """Principal axes of the rows: the float64 mean and covariance (sum of the
+    centred outer products divided by N), their eigen-decomposition
+    (``numpy.linalg.eigh``), the k axes of largest variance in decreasing
+    order, each signed so that its largest-magnitude component (lowest index
+    on ties) is positive.  Returns ``(mu, P, lam)``: FP32 mean (K), FP32 axes
+    (k x K, one per row) and their float64 variances."""
+    Xd = np.asarray(X).astype(np.float64)
+    N, K = Xd.shape
+    if not 1 <= k <= K:
+        raise ValueError("k must be in [1, K]")
+    mu = Xd.mean(axis=0)
+    Xc = Xd - mu
+    cov = Xc.T @ Xc / N
+    lam, V = np.linalg.eigh(cov)
+    pick = np.argsort(-lam, kind="stable")[:k]
+    P = V[:, pick].T.copy()
+    for i in range(k):
+        j = int(np.argmax(np.abs(P[i])))
+        if P[i, j] < 0:
+            P[i] = -P[i]
+    return mu.astype(np.float32), P.astype(np.float32), lam[pick]
+
+
+def project(X, mu, P):
+    """Keys P (x - mu) of the rows of ``X`` in FP32 term by term (reading R11);
+    ``mu`` may be None (no centring)."""
+    X, px, dt = _rows(X)
+    N, K = X.shape
+    P, pp = _arr(P, np.float32)
+    k = P.shape[0]
+    if P.shape[1] != K:
+        raise ValueError("P must be k x K")
+    if mu is None:
+        pm = None
+    else:
+        mu, pm = _arr(mu, np.float32)
+    out = np.empty((N, k), dtype=np.float32)
+    rc = lib().orc_project(px, dt, N, K, pm, pp, k, out.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise ValueError(f"orc_project failed ({rc})")
+    return out
+
+
+def build_index_proj(X, G: int, mu, P):
+    """One table built from the rows' keys P (x - mu); distances stay on the rows."""
+    idx = build_index(project(X, mu, P), G)
+    idx["mu"] = None if mu is None else np.ascontiguousarray(mu, dtype=np.float32)
+    idx["P"] = np.ascontiguousarray(P, dtype=np.float32)
+    return idx
+
+
+def search_proj(X, index, Y, B: int, nthreads: int = 0):
+    """Algorithm 1 on a keyed table: each query walks the cones of its own key,
+    candidates are compared on all components.  ``(idx, d32, d64, ncand)``."""
+    Yk = project(Y, index["mu"], index["P"])
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    N, K = X.shape
+    Q = Y.shape[0]
+    Kk = Yk.shape[1]
+    off, po = _arr(index["offsets"], np.int64)
+    perm, pp = _arr(index["perm"], np.int64)
+    idx = np.empty(Q, dtype=np.int64)
+    d32 = np.empty(Q, dtype=np.float32)
+    d64 = np.empty(Q, dtype=np.float64)
+    nca = np.empty(Q, dtype=np.int64)
+    rc = lib().orc_search_keyed(px, xdt, N, K, Kk, index["G"], po, pp, py, ydt,
+                                Yk.ctypes.data_as(C.c_void_p), Q, int(B),
+                                idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
+                                d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
+                                int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_search_keyed failed ({rc})")
     return idx, d32, d64, nca

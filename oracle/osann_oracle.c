@@ -35,6 +35,12 @@
  *   R10 several bases: the l-th cone of every basis (empty cones included)
  *       forms level l; the budget counts the rows of visited cones, rows seen
  *       again in another basis included; ncand counts distinct rows.
+ *   R11 PCA front-end (Section 4.B): the key of a vector is P (x - mu), the
+ *       first k principal coordinates of the centred vector, in FP32 term by
+ *       term (the difference, each product and each sum rounded, ascending
+ *       j); cones come from the keys, distances from the full original
+ *       vectors (the paper computes them over all components of the rotated
+ *       vectors, which is the same distance).
  *
  * Precision: distances are produced both in double (the definition, eq. (1))
  * and in FP32 evaluated term by term in ascending component order with each
@@ -377,26 +383,35 @@ static void set_threads(int nthreads)
 #endif
 }
 
-/* Approximate NN search with one basis (Algorithm 1 with R = 1): the query's
- * cones are probed in order until B candidates are reached, and every row
- * of those cones is compared with the query.  Outputs per query: the row
- * (out_idx), its FP32 and double distances, and the number of candidates. */
-int orc_search(const void *X, int xdtype, int64_t N, int K, int G,
-               const int64_t *offsets, const int64_t *perm,
-               const void *Y, int ydtype, int64_t Q, int64_t B,
-               int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
-               int nthreads)
+/* Approximate NN search with one basis (Algorithm 1 with R = 1), with the
+ * cones taken from keys (reading R11): the table was built from the rows'
+ * keys of length Kk; each query walks the cones of its key (row q of Yk, or
+ * the query itself when Yk is NULL, Kk = K), its probes are visited in order
+ * until B candidates are reached, and every row of those cones is compared
+ * with the query on all K components.  Outputs per query: the row (out_idx),
+ * its FP32 and double distances, and the number of candidates. */
+int orc_search_keyed(const void *X, int xdtype, int64_t N, int K, int Kk, int G,
+                     const int64_t *offsets, const int64_t *perm,
+                     const void *Y, int ydtype, const float *Yk, int64_t Q, int64_t B,
+                     int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
+                     int nthreads)
 {
     (void)N;
-    if (K < 1 || K > 256 || G < 1 || G > K || B < 1)
+    if (K < 1 || K > 256 || Kk < 1 || Kk > 256 || G < 1 || G > Kk || B < 1)
         return -1;
-    int64_t NC = orc_num_cones(K, G);
+    if (!Yk && Kk != K)
+        return -1;
+    int64_t NC = orc_num_cones(Kk, G);
     set_threads(nthreads);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t q = 0; q < Q; q++) {
-        float y[256], x[256];
+        float y[256], yk[256], x[256];
         load_row(Y, ydtype, q, K, y);
+        if (Yk)
+            memcpy(yk, Yk + q * Kk, sizeof(float) * (size_t)Kk);
+        else
+            memcpy(yk, y, sizeof(float) * (size_t)K);
         int64_t *probes = (int64_t *)malloc(sizeof(int64_t) * (size_t)NC);
         if (!probes) {
 #pragma omp atomic write
@@ -404,7 +419,7 @@ int orc_search(const void *X, int xdtype, int64_t N, int K, int G,
             continue;
         }
         int64_t ncand = 0;
-        int64_t np = orc_probe(y, K, G, offsets, B, probes, NC, &ncand);
+        int64_t np = orc_probe(yk, Kk, G, offsets, B, probes, NC, &ncand);
         float best_d = INFINITY;
         int64_t best_row = INT64_MAX;
         double best_d64 = INFINITY;
@@ -429,6 +444,19 @@ int orc_search(const void *X, int xdtype, int64_t N, int K, int G,
         free(probes);
     }
     return bad ? -2 : 0;
+}
+
+/* Approximate NN search with one basis (Algorithm 1 with R = 1): the query's
+ * cones are probed in order until B candidates are reached, and every row
+ * of those cones is compared with the query. */
+int orc_search(const void *X, int xdtype, int64_t N, int K, int G,
+               const int64_t *offsets, const int64_t *perm,
+               const void *Y, int ydtype, int64_t Q, int64_t B,
+               int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
+               int nthreads)
+{
+    return orc_search_keyed(X, xdtype, N, K, K, G, offsets, perm, Y, ydtype, NULL, Q, B,
+                            out_idx, out_d32, out_d64, out_ncand, nthreads);
 }
 
 /* Exact NN by linear search over all rows (eq. (1)).  idx32/d32 take the
@@ -762,4 +790,32 @@ int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, co
         free(analyzed);
     }
     return bad ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PCA front-end (Section 4.B)                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Keys in a reduced basis (reading R11): out[n][i] = sum_j P[i][j] (x[n][j] -
+ * mu[j]) for i < k, with P a k x K row-major matrix and mu of length K (NULL:
+ * no centring), in FP32 with ascending j and the difference, each product
+ * and each sum rounded separately. */
+int orc_project(const void *X, int dtype, int64_t N, int K, const float *mu, const float *P, int k, float *out)
+{
+    if (K < 1 || K > 256 || k < 1 || k > 256)
+        return -1;
+    for (int64_t n = 0; n < N; n++) {
+        float x[256];
+        load_row(X, dtype, n, K, x);
+        for (int i = 0; i < k; i++) {
+            float acc = 0.0f;
+            for (int j = 0; j < K; j++) {
+                float c = mu ? x[j] - mu[j] : x[j];
+                float pr = P[(int64_t)i * K + j] * c;
+                acc = acc + pr;
+            }
+            out[n * k + i] = acc;
+        }
+    }
+    return 0;
 }
