@@ -178,6 +178,40 @@ int os_ann_search_ex(const os_ann_index *idx, const void *queries, int64_t Q,
                      int64_t max_candidates, const os_ann_search_opts *opts,
                      int64_t *out_idx, float *out_dist, int64_t *out_ncand);
 
+/*
+ * Principal axes of the database, for the PCA front-end of Section 4.B
+ * (classify on the first principal components, compare on all of them).
+ * The float64 mean and covariance (sum of the centred outer products divided
+ * by N) are computed on the device in fixed order; the covariance is
+ * diagonalised on the host (cyclic Jacobi, float64).  Outputs, host memory:
+ * mean_out[D] (FP32 mean), basis_out[k][D] (the k axes of largest variance in
+ * decreasing order, FP32, one per row, each signed so that its
+ * largest-magnitude component, lowest index on ties, is positive), var_out[k]
+ * (their variances, float64; may be NULL).  db is device memory of
+ * opts->dtype.  Synchronous.  Errors: EINVAL (null pointers, k outside
+ * [1, D]), ENOMEM, EDEVICE, ENONFINITE.
+ */
+int os_ann_pca(const void *db, int64_t N, int32_t D, int32_t k, const os_ann_build_opts *opts,
+               float *mean_out, float *basis_out, double *var_out);
+
+/*
+ * Build an index whose cones come from keys (the PCA front-end of Section
+ * 4.B): the key of a vector x is P (x - mean), the k components
+ * sum_j P[i][j] (x[j] - mean[j]) evaluated in FP32 term by term (ascending
+ * j; the difference, each product and each sum rounded).  basis (k x D,
+ * row-major) and mean (D, or NULL for no centring) are FP32 device memory,
+ * copied by the library; typically the output of os_ann_pca.  The table
+ * hashes the rows' keys (L <= min(k, 7)) and holds the original rows; a
+ * search projects each query the same way, walks the cones of its key and
+ * compares candidates on all D components (exact FP32 distances, as for any
+ * index).  Searches run in OS_ANN_MODE_FP32 only (tiled: ENOTSUP);
+ * opts->want_lowp must be 0; os_ann_classify is not available (ENOTSUP).
+ * Synchronous.  Errors: EINVAL, ENOMEM, EDEVICE, ENOTSUP, ENONFINITE
+ * (returns NULL).
+ */
+os_ann_index *os_ann_build_proj(const void *db, int64_t N, int32_t D, int32_t L, const float *mean,
+                                const float *basis, int32_t k, const os_ann_build_opts *opts);
+
 /* Bytes of device scratch a search with these arguments needs (>= 0), or a
  * negative error code.  Used to size caller-owned workspaces and by
  * admission control. */

@@ -50,6 +50,10 @@ SIGNATURES = {
                                      C.POINTER(os_ann_build_opts)]),
     "os_ann_build_rot": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
                                       C.POINTER(os_ann_build_opts)]),
+    "os_ann_pca": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.POINTER(os_ann_build_opts),
+                             C.c_void_p, C.c_void_p, C.c_void_p]),
+    "os_ann_build_proj": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_int32, C.POINTER(os_ann_build_opts)]),
     "os_ann_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
     "os_ann_search_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                    C.POINTER(os_ann_search_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -145,6 +149,41 @@ def os_ann_build_rot(db: torch.Tensor, L: int, rot: torch.Tensor, stream=None) -
         raise ValueError("rot must hold D x D matrices")
     o = os_ann_build_opts(_check_rows(db, "db"), 0, _stream_ptr(stream))
     h = lib().os_ann_build_rot(_ptr(db), db.shape[0], db.shape[1], int(L), _ptr(rot), rot.shape[0], C.byref(o))
+    if not h:
+        _raise()
+    return h
+
+
+def os_ann_pca(db: torch.Tensor, k: int, stream=None):
+    """Principal axes of the rows of ``db``: ``(mean [D], basis [k, D], var [k])``
+    as host numpy arrays (FP32, FP32, float64)."""
+    import numpy as np
+    D = db.shape[1]
+    mean = np.empty(D, dtype=np.float32)
+    basis = np.empty((int(k), D), dtype=np.float32)
+    var = np.empty(int(k), dtype=np.float64)
+    o = os_ann_build_opts(_check_rows(db, "db"), 0, _stream_ptr(stream))
+    rc = lib().os_ann_pca(_ptr(db), db.shape[0], D, int(k), C.byref(o), mean.ctypes.data_as(C.c_void_p),
+                          basis.ctypes.data_as(C.c_void_p), var.ctypes.data_as(C.c_void_p))
+    if rc:
+        _raise(rc)
+    return mean, basis, var
+
+
+def os_ann_build_proj(db: torch.Tensor, L: int, basis: torch.Tensor, mean: torch.Tensor | None = None,
+                      stream=None) -> int:
+    """Index whose cones come from the keys basis (x - mean); ``basis`` is a
+    device FP32 tensor [k, D], ``mean`` a device FP32 tensor [D] or None."""
+    D = db.shape[1]
+    if basis.dtype != torch.float32 or basis.dim() != 2 or not basis.is_contiguous() or basis.device != db.device \
+            or basis.shape[1] != D:
+        raise ValueError("basis must be a contiguous FP32 [k, D] tensor on the db's device")
+    if mean is not None and (mean.dtype != torch.float32 or mean.shape != (D,) or not mean.is_contiguous()
+                             or mean.device != db.device):
+        raise ValueError("mean must be a contiguous FP32 [D] tensor on the db's device")
+    o = os_ann_build_opts(_check_rows(db, "db"), 0, _stream_ptr(stream))
+    h = lib().os_ann_build_proj(_ptr(db), db.shape[0], D, int(L), _ptr(mean), _ptr(basis), basis.shape[0],
+                                C.byref(o))
     if not h:
         _raise()
     return h

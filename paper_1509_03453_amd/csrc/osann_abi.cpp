@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -75,6 +76,7 @@ struct GraphEntry {
 struct os_ann_index {
     int64_t N = 0;
     int32_t D = 0, L = 0, dtype = 0;
+    int32_t Dk = 0;  // length of the keys the cones come from (D, or k for a projected table)
     int64_t n_cones = 0, n_sub = 0, n_nonempty = 0;
     int nch = 0, epc = 0;
     int device = 0, num_cu = 256;
@@ -113,6 +115,10 @@ struct os_ann_index {
     uint32_t* rot_perm = nullptr;     // [R][N]
     uint64_t* xtop = nullptr;         // [R][R][N]
     void** planes_tab = nullptr;      // [R] device copies of the tables' plane pointers
+    // PCA front-end (Section 4.B): keys are P (x - mu), k = Dk components
+    bool proj = false;
+    float* proj_mu = nullptr;  // [D], or null: no centring
+    float* proj_P = nullptr;   // [k][D]
 };
 
 namespace {
@@ -231,7 +237,7 @@ void release(os_ann_index* ix, bool synced = false) {
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
                     ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
-                    ix->planes_tab};
+                    ix->planes_tab, ix->proj_mu, ix->proj_P};
     for (void* p : ptrs) dev_free(p);
     delete ix;
 }
@@ -304,6 +310,7 @@ struct SearchPlan {
     size_t off_ql = 0, off_qcone = 0, off_sort = 0, off_qorder = 0, off_qsorted = 0, off_part = 0,
            off_counter = 0, off_qbits = 0, off_cmin = 0;
     size_t off_yr = 0;  // several bases: query coordinates [R][Q][D]
+    size_t off_yk = 0;  // projected table: query keys [Q][Dk]
     size_t bytes = 0;
 };
 
@@ -337,10 +344,11 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         p.bytes = at;
         return p;
     }
-    p.off_order = take((size_t)Q * ix->D);
-    p.off_sbit = take((size_t)Q * ix->D);
+    p.off_order = take((size_t)Q * ix->Dk);
+    p.off_sbit = take((size_t)Q * ix->Dk);
     p.off_jstop = take((size_t)Q * sizeof(uint32_t));
     p.off_np = take((size_t)Q * sizeof(uint32_t));
+    if (ix->proj) p.off_yk = take((size_t)Q * ix->Dk * sizeof(float));
     p.off_nc = take((size_t)Q * sizeof(int64_t));
     if (mode == OS_ANN_MODE_TILED) {
         const int64_t ne = ix->n_nonempty > 0 ? ix->n_nonempty : 1;
@@ -388,6 +396,8 @@ int search_checks(const os_ann_index* ix, const void* queries, int64_t Q, int64_
             return fail(OS_ANN_EINVAL, "rerank_r must be 4, 8 or 16");
         if (o->mode == OS_ANN_MODE_TILED && ix->n_rot > 0)
             return fail(OS_ANN_ENOTSUP, "several bases: FP32 mode only");
+        if (o->mode == OS_ANN_MODE_TILED && ix->proj)
+            return fail(OS_ANN_ENOTSUP, "projected table: FP32 mode only");
     }
     return OS_ANN_OK;
 }
@@ -515,7 +525,7 @@ ProbeArgs probe_args(const Call& c) {
     pa.Y = c.queries;
     pa.qtype = c.qtype;
     pa.Q = c.Q;
-    pa.D = ix->D;
+    pa.D = ix->Dk;
     pa.L = ix->L;
     pa.offsets = ix->offsets;
     pa.n_cones = ix->n_cones;
@@ -550,13 +560,39 @@ ProbeArgs probe_args(const Call& c) {
 hipError_t enqueue_fp32(const Call& c) {
     os_ann_index* ix = c.ix;
     const ProbeArgs pa = probe_args(c);
-    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] { return launch_probe(pa, c.s); });
+    hipError_t e;
+    if (ix->proj) {
+        // the FP32 copy of the queries (all D components), their keys, then
+        // the walk on the keys
+        ProbeArgs pf{};
+        pf.Y = c.queries;
+        pf.qtype = c.qtype;
+        pf.Q = c.Q;
+        pf.D = ix->D;
+        pf.L = ix->L;
+        pf.yf = pa.yf;
+        pf.dpad = pa.dpad;
+        ProbeArgs pk = pa;
+        float* yk = reinterpret_cast<float*>(c.base + c.p.off_yk);
+        pk.Y = yk;
+        pk.qtype = kF32;
+        pk.yf = nullptr;
+        e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] {
+            hipError_t r = launch_probe(pf, c.s);
+            if (r == hipSuccess)
+                r = launch_project(c.queries, c.qtype, c.Q, ix->D, ix->proj_mu, ix->proj_P, ix->Dk, yk, c.s);
+            if (r == hipSuccess) r = launch_probe(pk, c.s);
+            return r;
+        });
+    } else {
+        e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] { return launch_probe(pa, c.s); });
+    }
     if (e != hipSuccess) return e;
     ScanArgs sa{};
     sa.planes = ix->planes;
     sa.dtype = ix->dtype;
     sa.N = ix->N;
-    sa.D = ix->D;
+    sa.D = ix->Dk;  // the walk state's length
     sa.L = ix->L;
     sa.nch = ix->nch;
     sa.yf = pa.yf;
@@ -840,20 +876,62 @@ const char* os_ann_version(void) { return "osann 0.2 gfx950"; }
 }  // extern "C"
 
 namespace {
+// Eigen-decomposition of the symmetric n x n matrix A (row-major, float64)
+// by cyclic Jacobi rotations: on return A's diagonal holds the eigenvalues
+// and column i of V the eigenvector of A[i][i].  Sweeps stop when the
+// off-diagonal mass falls below 1e-30 of the total (or after 100 sweeps).
+void jacobi_eigen(std::vector<double>& A, int n, std::vector<double>& V) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    double total = 0.0;
+    for (double v : A) total += v * v;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += 2.0 * A[(size_t)p * n + q] * A[(size_t)p * n + q];
+        if (off <= 1e-30 * total) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // A <- A J (columns p, q)
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // A <- J^T A (rows p, q)
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {  // V <- V J
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+}
+
 // One table: the rows `keys` (type key_dtype) are hashed and bucketed; the
 // table stores the rows `db` (type dtype) in that bucket order.  For one
 // basis both are the database; for basis r of several, keys holds the
 // database's coordinates in that basis.
-os_ann_index* build_table(const void* keys, int32_t key_dtype, const void* db, int32_t dtype, int64_t N, int32_t D,
-                          int32_t L, int64_t nc, hipStream_t s) {
+os_ann_index* build_table(const void* keys, int32_t key_dtype, int32_t Dk, const void* db, int32_t dtype, int64_t N,
+                          int32_t D, int32_t L, int64_t nc, hipStream_t s) {
 
     auto* ix = new os_ann_index();
     ix->N = N;
     ix->D = D;
+    ix->Dk = Dk;
     ix->L = L;
     ix->dtype = dtype;
     ix->n_cones = nc;
-    ix->n_sub = binom_host(D, L);
+    ix->n_sub = binom_host(Dk, L);
     ix->epc = chunk_elems(dtype);
     ix->nch = (D + ix->epc - 1) / ix->epc;
     (void)hipGetDevice(&ix->device);
@@ -892,11 +970,11 @@ os_ann_index* build_table(const void* keys, int32_t key_dtype, const void* db, i
         return true;
     };
     if (!step(hipMemsetAsync(small, 0, 16, s), "memset") ||
-        !step(launch_row_keys(keys, key_dtype, N, D, L, ix->row_cone, ix->row_top, small, s), "key kernel") ||
+        !step(launch_row_keys(keys, key_dtype, N, Dk, L, ix->row_cone, ix->row_top, small, s), "key kernel") ||
         !step(launch_sort_by_cone(ix->row_cone, N, nc, tmp, ix->perm, ix->sorted_cone, s), "radix sort") ||
         !step(launch_offsets(ix->sorted_cone, N, nc, ix->offsets, s), "offsets") ||
         !step(launch_gather_planes(db, dtype, N, D, ix->perm, ix->planes, s), "gather") ||
-        !step(launch_probe_tables(D, L, ix->lexsub, ix->maskord, s), "probe tables") ||
+        !step(launch_probe_tables(Dk, L, ix->lexsub, ix->maskord, s), "probe tables") ||
         !step(launch_binom_table(ix->binom, s), "binomial table") ||
         !step(launch_count_nonempty(ix->offsets, nc, small + 1, s), "count"))
         return bail(0);
@@ -932,7 +1010,7 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L, c
         return nullptr;
     }
     if (check_shape(N, D, L, &nc)) return nullptr;
-    os_ann_index* ix = build_table(db, dtype, db, dtype, N, D, L, nc, s);
+    os_ann_index* ix = build_table(db, dtype, D, db, dtype, N, D, L, nc, s);
     if (ix && opts && opts->want_lowp && ensure_lowp(ix, s)) {
         release(ix);
         return nullptr;
@@ -966,6 +1044,7 @@ os_ann_index* os_ann_build_rot(const void* db, int64_t N, int32_t D, int32_t L, 
     auto* ix = new os_ann_index();
     ix->N = N;
     ix->D = D;
+    ix->Dk = D;
     ix->L = L;
     ix->dtype = dtype;
     ix->n_cones = nc;
@@ -993,7 +1072,7 @@ os_ann_index* os_ann_build_rot(const void* db, int64_t N, int32_t D, int32_t L, 
     for (int r = 0; r < n_rot && e == hipSuccess; ++r) {
         e = launch_rotate(db, dtype, N, D, ix->rot + (size_t)r * D * D, coords, s);
         if (e != hipSuccess) break;
-        os_ann_index* t = build_table(coords, kF32, db, dtype, N, D, L, nc, s);
+        os_ann_index* t = build_table(coords, kF32, D, db, dtype, N, D, L, nc, s);
         if (!t) return bail();
         ix->sub.push_back(t);
         ix->device_bytes += t->device_bytes;
@@ -1018,6 +1097,111 @@ os_ann_index* os_ann_build_rot(const void* db, int64_t N, int32_t D, int32_t L, 
     }
     dev_free(coords);
     ix->n_nonempty = ix->sub[0]->n_nonempty;
+    return ix;
+}
+
+int os_ann_pca(const void* db, int64_t N, int32_t D, int32_t k, const os_ann_build_opts* opts, float* mean_out,
+               float* basis_out, double* var_out) {
+    clear_error();
+    const int32_t dtype = opts ? opts->dtype : kF32;
+    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    if (!db || !mean_out || !basis_out) return fail(OS_ANN_EINVAL, "null db or output");
+    if (!dtype_ok(dtype)) return fail(OS_ANN_EINVAL, "bad db dtype");
+    if (N < 1 || N >= (int64_t(1) << 31)) return fail(OS_ANN_EINVAL, "N must be in [1, 2^31)");
+    if (D < 1 || D > kMaxD) return fail(OS_ANN_EINVAL, "D must be in [1, 256]");
+    if (k < 1 || k > D) return fail(OS_ANN_EINVAL, "k must be in [1, D]");
+    double *mean = nullptr, *cov = nullptr, *scratch = nullptr;
+    auto done = [&](int code) {
+        (void)hipDeviceSynchronize();
+        dev_free(mean);
+        dev_free(cov);
+        dev_free(scratch);
+        return code;
+    };
+    int rc = dev_alloc(nullptr, (void**)&mean, (size_t)D * 8, "pca mean");
+    if (!rc) rc = dev_alloc(nullptr, (void**)&cov, (size_t)D * D * 8, "pca covariance");
+    if (!rc) rc = dev_alloc(nullptr, (void**)&scratch, moments_scratch_doubles(N, D) * 8, "pca scratch");
+    if (rc) return done(rc);
+    std::vector<double> hmean(D), A((size_t)D * D);
+    hipError_t e = launch_moments(db, dtype, N, D, mean, cov, scratch, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hmean.data(), mean, (size_t)D * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(A.data(), cov, (size_t)D * D * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(hip_fail(e, "pca moments"));
+    done(OS_ANN_OK);
+    for (double v : A)
+        if (!std::isfinite(v)) return fail(OS_ANN_ENONFINITE, "database holds NaN or infinity");
+    std::vector<double> V;
+    jacobi_eigen(A, D, V);
+    std::vector<int> pick(D);
+    for (int i = 0; i < D; ++i) pick[i] = i;
+    std::stable_sort(pick.begin(), pick.end(), [&](int a, int b) {
+        return A[(size_t)a * D + a] > A[(size_t)b * D + b];
+    });
+    for (int r = 0; r < k; ++r) {
+        const int col = pick[r];
+        int jm = 0;
+        for (int j = 1; j < D; ++j)
+            if (std::fabs(V[(size_t)j * D + col]) > std::fabs(V[(size_t)jm * D + col])) jm = j;
+        const double sg = V[(size_t)jm * D + col] < 0 ? -1.0 : 1.0;
+        for (int j = 0; j < D; ++j) basis_out[(size_t)r * D + j] = (float)(sg * V[(size_t)j * D + col]);
+        if (var_out) var_out[r] = A[(size_t)col * D + col];
+    }
+    for (int j = 0; j < D; ++j) mean_out[j] = (float)hmean[j];
+    return OS_ANN_OK;
+}
+
+os_ann_index* os_ann_build_proj(const void* db, int64_t N, int32_t D, int32_t L, const float* mean,
+                                const float* basis, int32_t k, const os_ann_build_opts* opts) {
+    clear_error();
+    const int32_t dtype = opts ? opts->dtype : kF32;
+    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    int64_t nc = 0, nc_rows = 0;
+    if (!db || !basis) {
+        fail(OS_ANN_EINVAL, "null db or basis");
+        return nullptr;
+    }
+    if (!dtype_ok(dtype)) {
+        fail(OS_ANN_EINVAL, "bad db dtype");
+        return nullptr;
+    }
+    if (opts && opts->want_lowp) {
+        fail(OS_ANN_ENOTSUP, "projected table: FP32 mode only");
+        return nullptr;
+    }
+    if (check_shape(N, D, 1, &nc_rows)) return nullptr;
+    if (k < 1 || k > D) {
+        fail(OS_ANN_EINVAL, "k must be in [1, D]");
+        return nullptr;
+    }
+    if (check_shape(N, k, L, &nc)) return nullptr;
+    float *mu = nullptr, *P = nullptr, *keys = nullptr;
+    auto bail = [&]() -> os_ann_index* {
+        (void)hipDeviceSynchronize();
+        dev_free(mu);
+        dev_free(P);
+        dev_free(keys);
+        return nullptr;
+    };
+    if ((mean && dev_alloc(nullptr, (void**)&mu, (size_t)D * 4, "projection mean")) ||
+        dev_alloc(nullptr, (void**)&P, (size_t)k * D * 4, "projection basis") ||
+        dev_alloc(nullptr, (void**)&keys, (size_t)N * k * 4, "keys"))
+        return bail();
+    hipError_t e = hipSuccess;
+    if (mean) e = hipMemcpyAsync(mu, mean, (size_t)D * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P, basis, (size_t)k * D * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_project(db, dtype, N, D, mu, P, k, keys, s);
+    if (e != hipSuccess) {
+        hip_fail(e, "projection");
+        return bail();
+    }
+    os_ann_index* ix = build_table(keys, kF32, k, db, dtype, N, D, L, nc, s);  // synchronizes
+    if (!ix) return bail();
+    dev_free(keys);
+    ix->proj = true;
+    ix->proj_mu = mu;
+    ix->proj_P = P;
+    ix->device_bytes += (mu ? (size_t)D * 4 : 0) + (size_t)k * D * 4;
     return ix;
 }
 
@@ -1108,6 +1292,7 @@ int os_ann_classify(const os_ann_index* cidx, const void* queries, int32_t query
                     void* stream) {
     clear_error();
     if (cidx && cidx->n_rot > 0) return fail(OS_ANN_ENOTSUP, "classify: one basis only");
+    if (cidx && cidx->proj) return fail(OS_ANN_ENOTSUP, "classify: not for a projected table");
     os_ann_search_opts o{};
     o.query_dtype = query_dtype;
     int rc = search_checks(cidx, queries, Q, max_candidates, &o);
@@ -1119,7 +1304,7 @@ int os_ann_classify(const os_ann_index* cidx, const void* queries, int32_t query
     pa.Y = queries;
     pa.qtype = query_dtype;
     pa.Q = Q;
-    pa.D = ix->D;
+    pa.D = ix->Dk;
     pa.L = ix->L;
     pa.offsets = ix->offsets;
     pa.n_cones = ix->n_cones;

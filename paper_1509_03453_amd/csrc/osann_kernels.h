@@ -167,6 +167,14 @@ struct RotArgs {
     int waves_per_query;              // 1, 2 or 4
 };
 hipError_t launch_rotate(const void* X, int dtype, int64_t N, int D, const float* M, float* out, hipStream_t s);
+
+// PCA front-end (Section 4.B): keys P (x - mu) (mu may be null), and the
+// float64 mean and covariance of the rows (scratch: moments_scratch_doubles).
+hipError_t launch_project(const void* X, int dtype, int64_t N, int D, const float* mu, const float* P, int k,
+                          float* out, hipStream_t s);
+size_t moments_scratch_doubles(int64_t N, int D);
+hipError_t launch_moments(const void* X, int dtype, int64_t N, int D, double* mean, double* cov, double* scratch,
+                          hipStream_t s);
 hipError_t launch_probe_rot(const RotArgs& a, hipStream_t s);
 hipError_t launch_scan_rot(const RotArgs& a, hipStream_t s);
 hipError_t launch_gather_top(const uint32_t* perm, int64_t N, const uint64_t* top2, uint64_t* xt, hipStream_t s);
