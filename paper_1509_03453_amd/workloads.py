@@ -36,6 +36,7 @@ SEEDS = {
     "gauss16_db": 1001, "gauss16_q": 1002,
     "gauss64_db": 2001, "gauss64_q": 2002,
     "desc_db": 3001, "desc_pick": 3002, "desc_noise": 3003,
+    "sift_db": 3011,
     "patch_field": 4001, "patch_noise": 4002, "patch_sample": 4003,
     "serve_arrivals": 5001,
     "bases": 6001,
@@ -60,6 +61,28 @@ def descriptor_db(n: int, d: int = 128, seed: int = SEEDS["desc_db"]) -> np.ndar
     """uint8 rows ``rint(min(255, 40*G))`` with ``G ~ Gamma(shape 0.6, scale 1)``."""
     g = _rng(seed).gamma(0.6, 1.0, size=(int(n), int(d)))
     return np.rint(np.minimum(255.0, 40.0 * g)).astype(np.uint8)
+
+
+def sift_like_db(n: int, d: int = 128, seed: int = SEEDS["sift_db"], decay: float = 1.1,
+                 scale: float = 130.0, mean: float = 40.0) -> np.ndarray:
+    """uint8 rows with strongly correlated components, a stand-in for the SIFT
+    descriptors of Section 4.B: ``rint(clip(mean + A z, 0, 255))`` with ``A`` a
+    seeded Haar-random orthonormal ``d x d`` matrix and independent
+    ``z_i ~ N(0, scale^2 i^-decay)`` (i = 1..d), so that the first 16
+    principal components hold about 70% of the energy (the share the paper
+    reports for its SIFT sets)."""
+    r = _rng(seed)
+    a = r.standard_normal((int(d), int(d)))
+    q, rr = np.linalg.qr(a)
+    q = q * np.sign(np.diag(rr))[None, :]
+    sig = scale * np.arange(1, int(d) + 1, dtype=np.float64) ** (-decay / 2.0)
+    out = np.empty((int(n), int(d)), dtype=np.uint8)
+    chunk = 1 << 16
+    for s in range(0, int(n), chunk):
+        m = min(chunk, int(n) - s)
+        z = r.standard_normal((m, int(d))) * sig[None, :]
+        out[s:s + m] = np.rint(np.clip(mean + z @ q.T, 0.0, 255.0)).astype(np.uint8)
+    return out
 
 
 def descriptor_queries(db_u8: np.ndarray, q: int,

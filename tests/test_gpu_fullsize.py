@@ -8,6 +8,7 @@ oracle recomputes one by one.
 * ~4.2e6 mean-removed 8x8 FP16 patches of a 2048x2048 1/f field, L=2, queries
   are all patches of the shifted noisy field (~4.2e6), tiled mode.
 * the 1e6 x 64 Gaussian workload with four bases (Section 3.A).
+* the descriptor workload through the PCA front-end (Section 4.B), k = 16.
 
 The index itself (every key, bucket offset and permutation entry) is compared
 in full; searches are compared on a spread sample of queries."""
@@ -151,6 +152,42 @@ def test_several_bases_1m_d64(orc):
             torch.cuda.synchronize()
             gi, gd, gn = gi.cpu().numpy()[s], gd.cpu().numpy()[s], gn.cpu().numpy()[s]
             oi, od32, od64, on = orc.search_rot(X, o, Y[s], budget)
+            assert np.array_equal(gn, on) and np.array_equal(gi, oi), budget
+            assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), budget
+    finally:
+        B.os_ann_free(h)
+
+
+def test_descriptor_1m_pca16(orc):
+    # the PCA front-end at the full descriptor size: axes against the
+    # oracle's, then the keyed table (with the oracle's axes on both sides)
+    # compared in full and searched in the benchmark's launch shape
+    X = W.descriptor_db(1_000_000, 128)
+    Y, _ = W.descriptor_queries(X, 10_000)
+    say("[full] pca: axes of 1e6 x 128 u8")
+    mu, P, var = B.os_ann_pca(dev(X), 16)
+    omu, oP, ovar = orc.pca_basis(X, 16)
+    assert np.allclose(mu, omu, rtol=1e-6, atol=1e-6)
+    assert np.allclose(var, ovar, rtol=1e-9)
+    assert np.allclose(P, oP, atol=1e-5)
+    say("[full] pca: keyed table")
+    h = B.os_ann_build_proj(dev(X), 2, dev(oP), dev(omu))
+    o = orc.build_index_proj(X, 2, omu, oP)
+    try:
+        ex = B.os_ann_export(h)
+        torch.cuda.synchronize()
+        assert np.array_equal(ex["cone"].cpu().numpy().view(np.uint32).astype(np.int64), o["cone"])
+        assert np.array_equal(ex["offsets"].cpu().numpy(), o["offsets"])
+        assert np.array_equal(ex["perm"].cpu().numpy(), o["perm"])
+        del ex
+        yq = dev(Y)
+        for budget, n in ((64, 300), (1024, 200)):
+            s = sample_ids(len(Y), n)
+            say(f"[full] pca: budget {budget}")
+            gi, gd, gn = B.os_ann_search_ex(h, yq, budget)
+            torch.cuda.synchronize()
+            gi, gd, gn = gi.cpu().numpy()[s], gd.cpu().numpy()[s], gn.cpu().numpy()[s]
+            oi, od32, od64, on = orc.search_proj(X, o, Y[s], budget)
             assert np.array_equal(gn, on) and np.array_equal(gi, oi), budget
             assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), budget
     finally:
