@@ -83,6 +83,13 @@ def lib():
                                            p, p, p, p, i32]
             L.orc_project.restype = i32
             L.orc_project.argtypes = [p, i32, i64, i32, p, p, i32, p]
+            L.orc_assign.restype = i32
+            L.orc_assign.argtypes = [p, i32, i64, i32, p, i32, p]
+            L.orc_kmeans_update.restype = i32
+            L.orc_kmeans_update.argtypes = [p, i32, i64, i32, p, i32, p, p]
+            L.orc_search_ivf.restype = i32
+            L.orc_search_ivf.argtypes = [p, i32, i64, i32, i32, p, i32, p, p, p, i32, i64, i64, i32,
+                                         p, p, p, p, i32]
             _lib = L
     return _lib
 
@@ -403,4 +410,72 @@ def search_proj(X, index, Y, B: int, nthreads: int = 0):
                                 int(nthreads))
     if rc != 0:
         raise RuntimeError(f"orc_search_keyed failed ({rc})")
+    return idx, d32, d64, nca
+
+
+# ---------------------------------------------------------------------------
+# Coarse clusters (ROSANNA+, Section 4.B; reading R12)
+# ---------------------------------------------------------------------------
+
+def assign(X, cent):
+    """Nearest centroid of each row (FP32 term-by-term distance, lower id on ties)."""
+    X, px, dt = _rows(X)
+    N, K = X.shape
+    cent, pc = _arr(cent, np.float32)
+    out = np.empty(N, dtype=np.int32)
+    rc = lib().orc_assign(px, dt, N, K, pc, cent.shape[0], out.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise ValueError(f"orc_assign failed ({rc})")
+    return out
+
+
+def kmeans(X, init, iters: int):
+    """Lloyd k-means from ``init`` (C x K FP32) for ``iters`` iterations;
+    returns the FP32 centroids."""
+    X, px, dt = _rows(X)
+    N, K = X.shape
+    cent = np.ascontiguousarray(init, dtype=np.float32).copy()
+    for _ in range(int(iters)):
+        a = assign(X, cent)
+        new = np.empty_like(cent)
+        rc = lib().orc_kmeans_update(px, dt, N, K, a.ctypes.data_as(C.c_void_p), cent.shape[0],
+                                     cent.ctypes.data_as(C.c_void_p), new.ctypes.data_as(C.c_void_p))
+        if rc != 0:
+            raise ValueError(f"orc_kmeans_update failed ({rc})")
+        cent = new
+    return cent
+
+
+def build_index_ivf(X, G: int, cent):
+    """Rows bucketed by (cluster, cone of the residual x - c): bucket id
+    cluster * N_C + cone, offsets over C * N_C buckets."""
+    cent = np.ascontiguousarray(cent, dtype=np.float32)
+    a = assign(X, cent)
+    R = np.asarray(X).astype(np.float32) - cent[a]
+    top, sg, cone = hash_rows(R, G)
+    nc = num_cones(X.shape[1], G)
+    comp = a.astype(np.int64) * nc + cone
+    off, perm = bucket(comp, nc * cent.shape[0])
+    return {"top": top, "sign": sg, "cone": comp, "assign": a, "offsets": off, "perm": perm,
+            "n_cones": nc, "K": X.shape[1], "G": G, "cent": cent}
+
+
+def search_ivf(X, index, Y, B: int, nprobe: int, nthreads: int = 0):
+    """Search in the nprobe nearest clusters: ``(idx, d32, d64, ncand)``."""
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    N, K = X.shape
+    Q = Y.shape[0]
+    cent, pc = _arr(index["cent"], np.float32)
+    off, po = _arr(index["offsets"], np.int64)
+    perm, pp = _arr(index["perm"], np.int64)
+    idx = np.empty(Q, dtype=np.int64)
+    d32 = np.empty(Q, dtype=np.float32)
+    d64 = np.empty(Q, dtype=np.float64)
+    nca = np.empty(Q, dtype=np.int64)
+    rc = lib().orc_search_ivf(px, xdt, N, K, index["G"], pc, cent.shape[0], po, pp, py, ydt, Q, int(B),
+                              int(nprobe), idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
+                              d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_search_ivf failed ({rc})")
     return idx, d32, d64, nca

@@ -41,6 +41,17 @@
  *       j); cones come from the keys, distances from the full original
  *       vectors (the paper computes them over all components of the rotated
  *       vectors, which is the same distance).
+ *   R12 coarse clusters (ROSANNA+, Section 4.B): Lloyd k-means from given
+ *       initial centroids, a fixed number of iterations; a row goes to the
+ *       centroid at the smallest FP32 term-by-term squared distance (lower
+ *       centroid on ties); a centroid becomes the float64 mean of its rows
+ *       (summed in ascending row order) rounded to FP32, and keeps its value
+ *       when no row is assigned.  The table buckets rows by (cluster, cone of
+ *       the residual x - c in FP32).  A query takes the nprobe centroids
+ *       nearest to it (FP32 distance, lower centroid on ties); in each it
+ *       walks the cones of its residual with budget ceil(B / nprobe); every
+ *       row met is compared on the full vectors; ncand sums the clusters'
+ *       candidates.
  *
  * Precision: distances are produced both in double (the definition, eq. (1))
  * and in FP32 evaluated term by term in ascending component order with each
@@ -818,4 +829,140 @@ int orc_project(const void *X, int dtype, int64_t N, int K, const float *mu, con
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coarse clusters (ROSANNA+, Section 4.B)                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Nearest centroid of each row (reading R12): FP32 term-by-term squared
+ * distance, lower centroid on ties.  cent is C x K row-major FP32. */
+int orc_assign(const void *X, int dtype, int64_t N, int K, const float *cent, int C, int32_t *out)
+{
+    if (K < 1 || K > 256 || C < 1)
+        return -1;
+    for (int64_t n = 0; n < N; n++) {
+        float x[256];
+        load_row(X, dtype, n, K, x);
+        float best = INFINITY;
+        int bc = 0;
+        for (int c = 0; c < C; c++) {
+            float d32;
+            double d64;
+            dist2(x, cent + (int64_t)c * K, K, &d32, &d64);
+            if (d32 < best) {
+                best = d32;
+                bc = c;
+            }
+        }
+        out[n] = bc;
+    }
+    return 0;
+}
+
+/* Lloyd update (reading R12): centroid c = float64 sum of its rows in
+ * ascending row order, divided by their count, rounded to FP32; unchanged
+ * when the cluster is empty. */
+int orc_kmeans_update(const void *X, int dtype, int64_t N, int K, const int32_t *assign, int C,
+                      const float *old_cent, float *new_cent)
+{
+    if (K < 1 || K > 256 || C < 1)
+        return -1;
+    double *sum = (double *)calloc((size_t)C * K, sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)C, sizeof(int64_t));
+    if (!sum || !cnt) {
+        free(sum);
+        free(cnt);
+        return -2;
+    }
+    for (int64_t n = 0; n < N; n++) {
+        float x[256];
+        load_row(X, dtype, n, K, x);
+        int c = assign[n];
+        for (int j = 0; j < K; j++)
+            sum[(int64_t)c * K + j] += (double)x[j];
+        cnt[c]++;
+    }
+    for (int c = 0; c < C; c++)
+        for (int j = 0; j < K; j++)
+            new_cent[(int64_t)c * K + j] = cnt[c] ? (float)(sum[(int64_t)c * K + j] / (double)cnt[c])
+                                                  : old_cent[(int64_t)c * K + j];
+    free(sum);
+    free(cnt);
+    return 0;
+}
+
+/* Search in clusters (reading R12).  offsets has C * N_C + 1 entries: bucket
+ * (c, cone) is c * N_C + cone; perm maps sorted positions to rows. */
+int orc_search_ivf(const void *X, int xdtype, int64_t N, int K, int G, const float *cent, int C,
+                   const int64_t *offsets, const int64_t *perm, const void *Y, int ydtype, int64_t Q,
+                   int64_t B, int nprobe, int64_t *out_idx, float *out_d32, double *out_d64,
+                   int64_t *out_ncand, int nthreads)
+{
+    (void)N;
+    if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || nprobe < 1 || nprobe > C)
+        return -1;
+    int64_t NC = orc_num_cones(K, G);
+    int64_t Bc = (B + nprobe - 1) / nprobe;
+    set_threads(nthreads);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < Q; q++) {
+        float y[256], r[256], x[256];
+        load_row(Y, ydtype, q, K, y);
+        int64_t *probes = (int64_t *)malloc(sizeof(int64_t) * (size_t)NC);
+        float *cd = (float *)malloc(sizeof(float) * (size_t)C);
+        char *taken = (char *)calloc((size_t)C, 1);
+        if (!probes || !cd || !taken) {
+#pragma omp atomic write
+            bad = 1;
+            free(probes);
+            free(cd);
+            free(taken);
+            continue;
+        }
+        for (int c = 0; c < C; c++) {
+            double d64;
+            dist2(y, cent + (int64_t)c * K, K, &cd[c], &d64);
+        }
+        float best_d = INFINITY;
+        int64_t best_row = INT64_MAX;
+        double best_d64 = INFINITY;
+        int64_t ncand = 0;
+        for (int t = 0; t < nprobe; t++) {
+            int bc = -1;
+            for (int c = 0; c < C; c++)
+                if (!taken[c] && (bc < 0 || cd[c] < cd[bc]))
+                    bc = c;
+            taken[bc] = 1;
+            for (int j = 0; j < K; j++)
+                r[j] = y[j] - cent[(int64_t)bc * K + j];
+            const int64_t *off = offsets + (int64_t)bc * NC;
+            int64_t nc_c = 0;
+            int64_t np = orc_probe(r, K, G, off, Bc, probes, NC, &nc_c);
+            ncand += nc_c;
+            for (int64_t k = 0; k < np; k++) {
+                int64_t cone = probes[k];
+                for (int64_t pos = off[cone]; pos < off[cone + 1]; pos++) {
+                    int64_t row = perm[pos];
+                    float d32;
+                    double d64;
+                    load_row(X, xdtype, row, K, x);
+                    dist2(x, y, K, &d32, &d64);
+                    int64_t before = best_row;
+                    argmin_update(d32, row, &best_d, &best_row);
+                    if (best_row != before)
+                        best_d64 = d64;
+                }
+            }
+        }
+        out_idx[q] = best_row;
+        out_d32[q] = best_d;
+        out_d64[q] = best_d64;
+        out_ncand[q] = ncand;
+        free(probes);
+        free(cd);
+        free(taken);
+    }
+    return bad ? -2 : 0;
 }
