@@ -212,6 +212,45 @@ int os_ann_pca(const void *db, int64_t N, int32_t D, int32_t k, const os_ann_bui
 os_ann_index *os_ann_build_proj(const void *db, int64_t N, int32_t D, int32_t L, const float *mean,
                                 const float *basis, int32_t k, const os_ann_build_opts *opts);
 
+/*
+ * Lloyd k-means for the coarse clusters of ROSANNA+ (Section 4.B): from the
+ * C initial centroids init[C][D] (FP32, device), iters times: every row goes
+ * to the centroid at the smallest FP32 squared distance (evaluated term by
+ * term, lower centroid on ties), then every centroid becomes the float64 mean
+ * of its rows (summed in ascending row order) rounded to FP32, or keeps its
+ * value if no row is assigned.  out[C][D] (FP32, device) receives the
+ * result; db is device memory of opts->dtype.  Synchronous.
+ * Errors: EINVAL (null pointers, C outside [1, 4096], iters < 0), ENOMEM,
+ * EDEVICE.
+ */
+int os_ann_kmeans(const void *db, int64_t N, int32_t D, int32_t C, int32_t iters, const float *init,
+                  const os_ann_build_opts *opts, float *out);
+
+/*
+ * Build a clustered index (ROSANNA+, Section 4.B): every row goes to its
+ * nearest centroid (as in os_ann_kmeans) and is hashed on its residual
+ * x - c (FP32); the table's buckets are (cluster, cone), bucket id
+ * cluster * C(D,L) 2^L + cone (os_ann_info reports their count as n_cones,
+ * os_ann_export their offsets).  centroids[C][D] is FP32 device memory,
+ * copied.  A search compares each query with every centroid (FP32 distance,
+ * lower centroid on ties), and in each of the nprobe nearest clusters walks
+ * the cones of the query's residual with budget ceil(max_candidates /
+ * nprobe); the rows met are compared on the full vectors and the best
+ * (distance, row) wins; ncand sums the clusters' candidates (-1 as the row
+ * if every searched cluster is empty).  FP32 mode only (tiled: ENOTSUP);
+ * opts->want_lowp must be 0; os_ann_classify: ENOTSUP.  Requires
+ * 1 <= nprobe <= min(C, 64), C <= 4096 and C * C(D,L) 2^L <= 2^24.
+ * Synchronous.  Errors: EINVAL, ENOMEM, EDEVICE, ENOTSUP, ENONFINITE
+ * (returns NULL).
+ */
+os_ann_index *os_ann_build_ivf(const void *db, int64_t N, int32_t D, int32_t L, const float *centroids,
+                               int32_t C, int32_t nprobe, const os_ann_build_opts *opts);
+
+/* Change the number of clusters a clustered index searches per query (same
+ * limits as os_ann_build_ivf).  Not to be called while a search on the index
+ * is in flight.  Errors: EINVAL. */
+int os_ann_set_nprobe(os_ann_index *idx, int32_t nprobe);
+
 /* Bytes of device scratch a search with these arguments needs (>= 0), or a
  * negative error code.  Used to size caller-owned workspaces and by
  * admission control. */

@@ -956,7 +956,7 @@ int orc_search_ivf(const void *X, int xdtype, int64_t N, int K, int G, const flo
                 }
             }
         }
-        out_idx[q] = best_row;
+        out_idx[q] = best_row == INT64_MAX ? -1 : best_row;  /* -1: every cluster searched was empty */
         out_d32[q] = best_d;
         out_d64[q] = best_d64;
         out_ncand[q] = ncand;

@@ -54,6 +54,11 @@ SIGNATURES = {
                              C.c_void_p, C.c_void_p, C.c_void_p]),
     "os_ann_build_proj": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                        C.c_int32, C.POINTER(os_ann_build_opts)]),
+    "os_ann_kmeans": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                C.POINTER(os_ann_build_opts), C.c_void_p]),
+    "os_ann_build_ivf": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                      C.c_int32, C.POINTER(os_ann_build_opts)]),
+    "os_ann_set_nprobe": (C.c_int, [C.c_void_p, C.c_int32]),
     "os_ann_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
     "os_ann_search_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                    C.POINTER(os_ann_search_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -187,6 +192,40 @@ def os_ann_build_proj(db: torch.Tensor, L: int, basis: torch.Tensor, mean: torch
     if not h:
         _raise()
     return h
+
+
+def os_ann_kmeans(db: torch.Tensor, init: torch.Tensor, iters: int, stream=None) -> torch.Tensor:
+    """Lloyd k-means from the device FP32 centroids ``init`` [C, D]; returns the new centroids."""
+    D = db.shape[1]
+    if init.dtype != torch.float32 or init.dim() != 2 or init.shape[1] != D or not init.is_contiguous() \
+            or init.device != db.device:
+        raise ValueError("init must be a contiguous FP32 [C, D] tensor on the db's device")
+    out = torch.empty_like(init)
+    o = os_ann_build_opts(_check_rows(db, "db"), 0, _stream_ptr(stream))
+    rc = lib().os_ann_kmeans(_ptr(db), db.shape[0], D, init.shape[0], int(iters), _ptr(init), C.byref(o), _ptr(out))
+    if rc:
+        _raise(rc)
+    return out
+
+
+def os_ann_build_ivf(db: torch.Tensor, L: int, centroids: torch.Tensor, nprobe: int, stream=None) -> int:
+    """Clustered index over the device FP32 centroids [C, D]; searches visit ``nprobe`` clusters."""
+    D = db.shape[1]
+    if centroids.dtype != torch.float32 or centroids.dim() != 2 or centroids.shape[1] != D \
+            or not centroids.is_contiguous() or centroids.device != db.device:
+        raise ValueError("centroids must be a contiguous FP32 [C, D] tensor on the db's device")
+    o = os_ann_build_opts(_check_rows(db, "db"), 0, _stream_ptr(stream))
+    h = lib().os_ann_build_ivf(_ptr(db), db.shape[0], D, int(L), _ptr(centroids), centroids.shape[0], int(nprobe),
+                               C.byref(o))
+    if not h:
+        _raise()
+    return h
+
+
+def os_ann_set_nprobe(index: int, nprobe: int) -> None:
+    rc = lib().os_ann_set_nprobe(index, int(nprobe))
+    if rc:
+        _raise(rc)
 
 
 def _search_opts(queries, mode, stream, workspace, rerank_r=8, flags=0):

@@ -15,6 +15,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "osann_ivf.h"
 #include "osann_kernels.h"
 #include "osann_tiled.h"
 
@@ -119,6 +120,11 @@ struct os_ann_index {
     bool proj = false;
     float* proj_mu = nullptr;  // [D], or null: no centring
     float* proj_P = nullptr;   // [k][D]
+    // coarse clusters (ROSANNA+, Section 4.B): buckets are (cluster, cone) =
+    // cluster * n_cones + cone; the rows are hashed on their residuals
+    int32_t n_groups = 1;       // clusters (1: a plain table)
+    float* ivf_cent = nullptr;  // [n_groups][D]
+    int32_t nprobe = 0;         // clusters searched per query
 };
 
 namespace {
@@ -237,7 +243,7 @@ void release(os_ann_index* ix, bool synced = false) {
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
                     ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
-                    ix->planes_tab, ix->proj_mu, ix->proj_P};
+                    ix->planes_tab, ix->proj_mu, ix->proj_P, ix->ivf_cent};
     for (void* p : ptrs) dev_free(p);
     delete ix;
 }
@@ -311,6 +317,9 @@ struct SearchPlan {
            off_counter = 0, off_qbits = 0, off_cmin = 0;
     size_t off_yr = 0;  // several bases: query coordinates [R][Q][D]
     size_t off_yk = 0;  // projected table: query keys [Q][Dk]
+    // clustered table: per virtual query (query x searched cluster)
+    size_t off_vyr = 0, off_vyf = 0, off_vbase = 0, off_vidx = 0, off_vdist = 0;
+    int64_t Qv = 0;
     size_t bytes = 0;
 };
 
@@ -344,12 +353,22 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         p.bytes = at;
         return p;
     }
-    p.off_order = take((size_t)Q * ix->Dk);
-    p.off_sbit = take((size_t)Q * ix->Dk);
-    p.off_jstop = take((size_t)Q * sizeof(uint32_t));
-    p.off_np = take((size_t)Q * sizeof(uint32_t));
+    // walk state per query, or per (query, searched cluster) on a clustered table
+    const int64_t Qw = ix->ivf_cent ? Q * ix->nprobe : Q;
+    p.Qv = Qw;
+    p.off_order = take((size_t)Qw * ix->Dk);
+    p.off_sbit = take((size_t)Qw * ix->Dk);
+    p.off_jstop = take((size_t)Qw * sizeof(uint32_t));
+    p.off_np = take((size_t)Qw * sizeof(uint32_t));
     if (ix->proj) p.off_yk = take((size_t)Q * ix->Dk * sizeof(float));
-    p.off_nc = take((size_t)Q * sizeof(int64_t));
+    p.off_nc = take((size_t)Qw * sizeof(int64_t));
+    if (ix->ivf_cent) {
+        p.off_vyr = take((size_t)Qw * ix->D * sizeof(float));
+        p.off_vyf = take((size_t)Qw * p.dpad * sizeof(float));
+        p.off_vbase = take((size_t)Qw * sizeof(uint32_t));
+        p.off_vidx = take((size_t)Qw * sizeof(int64_t));
+        p.off_vdist = take((size_t)Qw * sizeof(float));
+    }
     if (mode == OS_ANN_MODE_TILED) {
         const int64_t ne = ix->n_nonempty > 0 ? ix->n_nonempty : 1;
         p.dk = (int)align_up((size_t)ix->D, 32);
@@ -398,6 +417,8 @@ int search_checks(const os_ann_index* ix, const void* queries, int64_t Q, int64_
             return fail(OS_ANN_ENOTSUP, "several bases: FP32 mode only");
         if (o->mode == OS_ANN_MODE_TILED && ix->proj)
             return fail(OS_ANN_ENOTSUP, "projected table: FP32 mode only");
+        if (o->mode == OS_ANN_MODE_TILED && ix->ivf_cent)
+            return fail(OS_ANN_ENOTSUP, "clustered table: FP32 mode only");
     }
     return OS_ANN_OK;
 }
@@ -808,8 +829,96 @@ hipError_t enqueue_rot(const Call& c) {
     return timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] { return launch_scan_rot(ra, c.s); });
 }
 
+// Clustered table: the FP32 queries, their nprobe nearest clusters and
+// residuals, the walk and scan of every (query, cluster) pair as its own
+// query with its cluster's bucket base, then the best pair per query.
+hipError_t enqueue_ivf(const Call& c) {
+    os_ann_index* ix = c.ix;
+    const SearchPlan& p = c.p;
+    const int np = ix->nprobe;
+    ProbeArgs pf{};
+    pf.Y = c.queries;
+    pf.qtype = c.qtype;
+    pf.Q = c.Q;
+    pf.D = ix->D;
+    pf.L = ix->L;
+    pf.yf = reinterpret_cast<float*>(c.base + p.off_yf);
+    pf.dpad = p.dpad;
+    IvfQueryArgs ia{};
+    ia.yf = pf.yf;
+    ia.dpad = p.dpad;
+    ia.D = ix->D;
+    ia.Q = c.Q;
+    ia.cent = ix->ivf_cent;
+    ia.C = ix->n_groups;
+    ia.nprobe = np;
+    ia.n_cones = ix->n_cones;
+    ia.yr = reinterpret_cast<float*>(c.base + p.off_vyr);
+    ia.yfv = reinterpret_cast<float*>(c.base + p.off_vyf);
+    ia.cone_base = reinterpret_cast<uint32_t*>(c.base + p.off_vbase);
+    ProbeArgs pk{};
+    pk.Y = ia.yr;
+    pk.qtype = kF32;
+    pk.Q = p.Qv;
+    pk.D = ix->D;
+    pk.L = ix->L;
+    pk.offsets = ix->offsets;
+    pk.n_cones = ix->n_cones;
+    pk.n_sub = ix->n_sub;
+    pk.N = INT64_MAX;  // a cluster's walk never takes the whole database
+    pk.budget = (c.budget + np - 1) / np;
+    pk.lexsub = ix->lexsub;
+    pk.maskord = ix->maskord;
+    pk.binom = ix->binom;
+    pk.order = reinterpret_cast<uint8_t*>(c.base + p.off_order);
+    pk.sbit = reinterpret_cast<uint8_t*>(c.base + p.off_sbit);
+    pk.jstop = reinterpret_cast<uint32_t*>(c.base + p.off_jstop);
+    pk.nprobe = reinterpret_cast<uint32_t*>(c.base + p.off_np);
+    pk.ncand = reinterpret_cast<int64_t*>(c.base + p.off_nc);
+    pk.cone_base = ia.cone_base;
+    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] {
+        hipError_t r = launch_probe(pf, c.s);
+        if (r == hipSuccess) r = launch_ivf_queries(ia, c.s);
+        if (r == hipSuccess) r = launch_probe(pk, c.s);
+        return r;
+    });
+    if (e != hipSuccess) return e;
+    ScanArgs sa{};
+    sa.planes = ix->planes;
+    sa.dtype = ix->dtype;
+    sa.N = ix->N;
+    sa.D = ix->D;
+    sa.L = ix->L;
+    sa.nch = ix->nch;
+    sa.yf = ia.yfv;
+    sa.Q = p.Qv;
+    sa.order = pk.order;
+    sa.sbit = pk.sbit;
+    sa.jstop = pk.jstop;
+    sa.offsets = ix->offsets;
+    sa.n_sub = ix->n_sub;
+    sa.lexsub = ix->lexsub;
+    sa.maskord = ix->maskord;
+    sa.binom = ix->binom;
+    sa.perm = ix->perm;
+    sa.cone_base = ia.cone_base;
+    int64_t* vidx = reinterpret_cast<int64_t*>(c.base + p.off_vidx);
+    float* vdist = reinterpret_cast<float*>(c.base + p.off_vdist);
+    sa.out_idx = vidx;
+    sa.out_dist = vdist;
+    sa.waves_per_query = std::min<int64_t>(pk.budget, ix->N) <= 8192 ? 1 : 4;
+    e = timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] {
+        hipError_t r = launch_scan_fp32(sa, c.s);
+        if (r == hipSuccess)
+            r = launch_ivf_combine(vidx, vdist, pk.ncand, c.Q, np, c.out_idx, c.out_dist, c.out_ncand, c.s);
+        return r;
+    });
+    return e;
+}
+
 hipError_t enqueue(const Call& c, int S) {
     if (c.ix->n_rot > 0) return enqueue_rot(c);
+    if (c.ix->ivf_cent) return enqueue_ivf(c);
     return c.p.mode == OS_ANN_MODE_TILED ? enqueue_tiled(c, S) : enqueue_fp32(c);
 }
 
@@ -922,7 +1031,8 @@ void jacobi_eigen(std::vector<double>& A, int n, std::vector<double>& V) {
 // basis both are the database; for basis r of several, keys holds the
 // database's coordinates in that basis.
 os_ann_index* build_table(const void* keys, int32_t key_dtype, int32_t Dk, const void* db, int32_t dtype, int64_t N,
-                          int32_t D, int32_t L, int64_t nc, hipStream_t s) {
+                          int32_t D, int32_t L, int64_t nc, hipStream_t s, const uint32_t* group = nullptr,
+                          int32_t n_groups = 1) {
 
     auto* ix = new os_ann_index();
     ix->N = N;
@@ -931,6 +1041,8 @@ os_ann_index* build_table(const void* keys, int32_t key_dtype, int32_t Dk, const
     ix->L = L;
     ix->dtype = dtype;
     ix->n_cones = nc;
+    ix->n_groups = n_groups;
+    const int64_t nb = nc * n_groups;  // buckets
     ix->n_sub = binom_host(Dk, L);
     ix->epc = chunk_elems(dtype);
     ix->nch = (D + ix->epc - 1) / ix->epc;
@@ -953,7 +1065,7 @@ os_ann_index* build_table(const void* keys, int32_t key_dtype, int32_t Dk, const
         dev_alloc(ix, (void**)&ix->row_top, n * 8, "row_top") ||
         dev_alloc(ix, (void**)&ix->perm, n * 4, "perm") ||
         dev_alloc(ix, (void**)&ix->sorted_cone, n * 4, "sorted_cone") ||
-        dev_alloc(ix, (void**)&ix->offsets, (size_t)(nc + 1) * 4, "offsets") ||
+        dev_alloc(ix, (void**)&ix->offsets, (size_t)(nb + 1) * 4, "offsets") ||
         dev_alloc(ix, &ix->planes, (size_t)ix->nch * n * 16, "planes") ||
         dev_alloc(ix, (void**)&ix->lexsub, (size_t)ix->n_sub * L, "lexsub") ||
         dev_alloc(ix, (void**)&ix->maskord, 128, "maskord") ||
@@ -971,12 +1083,13 @@ os_ann_index* build_table(const void* keys, int32_t key_dtype, int32_t Dk, const
     };
     if (!step(hipMemsetAsync(small, 0, 16, s), "memset") ||
         !step(launch_row_keys(keys, key_dtype, N, Dk, L, ix->row_cone, ix->row_top, small, s), "key kernel") ||
-        !step(launch_sort_by_cone(ix->row_cone, N, nc, tmp, ix->perm, ix->sorted_cone, s), "radix sort") ||
-        !step(launch_offsets(ix->sorted_cone, N, nc, ix->offsets, s), "offsets") ||
+        !step(group ? launch_compose_cones(ix->row_cone, group, N, nc, s) : hipSuccess, "cluster buckets") ||
+        !step(launch_sort_by_cone(ix->row_cone, N, nb, tmp, ix->perm, ix->sorted_cone, s), "radix sort") ||
+        !step(launch_offsets(ix->sorted_cone, N, nb, ix->offsets, s), "offsets") ||
         !step(launch_gather_planes(db, dtype, N, D, ix->perm, ix->planes, s), "gather") ||
         !step(launch_probe_tables(Dk, L, ix->lexsub, ix->maskord, s), "probe tables") ||
         !step(launch_binom_table(ix->binom, s), "binomial table") ||
-        !step(launch_count_nonempty(ix->offsets, nc, small + 1, s), "count"))
+        !step(launch_count_nonempty(ix->offsets, nb, small + 1, s), "count"))
         return bail(0);
     uint32_t host_small[2] = {0, 0};
     if (!step(hipMemcpyAsync(host_small, small, 8, hipMemcpyDeviceToHost, s), "copy flags") ||
@@ -1205,6 +1318,116 @@ os_ann_index* os_ann_build_proj(const void* db, int64_t N, int32_t D, int32_t L,
     return ix;
 }
 
+int os_ann_kmeans(const void* db, int64_t N, int32_t D, int32_t C, int32_t iters, const float* init,
+                  const os_ann_build_opts* opts, float* out) {
+    clear_error();
+    const int32_t dtype = opts ? opts->dtype : kF32;
+    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    if (!db || !init || !out) return fail(OS_ANN_EINVAL, "null db, init or out");
+    if (!dtype_ok(dtype)) return fail(OS_ANN_EINVAL, "bad db dtype");
+    if (N < 1 || N >= (int64_t(1) << 31)) return fail(OS_ANN_EINVAL, "N must be in [1, 2^31)");
+    if (D < 1 || D > kMaxD) return fail(OS_ANN_EINVAL, "D must be in [1, 256]");
+    if (C < 1 || C > 4096) return fail(OS_ANN_EINVAL, "C must be in [1, 4096]");
+    if (iters < 0) return fail(OS_ANN_EINVAL, "iters must be >= 0");
+    float *ca = nullptr, *cb = nullptr;
+    uint32_t *asg = nullptr, *tmp = nullptr, *members = nullptr, *sorted = nullptr, *off = nullptr;
+    auto done = [&](int code) {
+        (void)hipDeviceSynchronize();
+        for (void* q : {(void*)ca, (void*)cb, (void*)asg, (void*)tmp, (void*)members, (void*)sorted, (void*)off})
+            dev_free(q);
+        return code;
+    };
+    const size_t cd = (size_t)C * D * 4;
+    int rc = dev_alloc(nullptr, (void**)&ca, cd, "centroids");
+    if (!rc) rc = dev_alloc(nullptr, (void**)&cb, cd, "centroids");
+    if (!rc) rc = dev_alloc(nullptr, (void**)&asg, (size_t)N * 4, "assignment");
+    if (!rc) rc = dev_alloc(nullptr, (void**)&tmp, (size_t)(4 * N + radix_hist_words(N)) * 4, "sort scratch");
+    if (!rc) rc = dev_alloc(nullptr, (void**)&members, (size_t)N * 4, "members");
+    if (!rc) rc = dev_alloc(nullptr, (void**)&sorted, (size_t)N * 4, "sorted clusters");
+    if (!rc) rc = dev_alloc(nullptr, (void**)&off, (size_t)(C + 1) * 4, "cluster offsets");
+    if (rc) return done(rc);
+    hipError_t e = hipMemcpyAsync(ca, init, cd, hipMemcpyDeviceToDevice, s);
+    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+        e = launch_assign(db, dtype, N, D, ca, C, asg, s);
+        if (e == hipSuccess) e = launch_sort_by_cone(asg, N, C, tmp, members, sorted, s);
+        if (e == hipSuccess) e = launch_offsets(sorted, N, C, off, s);
+        if (e == hipSuccess) e = launch_centroid_update(db, dtype, N, D, members, off, C, ca, cb, s);
+        std::swap(ca, cb);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, ca, cd, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(hip_fail(e, "k-means"));
+    return done(OS_ANN_OK);
+}
+
+os_ann_index* os_ann_build_ivf(const void* db, int64_t N, int32_t D, int32_t L, const float* centroids, int32_t C,
+                               int32_t nprobe, const os_ann_build_opts* opts) {
+    clear_error();
+    const int32_t dtype = opts ? opts->dtype : kF32;
+    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    int64_t nc = 0;
+    if (!db || !centroids) {
+        fail(OS_ANN_EINVAL, "null db or centroids");
+        return nullptr;
+    }
+    if (!dtype_ok(dtype)) {
+        fail(OS_ANN_EINVAL, "bad db dtype");
+        return nullptr;
+    }
+    if (opts && opts->want_lowp) {
+        fail(OS_ANN_ENOTSUP, "clustered table: FP32 mode only");
+        return nullptr;
+    }
+    if (check_shape(N, D, L, &nc)) return nullptr;
+    if (C < 1 || C > 4096 || nprobe < 1 || nprobe > C || nprobe > 64) {
+        fail(OS_ANN_EINVAL, "need 1 <= nprobe <= min(C, 64) and C <= 4096");
+        return nullptr;
+    }
+    if (nc * C > kMaxCones) {
+        fail(OS_ANN_ENOTSUP, "clusters x cones exceeds 2^24 buckets");
+        return nullptr;
+    }
+    float *cent = nullptr, *keys = nullptr;
+    uint32_t* asg = nullptr;
+    auto bail = [&]() -> os_ann_index* {
+        (void)hipDeviceSynchronize();
+        dev_free(cent);
+        dev_free(keys);
+        dev_free(asg);
+        return nullptr;
+    };
+    if (dev_alloc(nullptr, (void**)&cent, (size_t)C * D * 4, "centroids") ||
+        dev_alloc(nullptr, (void**)&keys, (size_t)N * D * 4, "residuals") ||
+        dev_alloc(nullptr, (void**)&asg, (size_t)N * 4, "assignment"))
+        return bail();
+    hipError_t e = hipMemcpyAsync(cent, centroids, (size_t)C * D * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_assign(db, dtype, N, D, cent, C, asg, s);
+    if (e == hipSuccess) e = launch_residual_rows(db, dtype, N, D, cent, asg, keys, s);
+    if (e != hipSuccess) {
+        hip_fail(e, "cluster assignment");
+        return bail();
+    }
+    os_ann_index* ix = build_table(keys, kF32, D, db, dtype, N, D, L, nc, s, asg, C);  // synchronizes
+    if (!ix) return bail();
+    dev_free(keys);
+    dev_free(asg);
+    ix->ivf_cent = cent;
+    ix->nprobe = nprobe;
+    ix->device_bytes += (size_t)C * D * 4;
+    return ix;
+}
+
+int os_ann_set_nprobe(os_ann_index* ix, int32_t nprobe) {
+    clear_error();
+    if (!ix) return fail(OS_ANN_EINVAL, "null index");
+    if (!ix->ivf_cent) return fail(OS_ANN_EINVAL, "not a clustered table");
+    if (nprobe < 1 || nprobe > ix->n_groups || nprobe > 64) return fail(OS_ANN_EINVAL, "nprobe out of range");
+    std::lock_guard<std::mutex> g(ix->graph_mu);
+    drop_graphs(ix);  // captured searches used the old count
+    ix->nprobe = nprobe;
+    return OS_ANN_OK;
+}
+
 int os_ann_export_basis(const os_ann_index* ix, int32_t r, uint32_t* row_cone, uint64_t* row_top,
                         int64_t* offsets, int64_t* perm, void* stream) {
     clear_error();
@@ -1293,6 +1516,7 @@ int os_ann_classify(const os_ann_index* cidx, const void* queries, int32_t query
     clear_error();
     if (cidx && cidx->n_rot > 0) return fail(OS_ANN_ENOTSUP, "classify: one basis only");
     if (cidx && cidx->proj) return fail(OS_ANN_ENOTSUP, "classify: not for a projected table");
+    if (cidx && cidx->ivf_cent) return fail(OS_ANN_ENOTSUP, "classify: not for a clustered table");
     os_ann_search_opts o{};
     o.query_dtype = query_dtype;
     int rc = search_checks(cidx, queries, Q, max_candidates, &o);
@@ -1333,7 +1557,8 @@ int os_ann_export(const os_ann_index* ix, uint32_t* row_cone, uint64_t* row_top,
     if (row_top)
         OSANN_HIP(hipMemcpyAsync(row_top, ix->row_top, (size_t)ix->N * 8, hipMemcpyDeviceToDevice, s),
                   "export top");
-    if (offsets) OSANN_HIP(launch_widen_u32(ix->offsets, ix->n_cones + 1, offsets, s), "export offsets");
+    if (offsets)
+        OSANN_HIP(launch_widen_u32(ix->offsets, ix->n_cones * ix->n_groups + 1, offsets, s), "export offsets");
     if (perm) OSANN_HIP(launch_widen_u32(ix->perm, ix->N, perm, s), "export perm");
     return OS_ANN_OK;
 }
@@ -1386,7 +1611,7 @@ int os_ann_info(const os_ann_index* ix, int64_t* N, int32_t* D, int32_t* L, int6
     if (N) *N = ix->N;
     if (D) *D = ix->D;
     if (L) *L = ix->L;
-    if (n_cones) *n_cones = ix->n_cones;
+    if (n_cones) *n_cones = ix->n_cones * ix->n_groups;  // buckets
     if (n_nonempty) *n_nonempty = ix->n_nonempty;
     if (device_bytes) *device_bytes = (int64_t)ix->device_bytes;
     return OS_ANN_OK;

@@ -115,6 +115,7 @@ struct ProbeArgs {
     int64_t nw;
     const uint32_t* ne_id;  // cone -> rank among the non-empty cones
     int64_t n_ne;
+    const uint32_t* cone_base;  // [Q] first bucket of each query's cone ids in offsets (null: 0)
 };
 hipError_t launch_probe(const ProbeArgs& a, hipStream_t s);
 
@@ -138,6 +139,7 @@ struct ScanArgs {
     int64_t* out_idx;
     float* out_dist;
     int waves_per_query;    // 1, 2 or 4
+    const uint32_t* cone_base;  // [Q] first bucket of each query's cone ids in offsets (null: 0)
 };
 hipError_t launch_scan_fp32(const ScanArgs& a, hipStream_t s);
 

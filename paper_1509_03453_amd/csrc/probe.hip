@@ -110,6 +110,7 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
 
     // 5. walk the probe sequence 64 positions at a time until the budget is met
     const uint64_t budget = (uint64_t)a.budget;
+    const uint32_t* offs = a.offsets + (a.cone_base ? a.cone_base[q] : 0u);  // this query's buckets
     uint64_t carry = 0;
     uint32_t np = 0, stop_at = 0;
     for (int64_t j0 = 0; j0 < a.n_cones; j0 += 64) {
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
         uint32_t len = 0, c = 0;
         if (j < a.n_cones) {
             c = probe_cone(j, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
-            len = a.offsets[c + 1] - a.offsets[c];
+            len = offs[c + 1] - offs[c];
         }
         const uint32_t incl = wave_incl_scan(len);
         const uint64_t tot = carry + incl;

@@ -92,14 +92,15 @@ __global__ __launch_bounds__(256) void scan_fp32_kernel(ScanArgs a) {
     } else {
         uint32_t* st = s_start[w];
         uint32_t* in = s_incl[w];
+        const uint32_t* offs = a.offsets + (qv && a.cone_base ? a.cone_base[q] : 0u);  // this query's buckets
         for (uint32_t j0 = 0; j0 < jstop; j0 += 64) {
             // this wave's copy of the chunk's bucket starts and running counts
             const uint32_t j = j0 + l;
             uint32_t start = 0, len = 0;
             if (j < jstop) {
                 const uint32_t c = probe_cone(j, a.L, s_order[slot], s_sbit[slot], a.n_sub, a.lexsub, a.maskord, a.binom);
-                start = a.offsets[c];
-                len = a.offsets[c + 1] - start;
+                start = offs[c];
+                len = offs[c + 1] - start;
             }
             const uint32_t incl = wave_incl_scan(len);
             st[l] = start;
