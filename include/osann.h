@@ -239,7 +239,7 @@ int os_ann_kmeans(const void *db, int64_t N, int32_t D, int32_t C, int32_t iters
  * (distance, row) wins; ncand sums the clusters' candidates (-1 as the row
  * if every searched cluster is empty).  FP32 mode only (tiled: ENOTSUP);
  * opts->want_lowp must be 0; os_ann_classify: ENOTSUP.  Requires
- * 1 <= nprobe <= min(C, 64), C <= 4096 and C * C(D,L) 2^L <= 2^24.
+ * 1 <= nprobe <= min(C, 64), C <= 1024 and C * C(D,L) 2^L <= 2^24.
  * Synchronous.  Errors: EINVAL, ENOMEM, EDEVICE, ENOTSUP, ENONFINITE
  * (returns NULL).
  */

@@ -133,30 +133,39 @@ hipError_t launch_compose_cones(uint32_t* cone, const uint32_t* group, int64_t N
 
 constexpr int kMaxProbeClusters = 64;
 
-// One wave per query: lanes take centroids l, l + 64, ...; the nprobe
-// nearest are picked one at a time by a wave arg-min on (distance, id).
+// One wave per query: lanes compute the distances to centroids l, l + 64,
+// ... once into LDS; the nprobe nearest are then picked one at a time by a
+// wave arg-min on (distance, id) over the centroids not yet picked.
 __global__ __launch_bounds__(256) void ivf_queries_kernel(IvfQueryArgs a) {
 #pragma clang fp contract(off)
+    __shared__ float s_dist[4][kMaxClusters];
     __shared__ int s_sel[4][kMaxProbeClusters];
     const int w = threadIdx.x / 64, l = lane_id();
     const int64_t q = (int64_t)blockIdx.x * 4 + w;
     if (q >= a.Q) return;
     const float* y = a.yf + q * a.dpad;
-    uint64_t taken = 0;  // per lane: bit i = centroid l + 64 i already picked (C <= 64 * 64)
+    for (int c = l; c < a.C; c += 64) {
+        const float* m = a.cent + (int64_t)c * a.D;
+        float acc = 0.0f;
+        for (int j = 0; j < a.D; ++j) {
+            const float df = y[j] - m[j];
+            const float sq = df * df;
+            acc = acc + sq;
+        }
+        s_dist[w][c] = acc;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    uint32_t taken = 0;  // per lane: bit i = centroid l + 64 i already picked (C <= 64 * 32)
     for (int t = 0; t < a.nprobe; ++t) {
         float bd = __builtin_huge_valf();
         int bc = 0x7FFFFFFF;
         for (int c = l, i = 0; c < a.C; c += 64, ++i) {
-            if ((taken >> i) & 1ull) continue;
-            const float* m = a.cent + (int64_t)c * a.D;
-            float acc = 0.0f;
-            for (int j = 0; j < a.D; ++j) {
-                const float df = y[j] - m[j];
-                const float sq = df * df;
-                acc = acc + sq;
-            }
-            if (acc < bd || (acc == bd && c < bc)) {
-                bd = acc;
+            if ((taken >> i) & 1u) continue;
+            const float d = s_dist[w][c];
+            if (d < bd || (d == bd && c < bc)) {
+                bd = d;
                 bc = c;
             }
         }
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(256) void ivf_queries_kernel(IvfQueryArgs a) {
                 bc = oc;
             }
         }
-        if (bc % 64 == l) taken |= 1ull << (bc / 64);
+        if (bc % 64 == l) taken |= 1u << (bc / 64);
         if (l == 0) s_sel[w][t] = bc;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -186,7 +195,7 @@ __global__ __launch_bounds__(256) void ivf_queries_kernel(IvfQueryArgs a) {
 
 hipError_t launch_ivf_queries(const IvfQueryArgs& a, hipStream_t s) {
     if (a.Q <= 0) return hipSuccess;
-    if (a.nprobe < 1 || a.nprobe > kMaxProbeClusters || a.nprobe > a.C || a.C > 64 * 64)
+    if (a.nprobe < 1 || a.nprobe > kMaxProbeClusters || a.nprobe > a.C || a.C > kMaxClusters)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(ivf_queries_kernel, dim3((unsigned)((a.Q + 3) / 4)), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -1379,8 +1379,8 @@ os_ann_index* os_ann_build_ivf(const void* db, int64_t N, int32_t D, int32_t L, 
         return nullptr;
     }
     if (check_shape(N, D, L, &nc)) return nullptr;
-    if (C < 1 || C > 4096 || nprobe < 1 || nprobe > C || nprobe > 64) {
-        fail(OS_ANN_EINVAL, "need 1 <= nprobe <= min(C, 64) and C <= 4096");
+    if (C < 1 || C > kMaxClusters || nprobe < 1 || nprobe > C || nprobe > 64) {
+        fail(OS_ANN_EINVAL, "need 1 <= nprobe <= min(C, 64) and C <= 1024");
         return nullptr;
     }
     if (nc * C > kMaxCones) {

@@ -6,6 +6,8 @@
 
 namespace osann {
 
+constexpr int kMaxClusters = 1024;  // centroids of a clustered table (search keeps their distances in LDS)
+
 // Nearest centroid of each row: FP32 term-by-term squared distance, the lower
 // centroid on ties.  cent is C x D row-major FP32.
 hipError_t launch_assign(const void* X, int dtype, int64_t N, int D, const float* cent, int C, uint32_t* out,

@@ -36,7 +36,7 @@ SEEDS = {
     "gauss16_db": 1001, "gauss16_q": 1002,
     "gauss64_db": 2001, "gauss64_q": 2002,
     "desc_db": 3001, "desc_pick": 3002, "desc_noise": 3003,
-    "sift_db": 3011,
+    "sift_db": 3011, "kmeans_init": 3012,
     "patch_field": 4001, "patch_noise": 4002, "patch_sample": 4003,
     "serve_arrivals": 5001,
     "bases": 6001,
@@ -83,6 +83,12 @@ def sift_like_db(n: int, d: int = 128, seed: int = SEEDS["sift_db"], decay: floa
         z = r.standard_normal((m, int(d))) * sig[None, :]
         out[s:s + m] = np.rint(np.clip(mean + z @ q.T, 0.0, 255.0)).astype(np.uint8)
     return out
+
+
+def pick_rows(n: int, k: int, seed: int = SEEDS["kmeans_init"]) -> np.ndarray:
+    """``k`` distinct row ids out of ``n`` in increasing order (seeded), e.g.
+    the initial k-means centroids."""
+    return np.sort(_rng(seed).choice(int(n), size=int(k), replace=False))
 
 
 def descriptor_queries(db_u8: np.ndarray, q: int,
