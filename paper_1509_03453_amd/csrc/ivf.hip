@@ -40,14 +40,66 @@ __global__ void assign_kernel(const void* __restrict__ X, int64_t N, int D, cons
     out[n] = bc;
 }
 
+// The same decision with the row held in registers and the centroids staged
+// through LDS 32 at a time (every lane reads the same centroid element: a
+// broadcast); the j loop runs over the row's D components in order.
+template <typename E, int DMAX>
+__global__ __launch_bounds__(256) void assign_reg_kernel(const void* __restrict__ X, int64_t N, int D,
+                                                         const float* __restrict__ cent, int C,
+                                                         uint32_t* __restrict__ out) {
+#pragma clang fp contract(off)
+    constexpr int CT = 32;
+    __shared__ float sc[CT][DMAX];
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = n < N;
+    float xr[DMAX];
+    auto x = static_cast<const typename E::raw*>(X) + (valid ? n : 0) * D;
+#pragma unroll
+    for (int j = 0; j < DMAX; ++j) xr[j] = j < D && valid ? E::val(x[j]) : 0.0f;
+    float best = __builtin_huge_valf();
+    uint32_t bc = 0;
+    for (int c0 = 0; c0 < C; c0 += CT) {
+        const int nt = C - c0 < CT ? C - c0 : CT;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nt * D; e += blockDim.x) sc[e / D][e % D] = cent[(int64_t)c0 * D + e];
+        __syncthreads();
+        if (valid)
+            for (int ci = 0; ci < nt; ++ci) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int j = 0; j < DMAX; ++j)
+                    if (j < D) {
+                        const float df = xr[j] - sc[ci][j];
+                        const float sq = df * df;
+                        acc = acc + sq;
+                    }
+                if (acc < best) {
+                    best = acc;
+                    bc = (uint32_t)(c0 + ci);
+                }
+            }
+    }
+    if (valid) out[n] = bc;
+}
+
+template <typename E>
+static void assign_t(const void* X, int64_t N, int D, const float* cent, int C, uint32_t* out, hipStream_t s) {
+    const dim3 grid((unsigned)((N + 255) / 256));
+    if (D <= 64)
+        hipLaunchKernelGGL((assign_reg_kernel<E, 64>), grid, dim3(256), 0, s, X, N, D, cent, C, out);
+    else if (D <= 128)
+        hipLaunchKernelGGL((assign_reg_kernel<E, 128>), grid, dim3(256), 0, s, X, N, D, cent, C, out);
+    else
+        hipLaunchKernelGGL(assign_kernel<E>, grid, dim3(256), 0, s, X, N, D, cent, C, out);
+}
+
 hipError_t launch_assign(const void* X, int dtype, int64_t N, int D, const float* cent, int C, uint32_t* out,
                          hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((N + 255) / 256));
     switch (dtype) {
-        case kF32: hipLaunchKernelGGL(assign_kernel<F32>, grid, dim3(256), 0, s, X, N, D, cent, C, out); break;
-        case kF16: hipLaunchKernelGGL(assign_kernel<F16>, grid, dim3(256), 0, s, X, N, D, cent, C, out); break;
-        case kU8: hipLaunchKernelGGL(assign_kernel<U8>, grid, dim3(256), 0, s, X, N, D, cent, C, out); break;
+        case kF32: assign_t<F32>(X, N, D, cent, C, out, s); break;
+        case kF16: assign_t<F16>(X, N, D, cent, C, out, s); break;
+        case kU8: assign_t<U8>(X, N, D, cent, C, out, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
