@@ -58,6 +58,8 @@ def lib():
             L.orc_walk.argtypes = [p, i32, i32, p, i64]
             L.orc_probe.restype = i64
             L.orc_probe.argtypes = [p, i32, i32, p, i64, p, i64, p]
+            L.orc_probe_cones.restype = i64
+            L.orc_probe_cones.argtypes = [p, i32, i32, p, i64, p, i64, p]
             L.orc_search.restype = i32
             L.orc_search.argtypes = [p, i32, i64, i32, i32, p, p, p, i32, i64, i64, p, p, p, p, i32]
             L.orc_exhaustive.restype = i32
@@ -68,7 +70,7 @@ def lib():
             L.orc_pair_d32.argtypes = [p, i32, i32, p, i32, p, i64, p]
             L.orc_search_tiled.restype = i32
             L.orc_search_tiled.argtypes = [p, i32, i64, i32, i32, p, p, p, i32, i64, i64, i32, i32,
-                                           p, p, p, p, p, p, i32]
+                                           p, p, p, p, p, p, i32, i32]
             L.orc_pair_dtilde.restype = i32
             L.orc_pair_dtilde.argtypes = [p, i32, i32, p, i32, p, i64, i32, p]
             L.orc_round_short.restype = i32
@@ -77,10 +79,10 @@ def lib():
             L.orc_rotate.argtypes = [p, i32, i64, i32, p, p]
             L.orc_search_rot.restype = i32
             L.orc_search_rot.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, p, i32, i64, i64,
-                                         p, p, p, p, i32]
+                                         p, p, p, p, i32, i32]
             L.orc_search_keyed.restype = i32
             L.orc_search_keyed.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, i32, p, i64, i64,
-                                           p, p, p, p, i32]
+                                           p, p, p, p, i32, i32]
             L.orc_project.restype = i32
             L.orc_project.argtypes = [p, i32, i64, i32, p, p, i32, p]
             L.orc_assign.restype = i32
@@ -89,7 +91,7 @@ def lib():
             L.orc_kmeans_update.argtypes = [p, i32, i64, i32, p, i32, p, p]
             L.orc_search_ivf.restype = i32
             L.orc_search_ivf.argtypes = [p, i32, i64, i32, i32, p, i32, p, p, p, i32, i64, i64, i32,
-                                         p, p, p, p, i32]
+                                         p, p, p, p, i32, i32]
             _lib = L
     return _lib
 
@@ -185,8 +187,23 @@ def probe(y, G: int, offsets, B: int):
     return out[:n].copy(), int(nca[0])
 
 
-def search(X, index, Y, B: int, nthreads: int = 0):
-    """Algorithm 1 with one basis: ``(idx, d32, d64, ncand)`` per query."""
+def probe_cones(y, G: int, offsets, n_take: int):
+    """Fixed-C mode (reading R13): the non-empty cones among the first
+    ``n_take`` (the paper's C) cones of the walk, and their candidate count."""
+    y, py = _arr(y, np.float32)
+    off, po = _arr(offsets, np.int64)
+    K = y.shape[0]
+    nc = off.shape[0] - 1
+    out = np.empty(nc, dtype=np.int64)
+    nca = np.zeros(1, dtype=np.int64)
+    n = lib().orc_probe_cones(py, K, G, po, int(n_take), out.ctypes.data_as(C.c_void_p), nc,
+                              nca.ctypes.data_as(C.c_void_p))
+    return out[:n].copy(), int(nca[0])
+
+
+def search(X, index, Y, B: int, nthreads: int = 0, cones: bool = False):
+    """Algorithm 1 with one basis: ``(idx, d32, d64, ncand)`` per query.
+    With ``cones`` the budget ``B`` counts cones (reading R13)."""
     X, px, xdt = _rows(X)
     Y, py, ydt = _rows(Y)
     N, K = X.shape
@@ -197,10 +214,10 @@ def search(X, index, Y, B: int, nthreads: int = 0):
     d32 = np.empty(Q, dtype=np.float32)
     d64 = np.empty(Q, dtype=np.float64)
     nca = np.empty(Q, dtype=np.int64)
-    rc = lib().orc_search(px, xdt, N, K, index["G"], po, pp, py, ydt, Q, int(B),
-                          idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
-                          d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
-                          int(nthreads))
+    rc = lib().orc_search_keyed(px, xdt, N, K, K, index["G"], po, pp, py, ydt, None, Q, int(B),
+                                idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
+                                d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
+                                int(nthreads), int(bool(cones)))
     if rc != 0:
         raise RuntimeError(f"orc_search failed ({rc})")
     return idx, d32, d64, nca
@@ -242,8 +259,10 @@ def pair_d32(X, Y, rows) -> np.ndarray:
     return out
 
 
-def search_tiled(X, index, Y, B: int, R: int = 8, use_f16: bool | None = None, nthreads: int = 0):
+def search_tiled(X, index, Y, B: int, R: int = 8, use_f16: bool | None = None, nthreads: int = 0,
+                 cones: bool = False):
     """Screened search (reading R7): ``(idx, d32, d64, ncand, dt_R, top)``.
+    With ``cones`` the budget ``B`` counts cones (reading R13).
 
     ``use_f16`` defaults to True for float16 rows (the rows are kept as
     stored) and False otherwise (bfloat16 rounding)."""
@@ -264,7 +283,8 @@ def search_tiled(X, index, Y, B: int, R: int = 8, use_f16: bool | None = None, n
     rc = lib().orc_search_tiled(px, xdt, N, K, index["G"], po, pp, py, ydt, Q, int(B), int(R), int(use_f16),
                                 idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
                                 d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
-                                dtr.ctypes.data_as(C.c_void_p), top.ctypes.data_as(C.c_void_p), int(nthreads))
+                                dtr.ctypes.data_as(C.c_void_p), top.ctypes.data_as(C.c_void_p), int(nthreads),
+                                int(bool(cones)))
     if rc != 0:
         raise RuntimeError(f"orc_search_tiled failed ({rc})")
     return idx, d32, d64, nca, dtr, top
@@ -309,8 +329,9 @@ def build_index_rot(X, G: int, rots):
     return {"tables": tabs, "rots": rots, "G": G, "K": X.shape[1], "n_cones": tabs[0]["n_cones"]}
 
 
-def search_rot(X, index, Y, B: int, nthreads: int = 0):
-    """Algorithm 1 with several bases: ``(idx, d32, d64, ncand)`` per query."""
+def search_rot(X, index, Y, B: int, nthreads: int = 0, cones: bool = False):
+    """Algorithm 1 with several bases: ``(idx, d32, d64, ncand)`` per query.
+    With ``cones`` the search visits levels 0..B-1 of every basis (reading R13)."""
     X, px, xdt = _rows(X)
     Y, py, ydt = _rows(Y)
     N, K = X.shape
@@ -326,7 +347,7 @@ def search_rot(X, index, Y, B: int, nthreads: int = 0):
     rc = lib().orc_search_rot(px, xdt, N, K, index["G"], R, pr, po, pp, py, ydt, Q, int(B),
                               idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
                               d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
-                              int(nthreads))
+                              int(nthreads), int(bool(cones)))
     if rc != 0:
         raise RuntimeError(f"orc_search_rot failed ({rc})")
     return idx, d32, d64, nca
@@ -388,7 +409,7 @@ def build_index_proj(X, G: int, mu, P):
     return idx
 
 
-def search_proj(X, index, Y, B: int, nthreads: int = 0):
+def search_proj(X, index, Y, B: int, nthreads: int = 0, cones: bool = False):
     """Algorithm 1 on a keyed table: each query walks the cones of its own key,
     candidates are compared on all components.  ``(idx, d32, d64, ncand)``."""
     Yk = project(Y, index["mu"], index["P"])
@@ -407,7 +428,7 @@ def search_proj(X, index, Y, B: int, nthreads: int = 0):
                                 Yk.ctypes.data_as(C.c_void_p), Q, int(B),
                                 idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
                                 d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
-                                int(nthreads))
+                                int(nthreads), int(bool(cones)))
     if rc != 0:
         raise RuntimeError(f"orc_search_keyed failed ({rc})")
     return idx, d32, d64, nca
@@ -460,8 +481,10 @@ def build_index_ivf(X, G: int, cent):
             "n_cones": nc, "K": X.shape[1], "G": G, "cent": cent}
 
 
-def search_ivf(X, index, Y, B: int, nprobe: int, nthreads: int = 0):
-    """Search in the nprobe nearest clusters: ``(idx, d32, d64, ncand)``."""
+def search_ivf(X, index, Y, B: int, nprobe: int, nthreads: int = 0, cones: bool = False):
+    """Search in the nprobe nearest clusters: ``(idx, d32, d64, ncand)``.
+    With ``cones`` each searched cluster takes the first B cones of its walk
+    (reading R13)."""
     X, px, xdt = _rows(X)
     Y, py, ydt = _rows(Y)
     N, K = X.shape
@@ -475,7 +498,8 @@ def search_ivf(X, index, Y, B: int, nprobe: int, nthreads: int = 0):
     nca = np.empty(Q, dtype=np.int64)
     rc = lib().orc_search_ivf(px, xdt, N, K, index["G"], pc, cent.shape[0], po, pp, py, ydt, Q, int(B),
                               int(nprobe), idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
-                              d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p), int(nthreads))
+                              d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p), int(nthreads),
+                              int(bool(cones)))
     if rc != 0:
         raise RuntimeError(f"orc_search_ivf failed ({rc})")
     return idx, d32, d64, nca

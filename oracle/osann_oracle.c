@@ -52,6 +52,10 @@
  *       walks the cones of its residual with budget ceil(B / nprobe); every
  *       row met is compared on the full vectors; ncand sums the clusters'
  *       candidates.
+ *   R13 fixed-C mode (Section 3, Table III): the budget counts cones
+ *       instead of rows: the first C cones of the walk (empty ones included)
+ *       are visited, per basis (several bases: levels 0..C-1 of every basis)
+ *       and per searched cluster.
  *
  * Precision: distances are produced both in double (the definition, eq. (1))
  * and in FP32 evaluated term by term in ascending component order with each
@@ -354,6 +358,41 @@ int64_t orc_probe(const float *y, int K, int G, const int64_t *offsets, int64_t 
     return c.n;
 }
 
+struct cones_ctx {
+    const int64_t *offsets;
+    int64_t C, seen, cum;
+    int64_t *probes;
+    int64_t cap, n;
+};
+
+/* Reading R13: the first C cones of the walk, empty ones included; the
+ * non-empty ones are the probes. */
+static int take_first_cones(int64_t cone, void *vctx)
+{
+    struct cones_ctx *c = (struct cones_ctx *)vctx;
+    if (c->seen >= c->C)
+        return 1;
+    c->seen++;
+    int64_t size = c->offsets[cone + 1] - c->offsets[cone];
+    if (size > 0) {
+        if (c->n < c->cap)
+            c->probes[c->n] = cone;
+        c->n++;
+        c->cum += size;
+    }
+    return c->seen >= c->C;
+}
+
+/* Probe list of one query in fixed-C mode. */
+int64_t orc_probe_cones(const float *y, int K, int G, const int64_t *offsets, int64_t C,
+                        int64_t *probes, int64_t cap, int64_t *ncand)
+{
+    struct cones_ctx c = { offsets, C, 0, 0, probes, cap, 0 };
+    walk_cones(y, K, G, take_first_cones, &c);
+    *ncand = c.cum;
+    return c.n;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Distance and arg-min (eq. (1), Algorithm 1)                               */
 /* ------------------------------------------------------------------------ */
@@ -398,14 +437,15 @@ static void set_threads(int nthreads)
  * cones taken from keys (reading R11): the table was built from the rows'
  * keys of length Kk; each query walks the cones of its key (row q of Yk, or
  * the query itself when Yk is NULL, Kk = K), its probes are visited in order
- * until B candidates are reached, and every row of those cones is compared
- * with the query on all K components.  Outputs per query: the row (out_idx),
+ * until B candidates are reached (with cones set, reading R13: the first B
+ * cones of the walk), and every row of those cones is compared with the
+ * query on all K components.  Outputs per query: the row (out_idx),
  * its FP32 and double distances, and the number of candidates. */
 int orc_search_keyed(const void *X, int xdtype, int64_t N, int K, int Kk, int G,
                      const int64_t *offsets, const int64_t *perm,
                      const void *Y, int ydtype, const float *Yk, int64_t Q, int64_t B,
                      int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
-                     int nthreads)
+                     int nthreads, int cones)
 {
     (void)N;
     if (K < 1 || K > 256 || Kk < 1 || Kk > 256 || G < 1 || G > Kk || B < 1)
@@ -430,7 +470,8 @@ int orc_search_keyed(const void *X, int xdtype, int64_t N, int K, int Kk, int G,
             continue;
         }
         int64_t ncand = 0;
-        int64_t np = orc_probe(yk, Kk, G, offsets, B, probes, NC, &ncand);
+        int64_t np = cones ? orc_probe_cones(yk, Kk, G, offsets, B, probes, NC, &ncand)
+                           : orc_probe(yk, Kk, G, offsets, B, probes, NC, &ncand);
         float best_d = INFINITY;
         int64_t best_row = INT64_MAX;
         double best_d64 = INFINITY;
@@ -467,7 +508,7 @@ int orc_search(const void *X, int xdtype, int64_t N, int K, int G,
                int nthreads)
 {
     return orc_search_keyed(X, xdtype, N, K, K, G, offsets, perm, Y, ydtype, NULL, Q, B,
-                            out_idx, out_d32, out_d64, out_ncand, nthreads);
+                            out_idx, out_d32, out_d64, out_ncand, nthreads, 0);
 }
 
 /* Exact NN by linear search over all rows (eq. (1)).  idx32/d32 take the
@@ -595,7 +636,7 @@ int orc_search_tiled(const void *X, int xdtype, int64_t N, int K, int G,
                      const int64_t *offsets, const int64_t *perm,
                      const void *Y, int ydtype, int64_t Q, int64_t B, int R, int use_f16,
                      int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
-                     double *out_dt_R, int64_t *out_top, int nthreads)
+                     double *out_dt_R, int64_t *out_top, int nthreads, int cones)
 {
     (void)N;
     if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || R < 1 || R > 64)
@@ -617,7 +658,8 @@ int orc_search_tiled(const void *X, int xdtype, int64_t N, int K, int G,
             continue;
         }
         int64_t ncand = 0;
-        int64_t np = orc_probe(y, K, G, offsets, B, probes, NC, &ncand);
+        int64_t np = cones ? orc_probe_cones(y, K, G, offsets, B, probes, NC, &ncand)
+                           : orc_probe(y, K, G, offsets, B, probes, NC, &ncand);
         struct cand top[64];
         int kept = 0;
         for (int64_t k = 0; k < np; k++) {
@@ -733,13 +775,14 @@ int orc_rotate(const void *X, int dtype, int64_t N, int K, const float *M, float
  * gets its distance computed (on the original vectors), updates the arg-min
  * and is marked.  Reading R10: the budget counts the rows of the visited
  * cones, a row met again in another basis counting again, and the search
- * stops after the cone at which that count reaches B.  ncand is the number
- * of distinct rows whose distance was computed. */
+ * stops after the cone at which that count reaches B (with cones set,
+ * reading R13: after level B-1 of every basis).  ncand is the number of
+ * distinct rows whose distance was computed. */
 int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, const float *rot,
                    const int64_t *offsets, const int64_t *perms,
                    const void *Y, int ydtype, int64_t Q, int64_t B,
                    int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
-                   int nthreads)
+                   int nthreads, int cones)
 {
     if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || R < 1)
         return -1;
@@ -789,9 +832,11 @@ int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, co
                     ncand++;
                 }
                 visited += off[c + 1] - off[c];
-                if (visited >= B)
+                if (!cones && visited >= B)
                     done = 1;
             }
+            if (cones && l + 1 >= B)
+                done = 1;
         }
         out_idx[q] = best_row;
         out_d32[q] = best_d;
@@ -897,7 +942,7 @@ int orc_kmeans_update(const void *X, int dtype, int64_t N, int K, const int32_t 
 int orc_search_ivf(const void *X, int xdtype, int64_t N, int K, int G, const float *cent, int C,
                    const int64_t *offsets, const int64_t *perm, const void *Y, int ydtype, int64_t Q,
                    int64_t B, int nprobe, int64_t *out_idx, float *out_d32, double *out_d64,
-                   int64_t *out_ncand, int nthreads)
+                   int64_t *out_ncand, int nthreads, int cones)
 {
     (void)N;
     if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || nprobe < 1 || nprobe > C)
@@ -939,7 +984,8 @@ int orc_search_ivf(const void *X, int xdtype, int64_t N, int K, int G, const flo
                 r[j] = y[j] - cent[(int64_t)bc * K + j];
             const int64_t *off = offsets + (int64_t)bc * NC;
             int64_t nc_c = 0;
-            int64_t np = orc_probe(r, K, G, off, Bc, probes, NC, &nc_c);
+            int64_t np = cones ? orc_probe_cones(r, K, G, off, B, probes, NC, &nc_c)
+                               : orc_probe(r, K, G, off, Bc, probes, NC, &nc_c);
             ncand += nc_c;
             for (int64_t k = 0; k < np; k++) {
                 int64_t cone = probes[k];
