@@ -55,7 +55,8 @@
  *   R13 fixed-C mode (Section 3, Table III): the budget counts cones
  *       instead of rows: the first C cones of the walk (empty ones included)
  *       are visited, per basis (several bases: levels 0..C-1 of every basis)
- *       and per searched cluster.
+ *       and per searched cluster.  When every cone taken is empty the search
+ *       has no candidate: the row is -1 and the distance +inf.
  *
  * Precision: distances are produced both in double (the definition, eq. (1))
  * and in FP32 evaluated term by term in ascending component order with each
@@ -489,7 +490,7 @@ int orc_search_keyed(const void *X, int xdtype, int64_t N, int K, int Kk, int G,
                     best_d64 = d64;
             }
         }
-        out_idx[q] = best_row;
+        out_idx[q] = best_row == INT64_MAX ? -1 : best_row;  /* -1: no candidate (R13) */
         out_d32[q] = best_d;
         out_d64[q] = best_d64;
         out_ncand[q] = ncand;
@@ -698,7 +699,7 @@ int orc_search_tiled(const void *X, int xdtype, int64_t N, int K, int G,
             if (best_row != before)
                 best_d64 = d64;
         }
-        out_idx[q] = best_row;
+        out_idx[q] = best_row == INT64_MAX ? -1 : best_row;  /* -1: no candidate (R13) */
         out_d32[q] = best_d;
         out_d64[q] = best_d64;
         out_ncand[q] = ncand;
@@ -838,7 +839,7 @@ int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, co
             if (cones && l + 1 >= B)
                 done = 1;
         }
-        out_idx[q] = best_row;
+        out_idx[q] = best_row == INT64_MAX ? -1 : best_row;  /* -1: no candidate (R13) */
         out_d32[q] = best_d;
         out_d64[q] = best_d64;
         out_ncand[q] = ncand;

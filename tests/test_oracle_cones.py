@@ -163,3 +163,16 @@ def test_screened_search_takes_the_same_candidates():
         # the screened answer is a candidate whose distance is at least the arg-min's
         has = a[3] > 0
         assert (t[2][has] >= a[2][has]).all()
+
+
+def test_empty_cones_give_no_candidate():
+    # 300 rows over 180 cones: some queries' own cones are empty
+    X = W.gaussian_db(300, 10, seed=160)
+    Y = W.gaussian_queries(80, 10, seed=161)
+    ix = O.build_index(X, 2)
+    empty = _sizes(ix)[O.hash_rows(Y, 2)[2]] == 0
+    assert empty.any()
+    for res in (O.search(X, ix, Y, 1, cones=True), O.search_tiled(X, ix, Y, 1, cones=True)):
+        assert np.array_equal(res[3] == 0, empty)
+        assert (res[0][empty] == -1).all() and np.isinf(res[1][empty]).all()
+        assert (res[0][~empty] >= 0).all()
