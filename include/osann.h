@@ -81,6 +81,15 @@ extern "C" {
                                        first call with these exact arguments (pointers,
                                        sizes, stream; non-null stream only) and replay it
                                        on later identical calls */
+#define OS_ANN_FLAG_BUDGET_CONES 4  /* fixed-C mode (Section 3, Table III): max_candidates
+                                       is the number C of cones each walk takes, empty
+                                       ones included, not a number of rows; with several
+                                       bases the search takes levels 0..C-1 of every
+                                       basis, on a clustered table the first C cones of
+                                       each searched cluster.  out_ncand is then the rows
+                                       the search compared (distinct rows with several
+                                       bases; 0 and out_idx = -1, out_dist = +inf when
+                                       every cone taken is empty) */
 
 /* Kernel ids of os_ann_kernel_time. */
 #define OS_ANN_KERNEL_PROBE  0  /* query classification + walk state */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libosann.so
 OS_ANN_OK, OS_ANN_EINVAL, OS_ANN_ENOMEM, OS_ANN_EDEVICE, OS_ANN_ENOTSUP, OS_ANN_ENONFINITE = 0, -1, -2, -3, -4, -5
 OS_ANN_F32, OS_ANN_F16, OS_ANN_U8 = 0, 1, 2
 OS_ANN_MODE_FP32, OS_ANN_MODE_TILED = 0, 1
-OS_ANN_FLAG_TIME_KERNELS, OS_ANN_FLAG_GRAPH = 1, 2
+OS_ANN_FLAG_TIME_KERNELS, OS_ANN_FLAG_GRAPH, OS_ANN_FLAG_BUDGET_CONES = 1, 2, 4
 OS_ANN_KERNEL_PROBE, OS_ANN_KERNEL_SCAN, OS_ANN_KERNEL_SCREEN, OS_ANN_KERNEL_FINISH, OS_ANN_KERNEL_GRAPH = 0, 1, 2, 3, 4
 
 _DTYPE_CODE = {torch.float32: OS_ANN_F32, torch.float16: OS_ANN_F16, torch.uint8: OS_ANN_U8}
@@ -256,8 +256,12 @@ def os_ann_search(index: int, queries: torch.Tensor, max_candidates: int,
 def os_ann_search_ex(index: int, queries: torch.Tensor, max_candidates: int, mode: int = OS_ANN_MODE_FP32,
                      stream=None, workspace: torch.Tensor | None = None, rerank_r: int = 8,
                      out_idx=None, out_dist=None, out_ncand=None, want_ncand: bool = True,
-                     flags: int = 0):
-    """As os_ann_search with options; returns ``(idx, dist, ncand or None)``."""
+                     flags: int = 0, cones: bool = False):
+    """As os_ann_search with options; returns ``(idx, dist, ncand or None)``.
+    ``cones``: max_candidates is the number C of cones each walk takes
+    (OS_ANN_FLAG_BUDGET_CONES)."""
+    if cones:
+        flags |= OS_ANN_FLAG_BUDGET_CONES
     o = _search_opts(queries, mode, stream, workspace, rerank_r, flags)
     Q = queries.shape[0]
     dev = queries.device
@@ -273,8 +277,9 @@ def os_ann_search_ex(index: int, queries: torch.Tensor, max_candidates: int, mod
 
 
 def os_ann_workspace_bytes(index: int, Q: int, max_candidates: int, mode: int = OS_ANN_MODE_FP32,
-                           rerank_r: int = 8) -> int:
-    o = os_ann_search_opts(int(mode), int(rerank_r), OS_ANN_F32, 0, None, None, 0)
+                           rerank_r: int = 8, cones: bool = False) -> int:
+    o = os_ann_search_opts(int(mode), int(rerank_r), OS_ANN_F32, OS_ANN_FLAG_BUDGET_CONES if cones else 0,
+                           None, None, 0)
     n = lib().os_ann_workspace_bytes(index, int(Q), int(max_candidates), C.byref(o))
     if n < 0:
         _raise(n)

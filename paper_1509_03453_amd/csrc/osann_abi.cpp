@@ -15,6 +15,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "osann_fixedc.h"
 #include "osann_ivf.h"
 #include "osann_kernels.h"
 #include "osann_tiled.h"
@@ -308,6 +309,7 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
 struct SearchPlan {
     int64_t Q = 0;
     int dpad = 0, mode = OS_ANN_MODE_FP32, R = 8;
+    bool cones = false;  // fixed-C mode: the budget counts cones per walk
     size_t off_yf = 0, off_order = 0, off_sbit = 0, off_jstop = 0, off_np = 0, off_nc = 0;
     // tiled mode
     int dk = 0, smin = 1, smax = 1, mq = 0;
@@ -329,11 +331,20 @@ int64_t split_span(int64_t n_ne, int S) {
     return (per + 63) / 64 * 64;
 }
 
-SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mode, int R) {
+// Rows a walk is expected to take: the budget, or in fixed-C mode C cones of
+// the mean non-empty bucket size.
+int64_t expected_rows(const os_ann_index* ix, int64_t budget, bool cones) {
+    if (!cones) return std::min<int64_t>(budget, ix->N);
+    const int64_t mean = std::max<int64_t>(1, ix->N / std::max<int64_t>(1, ix->n_nonempty));
+    return budget >= ix->N / mean ? ix->N : std::min<int64_t>(ix->N, budget * mean);
+}
+
+SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mode, int R, bool cones) {
     SearchPlan p;
     p.Q = Q;
     p.mode = mode;
     p.R = R;
+    p.cones = cones;
     p.dpad = ix->nch * ix->epc;
     size_t at = 0;
     auto take = [&](size_t bytes) {
@@ -385,7 +396,8 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         // probed-cone bitmaps pay off once a query probes many cones and stay small
         const int64_t mean_bucket = std::max<int64_t>(1, ix->N / ne);
         const int64_t probes = std::min<int64_t>(budget, ix->N) / mean_bucket + 1;
-        p.bitmap = probes >= 32 && p.nw <= 512 && (size_t)Q * p.nw * 8 <= ((size_t)1 << 30);
+        // (fixed-C walks are regenerated by the screen, without bitmaps)
+        p.bitmap = !cones && probes >= 32 && p.nw <= 512 && (size_t)Q * p.nw * 8 <= ((size_t)1 << 30);
         p.off_ql = take((size_t)Q * p.dk * 2);
         p.off_qcone = take((size_t)Q * 4);
         p.off_sort = take((size_t)(4 * Q + radix_hist_words(Q)) * 4);
@@ -518,8 +530,9 @@ std::string tune_key(const os_ann_index* ix, const SearchPlan& p, int64_t budget
     const int64_t qb = pow2_ceil(p.Q);
     const int64_t bb = pow2_ceil(std::min<int64_t>(budget, ix->N));
     char buf[256];
-    std::snprintf(buf, sizeof buf, "gfx950:D%d:L%d:t%d:R%d:ne%lld:N%lld:Q%lld:B%lld", ix->D, ix->L, ix->dtype,
-                  p.R, (long long)ix->n_nonempty, (long long)pow2_ceil(ix->N), (long long)qb, (long long)bb);
+    std::snprintf(buf, sizeof buf, "gfx950:D%d:L%d:t%d:R%d:ne%lld:N%lld:Q%lld:B%lld%s", ix->D, ix->L, ix->dtype,
+                  p.R, (long long)ix->n_nonempty, (long long)pow2_ceil(ix->N), (long long)qb, (long long)bb,
+                  p.cones ? ":cones" : "");
     return buf;
 }
 
@@ -578,6 +591,39 @@ ProbeArgs probe_args(const Call& c) {
     return pa;
 }
 
+// Walk lengths.  Row budget: the probe kernel finds them.  Fixed-C mode
+// (Section 3, Table III): the probe kernel only ranks each walk's query (its
+// length outputs left out), then the cones kernel takes the first C
+// positions and counts the non-empty cones and their rows.
+hipError_t launch_walk(const ProbeArgs& pa, bool cones, int64_t take, hipStream_t s) {
+    if (!cones) return launch_probe(pa, s);
+    ProbeArgs pr = pa;
+    pr.jstop = nullptr;
+    pr.nprobe = nullptr;
+    pr.ncand = nullptr;
+    pr.qbits = nullptr;
+    hipError_t e = launch_probe(pr, s);
+    if (e != hipSuccess) return e;
+    ConesArgs ca{};
+    ca.Q = pa.Q;
+    ca.D = pa.D;
+    ca.L = pa.L;
+    ca.n_cones = pa.n_cones;
+    ca.n_sub = pa.n_sub;
+    ca.take = take;
+    ca.offsets = pa.offsets;
+    ca.cone_base = pa.cone_base;
+    ca.lexsub = pa.lexsub;
+    ca.maskord = pa.maskord;
+    ca.binom = pa.binom;
+    ca.order = pa.order;
+    ca.sbit = pa.sbit;
+    ca.jstop = pa.jstop;
+    ca.nprobe = pa.nprobe;
+    ca.ncand = pa.ncand;
+    return launch_cones(ca, s);
+}
+
 hipError_t enqueue_fp32(const Call& c) {
     os_ann_index* ix = c.ix;
     const ProbeArgs pa = probe_args(c);
@@ -602,11 +648,12 @@ hipError_t enqueue_fp32(const Call& c) {
             hipError_t r = launch_probe(pf, c.s);
             if (r == hipSuccess)
                 r = launch_project(c.queries, c.qtype, c.Q, ix->D, ix->proj_mu, ix->proj_P, ix->Dk, yk, c.s);
-            if (r == hipSuccess) r = launch_probe(pk, c.s);
+            if (r == hipSuccess) r = launch_walk(pk, c.p.cones, c.budget, c.s);
             return r;
         });
     } else {
-        e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] { return launch_probe(pa, c.s); });
+        e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s,
+                         [&] { return launch_walk(pa, c.p.cones, c.budget, c.s); });
     }
     if (e != hipSuccess) return e;
     ScanArgs sa{};
@@ -629,8 +676,7 @@ hipError_t enqueue_fp32(const Call& c) {
     sa.perm = ix->perm;
     sa.out_idx = c.out_idx;
     sa.out_dist = c.out_dist;
-    const int64_t expect = std::min<int64_t>(c.budget, ix->N);
-    sa.waves_per_query = expect <= 8192 ? 1 : 4;
+    sa.waves_per_query = expected_rows(ix, c.budget, c.p.cones) <= 8192 ? 1 : 4;
     return timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] { return launch_scan_fp32(sa, c.s); });
 }
 
@@ -638,7 +684,8 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     os_ann_index* ix = c.ix;
     const SearchPlan& p = c.p;
     const ProbeArgs pa = probe_args(c);
-    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] { return launch_probe(pa, c.s); });
+    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s,
+                                [&] { return launch_walk(pa, c.p.cones, c.budget, c.s); });
     if (e != hipSuccess) return e;
     uint32_t* qorder = reinterpret_cast<uint32_t*>(c.base + p.off_qorder);
     e = launch_sort_by_cone(pa.q_cone, c.Q, ix->n_cones, reinterpret_cast<uint32_t*>(c.base + p.off_sort), qorder,
@@ -663,7 +710,8 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     // The seed reads up to sd.rows rows of each query's own cone; keep that
     // near a sixteenth of the budget (16 .. 256 rows), a small share of what
     // the screen then reads per query.
-    sd.rows = (int)std::min<int64_t>(256, std::max<int64_t>(16, pow2_ceil(std::max<int64_t>(c.budget / 16, 1))));
+    const int64_t rows = expected_rows(ix, c.budget, p.cones);
+    sd.rows = (int)std::min<int64_t>(256, std::max<int64_t>(16, pow2_ceil(std::max<int64_t>(rows / 16, 1))));
     e = launch_tiled_seed(sd, p.R, ix->lp.f16, c.s);
     if (e != hipSuccess) return e;
     TiledArgs ta{};
@@ -809,7 +857,7 @@ hipError_t enqueue_rot(const Call& c) {
     ra.perm = ix->rot_perm;
     ra.xtop = ix->xtop;
     ra.planes_tab = reinterpret_cast<const uint4* const*>(ix->planes_tab);
-    ra.waves_per_query = std::min<int64_t>(c.budget, ix->N) <= 8192 ? 1 : 4;
+    ra.waves_per_query = expected_rows(ix, c.budget, p.cones) <= 8192 ? 1 : 4;
     ra.lexsub = ix->sub[0]->lexsub;
     ra.maskord = ix->sub[0]->maskord;
     ra.binom = ix->sub[0]->binom;
@@ -824,7 +872,13 @@ hipError_t enqueue_rot(const Call& c) {
     ra.out_idx = c.out_idx;
     ra.out_dist = c.out_dist;
     ra.out_ncand = c.out_ncand;
-    e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] { return launch_probe_rot(ra, c.s); });
+    e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] {
+        hipError_t r = launch_probe_rot(ra, c.s);
+        // fixed-C mode: levels 0..C-1 of every basis
+        if (r == hipSuccess && p.cones)
+            r = launch_fill_u32(ra.kstop, c.Q, (uint32_t)(std::min<int64_t>(c.budget, ix->n_cones) * R), c.s);
+        return r;
+    });
     if (e != hipSuccess) return e;
     return timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] { return launch_scan_rot(ra, c.s); });
 }
@@ -879,7 +933,7 @@ hipError_t enqueue_ivf(const Call& c) {
     hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] {
         hipError_t r = launch_probe(pf, c.s);
         if (r == hipSuccess) r = launch_ivf_queries(ia, c.s);
-        if (r == hipSuccess) r = launch_probe(pk, c.s);
+        if (r == hipSuccess) r = launch_walk(pk, p.cones, c.budget, c.s);
         return r;
     });
     if (e != hipSuccess) return e;
@@ -906,7 +960,9 @@ hipError_t enqueue_ivf(const Call& c) {
     float* vdist = reinterpret_cast<float*>(c.base + p.off_vdist);
     sa.out_idx = vidx;
     sa.out_dist = vdist;
-    sa.waves_per_query = std::min<int64_t>(pk.budget, ix->N) <= 8192 ? 1 : 4;
+    sa.waves_per_query = (p.cones ? expected_rows(ix, c.budget, true) : std::min<int64_t>(pk.budget, ix->N)) <= 8192
+                             ? 1
+                             : 4;
     e = timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] {
         hipError_t r = launch_scan_fp32(sa, c.s);
         if (r == hipSuccess)
@@ -927,6 +983,7 @@ int run_graph(Call& c, int S) {
     os_ann_index* ix = c.ix;
     std::vector<int64_t> key = {c.p.mode,
                                 c.p.R,
+                                c.p.cones,
                                 S,
                                 c.Q,
                                 c.budget,
@@ -1461,7 +1518,8 @@ int64_t os_ann_workspace_bytes(const os_ann_index* idx, int64_t Q, int64_t max_c
     if (rc) return rc;
     const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
-    return (int64_t)plan_search(idx, Q, max_candidates, mode, R).bytes;
+    const bool cones = opts && (opts->flags & OS_ANN_FLAG_BUDGET_CONES);
+    return (int64_t)plan_search(idx, Q, max_candidates, mode, R, cones).bytes;
 }
 
 int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, int64_t max_candidates,
@@ -1486,7 +1544,7 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     c.timing = opts && (opts->flags & OS_ANN_FLAG_TIME_KERNELS);
     const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
-    c.p = plan_search(ix, Q, max_candidates, mode, R);
+    c.p = plan_search(ix, Q, max_candidates, mode, R, opts && (opts->flags & OS_ANN_FLAG_BUDGET_CONES));
     if (!c.p.fits)
         return fail(OS_ANN_ENOTSUP, "tiled mode: too many non-empty cones for the LDS cone list at this D");
     if ((rc = get_scratch(ix, opts, c.p.bytes, &c.base))) return rc;
