@@ -240,6 +240,42 @@ def bases_leg(X, db, q, nn_d64, R=4, sweep=(65536, 98304, 131072, 196608, 262144
                     "in every basis + scan analyzing each row once"}
 
 
+def cones_leg(db, q, nn_d64, modes, sweep=(512, 1024, 1536, 2048, 3072, 4096)):
+    """Fixed-C mode (Section 3, Table III): every walk takes its first C cones,
+    empty ones included.  Per mode, the smallest swept C with recall@1 >= 0.9
+    on the headline workload, with its search time (index resident)."""
+    import torch
+    from paper_1509_03453_amd import binding as B
+    mcode = {"fp32": B.OS_ANN_MODE_FP32, "tiled": B.OS_ANN_MODE_TILED}
+    kern = {"fp32": B.OS_ANN_KERNEL_SCAN, "tiled": B.OS_ANN_KERNEL_SCREEN}
+    h = B.os_ann_build_ex(db, L_HASH, want_lowp="tiled" in modes)
+    out = {}
+    for m in modes:
+        rows = []
+        for C in sweep:
+            B.os_ann_search_ex(h, q, C, mode=mcode[m], rerank_r=RERANK, cones=True)  # warm (and tune)
+            torch.cuda.synchronize()
+            for k in range(5):
+                B.os_ann_kernel_time(h, k)
+            t0 = time.perf_counter()
+            i, d, n = B.os_ann_search_ex(h, q, C, mode=mcode[m], rerank_r=RERANK, cones=True,
+                                         flags=B.OS_ANN_FLAG_TIME_KERNELS)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            nk, msk = B.os_ann_kernel_time(h, kern[m])
+            rec = float((pair_d64_torch(db, q, i) == nn_d64).double().mean())
+            rows.append({"cones": C, "recall_at_1": round(rec, 4), "mean_ncand": round(float(n.double().mean()), 1),
+                         "search_ms": round(ms, 3), "search_qps": round(N_Q / ms * 1e3, 1),
+                         "main_kernel_ms": round(msk / max(nk, 1), 4)})
+            log(f"[bench] cones {m} {rows[-1]}")
+            if rec >= 0.9:
+                break
+        out[m] = {"sweep": rows, "cones": rows[-1]["cones"], "recall_at_1": rows[-1]["recall_at_1"],
+                  "search_qps": rows[-1]["search_qps"]}
+    B.os_ann_free(h)
+    return out
+
+
 def patches_leg(budgets=(64, 256, 1024, 4096), n_sample=10_000):
     """Batching at scale: every 8x8 patch of a 2048x2048 1/f field (FP16,
     ~4.2e6 rows) against every patch of the shifted noisy field (~4.2e6
@@ -426,6 +462,7 @@ def main():
     ap.add_argument("--no-patches", action="store_true", help="skip the 4.2e6-patch batching leg")
     ap.add_argument("--no-pca", action="store_true", help="skip the PCA front-end leg")
     ap.add_argument("--no-ivf", action="store_true", help="skip the coarse-cluster leg")
+    ap.add_argument("--no-cones", action="store_true", help="skip the fixed-C cone leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -601,6 +638,9 @@ def main():
         "index": {"n_cones": info["n_cones"], "n_nonempty": info["n_nonempty"],
                   "device_bytes": info["device_bytes"]},
     }
+    if not args.no_cones:
+        log("[bench] fixed-C cones")
+        out["fixed_cones"] = cones_leg(db, q, nn_d64, modes)
     if not args.no_bases and "fp32" in modes:
         log("[bench] several bases")
         out["several_bases"] = bases_leg(X, db, q, nn_d64)

@@ -395,9 +395,8 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         while (p.smax > 1 && split_span(ne, p.smax) < 64 * 2) p.smax >>= 1;
         // probed-cone bitmaps pay off once a query probes many cones and stay small
         const int64_t mean_bucket = std::max<int64_t>(1, ix->N / ne);
-        const int64_t probes = std::min<int64_t>(budget, ix->N) / mean_bucket + 1;
-        // (fixed-C walks are regenerated by the screen, without bitmaps)
-        p.bitmap = !cones && probes >= 32 && p.nw <= 512 && (size_t)Q * p.nw * 8 <= ((size_t)1 << 30);
+        const int64_t probes = cones ? std::min<int64_t>(budget, ne) : std::min<int64_t>(budget, ix->N) / mean_bucket + 1;
+        p.bitmap = probes >= 32 && p.nw <= 512 && (size_t)Q * p.nw * 8 <= ((size_t)1 << 30);
         p.off_ql = take((size_t)Q * p.dk * 2);
         p.off_qcone = take((size_t)Q * 4);
         p.off_sort = take((size_t)(4 * Q + radix_hist_words(Q)) * 4);
@@ -621,6 +620,9 @@ hipError_t launch_walk(const ProbeArgs& pa, bool cones, int64_t take, hipStream_
     ca.jstop = pa.jstop;
     ca.nprobe = pa.nprobe;
     ca.ncand = pa.ncand;
+    ca.qbits = pa.qbits;
+    ca.nw = pa.nw;
+    ca.ne_id = pa.ne_id;
     return launch_cones(ca, s);
 }
 

@@ -24,6 +24,11 @@ struct ConesArgs {
     uint32_t* jstop;         // [Q] min(C, N_C)
     uint32_t* nprobe;        // [Q] non-empty cones among them
     int64_t* ncand;          // [Q] rows of those cones
+    // optional bitmap of the taken non-empty cones, [Q][nw] words (bit e:
+    // the cone whose rank among the non-empty cones is e)
+    uint64_t* qbits;
+    int64_t nw;
+    const uint32_t* ne_id;   // cone -> rank among the non-empty cones
 };
 hipError_t launch_cones(const ConesArgs& a, hipStream_t s);
 

@@ -9,6 +9,7 @@ oracle recomputes one by one.
   are all patches of the shifted noisy field (~4.2e6), tiled mode.
 * the 1e6 x 64 Gaussian workload with four bases (Section 3.A).
 * the descriptor workload through the PCA front-end (Section 4.B), k = 16.
+* the Gaussian workload in fixed-C mode (C = 16, 512, 2048 cones), both modes.
 
 The index itself (every key, bucket offset and permutation entry) is compared
 in full; searches are compared on a spread sample of queries."""
@@ -51,25 +52,25 @@ def sample_ids(Q, n):
     return np.unique(np.linspace(0, Q - 1, n).astype(np.int64))
 
 
-def fp32_sampled(orc, X, o, h, Y, yq, budget, sample, tag):
-    say(f"[full] {tag}: fp32 Q={Y.shape[0]} B={budget}")
-    gi, gd, gn = B.os_ann_search_ex(h, yq, budget, mode=B.OS_ANN_MODE_FP32)
+def fp32_sampled(orc, X, o, h, Y, yq, budget, sample, tag, cones=False):
+    say(f"[full] {tag}: fp32 Q={Y.shape[0]} B={budget} cones={cones}")
+    gi, gd, gn = B.os_ann_search_ex(h, yq, budget, mode=B.OS_ANN_MODE_FP32, cones=cones)
     torch.cuda.synchronize()
     gi, gd, gn = gi.cpu().numpy()[sample], gd.cpu().numpy()[sample], gn.cpu().numpy()[sample]
-    oi, od32, od64, on = orc.search(X, o, Y[sample], budget)
+    oi, od32, od64, on = orc.search(X, o, Y[sample], budget, cones=cones)
     assert np.array_equal(gn, on), tag
     assert np.array_equal(gi, oi), tag
     assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), tag
     assert (np.abs(gd - od64) <= RTOL * np.maximum(od64, 1e-300)).all(), tag
 
 
-def tiled_sampled(orc, X, o, h, Y, yq, budget, sample, tag, R=8, max_mismatch=0.02):
-    say(f"[full] {tag}: tiled Q={Y.shape[0]} B={budget}")
-    gi, gd, gn = B.os_ann_search_ex(h, yq, budget, mode=B.OS_ANN_MODE_TILED, rerank_r=R)
+def tiled_sampled(orc, X, o, h, Y, yq, budget, sample, tag, R=8, max_mismatch=0.02, cones=False):
+    say(f"[full] {tag}: tiled Q={Y.shape[0]} B={budget} cones={cones}")
+    gi, gd, gn = B.os_ann_search_ex(h, yq, budget, mode=B.OS_ANN_MODE_TILED, rerank_r=R, cones=cones)
     torch.cuda.synchronize()
     gi, gd, gn = gi.cpu().numpy()[sample], gd.cpu().numpy()[sample], gn.cpu().numpy()[sample]
     Ys = Y[sample]
-    oi, od32, od64, on, dtr, top = orc.search_tiled(X, o, Ys, budget, R=R)
+    oi, od32, od64, on, dtr, top = orc.search_tiled(X, o, Ys, budget, R=R, cones=cones)
     assert np.array_equal(gn, on), tag
     assert np.array_equal(gd.view(np.uint32), orc.pair_d32(X, Ys, gi).view(np.uint32)), tag
     f16 = X.dtype == np.float16
@@ -98,6 +99,11 @@ def test_gaussian_1m_d64(orc):
             s = sample_ids(len(Y), n)
             fp32_sampled(orc, X, o, h, Y, yq, budget, s, "gauss 1e6x64")
             tiled_sampled(orc, X, o, h, Y, yq, budget, s, "gauss 1e6x64")
+        # fixed-C mode (Section 3, Table III) in the same launch shape
+        for C, n in ((16, 300), (512, 100), (2048, 48)):
+            s = sample_ids(len(Y), n)
+            fp32_sampled(orc, X, o, h, Y, yq, C, s, "gauss 1e6x64", cones=True)
+            tiled_sampled(orc, X, o, h, Y, yq, C, s, "gauss 1e6x64", cones=True)
     finally:
         B.os_ann_free(h)
 
