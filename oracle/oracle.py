@@ -79,7 +79,9 @@ def lib():
             L.orc_rotate.argtypes = [p, i32, i64, i32, p, p]
             L.orc_search_rot.restype = i32
             L.orc_search_rot.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, p, i32, i64, i64,
-                                         p, p, p, p, i32, i32]
+                                         p, p, p, p, i32, i32, i32]
+            L.orc_wht.restype = i32
+            L.orc_wht.argtypes = [p, i32, i64, i32, p, p]
             L.orc_search_keyed.restype = i32
             L.orc_search_keyed.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, i32, p, i64, i64,
                                            p, p, p, p, i32, i32]
@@ -321,6 +323,28 @@ def rotate(X, M):
     return out
 
 
+def wht(X, signs):
+    """Coordinates in the structured basis H diag(signs) (fast Walsh-Hadamard
+    transform in FP32, unnormalised; reading R14)."""
+    X, px, dt = _rows(X)
+    N, K = X.shape
+    sg, ps = _arr(signs, np.float32)
+    if sg.shape != (K,):
+        raise ValueError("signs must have one entry per component")
+    out = np.empty((N, K), dtype=np.float32)
+    rc = lib().orc_wht(px, dt, N, K, ps, out.ctypes.data_as(C.c_void_p))
+    if rc != 0:
+        raise ValueError(f"orc_wht failed ({rc})")
+    return out
+
+
+def build_index_wht(X, G: int, signs):
+    """Several structured bases (reading R14): basis r is H diag(signs[r])."""
+    signs = np.ascontiguousarray(signs, dtype=np.float32)
+    tabs = [build_index(wht(X, signs[r]), G) for r in range(signs.shape[0])]
+    return {"tables": tabs, "rots": signs, "wht": True, "G": G, "K": X.shape[1], "n_cones": tabs[0]["n_cones"]}
+
+
 def build_index_rot(X, G: int, rots):
     """One table per basis (Section 3.A): the rows' coordinates in basis r
     are hashed and bucketed; every table refers to the original rows."""
@@ -347,7 +371,7 @@ def search_rot(X, index, Y, B: int, nthreads: int = 0, cones: bool = False):
     rc = lib().orc_search_rot(px, xdt, N, K, index["G"], R, pr, po, pp, py, ydt, Q, int(B),
                               idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
                               d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
-                              int(nthreads), int(bool(cones)))
+                              int(nthreads), int(bool(cones)), int(bool(index.get("wht", False))))
     if rc != 0:
         raise RuntimeError(f"orc_search_rot failed ({rc})")
     return idx, d32, d64, nca

@@ -57,6 +57,14 @@
  *       are visited, per basis (several bases: levels 0..C-1 of every basis)
  *       and per searched cluster.  When every cone taken is empty the search
  *       has no candidate: the row is -1 and the distance +inf.
+ *   R14 structured bases (Section 3.D, Walsh-Hadamard matrices in place of
+ *       pseudo-random ones): basis r is H diag(s_r) / sqrt(K), H the
+ *       Sylvester-ordered Hadamard matrix (K a power of two), s_r a vector
+ *       of signs.  Coordinates come from the fast transform (sign flips,
+ *       then butterflies with strides 1, 2, 4, ..., each (a, b) -> (a + b,
+ *       a - b) rounded in FP32), left unnormalised: the positive factor
+ *       1/sqrt(K) changes neither the order of the magnitudes nor the signs,
+ *       so the cones are those of the orthonormal basis.
  *
  * Precision: distances are produced both in double (the definition, eq. (1))
  * and in FP32 evaluated term by term in ascending component order with each
@@ -767,9 +775,35 @@ int orc_rotate(const void *X, int dtype, int64_t N, int K, const float *M, float
     return 0;
 }
 
+/* Coordinates in a structured basis (reading R14): for each row, v = s * x
+ * (sign flips, exact), then for strides h = 1, 2, ..., K/2 every pair (j,
+ * j + h) with j & h == 0 becomes (v_j + v_{j+h}, v_j - v_{j+h}) in FP32: the
+ * fast Walsh-Hadamard transform, out = H diag(s) x without the 1/sqrt(K). */
+int orc_wht(const void *X, int dtype, int64_t N, int K, const float *signs, float *out)
+{
+    if (K < 1 || K > 256 || (K & (K - 1)))
+        return -1;
+    for (int64_t n = 0; n < N; n++) {
+        float v[256];
+        load_row(X, dtype, n, K, v);
+        for (int j = 0; j < K; j++)
+            v[j] = signs[j] * v[j];
+        for (int h = 1; h < K; h <<= 1)
+            for (int j = 0; j < K; j++)
+                if (!(j & h)) {
+                    float a = v[j], b = v[j + h];
+                    v[j] = a + b;
+                    v[j + h] = a - b;
+                }
+        memcpy(out + n * K, v, sizeof(float) * (size_t)K);
+    }
+    return 0;
+}
+
 /* Algorithm 1 with R bases.  Basis r has its own table (offsets_r, perm_r
  * built from the rows' coordinates in that basis by orc_hash/orc_bucket);
- * rot holds the R matrices.  For each query: its coordinates in every basis
+ * rot holds the R matrices (wht set: R sign vectors of length K, the bases
+ * of reading R14).  For each query: its coordinates in every basis
  * and each basis's full probe order (Section 3.B); then, for l = 0, 1, ...
  * (the l-th cone of every basis's order, empty cones included) and for
  * r = 0..R-1, every row of cone l of basis r that is not yet marked analyzed
@@ -783,9 +817,9 @@ int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, co
                    const int64_t *offsets, const int64_t *perms,
                    const void *Y, int ydtype, int64_t Q, int64_t B,
                    int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
-                   int nthreads, int cones)
+                   int nthreads, int cones, int wht)
 {
-    if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || R < 1)
+    if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || R < 1 || (wht && (K & (K - 1))))
         return -1;
     int64_t NC = orc_num_cones(K, G);
     set_threads(nthreads);
@@ -804,7 +838,10 @@ int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, co
             continue;
         }
         for (int r = 0; r < R; r++) {
-            orc_rotate(y, ORC_F32, 1, K, rot + (int64_t)r * K * K, yr);
+            if (wht)
+                orc_wht(y, ORC_F32, 1, K, rot + (int64_t)r * K, yr);
+            else
+                orc_rotate(y, ORC_F32, 1, K, rot + (int64_t)r * K * K, yr);
             orc_walk(yr, K, G, walks + (int64_t)r * NC, NC);
         }
         float best_d = INFINITY;
