@@ -155,6 +155,25 @@ os_ann_index *os_ann_build_rot(const void *db, int64_t N, int32_t D, int32_t L, 
                                int32_t n_rot, const os_ann_build_opts *opts);
 
 /*
+ * Several structured bases (Section 3.D: Walsh-Hadamard matrices in place of
+ * pseudo-random ones, which cuts the rotation cost from D^2 to D log2 D per
+ * vector).  Basis r is H diag(signs[r]) / sqrt(D), H the Sylvester-ordered
+ * D x D Hadamard matrix (entry (i, j) = (-1)^popcount(i & j)); signs holds
+ * n_rot (1..16) vectors of D entries, each exactly +1 or -1, FP32, device
+ * memory.  D must be a power of two.  Coordinates come from the fast
+ * transform: the sign flips, then butterflies with strides 1, 2, ..., D/2,
+ * each pair (a, b) becoming (a + b, a - b) rounded in FP32, without the
+ * 1/sqrt(D) factor (a positive scale changes neither the order of the
+ * magnitudes nor the signs, so the cones are those of the orthonormal
+ * basis).  Everything else is as in os_ann_build_rot: one table per basis
+ * over the original rows, distances on the original rows, FP32 mode only.
+ * Errors: EINVAL (also D not a power of two, a sign other than +-1), ENOMEM,
+ * EDEVICE, ENOTSUP, ENONFINITE (returns NULL).
+ */
+os_ann_index *os_ann_build_wht(const void *db, int64_t N, int32_t D, int32_t L, const float *signs,
+                               int32_t n_rot, const os_ann_build_opts *opts);
+
+/*
  * Approximate NN of Q FP32 queries (row-major queries[Q][D]), Algorithm 1
  * with one basis: each query's cones are visited in the Section 3.B order
  * (own cone first; then the other profiles that share the query's signs, in

@@ -50,6 +50,8 @@ SIGNATURES = {
                                      C.POINTER(os_ann_build_opts)]),
     "os_ann_build_rot": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
                                       C.POINTER(os_ann_build_opts)]),
+    "os_ann_build_wht": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                      C.POINTER(os_ann_build_opts)]),
     "os_ann_pca": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.POINTER(os_ann_build_opts),
                              C.c_void_p, C.c_void_p, C.c_void_p]),
     "os_ann_build_proj": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
@@ -154,6 +156,21 @@ def os_ann_build_rot(db: torch.Tensor, L: int, rot: torch.Tensor, stream=None) -
         raise ValueError("rot must hold D x D matrices")
     o = os_ann_build_opts(_check_rows(db, "db"), 0, _stream_ptr(stream))
     h = lib().os_ann_build_rot(_ptr(db), db.shape[0], db.shape[1], int(L), _ptr(rot), rot.shape[0], C.byref(o))
+    if not h:
+        _raise()
+    return h
+
+
+def os_ann_build_wht(db: torch.Tensor, L: int, signs: torch.Tensor, stream=None) -> int:
+    """Index with several structured bases H diag(s); ``signs`` is a device
+    FP32 tensor [n_rot, D] of +-1 (D a power of two)."""
+    if signs.dtype != torch.float32 or signs.dim() != 2 or not signs.is_contiguous() or signs.device != db.device:
+        raise ValueError("signs must be a contiguous FP32 [n_rot, D] tensor on the db's device")
+    if signs.shape[1] != db.shape[1]:
+        raise ValueError("signs must hold D entries per basis")
+    o = os_ann_build_opts(_check_rows(db, "db"), 0, _stream_ptr(stream))
+    h = lib().os_ann_build_wht(_ptr(db), db.shape[0], db.shape[1], int(L), _ptr(signs), signs.shape[0],
+                               C.byref(o))
     if not h:
         _raise()
     return h

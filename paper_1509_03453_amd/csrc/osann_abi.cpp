@@ -19,6 +19,7 @@
 #include "osann_ivf.h"
 #include "osann_kernels.h"
 #include "osann_tiled.h"
+#include "osann_wht.h"
 
 using namespace osann;
 
@@ -113,6 +114,7 @@ struct os_ann_index {
     int n_rot = 0;
     std::vector<os_ann_index*> sub;
     float* rot = nullptr;            // [R][D][D]
+    float* rot_signs = nullptr;      // structured bases: [R][D] signs of H diag(s) (rot unused)
     uint32_t* rot_offsets = nullptr;  // [R][n_cones+1]
     uint32_t* rot_perm = nullptr;     // [R][N]
     uint64_t* xtop = nullptr;         // [R][R][N]
@@ -244,7 +246,7 @@ void release(os_ann_index* ix, bool synced = false) {
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
                     ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
-                    ix->planes_tab, ix->proj_mu, ix->proj_P, ix->ivf_cent};
+                    ix->planes_tab, ix->proj_mu, ix->proj_P, ix->ivf_cent, ix->rot_signs};
     for (void* p : ptrs) dev_free(p);
     delete ix;
 }
@@ -840,8 +842,10 @@ hipError_t enqueue_rot(const Call& c) {
     hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] {
         hipError_t r = launch_probe(pa, c.s);
         for (int b = 0; b < R && r == hipSuccess; ++b)
-            r = launch_rotate(c.queries, c.qtype, c.Q, ix->D, ix->rot + (size_t)b * ix->D * ix->D,
-                              yr + (size_t)b * c.Q * ix->D, c.s);
+            r = ix->rot_signs ? launch_wht(c.queries, c.qtype, c.Q, ix->D, ix->rot_signs + (size_t)b * ix->D,
+                                           yr + (size_t)b * c.Q * ix->D, c.s)
+                              : launch_rotate(c.queries, c.qtype, c.Q, ix->D, ix->rot + (size_t)b * ix->D * ix->D,
+                                              yr + (size_t)b * c.Q * ix->D, c.s);
         return r;
     });
     if (e != hipSuccess) return e;
@@ -1164,6 +1168,110 @@ os_ann_index* build_table(const void* keys, int32_t key_dtype, int32_t Dk, const
     tmp = small = nullptr;
     return ix;
 }
+// Several bases: a table per basis from the rows' coordinates in it.  basis
+// holds n_rot dense D x D matrices, or (wht) n_rot sign vectors of H diag(s).
+os_ann_index* build_bases(const void* db, int64_t N, int32_t D, int32_t L, const float* basis, int32_t n_rot,
+                          bool wht, const os_ann_build_opts* opts) {
+    clear_error();
+    const int32_t dtype = opts ? opts->dtype : kF32;
+    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    int64_t nc = 0;
+    if (!db || !basis) {
+        fail(OS_ANN_EINVAL, "null db or bases");
+        return nullptr;
+    }
+    if (!dtype_ok(dtype)) {
+        fail(OS_ANN_EINVAL, "bad db dtype");
+        return nullptr;
+    }
+    if (n_rot < 1 || n_rot > kMaxRot) {
+        fail(OS_ANN_EINVAL, "n_rot must be in [1, 16]");
+        return nullptr;
+    }
+    if (opts && opts->want_lowp) {
+        fail(OS_ANN_ENOTSUP, "several bases: FP32 mode only");
+        return nullptr;
+    }
+    if (check_shape(N, D, L, &nc)) return nullptr;
+    const size_t n = (size_t)N, R = (size_t)n_rot;
+    const size_t basis_floats = wht ? R * D : R * D * D;
+    if (wht) {
+        if (D & (D - 1)) {
+            fail(OS_ANN_EINVAL, "structured bases need D a power of two");
+            return nullptr;
+        }
+        std::vector<float> hs(basis_floats);
+        hipError_t e = hipMemcpy(hs.data(), basis, basis_floats * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            hip_fail(e, "reading the signs");
+            return nullptr;
+        }
+        for (float v : hs)
+            if (v != 1.0f && v != -1.0f) {
+                fail(OS_ANN_EINVAL, "every sign must be +1 or -1");
+                return nullptr;
+            }
+    }
+    auto* ix = new os_ann_index();
+    ix->N = N;
+    ix->D = D;
+    ix->Dk = D;
+    ix->L = L;
+    ix->dtype = dtype;
+    ix->n_cones = nc;
+    ix->n_sub = binom_host(D, L);
+    ix->epc = chunk_elems(dtype);
+    ix->nch = (D + ix->epc - 1) / ix->epc;
+    ix->n_rot = n_rot;
+    (void)hipGetDevice(&ix->device);
+    float* coords = nullptr;
+    auto bail = [&]() -> os_ann_index* {
+        (void)hipDeviceSynchronize();
+        dev_free(coords);
+        release(ix);
+        return nullptr;
+    };
+    float** keep = wht ? &ix->rot_signs : &ix->rot;
+    if (dev_alloc(ix, (void**)keep, basis_floats * 4, "bases") ||
+        dev_alloc(ix, (void**)&ix->rot_offsets, R * (size_t)(nc + 1) * 4, "basis offsets") ||
+        dev_alloc(ix, (void**)&ix->rot_perm, R * n * 4, "basis perms") ||
+        dev_alloc(ix, (void**)&ix->xtop, R * R * n * 8, "cross tops") ||
+        dev_alloc(ix, (void**)&ix->planes_tab, R * sizeof(void*), "plane table") ||
+        dev_alloc(nullptr, (void**)&coords, n * D * 4, "coordinates"))
+        return bail();
+    hipError_t e = hipMemcpyAsync(*keep, basis, basis_floats * 4, hipMemcpyDeviceToDevice, s);
+    for (int r = 0; r < n_rot && e == hipSuccess; ++r) {
+        e = wht ? launch_wht(db, dtype, N, D, ix->rot_signs + (size_t)r * D, coords, s)
+                : launch_rotate(db, dtype, N, D, ix->rot + (size_t)r * D * D, coords, s);
+        if (e != hipSuccess) break;
+        os_ann_index* t = build_table(coords, kF32, D, db, dtype, N, D, L, nc, s);
+        if (!t) return bail();
+        ix->sub.push_back(t);
+        ix->device_bytes += t->device_bytes;
+        e = hipMemcpyAsync(ix->rot_offsets + (size_t)r * (nc + 1), t->offsets, (size_t)(nc + 1) * 4,
+                           hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ix->rot_perm + (size_t)r * n, t->perm, n * 4, hipMemcpyDeviceToDevice, s);
+    }
+    for (int r = 0; r < n_rot && e == hipSuccess; ++r)
+        for (int r2 = 0; r2 < n_rot && e == hipSuccess; ++r2)
+            if (r2 != r)
+                e = launch_gather_top(ix->sub[r]->perm, N, ix->sub[r2]->row_top,
+                                      ix->xtop + ((size_t)r * R + r2) * n, s);
+    std::vector<void*> tab_host;
+    for (auto* t : ix->sub) tab_host.push_back(t->planes);
+    if (e == hipSuccess && (int)tab_host.size() == n_rot)
+        e = hipMemcpyAsync(ix->planes_tab, tab_host.data(), R * sizeof(void*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hip_fail(e, "several-bases build");
+        return bail();
+    }
+    dev_free(coords);
+    ix->n_nonempty = ix->sub[0]->n_nonempty;
+    return ix;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1192,84 +1300,12 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L, c
 
 os_ann_index* os_ann_build_rot(const void* db, int64_t N, int32_t D, int32_t L, const float* rot, int32_t n_rot,
                                const os_ann_build_opts* opts) {
-    clear_error();
-    const int32_t dtype = opts ? opts->dtype : kF32;
-    hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
-    int64_t nc = 0;
-    if (!db || !rot) {
-        fail(OS_ANN_EINVAL, "null db or bases");
-        return nullptr;
-    }
-    if (!dtype_ok(dtype)) {
-        fail(OS_ANN_EINVAL, "bad db dtype");
-        return nullptr;
-    }
-    if (n_rot < 1 || n_rot > kMaxRot) {
-        fail(OS_ANN_EINVAL, "n_rot must be in [1, 16]");
-        return nullptr;
-    }
-    if (opts && opts->want_lowp) {
-        fail(OS_ANN_ENOTSUP, "several bases: FP32 mode only");
-        return nullptr;
-    }
-    if (check_shape(N, D, L, &nc)) return nullptr;
-    auto* ix = new os_ann_index();
-    ix->N = N;
-    ix->D = D;
-    ix->Dk = D;
-    ix->L = L;
-    ix->dtype = dtype;
-    ix->n_cones = nc;
-    ix->n_sub = binom_host(D, L);
-    ix->epc = chunk_elems(dtype);
-    ix->nch = (D + ix->epc - 1) / ix->epc;
-    ix->n_rot = n_rot;
-    (void)hipGetDevice(&ix->device);
-    float* coords = nullptr;
-    auto bail = [&]() -> os_ann_index* {
-        (void)hipDeviceSynchronize();
-        dev_free(coords);
-        release(ix);
-        return nullptr;
-    };
-    const size_t n = (size_t)N, R = (size_t)n_rot;
-    if (dev_alloc(ix, (void**)&ix->rot, R * D * D * 4, "bases") ||
-        dev_alloc(ix, (void**)&ix->rot_offsets, R * (size_t)(nc + 1) * 4, "basis offsets") ||
-        dev_alloc(ix, (void**)&ix->rot_perm, R * n * 4, "basis perms") ||
-        dev_alloc(ix, (void**)&ix->xtop, R * R * n * 8, "cross tops") ||
-        dev_alloc(ix, (void**)&ix->planes_tab, R * sizeof(void*), "plane table") ||
-        dev_alloc(nullptr, (void**)&coords, n * D * 4, "coordinates"))
-        return bail();
-    hipError_t e = hipMemcpyAsync(ix->rot, rot, R * D * D * 4, hipMemcpyDeviceToDevice, s);
-    for (int r = 0; r < n_rot && e == hipSuccess; ++r) {
-        e = launch_rotate(db, dtype, N, D, ix->rot + (size_t)r * D * D, coords, s);
-        if (e != hipSuccess) break;
-        os_ann_index* t = build_table(coords, kF32, D, db, dtype, N, D, L, nc, s);
-        if (!t) return bail();
-        ix->sub.push_back(t);
-        ix->device_bytes += t->device_bytes;
-        e = hipMemcpyAsync(ix->rot_offsets + (size_t)r * (nc + 1), t->offsets, (size_t)(nc + 1) * 4,
-                           hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(ix->rot_perm + (size_t)r * n, t->perm, n * 4, hipMemcpyDeviceToDevice, s);
-    }
-    for (int r = 0; r < n_rot && e == hipSuccess; ++r)
-        for (int r2 = 0; r2 < n_rot && e == hipSuccess; ++r2)
-            if (r2 != r)
-                e = launch_gather_top(ix->sub[r]->perm, N, ix->sub[r2]->row_top,
-                                      ix->xtop + ((size_t)r * R + r2) * n, s);
-    std::vector<void*> tab_host;
-    for (auto* t : ix->sub) tab_host.push_back(t->planes);
-    if (e == hipSuccess && (int)tab_host.size() == n_rot)
-        e = hipMemcpyAsync(ix->planes_tab, tab_host.data(), R * sizeof(void*), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-        hip_fail(e, "several-bases build");
-        return bail();
-    }
-    dev_free(coords);
-    ix->n_nonempty = ix->sub[0]->n_nonempty;
-    return ix;
+    return build_bases(db, N, D, L, rot, n_rot, false, opts);
+}
+
+os_ann_index* os_ann_build_wht(const void* db, int64_t N, int32_t D, int32_t L, const float* signs, int32_t n_rot,
+                               const os_ann_build_opts* opts) {
+    return build_bases(db, N, D, L, signs, n_rot, true, opts);
 }
 
 int os_ann_pca(const void* db, int64_t N, int32_t D, int32_t k, const os_ann_build_opts* opts, float* mean_out,
