@@ -181,14 +181,18 @@ def serving_leg(X2, db2, budget2, n_req=600, rate=400.0):
 
 
 def bases_leg(X, db, q, nn_d64, R=4, sweep=(65536, 98304, 131072, 196608, 262144), steps=3):
-    """Several bases (Section 3.A): R bases (the first the identity), FP32
-    mode, smallest swept budget with recall@1 >= 0.9; whole steps (build of
-    the R tables + search) and the scan kernel's roofline."""
+    """Several bases (Section 3.A), FP32 mode, smallest swept budget with
+    recall@1 >= 0.9; whole steps (build of the R tables + search) and the
+    scan kernel's roofline.  Then the structured bases of Section 3.D (R
+    Walsh-Hadamard bases H diag(s)) at that budget, build and step times."""
     import torch
     from paper_1509_03453_amd import binding as B
     from paper_1509_03453_amd import workloads as W
     rots = torch.from_numpy(W.random_bases(R, DIM)).cuda()
-    h = B.os_ann_build_rot(db, L_HASH, rots)
+    signs = torch.from_numpy(W.random_signs(R, DIM)).cuda()
+    build = {"dense": lambda: B.os_ann_build_rot(db, L_HASH, rots),
+             "wht": lambda: B.os_ann_build_wht(db, L_HASH, signs)}
+    h = build["dense"]()
     sweep_out, chosen = [], None
     for budget in sweep:
         B.os_ann_search_ex(h, q, budget)
@@ -208,21 +212,30 @@ def bases_leg(X, db, q, nn_d64, R=4, sweep=(65536, 98304, 131072, 196608, 262144
             break
     B.os_ann_free(h)
     budget = chosen or sweep[-1]
-    step_ms, kern_ms, ncs = [], [], []
-    for it in range(steps + 1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hh = B.os_ann_build_rot(db, L_HASH, rots)
-        i, d, n = B.os_ann_search_ex(hh, q, budget, flags=B.OS_ANN_FLAG_TIME_KERNELS)
-        torch.cuda.synchronize()
-        if it > 0:  # the first step warms up
-            step_ms.append((time.perf_counter() - t0) * 1e3)
-            nk, msk = B.os_ann_kernel_time(hh, B.OS_ANN_KERNEL_SCAN)
-            kern_ms.append(msk / max(nk, 1))
-            ncs.append(float(n.double().sum()))
-        B.os_ann_free(hh)
-    kavg = float(np.mean(kern_ms))
-    distinct = float(np.mean(ncs))
+
+    def steps_of(kind):
+        step_ms, build_ms, kern_ms, ncs, recs = [], [], [], [], []
+        for it in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hh = build[kind]()
+            t1 = time.perf_counter()
+            i, d, n = B.os_ann_search_ex(hh, q, budget, flags=B.OS_ANN_FLAG_TIME_KERNELS)
+            torch.cuda.synchronize()
+            if it > 0:  # the first step warms up
+                step_ms.append((time.perf_counter() - t0) * 1e3)
+                build_ms.append((t1 - t0) * 1e3)
+                nk, msk = B.os_ann_kernel_time(hh, B.OS_ANN_KERNEL_SCAN)
+                kern_ms.append(msk / max(nk, 1))
+                ncs.append(float(n.double().sum()))
+                recs.append(float((pair_d64_torch(db, q, i) <= nn_d64).double().mean()))
+            B.os_ann_free(hh)
+        return (float(np.mean(step_ms)), float(np.mean(build_ms)), float(np.mean(kern_ms)), float(np.mean(ncs)),
+                recs[-1])
+
+    step_avg, build_avg, kavg, distinct, _ = steps_of("dense")
+    w_step, w_build, w_kavg, w_distinct, w_rec = steps_of("wht")
+    log(f"[bench] bases R={R} dense build {build_avg:.2f} ms, wht build {w_build:.2f} ms, wht recall {w_rec}")
     # distinct rows' FP32 components + the other bases' 8-byte top-L words of
     # every visited row + query in, result out
     bytes_ = distinct * DIM * 4 + N_Q * budget * (R - 1) * 8 + N_Q * (DIM * 4 + 12)
@@ -230,12 +243,16 @@ def bases_leg(X, db, q, nn_d64, R=4, sweep=(65536, 98304, 131072, 196608, 262144
     pick = sweep_out[-1]
     return {"bases": R, "budget": budget, "recall_at_1": pick["recall_at_1"],
             "mean_distinct_candidates": pick["mean_distinct_candidates"],
-            "value": round(N_Q / (float(np.mean(step_ms)) / 1e3), 2), "unit": "queries/s",
-            "ms_per_step": round(float(np.mean(step_ms)), 3),
+            "value": round(N_Q / (step_avg / 1e3), 2), "unit": "queries/s",
+            "ms_per_step": round(step_avg, 3), "build_ms": round(build_avg, 3),
             "search_qps": round(N_Q / (kavg / 1e3), 1), "sweep": sweep_out,
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "scan_rot_kernel",
                          "algorithmic_bytes_per_launch": bytes_},
+            "structured": {"bases": f"{R} x H diag(s)", "budget": budget, "recall_at_1": round(w_rec, 4),
+                           "mean_distinct_candidates": round(w_distinct / N_Q, 1),
+                           "value": round(N_Q / (w_step / 1e3), 2), "ms_per_step": round(w_step, 3),
+                           "build_ms": round(w_build, 3), "scan_ms": round(w_kavg, 3)},
             "step": "build of the R tables (rotation, hashing, bucketing, cross-basis tops) + classify/probe "
                     "in every basis + scan analyzing each row once"}
 

@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "gaussian_db", "gaussian_queries", "descriptor_db", "descriptor_queries",
     "patch_field", "patch_rows", "patch_pair", "serving_requests",
-    "tie_heavy", "random_bases", "SEEDS",
+    "tie_heavy", "random_bases", "random_signs", "SEEDS",
 ]
 
 # One seed per array, 1000*workload + k.
@@ -39,7 +39,7 @@ SEEDS = {
     "sift_db": 3011, "kmeans_init": 3012,
     "patch_field": 4001, "patch_noise": 4002, "patch_sample": 4003,
     "serve_arrivals": 5001,
-    "bases": 6001,
+    "bases": 6001, "wht_signs": 6002,
 }
 
 
@@ -193,3 +193,10 @@ def random_bases(n: int, d: int, seed: int = SEEDS["bases"], identity_first: boo
         q = q * np.sign(np.diag(rr))[None, :]
         out[k] = q.astype(np.float32)
     return out
+
+
+def random_signs(n: int, d: int, seed: int = SEEDS["wht_signs"]) -> np.ndarray:
+    """``n`` vectors of ``d`` independent fair signs (+1.0 / -1.0, FP32): the
+    diagonal of the structured bases H diag(s)."""
+    return np.where(_rng(seed).random((int(n), int(d))) < 0.5, -1.0, 1.0).astype(np.float32)
+
