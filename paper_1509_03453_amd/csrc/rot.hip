@@ -171,17 +171,19 @@ __device__ inline int64_t walk_position(uint64_t top, int L, int D, const uint8_
     return n_sub * (int64_t)hstart[h] + lex * (int64_t)binom[L * 8 + h] + mrank[mask];
 }
 
-// Squared FP32 distance of the row at position pos of a chunk-major table
-// (term by term, ascending components); NCH > 0 issues all chunk loads first.
-template <typename E, int NCH>
-__device__ inline float rot_row_dist(const uint4* __restrict__ planes, int64_t N, int nch, int64_t pos,
-                                     const float* y) {
-#pragma clang fp contract(off)
-    constexpr int EPC = Unpack<E>::n;
-    if (!NCH) return row_dist_fp32<E>(planes, N, nch, pos, y);
-    uint4 v[NCH ? NCH : 1];
+// The NCH 16-byte chunks of the row at position pos of a chunk-major table.
+template <int NCH>
+__device__ inline void rot_row_load(const uint4* __restrict__ planes, int64_t N, int64_t pos, uint4 (&v)[NCH]) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) v[c] = planes[(int64_t)c * N + pos];
+}
+
+// Squared FP32 distance of loaded chunks to y (term by term, ascending
+// components, each subtraction, product and sum rounded).
+template <typename E, int NCH>
+__device__ inline float rot_row_dist(const uint4 (&v)[NCH], const float* y) {
+#pragma clang fp contract(off)
+    constexpr int EPC = Unpack<E>::n;
     float acc = 0.0f;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
@@ -197,17 +199,24 @@ __device__ inline float rot_row_dist(const uint4* __restrict__ planes, int64_t N
     return acc;
 }
 
+// Cross-basis tops fetched together with the row (the others, if R > kRotPre + 1,
+// as the checks reach them).
+constexpr int kRotPre = 3;
+
 // One to four waves per query.  The schedule's slots are taken 64 at a time
 // (cone starts and running row counts in LDS); lane f of the query's waves
 // takes rows f, f + 64*wpq, ... of that chunk through a cursor over the
 // running counts.  A row is skipped if another basis reaches it first, else
-// its FP32 distance feeds the arg-min on (distance, original row).
+// its FP32 distance feeds the arg-min on (distance, original row).  The
+// walk state of the block's queries (order, sign bits and ranks per basis,
+// 3 * R * D bytes per query) sits in dynamic LDS sized for this R and D, so
+// that many blocks share a compute unit; registers are capped for four waves
+// per SIMD (the row chunks of a visit are in flight together with its tops).
 template <typename E, int NCH>
-__global__ __launch_bounds__(256) void scan_rot_kernel(RotArgs a) {
-    __shared__ uint8_t order[4][kMaxRot][kMaxD];
-    __shared__ uint8_t sbit[4][kMaxRot][kMaxD];
-    __shared__ uint8_t rank_of[4][kMaxRot][kMaxD];
+__global__ __launch_bounds__(256, 4) void scan_rot_kernel(RotArgs a) {
+    extern __shared__ uint8_t walk_lds[];  // [qpb][3][R][D]
     __shared__ float ys[4][kMaxD];
+    __shared__ const uint4* s_planes[kMaxRot];
     __shared__ uint32_t s_start[4][64];
     __shared__ uint32_t s_incl[4][64];
     __shared__ uint8_t mrank[128];
@@ -221,12 +230,16 @@ __global__ __launch_bounds__(256) void scan_rot_kernel(RotArgs a) {
     const int64_t q = (int64_t)blockIdx.x * qpb + slot;
     const bool qv = q < a.Q;
     const int D = a.D, R = a.R, L = a.L;
+    uint8_t* const w_order = walk_lds + (size_t)slot * 3 * R * D;
+    uint8_t* const w_sbit = w_order + R * D;
+    uint8_t* const w_rank = w_sbit + R * D;
     if (threadIdx.x < 128) {  // rank of each mask among the masks of its popcount
         const int m = threadIdx.x;
         int c = 0;
         for (int v = 0; v < m; ++v) c += __popc(v) == __popc(m);
         mrank[m] = (uint8_t)c;
     }
+    if (threadIdx.x < R) s_planes[threadIdx.x] = a.planes_tab[threadIdx.x];
     if (threadIdx.x < 8) {
         uint32_t s = 0;
         for (int h = 0; h < (int)threadIdx.x; ++h) s += a.binom[L * 8 + h];
@@ -236,9 +249,9 @@ __global__ __launch_bounds__(256) void scan_rot_kernel(RotArgs a) {
     for (int r = 0; r < R; ++r)
         for (int i = sub * 64 + l; i < D; i += wpq * 64) {
             const uint8_t o = qv ? a.order[(q * R + r) * D + i] : (uint8_t)i;
-            order[slot][r][i] = o;
-            rank_of[slot][r][o] = (uint8_t)i;
-            sbit[slot][r][i] = qv ? a.sbit[(q * R + r) * D + i] : 0;
+            w_order[r * D + i] = o;
+            w_rank[r * D + o] = (uint8_t)i;
+            w_sbit[r * D + i] = qv ? a.sbit[(q * R + r) * D + i] : 0;
         }
     __syncthreads();
     const float* y = ys[slot];
@@ -253,7 +266,7 @@ __global__ __launch_bounds__(256) void scan_rot_kernel(RotArgs a) {
         uint32_t start = 0, len = 0;
         if (kl < kstop) {
             const int r = (int)(kl % R);
-            const uint32_t c = probe_cone(kl / R, L, order[slot][r], sbit[slot][r], a.n_sub, a.lexsub, a.maskord,
+            const uint32_t c = probe_cone(kl / R, L, w_order + r * D, w_sbit + r * D, a.n_sub, a.lexsub, a.maskord,
                                           a.binom);
             const uint32_t* off = a.offsets + (int64_t)r * (a.n_cones + 1);
             start = off[c];
@@ -274,17 +287,36 @@ __global__ __launch_bounds__(256) void scan_rot_kernel(RotArgs a) {
             const int r = (int)(kk % R);
             const int64_t lv = kk / R;
             const int64_t p = (int64_t)st[k] + (f - before);
+            // every load of this visit at once: the row's tops in (up to
+            // kRotPre) other bases and, speculatively, the row itself
+            const uint64_t* xt = a.xtop + (int64_t)r * R * a.N + p;
+            uint64_t tops[kRotPre];
+#pragma unroll
+            for (int t = 0; t < kRotPre; ++t) {
+                const int r2 = t < r ? t : t + 1;  // the t-th basis other than r
+                tops[t] = r2 < R ? xt[(int64_t)r2 * a.N] : 0;
+            }
+            uint4 v[NCH ? NCH : 1];
+            if (NCH) rot_row_load<NCH ? NCH : 1>(s_planes[r], a.N, p, v);
+            // a row is analyzed at its first visit: no other basis r2 reaches
+            // it at an earlier level, or at this level with r2 < r
             bool first = true;
-            for (int r2 = 0; r2 < R && first; ++r2) {
-                if (r2 == r) continue;
-                const uint64_t top = a.xtop[((int64_t)r * R + r2) * a.N + p];
-                const int64_t pos2 = walk_position(top, L, D, rank_of[slot][r2], sbit[slot][r2], a.n_sub, a.binom,
+            auto check = [&](int r2, uint64_t top) {
+                const int64_t pos2 = walk_position(top, L, D, w_rank + r2 * D, w_sbit + r2 * D, a.n_sub, a.binom,
                                                    mrank, hstart);
                 first = !(pos2 < lv || (pos2 == lv && r2 < r));
+            };
+#pragma unroll
+            for (int t = 0; t < kRotPre; ++t)
+                if (first && t < R - 1) check(t < r ? t : t + 1, tops[t]);
+            for (int t = kRotPre; t < R - 1 && first; ++t) {
+                const int r2 = t < r ? t : t + 1;
+                check(r2, xt[(int64_t)r2 * a.N]);
             }
             if (!first) continue;
             ++analyzed;
-            const float d = rot_row_dist<E, NCH>(a.planes_tab[r], a.N, a.nch, p, y);
+            const float d = NCH ? rot_row_dist<E, NCH ? NCH : 1>(v, y)
+                                : row_dist_fp32<E>(s_planes[r], a.N, a.nch, p, y);
             if (d <= best) {
                 const uint32_t row = a.perm[(int64_t)r * a.N + p];
                 if (d < best || row < brow) {
@@ -337,15 +369,16 @@ template <typename E>
 static hipError_t dispatch_scan_rot(const RotArgs& a, hipStream_t s) {
     const int qpb = 4 / a.waves_per_query;
     const dim3 grid((unsigned)((a.Q + qpb - 1) / qpb)), block(256);
+    const size_t lds = (size_t)qpb * 3 * a.R * a.D;
     switch (a.nch) {
-#define OSANN_ROT_CASE(C)                                                   \
-    case C:                                                                 \
-        hipLaunchKernelGGL((scan_rot_kernel<E, C>), grid, block, 0, s, a);  \
+#define OSANN_ROT_CASE(C)                                                     \
+    case C:                                                                   \
+        hipLaunchKernelGGL((scan_rot_kernel<E, C>), grid, block, lds, s, a);  \
         break;
         OSANN_ROT_CASE(1) OSANN_ROT_CASE(2) OSANN_ROT_CASE(4) OSANN_ROT_CASE(8) OSANN_ROT_CASE(16)
 #undef OSANN_ROT_CASE
         default:
-            hipLaunchKernelGGL((scan_rot_kernel<E, 0>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((scan_rot_kernel<E, 0>), grid, block, lds, s, a);
     }
     return hipGetLastError();
 }
