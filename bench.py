@@ -247,7 +247,8 @@ def bases_leg(X, db, q, nn_d64, R=4, sweep=(65536, 98304, 131072, 196608, 262144
             "ms_per_step": round(step_avg, 3), "build_ms": round(build_avg, 3),
             "search_qps": round(N_Q / (kavg / 1e3), 1), "sweep": sweep_out,
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "scan_rot_kernel",
+                         "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": stored_traffic("scan_rot_kernel", budget),
+                         "kernel": "scan_rot_kernel",
                          "algorithmic_bytes_per_launch": bytes_},
             "structured": {"bases": f"{R} x H diag(s)", "budget": budget, "recall_at_1": round(w_rec, 4),
                            "mean_distinct_candidates": round(w_distinct / N_Q, 1),
