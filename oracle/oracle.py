@@ -82,6 +82,13 @@ def lib():
                                          p, p, p, p, i32, i32, i32]
             L.orc_wht.restype = i32
             L.orc_wht.argtypes = [p, i32, i64, i32, p, p]
+            L.orc_bucket_sparse.restype = i64
+            L.orc_bucket_sparse.argtypes = [p, i64, p, p, p]
+            L.orc_walk_prefix.restype = i64
+            L.orc_walk_prefix.argtypes = [p, i32, i32, p, i64]
+            L.orc_search_sparse.restype = i32
+            L.orc_search_sparse.argtypes = [p, i32, i64, i32, i32, p, i64, p, p, p, i32, i64, i64, i32,
+                                            p, p, p, p, i32]
             L.orc_search_keyed.restype = i32
             L.orc_search_keyed.argtypes = [p, i32, i64, i32, i32, i32, p, p, p, i32, p, i64, i64,
                                            p, p, p, p, i32, i32]
@@ -527,3 +534,53 @@ def search_ivf(X, index, Y, B: int, nprobe: int, nthreads: int = 0, cones: bool 
     if rc != 0:
         raise RuntimeError(f"orc_search_ivf failed ({rc})")
     return idx, d32, d64, nca
+
+
+# ---------------------------------------------------------------------------
+# Sparse table (Section 4, second-level hash; reading R15)
+# ---------------------------------------------------------------------------
+
+def walk_prefix(y, G: int, n: int) -> np.ndarray:
+    """The first ``n`` cones of the query's walk (Section 3.B), empty or not."""
+    y, py = _arr(y, np.float32)
+    out = np.empty(int(n), dtype=np.int64)
+    m = lib().orc_walk_prefix(py, y.shape[0], G, out.ctypes.data_as(C.c_void_p), int(n))
+    return out[:m].copy()
+
+
+def build_index_sparse(X, G: int):
+    """Rows hashed as for one basis, then kept as a sparse table: the distinct
+    non-empty cones in ascending order (``keys``) and their rows' offsets."""
+    top, sg, cone = hash_rows(X, G)
+    N = cone.shape[0]
+    keys = np.empty(N, dtype=np.int64)
+    off = np.empty(N + 1, dtype=np.int64)
+    perm = np.empty(N, dtype=np.int64)
+    u = lib().orc_bucket_sparse(cone.ctypes.data_as(C.c_void_p), N, keys.ctypes.data_as(C.c_void_p),
+                                off.ctypes.data_as(C.c_void_p), perm.ctypes.data_as(C.c_void_p))
+    if u < 0:
+        raise MemoryError("orc_bucket_sparse")
+    return {"top": top, "sign": sg, "cone": cone, "keys": keys[:u].copy(), "offsets": off[:u + 1].copy(),
+            "perm": perm, "n_cones": num_cones(X.shape[1], G), "K": X.shape[1], "G": G, "sparse": True}
+
+
+def search_sparse(X, index, Y, B: int, cones: bool = False, nthreads: int = 0):
+    """Algorithm 1 on a sparse table: ``(idx, d32, d64, ncand)`` per query."""
+    X, px, xdt = _rows(X)
+    Y, py, ydt = _rows(Y)
+    N, K = X.shape
+    Q = Y.shape[0]
+    keys, pk = _arr(index["keys"], np.int64)
+    off, po = _arr(index["offsets"], np.int64)
+    perm, pp = _arr(index["perm"], np.int64)
+    idx = np.empty(Q, dtype=np.int64)
+    d32 = np.empty(Q, dtype=np.float32)
+    d64 = np.empty(Q, dtype=np.float64)
+    nca = np.empty(Q, dtype=np.int64)
+    rc = lib().orc_search_sparse(px, xdt, N, K, index["G"], pk, keys.shape[0], po, pp, py, ydt, Q, int(B),
+                                 int(bool(cones)), idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
+                                 d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"orc_search_sparse failed ({rc})")
+    return idx, d32, d64, nca
+

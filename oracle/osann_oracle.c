@@ -65,6 +65,14 @@
  *       a - b) rounded in FP32), left unnormalised: the positive factor
  *       1/sqrt(K) changes neither the order of the magnitudes nor the signs,
  *       so the cones are those of the orthonormal basis.
+ *   R15 sparse table (Section 4: a second-level hash table manages the
+ *       tables when the number of cones is very large): only the non-empty
+ *       cones are stored, as a list of distinct cone ids in ascending order
+ *       with the offsets of their rows (rows sorted by cone, then by row
+ *       id); a cone of the walk that is not in the list is empty.  The walk
+ *       and the stopping rules are those of the dense table (row budget:
+ *       reading R5; fixed C: reading R13), so both tables give the same
+ *       search; a budget of at least N (or C >= N_C) takes every row.
  *
  * Precision: distances are produced both in double (the definition, eq. (1))
  * and in FP32 evaluated term by term in ascending component order with each
@@ -1050,3 +1058,182 @@ int orc_search_ivf(const void *X, int xdtype, int64_t N, int K, int G, const flo
     }
     return bad ? -2 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sparse table (Section 4, second-level hash; reading R15)                  */
+/* ------------------------------------------------------------------------ */
+
+struct cone_row {
+    int64_t cone, row;
+};
+
+static int cone_row_cmp(const void *a, const void *b)
+{
+    const struct cone_row *x = (const struct cone_row *)a, *y = (const struct cone_row *)b;
+    if (x->cone != y->cone)
+        return x->cone < y->cone ? -1 : 1;
+    return x->row < y->row ? -1 : (x->row > y->row);
+}
+
+/* Rows sorted by (cone, row) into perm; keys[u] is the u-th distinct cone in
+ * ascending order and its rows are perm[offsets[u] .. offsets[u+1]).
+ * keys, offsets and perm hold N, N + 1 and N entries.  Returns the number
+ * of distinct cones, or -1 when out of memory. */
+int64_t orc_bucket_sparse(const int64_t *cone, int64_t N, int64_t *keys, int64_t *offsets, int64_t *perm)
+{
+    struct cone_row *cr = (struct cone_row *)malloc(sizeof(struct cone_row) * (size_t)(N > 0 ? N : 1));
+    if (!cr)
+        return -1;
+    for (int64_t n = 0; n < N; n++) {
+        cr[n].cone = cone[n];
+        cr[n].row = n;
+    }
+    qsort(cr, (size_t)N, sizeof(struct cone_row), cone_row_cmp);
+    int64_t u = 0;
+    for (int64_t i = 0; i < N; i++) {
+        if (i == 0 || cr[i].cone != cr[i - 1].cone) {
+            keys[u] = cr[i].cone;
+            offsets[u] = i;
+            u++;
+        }
+        perm[i] = cr[i].row;
+    }
+    offsets[u] = N;
+    free(cr);
+    return u;
+}
+
+/* Position of cone in keys[0..n) (ascending), or -1 if absent (empty cone). */
+static int64_t sparse_find(const int64_t *keys, int64_t n, int64_t cone)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] < cone)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < n && keys[lo] == cone ? lo : -1;
+}
+
+struct sparse_ctx {
+    const int64_t *keys, *offsets;
+    int64_t n_keys;
+    int cones;
+    int64_t B, seen, cum;
+    int64_t *probes;
+    int64_t cap, n;
+};
+
+/* One walk position: the row budget of reading R5 or the first B cones of
+ * reading R13, with the cone's rows looked up in the sparse table. */
+static int take_sparse(int64_t cone, void *vctx)
+{
+    struct sparse_ctx *c = (struct sparse_ctx *)vctx;
+    if (c->cones && c->seen >= c->B)
+        return 1;
+    c->seen++;
+    int64_t u = sparse_find(c->keys, c->n_keys, cone);
+    int64_t size = u < 0 ? 0 : c->offsets[u + 1] - c->offsets[u];
+    if (size > 0) {
+        if (c->n < c->cap)
+            c->probes[c->n] = u;
+        c->n++;
+        c->cum += size;
+    }
+    if (c->cones)
+        return c->seen >= c->B;
+    return size > 0 && c->cum >= c->B;
+}
+
+/* The walk's first n positions (cones, empty or not); returns how many were
+ * written (fewer only when N_C < n). */
+struct prefix_ctx {
+    int64_t *out;
+    int64_t cap, n;
+};
+
+static int take_prefix(int64_t cone, void *vctx)
+{
+    struct prefix_ctx *c = (struct prefix_ctx *)vctx;
+    c->out[c->n++] = cone;
+    return c->n >= c->cap;
+}
+
+int64_t orc_walk_prefix(const float *y, int K, int G, int64_t *cones, int64_t n)
+{
+    if (n < 1)
+        return 0;
+    struct prefix_ctx c = { cones, n, 0 };
+    walk_cones(y, K, G, take_prefix, &c);
+    return c.n;
+}
+
+/* Probe list of one query on a sparse table: bucket numbers u (positions in
+ * keys) of the non-empty cones taken, in walk order; *ncand their rows. */
+int64_t orc_probe_sparse(const float *y, int K, int G, const int64_t *keys, int64_t n_keys,
+                         const int64_t *offsets, int64_t N, int64_t B, int cones, int64_t *probes, int64_t cap,
+                         int64_t *ncand)
+{
+    int64_t NC = orc_num_cones(K, G);
+    if ((!cones && B >= N) || (cones && B >= NC)) {  /* every row */
+        for (int64_t u = 0; u < n_keys && u < cap; u++)
+            probes[u] = u;
+        *ncand = offsets[n_keys];
+        return n_keys;
+    }
+    struct sparse_ctx c = { keys, offsets, n_keys, cones, B, 0, 0, probes, cap, 0 };
+    walk_cones(y, K, G, take_sparse, &c);
+    *ncand = c.cum;
+    return c.n;
+}
+
+/* Algorithm 1 with one basis on a sparse table (reading R15); outputs as in
+ * orc_search_keyed (row -1 and +inf when there is no candidate). */
+int orc_search_sparse(const void *X, int xdtype, int64_t N, int K, int G, const int64_t *keys, int64_t n_keys,
+                      const int64_t *offsets, const int64_t *perm, const void *Y, int ydtype, int64_t Q, int64_t B,
+                      int cones, int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand, int nthreads)
+{
+    if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || n_keys < 1)
+        return -1;
+    set_threads(nthreads);
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < Q; q++) {
+        float y[256], x[256];
+        load_row(Y, ydtype, q, K, y);
+        int64_t *probes = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_keys);
+        if (!probes) {
+#pragma omp atomic write
+            bad = 1;
+            continue;
+        }
+        int64_t ncand = 0;
+        int64_t np = orc_probe_sparse(y, K, G, keys, n_keys, offsets, N, B, cones, probes, n_keys, &ncand);
+        float best_d = INFINITY;
+        int64_t best_row = INT64_MAX;
+        double best_d64 = INFINITY;
+        for (int64_t k = 0; k < np; k++) {
+            int64_t u = probes[k];
+            for (int64_t pos = offsets[u]; pos < offsets[u + 1]; pos++) {
+                int64_t row = perm[pos];
+                float d32;
+                double d64;
+                load_row(X, xdtype, row, K, x);
+                dist2(x, y, K, &d32, &d64);
+                int64_t before = best_row;
+                argmin_update(d32, row, &best_d, &best_row);
+                if (best_row != before)
+                    best_d64 = d64;
+            }
+        }
+        out_idx[q] = best_row == INT64_MAX ? -1 : best_row;
+        out_d32[q] = best_d;
+        out_d64[q] = best_d64;
+        out_ncand[q] = ncand;
+        free(probes);
+    }
+    return bad ? -2 : 0;
+}
+
