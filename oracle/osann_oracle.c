@@ -72,7 +72,10 @@
  *       id); a cone of the walk that is not in the list is empty.  The walk
  *       and the stopping rules are those of the dense table (row budget:
  *       reading R5; fixed C: reading R13), so both tables give the same
- *       search; a budget of at least N (or C >= N_C) takes every row.
+ *       search; a budget of at least N (or C >= N_C) takes every row.  A
+ *       walk takes at most 2^22 positions: a row budget not met by then (or
+ *       a C beyond it) stops there, which bounds the work of a walk through
+ *       mostly empty cones.
  *
  * Precision: distances are produced both in double (the definition, eq. (1))
  * and in FP32 evaluated term by term in ascending component order with each
@@ -1117,11 +1120,13 @@ static int64_t sparse_find(const int64_t *keys, int64_t n, int64_t cone)
     return lo < n && keys[lo] == cone ? lo : -1;
 }
 
+#define ORC_SPARSE_WALK_CAP ((int64_t)1 << 22)
+
 struct sparse_ctx {
     const int64_t *keys, *offsets;
     int64_t n_keys;
     int cones;
-    int64_t B, seen, cum;
+    int64_t B, limit, seen, cum;
     int64_t *probes;
     int64_t cap, n;
 };
@@ -1131,7 +1136,7 @@ struct sparse_ctx {
 static int take_sparse(int64_t cone, void *vctx)
 {
     struct sparse_ctx *c = (struct sparse_ctx *)vctx;
-    if (c->cones && c->seen >= c->B)
+    if (c->seen >= c->limit)
         return 1;
     c->seen++;
     int64_t u = sparse_find(c->keys, c->n_keys, cone);
@@ -1143,8 +1148,8 @@ static int take_sparse(int64_t cone, void *vctx)
         c->cum += size;
     }
     if (c->cones)
-        return c->seen >= c->B;
-    return size > 0 && c->cum >= c->B;
+        return c->seen >= c->limit;
+    return (size > 0 && c->cum >= c->B) || c->seen >= c->limit;
 }
 
 /* The walk's first n positions (cones, empty or not); returns how many were
@@ -1183,7 +1188,10 @@ int64_t orc_probe_sparse(const float *y, int K, int G, const int64_t *keys, int6
         *ncand = offsets[n_keys];
         return n_keys;
     }
-    struct sparse_ctx c = { keys, offsets, n_keys, cones, B, 0, 0, probes, cap, 0 };
+    int64_t limit = NC < ORC_SPARSE_WALK_CAP ? NC : ORC_SPARSE_WALK_CAP;
+    if (cones && B < limit)
+        limit = B;
+    struct sparse_ctx c = { keys, offsets, n_keys, cones, B, limit, 0, 0, probes, cap, 0 };
     walk_cones(y, K, G, take_sparse, &c);
     *ncand = c.cum;
     return c.n;

@@ -91,3 +91,22 @@ def test_large_table_every_row():
     i32, e32, i64, e64 = O.exhaustive(X, Y[:5])
     assert np.array_equal(idx, i32) and np.array_equal(d32, e32)
     assert (nca == len(X)).all()
+
+
+def test_walk_cap():
+    # a budget the first 2^22 walk positions cannot meet stops there (R15)
+    X, Y, s = _big()
+    cap = 1 << 22
+    keys, off = s["keys"], s["offsets"]
+    for B, cones in ((5000, False), (cap * 2, True)):
+        idx, d32, d64, nca = O.search_sparse(X, s, Y[:2], B, cones=cones)
+        for q in range(2):
+            pre = O.walk_prefix(Y[q], 5, cap)
+            assert len(pre) == cap
+            at = np.searchsorted(keys, pre)
+            hit = (at < len(keys)) & (keys[np.minimum(at, len(keys) - 1)] == pre)
+            rows = np.concatenate([s["perm"][off[u]:off[u + 1]] for u in at[hit]])
+            assert nca[q] == len(rows) and len(rows) < 5000
+            dd = ((X[rows].astype(np.float64) - Y[q].astype(np.float64)) ** 2).sum(1)
+            assert idx[q] in set(rows.tolist())
+            assert d64[q] == pytest.approx(dd.min(), rel=1e-6)
