@@ -56,8 +56,9 @@ extern "C" {
                                  bad dtype or mode; workspace too small */
 #define OS_ANN_ENOMEM     -2  /* device allocation failed */
 #define OS_ANN_EDEVICE    -3  /* a HIP runtime call or kernel launch failed */
-#define OS_ANN_ENOTSUP    -4  /* N_C = C(D,L) * 2^L above 2^24; tiled mode with more
-                                 non-empty cones than its LDS cone list holds */
+#define OS_ANN_ENOTSUP    -4  /* N_C = C(D,L) * 2^L above 2^24 for a table kind without a
+                                 sparse form; tiled mode with more non-empty cones than
+                                 its LDS cone list holds, or on a sparse table */
 #define OS_ANN_ENONFINITE -5  /* NaN or infinity in the database (build only) */
 
 /* Storage types of database rows and queries. */
@@ -133,7 +134,19 @@ os_ann_index *os_ann_build(const float *db, int64_t N, int32_t D, int32_t L);
 
 /* As os_ann_build with rows stored as opts->dtype (FP32, FP16 or uint8) and
  * the build enqueued on opts->stream (still synchronous).  opts may be NULL
- * (FP32, null stream). */
+ * (FP32, null stream).
+ *
+ * Sparse table (Section 4: a second-level hash table manages the table when
+ * the cones are very many): when N_C = C(D,L) 2^L exceeds 2^24 (os_ann_build
+ * too), only the non-empty cones are kept: the rows' 64-bit cone ids sorted
+ * (rows of a cone in ascending order), the distinct ids with their row
+ * offsets, and a hash table from id to bucket.  Searches walk the same
+ * Section 3.B order (a cone missing from the table is empty) with the same
+ * row budget or fixed-C rule, except that a walk takes at most 2^22
+ * positions (a row budget not met by then stops there); a budget of at
+ * least N, or C >= N_C, takes every row.  FP32 mode only (tiled, and
+ * opts->want_lowp: ENOTSUP); os_ann_classify: ENOTSUP; os_ann_export gives
+ * row tops and perm only, the rest comes from os_ann_export_sparse. */
 os_ann_index *os_ann_build_ex(const void *db, int64_t N, int32_t D, int32_t L,
                               const os_ann_build_opts *opts);
 
@@ -312,6 +325,14 @@ int os_ann_export(const os_ann_index *idx, uint32_t *row_cone, uint64_t *row_top
  * os_ann_build_rot; r = 0 for any other index. */
 int os_ann_export_basis(const os_ann_index *idx, int32_t r, uint32_t *row_cone, uint64_t *row_top,
                         int64_t *offsets, int64_t *perm, void *stream);
+
+/* Sparse table only (EINVAL otherwise): cone_ids[n_nonempty] (uint64, the
+ * distinct non-empty cones in ascending order; n_nonempty from
+ * os_ann_info), offsets[n_nonempty+1] (int64; the rows of cone_ids[u] sit
+ * at sorted positions offsets[u] .. offsets[u+1]-1) and perm[N] (int64).
+ * Any output may be NULL.  Asynchronous on `stream`. */
+int os_ann_export_sparse(const os_ann_index *idx, uint64_t *cone_ids, int64_t *offsets, int64_t *perm,
+                         void *stream);
 
 /* Copy out the permuted rows, converted exactly to FP32: rows[N][D] with
  * rows[pos] = db[perm[pos]].  Asynchronous on `stream`. */

@@ -70,6 +70,7 @@ SIGNATURES = {
     "os_ann_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "os_ann_export_basis": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
+    "os_ann_export_sparse": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "os_ann_export_rows": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "os_ann_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "os_ann_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -366,6 +367,25 @@ def os_ann_export_basis(index: int, r: int, stream=None) -> dict:
     if rc:
         _raise(rc)
     return {"cone": cone, "top": top, "offsets": off, "perm": perm}
+
+
+def os_ann_export_sparse(index: int, stream=None) -> dict:
+    """Sparse table: distinct cone ids (int64 view of uint64), their row
+    offsets, the permutation and the packed top-L pairs of the rows."""
+    info = os_ann_info(index)
+    N, ne = info["N"], info["n_nonempty"]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ids = torch.empty(ne, dtype=torch.int64, device=dev)
+    off = torch.empty(ne + 1, dtype=torch.int64, device=dev)
+    perm = torch.empty(N, dtype=torch.int64, device=dev)
+    top = torch.empty(N, dtype=torch.int64, device=dev)
+    rc = lib().os_ann_export_sparse(index, _ptr(ids), _ptr(off), _ptr(perm), _stream_ptr(stream))
+    if rc:
+        _raise(rc)
+    rc = lib().os_ann_export(index, None, _ptr(top), None, None, _stream_ptr(stream))
+    if rc:
+        _raise(rc)
+    return {"cone_ids": ids, "offsets": off, "perm": perm, "top": top}
 
 
 def os_ann_export_rows(index: int, stream=None) -> torch.Tensor:

@@ -17,6 +17,7 @@
 
 #include "osann_fixedc.h"
 #include "osann_ivf.h"
+#include "osann_sparse.h"
 #include "osann_kernels.h"
 #include "osann_tiled.h"
 #include "osann_wht.h"
@@ -127,6 +128,13 @@ struct os_ann_index {
     // cluster * n_cones + cone; the rows are hashed on their residuals
     int32_t n_groups = 1;       // clusters (1: a plain table)
     float* ivf_cent = nullptr;  // [n_groups][D]
+    // sparse table (more than 2^24 cones): offsets are per non-empty cone
+    bool sparse = false;
+    uint64_t* sp_keys = nullptr;   // [n_nonempty] cone ids, ascending
+    uint64_t* sp_hkeys = nullptr;  // [sp_cap] hash slots
+    uint32_t* sp_hval = nullptr;   // [sp_cap]
+    uint64_t sp_cap = 0;
+    uint64_t* binom64 = nullptr;   // [257][8]
     int32_t nprobe = 0;         // clusters searched per query
 };
 
@@ -246,17 +254,18 @@ void release(os_ann_index* ix, bool synced = false) {
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
                     ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
-                    ix->planes_tab, ix->proj_mu, ix->proj_P, ix->ivf_cent, ix->rot_signs};
+                    ix->planes_tab, ix->proj_mu, ix->proj_P, ix->ivf_cent, ix->rot_signs,
+                    ix->sp_keys, ix->sp_hkeys, ix->sp_hval, ix->binom64};
     for (void* p : ptrs) dev_free(p);
     delete ix;
 }
 
-int check_shape(int64_t N, int32_t D, int32_t L, int64_t* n_cones) {
+int check_shape(int64_t N, int32_t D, int32_t L, int64_t* n_cones, bool allow_sparse = false) {
     if (N < 1 || N >= (int64_t(1) << 31)) return fail(OS_ANN_EINVAL, "N must be in [1, 2^31)");
     if (D < 1 || D > kMaxD) return fail(OS_ANN_EINVAL, "D must be in [1, 256]");
     if (L < 1 || L > kMaxL || L > D) return fail(OS_ANN_EINVAL, "L must be in [1, min(D, 7)]");
     const int64_t nc = binom_host(D, L) << L;
-    if (nc > kMaxCones) return fail(OS_ANN_ENOTSUP, "C(D,L)*2^L exceeds 2^24 cones");
+    if (nc > kMaxCones && !allow_sparse) return fail(OS_ANN_ENOTSUP, "C(D,L)*2^L exceeds 2^24 cones");
     *n_cones = nc;
     return OS_ANN_OK;
 }
@@ -355,6 +364,16 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         return here;
     };
     p.off_yf = take((size_t)Q * p.dpad * sizeof(float));
+    if (ix->sparse) {  // sparse table: FP32 scan, 64-bit walk lengths
+        p.mode = OS_ANN_MODE_FP32;
+        p.Qv = Q;
+        p.off_order = take((size_t)Q * ix->D);
+        p.off_sbit = take((size_t)Q * ix->D);
+        p.off_jstop = take((size_t)Q * sizeof(uint64_t));
+        p.off_nc = take((size_t)Q * sizeof(int64_t));
+        p.bytes = at;
+        return p;
+    }
     if (ix->n_rot > 0) {  // several bases: FP32 scan with per-basis walk state
         const size_t R = (size_t)ix->n_rot;
         p.mode = OS_ANN_MODE_FP32;
@@ -428,6 +447,8 @@ int search_checks(const os_ann_index* ix, const void* queries, int64_t Q, int64_
             return fail(OS_ANN_EINVAL, "rerank_r must be 4, 8 or 16");
         if (o->mode == OS_ANN_MODE_TILED && ix->n_rot > 0)
             return fail(OS_ANN_ENOTSUP, "several bases: FP32 mode only");
+        if (o->mode == OS_ANN_MODE_TILED && ix->sparse)
+            return fail(OS_ANN_ENOTSUP, "sparse table: FP32 mode only");
         if (o->mode == OS_ANN_MODE_TILED && ix->proj)
             return fail(OS_ANN_ENOTSUP, "projected table: FP32 mode only");
         if (o->mode == OS_ANN_MODE_TILED && ix->ivf_cent)
@@ -978,7 +999,69 @@ hipError_t enqueue_ivf(const Call& c) {
     return e;
 }
 
+// Sparse table: the probe kernel ranks the queries (walk state, FP32 copy),
+// the sparse walk finds the walk lengths, the sparse scan takes the rows.
+hipError_t enqueue_sparse(const Call& c) {
+    os_ann_index* ix = c.ix;
+    const SearchPlan& p = c.p;
+    ProbeArgs pa{};
+    pa.Y = c.queries;
+    pa.qtype = c.qtype;
+    pa.Q = c.Q;
+    pa.D = ix->D;
+    pa.L = ix->L;
+    pa.N = ix->N;
+    pa.yf = reinterpret_cast<float*>(c.base + p.off_yf);
+    pa.dpad = p.dpad;
+    pa.order = reinterpret_cast<uint8_t*>(c.base + p.off_order);
+    pa.sbit = reinterpret_cast<uint8_t*>(c.base + p.off_sbit);
+    SparseTable t{};
+    t.hkeys = ix->sp_hkeys;
+    t.hval = ix->sp_hval;
+    t.hmask = ix->sp_cap - 1;
+    t.offsets = ix->offsets;
+    t.binom = ix->binom64;
+    t.maskord = ix->maskord;
+    t.n_sub = ix->n_sub;
+    t.n_cones = ix->n_cones;
+    t.N = ix->N;
+    t.D = ix->D;
+    t.L = ix->L;
+    SparseWalkArgs wa{};
+    wa.t = t;
+    wa.order = pa.order;
+    wa.sbit = pa.sbit;
+    wa.Q = c.Q;
+    wa.budget = c.budget;
+    wa.cones = p.cones ? 1 : 0;
+    wa.jstop = reinterpret_cast<uint64_t*>(c.base + p.off_jstop);
+    wa.ncand = c.out_ncand ? c.out_ncand : reinterpret_cast<int64_t*>(c.base + p.off_nc);
+    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] {
+        hipError_t r = launch_probe(pa, c.s);
+        if (r == hipSuccess) r = launch_sparse_walk(wa, c.s);
+        return r;
+    });
+    if (e != hipSuccess) return e;
+    SparseScanArgs sa{};
+    sa.t = t;
+    sa.planes = ix->planes;
+    sa.dtype = ix->dtype;
+    sa.nch = ix->nch;
+    sa.yf = pa.yf;
+    sa.dpad = p.dpad;
+    sa.order = pa.order;
+    sa.sbit = pa.sbit;
+    sa.jstop = wa.jstop;
+    sa.perm = ix->perm;
+    sa.Q = c.Q;
+    sa.out_idx = c.out_idx;
+    sa.out_dist = c.out_dist;
+    sa.waves_per_query = expected_rows(ix, c.budget, p.cones) <= 8192 ? 1 : 4;
+    return timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] { return launch_sparse_scan(sa, c.s); });
+}
+
 hipError_t enqueue(const Call& c, int S) {
+    if (c.ix->sparse) return enqueue_sparse(c);
     if (c.ix->n_rot > 0) return enqueue_rot(c);
     if (c.ix->ivf_cent) return enqueue_ivf(c);
     return c.p.mode == OS_ANN_MODE_TILED ? enqueue_tiled(c, S) : enqueue_fp32(c);
@@ -1168,6 +1251,117 @@ os_ann_index* build_table(const void* keys, int32_t key_dtype, int32_t Dk, const
     tmp = small = nullptr;
     return ix;
 }
+// Sparse table (Section 4, second-level hash) for C(D,L) 2^L above 2^24:
+// 64-bit cone ids of the rows, a stable sort by id, the distinct ids with
+// their row offsets, and a hash table from id to bucket number.
+os_ann_index* build_sparse(const void* db, int32_t dtype, int64_t N, int32_t D, int32_t L, int64_t nc,
+                           hipStream_t s) {
+    auto* ix = new os_ann_index();
+    ix->N = N;
+    ix->D = D;
+    ix->Dk = D;
+    ix->L = L;
+    ix->dtype = dtype;
+    ix->n_cones = nc;
+    ix->n_sub = binom_host(D, L);
+    ix->epc = chunk_elems(dtype);
+    ix->nch = (D + ix->epc - 1) / ix->epc;
+    ix->sparse = true;
+    (void)hipGetDevice(&ix->device);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ix->device) == hipSuccess && ncu > 0)
+        ix->num_cu = ncu;
+    int end_bit = 1;
+    while (end_bit < 64 && ((uint64_t)(nc - 1) >> end_bit) != 0) ++end_bit;
+    const size_t n = (size_t)N;
+    const size_t sort_bytes = sparse_sort_tmp_bytes(N, end_bit);
+    uint64_t *key = nullptr, *sorted = nullptr;
+    uint32_t *flag = nullptr, *pos = nullptr, *scan_tmp = nullptr, *small = nullptr;
+    void* sort_tmp = nullptr;
+    auto bail = [&]() -> os_ann_index* {
+        (void)hipDeviceSynchronize();
+        dev_free(key);
+        dev_free(sorted);
+        dev_free(flag);
+        dev_free(pos);
+        dev_free(scan_tmp);
+        dev_free(small);
+        dev_free(sort_tmp);
+        release(ix);
+        return nullptr;
+    };
+    auto step = [&](hipError_t e, const char* what) -> bool {
+        if (e != hipSuccess) {
+            hip_fail(e, what);
+            return false;
+        }
+        return true;
+    };
+    if (dev_alloc(ix, (void**)&ix->row_cone, n * 4, "row_cone") ||
+        dev_alloc(ix, (void**)&ix->row_top, n * 8, "row_top") ||
+        dev_alloc(ix, (void**)&ix->perm, n * 4, "perm") ||
+        dev_alloc(ix, &ix->planes, (size_t)ix->nch * n * 16, "planes") ||
+        dev_alloc(ix, (void**)&ix->maskord, 128, "maskord") ||
+        dev_alloc(ix, (void**)&ix->binom64, 257 * 8 * 8, "binomials") ||
+        dev_alloc(nullptr, (void**)&key, n * 8, "sparse keys") ||
+        dev_alloc(nullptr, (void**)&sorted, n * 8, "sorted keys") ||
+        dev_alloc(nullptr, (void**)&flag, n * 4, "heads") ||
+        dev_alloc(nullptr, (void**)&pos, (n + 1) * 4, "head positions") ||
+        dev_alloc(nullptr, (void**)&scan_tmp, (size_t)exclusive_scan_tmp_words(N) * 4, "scan scratch") ||
+        dev_alloc(nullptr, (void**)&small, 16, "flags") ||
+        dev_alloc(nullptr, &sort_tmp, sort_bytes > 0 ? sort_bytes : 16, "sort scratch"))
+        return bail();
+    // C(n, k) for n <= 256, k <= 7, and the flip masks by popcount, then value
+    std::vector<uint64_t> hb(257 * 8, 0);
+    for (int nn = 0; nn <= 256; ++nn)
+        for (int k = 0; k < 8; ++k) hb[nn * 8 + k] = (uint64_t)binom_host(nn, k);
+    std::vector<uint8_t> hm(128, 0);
+    int at = 0;
+    for (int h = 0; h <= L; ++h)
+        for (int m = 0; m < (1 << L); ++m)
+            if (__builtin_popcount(m) == h) hm[at++] = (uint8_t)m;
+    uint32_t host_small[1] = {0};
+    uint32_t host_ne = 0;
+    if (!step(hipMemcpyAsync(ix->binom64, hb.data(), hb.size() * 8, hipMemcpyHostToDevice, s), "binomials") ||
+        !step(hipMemcpyAsync(ix->maskord, hm.data(), 128, hipMemcpyHostToDevice, s), "masks") ||
+        !step(hipMemsetAsync(small, 0, 16, s), "memset") ||
+        !step(launch_row_keys(db, dtype, N, D, L, ix->row_cone, ix->row_top, small, s), "key kernel") ||
+        !step(launch_sparse_keys(ix->row_top, N, L, ix->binom64, key, s), "cone ids") ||
+        !step(launch_sparse_sort(key, sorted, ix->perm, N, end_bit, sort_tmp, sort_bytes, s), "sort") ||
+        !step(launch_sparse_heads(sorted, N, flag, s), "heads") ||
+        !step(launch_exclusive_scan(flag, N, pos, scan_tmp, s), "head scan") ||
+        !step(hipMemcpyAsync(host_small, small, 4, hipMemcpyDeviceToHost, s), "copy flags") ||
+        !step(hipMemcpyAsync(&host_ne, pos + N, 4, hipMemcpyDeviceToHost, s), "copy count") ||
+        !step(hipStreamSynchronize(s), "build sync"))
+        return bail();
+    if (host_small[0]) {
+        fail(OS_ANN_ENONFINITE, "database holds NaN or infinity");
+        return bail();
+    }
+    uint64_t cap = 64;
+    while (cap < 2 * (uint64_t)host_ne) cap <<= 1;
+    ix->sp_cap = cap;
+    ix->n_nonempty = host_ne;
+    if (dev_alloc(ix, (void**)&ix->sp_keys, (size_t)host_ne * 8, "cone ids") ||
+        dev_alloc(ix, (void**)&ix->offsets, ((size_t)host_ne + 1) * 4, "offsets") ||
+        dev_alloc(ix, (void**)&ix->sp_hkeys, (size_t)cap * 8, "hash keys") ||
+        dev_alloc(ix, (void**)&ix->sp_hval, (size_t)cap * 4, "hash values"))
+        return bail();
+    if (!step(launch_sparse_compact(sorted, flag, pos, N, ix->sp_keys, ix->offsets, s), "compact") ||
+        !step(launch_sparse_hash(ix->sp_keys, host_ne, ix->sp_hkeys, ix->sp_hval, cap, s), "hash table") ||
+        !step(launch_gather_planes(db, dtype, N, D, ix->perm, ix->planes, s), "gather") ||
+        !step(hipStreamSynchronize(s), "build sync"))
+        return bail();
+    dev_free(key);
+    dev_free(sorted);
+    dev_free(flag);
+    dev_free(pos);
+    dev_free(scan_tmp);
+    dev_free(small);
+    dev_free(sort_tmp);
+    return ix;
+}
+
 // Several bases: a table per basis from the rows' coordinates in it.  basis
 // holds n_rot dense D x D matrices, or (wht) n_rot sign vectors of H diag(s).
 os_ann_index* build_bases(const void* db, int64_t N, int32_t D, int32_t L, const float* basis, int32_t n_rot,
@@ -1289,7 +1483,14 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L, c
         fail(OS_ANN_EINVAL, "bad db dtype");
         return nullptr;
     }
-    if (check_shape(N, D, L, &nc)) return nullptr;
+    if (check_shape(N, D, L, &nc, true)) return nullptr;
+    if (nc > kMaxCones) {  // sparse table
+        if (opts && opts->want_lowp) {
+            fail(OS_ANN_ENOTSUP, "sparse table: FP32 mode only");
+            return nullptr;
+        }
+        return build_sparse(db, dtype, N, D, L, nc, s);
+    }
     os_ann_index* ix = build_table(db, dtype, D, db, dtype, N, D, L, nc, s);
     if (ix && opts && opts->want_lowp && ensure_lowp(ix, s)) {
         release(ix);
@@ -1613,6 +1814,7 @@ int os_ann_classify(const os_ann_index* cidx, const void* queries, int32_t query
     if (cidx && cidx->n_rot > 0) return fail(OS_ANN_ENOTSUP, "classify: one basis only");
     if (cidx && cidx->proj) return fail(OS_ANN_ENOTSUP, "classify: not for a projected table");
     if (cidx && cidx->ivf_cent) return fail(OS_ANN_ENOTSUP, "classify: not for a clustered table");
+    if (cidx && cidx->sparse) return fail(OS_ANN_ENOTSUP, "classify: not for a sparse table");
     os_ann_search_opts o{};
     o.query_dtype = query_dtype;
     int rc = search_checks(cidx, queries, Q, max_candidates, &o);
@@ -1646,6 +1848,8 @@ int os_ann_export(const os_ann_index* ix, uint32_t* row_cone, uint64_t* row_top,
     clear_error();
     if (!ix) return fail(OS_ANN_EINVAL, "null index");
     if (ix->n_rot > 0) ix = ix->sub[0];  // basis 0
+    if (ix->sparse && (row_cone || offsets))
+        return fail(OS_ANN_ENOTSUP, "sparse table: cone ids and offsets through os_ann_export_sparse");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (row_cone)
         OSANN_HIP(hipMemcpyAsync(row_cone, ix->row_cone, (size_t)ix->N * 4, hipMemcpyDeviceToDevice, s),
@@ -1655,6 +1859,20 @@ int os_ann_export(const os_ann_index* ix, uint32_t* row_cone, uint64_t* row_top,
                   "export top");
     if (offsets)
         OSANN_HIP(launch_widen_u32(ix->offsets, ix->n_cones * ix->n_groups + 1, offsets, s), "export offsets");
+    if (perm) OSANN_HIP(launch_widen_u32(ix->perm, ix->N, perm, s), "export perm");
+    return OS_ANN_OK;
+}
+
+int os_ann_export_sparse(const os_ann_index* ix, uint64_t* cone_ids, int64_t* offsets, int64_t* perm,
+                         void* stream) {
+    clear_error();
+    if (!ix) return fail(OS_ANN_EINVAL, "null index");
+    if (!ix->sparse) return fail(OS_ANN_EINVAL, "not a sparse table");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (cone_ids)
+        OSANN_HIP(hipMemcpyAsync(cone_ids, ix->sp_keys, (size_t)ix->n_nonempty * 8, hipMemcpyDeviceToDevice, s),
+                  "export cone ids");
+    if (offsets) OSANN_HIP(launch_widen_u32(ix->offsets, ix->n_nonempty + 1, offsets, s), "export offsets");
     if (perm) OSANN_HIP(launch_widen_u32(ix->perm, ix->N, perm, s), "export perm");
     return OS_ANN_OK;
 }

@@ -1,0 +1,402 @@
+// Sparse table (Section 4: a second-level hash table manages the tables when
+// the cones are very many).  With C(D,L) 2^L above what a dense offsets
+// array can address, only the non-empty cones are kept: the rows' 64-bit
+// cone ids are sorted (stable, so the rows of a cone keep ascending ids),
+// the distinct ids get bucket numbers and row offsets, and an
+// open-addressing hash table maps a cone id to its bucket number.
+//
+// Searching walks the Section 3.B order as the dense path does, but walk
+// position j is decoded without the dense subset table: the subset of rank
+// positions is unranked from its lexicographic rank through the colex rank
+// of the reflected subset (greedy, one binary search over C(s, k) per
+// element), then the cone id is looked up; a missing id is an empty cone.
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
+
+#include "osann_device.h"
+#include "osann_kernels.h"
+#include "osann_sparse.h"
+
+namespace osann {
+
+namespace {
+
+// SplitMix64 output function (Steele, Lea and Flood, 2014) as the hash.
+__device__ inline uint64_t sparse_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Bucket number of a cone id, or -1 for an empty cone.  At least half the
+// slots are free, so every probe sequence ends at a free slot.
+__device__ inline int64_t sparse_lookup(const SparseTable& t, uint64_t key) {
+    uint64_t h = sparse_mix(key) & t.hmask;
+    for (uint64_t step = 0; step <= t.hmask; ++step) {
+        const uint64_t k = t.hkeys[h];
+        if (k == key) return t.hval[h];
+        if (k == kSparseEmpty) return -1;
+        h = (h + 1) & t.hmask;
+    }
+    return -1;
+}
+
+// 64-bit cone id of up to 7 (index, sign bit) pairs; entries beyond L hold
+// index 0x7FFF so that they sort last.  Colex rank of the ascending index
+// set times 2^L, plus the sign bits in ascending index order, the lowest
+// index most significant.
+__device__ inline uint64_t sparse_cone_id(int L, int (&idx)[7], int (&sg)[7], const uint64_t* __restrict__ binom) {
+#pragma unroll
+    for (int a = 1; a < 7; ++a)
+#pragma unroll
+        for (int b = 6; b >= a; --b)
+            if (idx[b - 1] > idx[b]) {
+                int u = idx[b]; idx[b] = idx[b - 1]; idx[b - 1] = u;
+                u = sg[b]; sg[b] = sg[b - 1]; sg[b - 1] = u;
+            }
+    uint64_t rank = 0, bits = 0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+        if (j < L) {
+            rank += binom[idx[j] * 8 + j + 1];
+            bits = (bits << 1) | (uint64_t)sg[j];
+        }
+    return (rank << L) | bits;
+}
+
+// Cone at walk position j: block h of C(D,L) C(L,h) positions (flipped
+// signs), the lexicographic L-subset T of rank positions and the flip mask;
+// T is unranked from the colex rank C(D,L) - 1 - t of {D-1-T_b}, whose
+// k-th largest element s_k is the largest s with C(s, k) <= the remaining
+// rank.  T_b = D-1-s_{L-b}, and mask bit L-1-b (= k-1) flips the sign of
+// component order[T_b].
+__device__ inline uint64_t sparse_walk_cone(uint64_t j, const SparseTable& t, const uint8_t* order,
+                                            const uint8_t* sbit) {
+    const int L = t.L, D = t.D;
+    const uint64_t nsub = (uint64_t)t.n_sub;
+    uint64_t tt = j;
+    int mask = 0;
+    if (j >= nsub) {
+        uint64_t base = nsub, cl = 1;
+        int mstart = 1;
+        for (int h = 1; h <= L; ++h) {
+            cl = t.binom[L * 8 + h];
+            const uint64_t sz = nsub * cl;
+            if (j < base + sz) break;
+            base += sz;
+            mstart += (int)cl;
+        }
+        const uint64_t jj = j - base;
+        tt = jj / cl;
+        mask = t.maskord[mstart + (int)(jj % cl)];
+    }
+    uint64_t r = nsub - 1 - tt;
+    int idx[7], sg[7];
+#pragma unroll
+    for (int k = 7; k >= 1; --k) {
+        idx[k - 1] = 0x7FFF;
+        sg[k - 1] = 0;
+        if (k <= L) {
+            int lo = k - 1, hi = D - 1;  // C(k-1, k) = 0 <= r
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (t.binom[mid * 8 + k] <= r)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            r -= t.binom[lo * 8 + k];
+            const int c = order[D - 1 - lo];
+            idx[k - 1] = c;
+            sg[k - 1] = sbit[c] ^ ((mask >> (k - 1)) & 1);
+        }
+    }
+    return sparse_cone_id(L, idx, sg, t.binom);
+}
+
+__global__ void sparse_keys_kernel(const uint64_t* __restrict__ row_top, int64_t N, int L,
+                                   const uint64_t* __restrict__ binom, uint64_t* __restrict__ key) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const uint64_t top = row_top[n];
+    int idx[7], sg[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        idx[j] = 0x7FFF;
+        sg[j] = 0;
+        if (j < L) {
+            const uint32_t pr = (uint32_t)(top >> (9 * j)) & 0x1FFu;
+            idx[j] = (int)(pr & 0xFFu);
+            sg[j] = (int)(pr >> 8);
+        }
+    }
+    key[n] = sparse_cone_id(L, idx, sg, binom);
+}
+
+__global__ void sparse_heads_kernel(const uint64_t* __restrict__ sorted, int64_t N, uint32_t* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) flag[i] = (i == 0 || sorted[i] != sorted[i - 1]) ? 1u : 0u;
+}
+
+__global__ void sparse_compact_kernel(const uint64_t* __restrict__ sorted, const uint32_t* __restrict__ flag,
+                                      const uint32_t* __restrict__ pos, int64_t N, uint64_t* __restrict__ keys,
+                                      uint32_t* __restrict__ offsets) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (flag[i]) {
+        keys[pos[i]] = sorted[i];
+        offsets[pos[i]] = (uint32_t)i;
+    }
+    if (i == N - 1) offsets[pos[N]] = (uint32_t)N;
+}
+
+__global__ void sparse_fill_kernel(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void sparse_insert_kernel(const uint64_t* __restrict__ keys, int64_t n, uint64_t* hkeys,
+                                     uint32_t* __restrict__ hval, uint64_t mask) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const uint64_t key = keys[u];
+    uint64_t h = sparse_mix(key) & mask;
+    for (uint64_t step = 0; step <= mask; ++step) {
+        const unsigned long long prev =
+            atomicCAS(reinterpret_cast<unsigned long long*>(hkeys + h), (unsigned long long)kSparseEmpty,
+                      (unsigned long long)key);
+        if (prev == (unsigned long long)kSparseEmpty) {
+            hval[h] = (uint32_t)u;
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+constexpr int kSparseWaves = 4;
+
+// One wave per query: walk 64 positions at a time until the row budget is
+// met (or the first C positions, or kSparseWalkCap positions).
+__global__ __launch_bounds__(64 * kSparseWaves) void sparse_walk_kernel(SparseWalkArgs a) {
+    __shared__ uint8_t order[kSparseWaves][kMaxD];
+    __shared__ uint8_t sbit[kSparseWaves][kMaxD];
+    const int w = threadIdx.x / 64, l = lane_id();
+    const int64_t q = (int64_t)blockIdx.x * kSparseWaves + w;
+    if (q >= a.Q) return;  // no block barrier in this kernel
+    const SparseTable& t = a.t;
+    const int D = t.D;
+    for (int i = l; i < D; i += 64) {
+        order[w][i] = a.order[q * D + i];
+        sbit[w][i] = a.sbit[q * D + i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint64_t nc = (uint64_t)t.n_cones, budget = (uint64_t)a.budget;
+    if ((!a.cones && budget >= (uint64_t)t.N) || (a.cones && budget >= nc)) {
+        if (l == 0) {
+            a.jstop[q] = kSparseAll;
+            if (a.ncand) a.ncand[q] = t.N;
+        }
+        return;
+    }
+    uint64_t limit = nc < kSparseWalkCap ? nc : kSparseWalkCap;
+    if (a.cones && budget < limit) limit = budget;
+    uint64_t carry = 0, stop_at = limit;
+    for (uint64_t j0 = 0; j0 < limit; j0 += 64) {
+        const uint64_t j = j0 + l;
+        uint32_t len = 0;
+        if (j < limit) {
+            const int64_t u = sparse_lookup(t, sparse_walk_cone(j, t, order[w], sbit[w]));
+            if (u >= 0) len = t.offsets[u + 1] - t.offsets[u];
+        }
+        const uint32_t incl = wave_incl_scan(len);  // distinct cones: 64 of them hold at most N rows
+        if (!a.cones) {
+            const uint64_t reached = __ballot(j < limit && carry + incl >= budget);
+            if (reached) {
+                const int st = __ffsll((unsigned long long)reached) - 1;
+                carry += shfl_u32(incl, st);
+                stop_at = j0 + st + 1;
+                break;
+            }
+        }
+        carry += shfl_u32(incl, 63);
+    }
+    if (l == 0) {
+        a.jstop[q] = stop_at;
+        if (a.ncand) a.ncand[q] = (int64_t)carry;
+    }
+}
+
+// One or four waves per query: the taken positions 64 at a time (bucket
+// starts and running row counts in LDS); lane f of the query's waves takes
+// rows f, f + 64 * wpq, ... of that chunk; FP32 distance term by term and
+// arg-min on (distance, original row).
+template <typename E>
+__global__ __launch_bounds__(256) void sparse_scan_kernel(SparseScanArgs a) {
+    __shared__ uint8_t order[4][kMaxD];
+    __shared__ uint8_t sbit[4][kMaxD];
+    __shared__ float ys[4][kMaxD];
+    __shared__ uint32_t s_start[4][64];
+    __shared__ uint32_t s_incl[4][64];
+    __shared__ float red_d[4];
+    __shared__ uint32_t red_r[4];
+    const int wpq = a.waves_per_query;
+    const int qpb = 4 / wpq;
+    const int w = threadIdx.x / 64, l = lane_id();
+    const int slot = w / wpq, sub = w % wpq;
+    const int64_t q = (int64_t)blockIdx.x * qpb + slot;
+    const bool qv = q < a.Q;
+    const SparseTable& t = a.t;
+    const int D = t.D;
+    for (int i = sub * 64 + l; i < a.dpad; i += wpq * 64) ys[slot][i] = qv ? a.yf[q * a.dpad + i] : 0.0f;
+    for (int i = sub * 64 + l; i < D; i += wpq * 64) {
+        order[slot][i] = qv ? a.order[q * D + i] : 0;
+        sbit[slot][i] = qv ? a.sbit[q * D + i] : 0;
+    }
+    __syncthreads();
+    const float* y = ys[slot];
+    const uint4* planes = static_cast<const uint4*>(a.planes);
+    const uint64_t jstop = qv ? a.jstop[q] : 0;
+    float best = __builtin_huge_valf();
+    uint32_t brow = 0xFFFFFFFFu;
+    auto visit = [&](int64_t p) {
+        const float d = row_dist_fp32<E>(planes, t.N, a.nch, p, y);
+        if (d <= best) {
+            const uint32_t row = a.perm[p];
+            if (d < best || row < brow) {
+                best = d;
+                brow = row;
+            }
+        }
+    };
+    if (jstop == kSparseAll) {
+        for (int64_t p = sub * 64 + l; p < t.N; p += wpq * 64) visit(p);
+    } else {
+        uint32_t* st = s_start[w];
+        uint32_t* in = s_incl[w];
+        for (uint64_t j0 = 0; j0 < jstop; j0 += 64) {
+            const uint64_t j = j0 + l;
+            uint32_t start = 0, len = 0;
+            if (j < jstop) {
+                const int64_t u = sparse_lookup(t, sparse_walk_cone(j, t, order[slot], sbit[slot]));
+                if (u >= 0) {
+                    start = t.offsets[u];
+                    len = t.offsets[u + 1] - start;
+                }
+            }
+            const uint32_t incl = wave_incl_scan(len);
+            st[l] = start;
+            in[l] = incl;
+            const uint32_t total = shfl_u32(incl, 63);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            uint32_t k = 0;
+            for (uint32_t f = sub * 64 + l; f < total; f += wpq * 64) {
+                while (in[k] <= f) ++k;
+                const uint32_t before = k ? in[k - 1] : 0u;
+                visit((int64_t)st[k] + (f - before));
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+    }
+    wave_argmin(best, brow);
+    if (wpq > 1) {
+        if (l == 0) {
+            red_d[w] = best;
+            red_r[w] = brow;
+        }
+        __syncthreads();
+        if (sub == 0 && l == 0)
+            for (int o = 1; o < wpq; ++o) {
+                const float od = red_d[w + o];
+                const uint32_t orow = red_r[w + o];
+                if (od < best || (od == best && orow < brow)) {
+                    best = od;
+                    brow = orow;
+                }
+            }
+    }
+    if (qv && sub == 0 && l == 0) {
+        a.out_idx[q] = brow == 0xFFFFFFFFu ? -1 : (int64_t)brow;
+        a.out_dist[q] = best;
+    }
+}
+
+inline dim3 grid_for(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
+
+}  // namespace
+
+hipError_t launch_sparse_keys(const uint64_t* row_top, int64_t N, int L, const uint64_t* binom, uint64_t* key,
+                              hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    if (L < 1 || L > 7) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sparse_keys_kernel, grid_for(N, 256), dim3(256), 0, s, row_top, N, L, binom, key);
+    return hipGetLastError();
+}
+
+size_t sparse_sort_tmp_bytes(int64_t N, int end_bit) {
+    size_t bytes = 0;
+    (void)rocprim::radix_sort_pairs(nullptr, bytes, static_cast<const uint64_t*>(nullptr),
+                                    static_cast<uint64_t*>(nullptr), rocprim::counting_iterator<uint32_t>(0u),
+                                    static_cast<uint32_t*>(nullptr), (unsigned)N, 0u, (unsigned)end_bit);
+    return bytes;
+}
+
+hipError_t launch_sparse_sort(const uint64_t* key_in, uint64_t* key_out, uint32_t* perm, int64_t N, int end_bit,
+                              void* tmp, size_t tmp_bytes, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    size_t bytes = tmp_bytes;
+    return rocprim::radix_sort_pairs(tmp, bytes, key_in, key_out, rocprim::counting_iterator<uint32_t>(0u), perm,
+                                     (unsigned)N, 0u, (unsigned)end_bit, s);
+}
+
+hipError_t launch_sparse_heads(const uint64_t* sorted, int64_t N, uint32_t* flag, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sparse_heads_kernel, grid_for(N, 256), dim3(256), 0, s, sorted, N, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_sparse_compact(const uint64_t* sorted, const uint32_t* flag, const uint32_t* pos, int64_t N,
+                                 uint64_t* keys, uint32_t* offsets, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sparse_compact_kernel, grid_for(N, 256), dim3(256), 0, s, sorted, flag, pos, N, keys, offsets);
+    return hipGetLastError();
+}
+
+hipError_t launch_sparse_hash(const uint64_t* keys, int64_t n, uint64_t* hkeys, uint32_t* hval, uint64_t cap,
+                              hipStream_t s) {
+    if (cap == 0 || (cap & (cap - 1)) || cap < 2 * (uint64_t)n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sparse_fill_kernel, grid_for((int64_t)cap, 256), dim3(256), 0, s, hkeys, cap, kSparseEmpty);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n <= 0) return e;
+    hipLaunchKernelGGL(sparse_insert_kernel, grid_for(n, 256), dim3(256), 0, s, keys, n, hkeys, hval, cap - 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_sparse_walk(const SparseWalkArgs& a, hipStream_t s) {
+    if (a.Q <= 0) return hipSuccess;
+    if (a.t.D < 1 || a.t.D > kMaxD || a.t.L < 1 || a.t.L > 7 || a.budget < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sparse_walk_kernel, grid_for(a.Q, kSparseWaves), dim3(64 * kSparseWaves), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sparse_scan(const SparseScanArgs& a, hipStream_t s) {
+    if (a.Q <= 0) return hipSuccess;
+    if (a.waves_per_query != 1 && a.waves_per_query != 4) return hipErrorInvalidValue;
+    if (a.t.D < 1 || a.t.D > kMaxD || a.dpad > kMaxD) return hipErrorInvalidValue;
+    const int qpb = 4 / a.waves_per_query;
+    const dim3 grid = grid_for(a.Q, qpb), block(256);
+    switch (a.dtype) {
+        case kF32: hipLaunchKernelGGL(sparse_scan_kernel<F32>, grid, block, 0, s, a); break;
+        case kF16: hipLaunchKernelGGL(sparse_scan_kernel<F16>, grid, block, 0, s, a); break;
+        case kU8: hipLaunchKernelGGL(sparse_scan_kernel<U8>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace osann

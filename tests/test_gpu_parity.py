@@ -156,9 +156,22 @@ def test_edge_cases(orc):
     with pytest.raises(B.OsAnnError) as e:
         B.os_ann_build_ex(dev(bad.astype(np.float16)), 2)
     assert e.value.code == B.OS_ANN_ENONFINITE
-    with pytest.raises(B.OsAnnError) as e:
-        B.os_ann_build_ex(dev(W.gaussian_db(10, 256, seed=4)), 7)
-    assert e.value.code == B.OS_ANN_ENOTSUP
+    # C(256,7) 2^7 = 1.7e15 cones: a sparse table (reading R15) of 10 rows
+    Xs = W.gaussian_db(10, 256, seed=4)
+    Ys = W.gaussian_queries(3, 256, seed=5)
+    hs = B.os_ann_build_ex(dev(Xs), 7)
+    try:
+        info = B.os_ann_info(hs)
+        assert info["n_cones"] == orc.num_cones(256, 7) and 1 <= info["n_nonempty"] <= 10
+        os_ = orc.build_index_sparse(Xs, 7)
+        for budget, cones in ((10, False), (1, True)):
+            gi, gd, gn = B.os_ann_search_ex(hs, dev(Ys), budget, cones=cones)
+            torch.cuda.synchronize()
+            oi, od32, od64, on = orc.search_sparse(Xs, os_, Ys, budget, cones=cones)
+            assert np.array_equal(gi.cpu().numpy(), oi) and np.array_equal(gn.cpu().numpy(), on)
+            assert np.array_equal(gd.cpu().numpy().view(np.uint32), od32.view(np.uint32))
+    finally:
+        B.os_ann_free(hs)
     with pytest.raises(B.OsAnnError) as e:
         B.os_ann_build_ex(dev(W.gaussian_db(10, 4, seed=4)), 5)
     assert e.value.code == B.OS_ANN_EINVAL

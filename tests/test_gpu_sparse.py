@@ -1,0 +1,98 @@
+"""GPU parity of the sparse table (Section 4: second-level hash when the
+cones are very many; reading R15) against the oracle through the C ABI.
+Index: every row's packed top-L pairs, the distinct non-empty cone ids, their
+row offsets and the permutation bit-exact.  Searches (row budget, fixed C,
+the 2^22-position walk cap, every row): result rows, FP32 distances and
+candidate counts bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1509_03453_amd import binding as B
+from paper_1509_03453_amd import workloads as W
+from tests.gpu_util import dev, say, unpack_top
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B.lib()
+
+
+def check_sparse(orc, X, Y, L, budgets, cones, tag):
+    say(f"[sparse] {tag} N={X.shape[0]} D={X.shape[1]} L={L} Q={Y.shape[0]} dtype={X.dtype}")
+    h = B.os_ann_build_ex(dev(X), L)
+    o = orc.build_index_sparse(X, L)
+    try:
+        info = B.os_ann_info(h)
+        assert info["n_cones"] == o["n_cones"] and info["n_cones"] > (1 << 24), tag
+        assert info["n_nonempty"] == len(o["keys"]), tag
+        ex = B.os_ann_export_sparse(h)
+        torch.cuda.synchronize()
+        assert np.array_equal(ex["cone_ids"].cpu().numpy(), o["keys"]), tag
+        assert np.array_equal(ex["offsets"].cpu().numpy(), o["offsets"]), tag
+        assert np.array_equal(ex["perm"].cpu().numpy(), o["perm"]), tag
+        ti, ts = unpack_top(ex["top"].cpu().numpy().view(np.uint64), L)
+        assert np.array_equal(ti, o["top"]) and np.array_equal(ts, o["sign"]), tag
+        yq = dev(Y)
+        for budget, c in [(b, False) for b in budgets] + [(b, True) for b in cones]:
+            say(f"[sparse] {tag} budget={budget} cones={c}")
+            gi, gd, gn = B.os_ann_search_ex(h, yq, budget, cones=c)
+            torch.cuda.synchronize()
+            gi, gd, gn = gi.cpu().numpy(), gd.cpu().numpy(), gn.cpu().numpy()
+            oi, od32, od64, on = orc.search_sparse(X, o, Y, budget, cones=c)
+            assert np.array_equal(gn, on), (tag, budget, c)
+            assert np.array_equal(gi, oi), (tag, budget, c)
+            assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), (tag, budget, c)
+    finally:
+        B.os_ann_free(h)
+
+
+def test_sparse_gaussian_d64_l5(orc):
+    # 2.4e8 cones, 20,000 rows: almost every row alone in its cone
+    X = W.gaussian_db(20000, 64, seed=9101)
+    Y = W.gaussian_queries(130, 64, seed=9102)
+    check_sparse(orc, X, Y, 5, (1, 3, 40, 20000), (1, 64, 5000, 10 ** 12), "gauss d64 L5")
+
+
+def test_sparse_walk_cap(orc):
+    # budgets the first 2^22 walk positions cannot meet stop at the cap
+    X = W.gaussian_db(20000, 64, seed=9103)
+    Y = W.gaussian_queries(9, 64, seed=9104)
+    check_sparse(orc, X, Y, 5, (5000,), (1 << 23,), "gauss d64 L5 cap")
+
+
+def test_sparse_other_shapes(orc):
+    X = W.descriptor_db(15000, 128)
+    Y, _ = W.descriptor_queries(X, 97)
+    check_sparse(orc, X, Y, 4, (1, 25, 300), (1, 200), "desc u8 d128 L4")
+    X = W.gaussian_db(12000, 256, seed=9105)
+    Y = W.gaussian_queries(71, 256, seed=9106)
+    check_sparse(orc, X, Y, 3, (1, 30), (2, 100), "gauss d256 L3")
+    img = W.patch_field(160)
+    Xp = W.patch_rows(img)
+    Xp = np.ascontiguousarray(Xp[:, :32])  # 32 components of each patch, FP16
+    Yp = np.ascontiguousarray(W.patch_rows(np.roll(img, (1, 2), axis=(0, 1)))[::97, :32])
+    check_sparse(orc, Xp, Yp, 6, (1, 50, 400), (3, 700), "patches f16 d32 L6")
+
+
+def test_sparse_errors():
+    X = W.gaussian_db(2000, 64, seed=9107)
+    with pytest.raises(B.OsAnnError) as e:
+        B.os_ann_build_ex(dev(X), 5, want_lowp=True)
+    assert e.value.code == B.OS_ANN_ENOTSUP
+    h = B.os_ann_build_ex(dev(X), 5)
+    try:
+        q = dev(W.gaussian_queries(3, 64, seed=1))
+        with pytest.raises(B.OsAnnError) as e:
+            B.os_ann_search_ex(h, q, 10, mode=B.OS_ANN_MODE_TILED)
+        assert e.value.code == B.OS_ANN_ENOTSUP
+        with pytest.raises(B.OsAnnError) as e:
+            B.os_ann_classify(h, q, 10)
+        assert e.value.code == B.OS_ANN_ENOTSUP
+        cone = torch.empty(2000, dtype=torch.int32, device="cuda")
+        assert B.lib().os_ann_export(h, cone.data_ptr(), None, None, None, None) == B.OS_ANN_ENOTSUP
+    finally:
+        B.os_ann_free(h)
