@@ -334,6 +334,40 @@ def patches_leg(budgets=(64, 256, 1024, 4096), n_sample=10_000):
     return out
 
 
+def sparse_leg(db, q, nn_d64, L=5, budgets=(1024, 4096, 16384)):
+    """Sparse table (Section 4, second-level hash): the headline rows hashed
+    with L = 5 (C(64,5) 2^5 = 2.4e8 cones, about one row per 240 cones);
+    build time, then per row budget the recall, candidates and search time."""
+    import torch
+    from paper_1509_03453_amd import binding as B
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = B.os_ann_build_ex(db, L)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = B.os_ann_info(h)
+    rows = []
+    for budget in budgets:
+        B.os_ann_search_ex(h, q, budget)  # warm
+        torch.cuda.synchronize()
+        for k in range(5):
+            B.os_ann_kernel_time(h, k)
+        t0 = time.perf_counter()
+        i, d, n = B.os_ann_search_ex(h, q, budget, flags=B.OS_ANN_FLAG_TIME_KERNELS)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        npb, msp = B.os_ann_kernel_time(h, B.OS_ANN_KERNEL_PROBE)
+        nk, msk = B.os_ann_kernel_time(h, B.OS_ANN_KERNEL_SCAN)
+        rec = float((pair_d64_torch(db, q, i) == nn_d64).double().mean())
+        rows.append({"budget": budget, "recall_at_1": round(rec, 4), "mean_ncand": round(float(n.double().mean()), 1),
+                     "search_ms": round(ms, 3), "search_qps": round(N_Q / ms * 1e3, 1),
+                     "probe_ms": round(msp / max(npb, 1), 3), "walk_scan_ms": round(msk / max(nk, 1), 3)})
+        log(f"[bench] sparse L={L} {rows[-1]}")
+    B.os_ann_free(h)
+    return {"L": L, "n_cones": info["n_cones"], "n_nonempty": info["n_nonempty"], "build_ms": round(build_ms, 2),
+            "device_bytes": info["device_bytes"], "sweep": rows}
+
+
 def pca_leg(budgets=(64, 256, 1024, 4096, 16384), k=16, n_q=10_000):
     """PCA front-end (Section 4.B) on SIFT-like data (1e6 x 128 uint8 rows
     with correlated components, the first 16 principal components holding
@@ -481,6 +515,7 @@ def main():
     ap.add_argument("--no-pca", action="store_true", help="skip the PCA front-end leg")
     ap.add_argument("--no-ivf", action="store_true", help="skip the coarse-cluster leg")
     ap.add_argument("--no-cones", action="store_true", help="skip the fixed-C cone leg")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-table leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -659,6 +694,9 @@ def main():
     if not args.no_cones:
         log("[bench] fixed-C cones")
         out["fixed_cones"] = cones_leg(db, q, nn_d64, modes)
+    if not args.no_sparse and "fp32" in modes:
+        log("[bench] sparse table")
+        out["sparse"] = sparse_leg(db, q, nn_d64)
     if not args.no_bases and "fp32" in modes:
         log("[bench] several bases")
         out["several_bases"] = bases_leg(X, db, q, nn_d64)

@@ -364,13 +364,11 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         return here;
     };
     p.off_yf = take((size_t)Q * p.dpad * sizeof(float));
-    if (ix->sparse) {  // sparse table: FP32 scan, 64-bit walk lengths
+    if (ix->sparse) {  // sparse table: walk state for the one-pass walk and scan
         p.mode = OS_ANN_MODE_FP32;
         p.Qv = Q;
         p.off_order = take((size_t)Q * ix->D);
         p.off_sbit = take((size_t)Q * ix->D);
-        p.off_jstop = take((size_t)Q * sizeof(uint64_t));
-        p.off_nc = take((size_t)Q * sizeof(int64_t));
         p.bytes = at;
         return p;
     }
@@ -1000,7 +998,7 @@ hipError_t enqueue_ivf(const Call& c) {
 }
 
 // Sparse table: the probe kernel ranks the queries (walk state, FP32 copy),
-// the sparse walk finds the walk lengths, the sparse scan takes the rows.
+// then one pass walks the cones and scans their rows.
 hipError_t enqueue_sparse(const Call& c) {
     os_ann_index* ix = c.ix;
     const SearchPlan& p = c.p;
@@ -1027,22 +1025,9 @@ hipError_t enqueue_sparse(const Call& c) {
     t.N = ix->N;
     t.D = ix->D;
     t.L = ix->L;
-    SparseWalkArgs wa{};
-    wa.t = t;
-    wa.order = pa.order;
-    wa.sbit = pa.sbit;
-    wa.Q = c.Q;
-    wa.budget = c.budget;
-    wa.cones = p.cones ? 1 : 0;
-    wa.jstop = reinterpret_cast<uint64_t*>(c.base + p.off_jstop);
-    wa.ncand = c.out_ncand ? c.out_ncand : reinterpret_cast<int64_t*>(c.base + p.off_nc);
-    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] {
-        hipError_t r = launch_probe(pa, c.s);
-        if (r == hipSuccess) r = launch_sparse_walk(wa, c.s);
-        return r;
-    });
+    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] { return launch_probe(pa, c.s); });
     if (e != hipSuccess) return e;
-    SparseScanArgs sa{};
+    SparseSearchArgs sa{};
     sa.t = t;
     sa.planes = ix->planes;
     sa.dtype = ix->dtype;
@@ -1051,13 +1036,14 @@ hipError_t enqueue_sparse(const Call& c) {
     sa.dpad = p.dpad;
     sa.order = pa.order;
     sa.sbit = pa.sbit;
-    sa.jstop = wa.jstop;
     sa.perm = ix->perm;
     sa.Q = c.Q;
+    sa.budget = c.budget;
+    sa.cones = p.cones ? 1 : 0;
     sa.out_idx = c.out_idx;
     sa.out_dist = c.out_dist;
-    sa.waves_per_query = expected_rows(ix, c.budget, p.cones) <= 8192 ? 1 : 4;
-    return timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] { return launch_sparse_scan(sa, c.s); });
+    sa.out_ncand = c.out_ncand;
+    return timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] { return launch_sparse_search(sa, c.s); });
 }
 
 hipError_t enqueue(const Call& c, int S) {

@@ -46,35 +46,24 @@ hipError_t launch_sparse_compact(const uint64_t* sorted, const uint32_t* flag, c
 hipError_t launch_sparse_hash(const uint64_t* keys, int64_t n, uint64_t* hkeys, uint32_t* hval, uint64_t cap,
                               hipStream_t s);
 
-// Walk lengths (row budget or the first C cones), from the walk state the
-// probe kernel wrote.
-struct SparseWalkArgs {
-    SparseTable t;
-    const uint8_t* order;  // [Q][D]
-    const uint8_t* sbit;   // [Q][D]
-    int64_t Q, budget;
-    int cones;             // 1: budget is the number C of cones
-    uint64_t* jstop;       // [Q] positions taken, or kSparseAll
-    int64_t* ncand;        // [Q] rows of the taken cones (may be null)
-};
-hipError_t launch_sparse_walk(const SparseWalkArgs& a, hipStream_t s);
-
-// FP32 scan and arg-min over the rows of the taken cones.
-struct SparseScanArgs {
+// Search: walk (row budget, the first C cones, or at most kSparseWalkCap
+// positions) and FP32 scan with arg-min in one pass per query, from the
+// walk state the probe kernel wrote.
+struct SparseSearchArgs {
     SparseTable t;
     const void* planes;    // chunk-major rows in bucket order
     int dtype, nch;
     const float* yf;       // [Q][dpad]
     int dpad;
-    const uint8_t* order;
-    const uint8_t* sbit;
-    const uint64_t* jstop;
+    const uint8_t* order;  // [Q][D]
+    const uint8_t* sbit;   // [Q][D]
     const uint32_t* perm;
-    int64_t Q;
+    int64_t Q, budget;
+    int cones;             // 1: budget is the number C of cones
     int64_t* out_idx;
     float* out_dist;
-    int waves_per_query;   // 1 or 4
+    int64_t* out_ncand;    // rows compared (may be null)
 };
-hipError_t launch_sparse_scan(const SparseScanArgs& a, hipStream_t s);
+hipError_t launch_sparse_search(const SparseSearchArgs& a, hipStream_t s);
 
 }  // namespace osann

@@ -10,6 +10,8 @@
 // positions is unranked from its lexicographic rank through the colex rank
 // of the reflected subset (greedy, one binary search over C(s, k) per
 // element), then the cone id is looked up; a missing id is an empty cone.
+// Walk and scan run in one pass, since the cones of a sparse table hold few
+// rows and a second walk would cost as much as the first.
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
 
@@ -175,89 +177,37 @@ __global__ void sparse_insert_kernel(const uint64_t* __restrict__ keys, int64_t 
 
 constexpr int kSparseWaves = 4;
 
-// One wave per query: walk 64 positions at a time until the row budget is
-// met (or the first C positions, or kSparseWalkCap positions).
-__global__ __launch_bounds__(64 * kSparseWaves) void sparse_walk_kernel(SparseWalkArgs a) {
+// One wave per query, 64 walk positions at a time: each lane decodes its
+// position and looks the cone up; a wave prefix sum of the bucket sizes
+// finds where the row budget is met (row budget) or the positions end
+// (first C cones, or the walk cap); the rows of the taken cones go to the
+// lanes through a cursor over the running counts; FP32 distance term by
+// term and arg-min on (distance, original row).  The binomials and the walk
+// state sit in LDS.
+template <typename E>
+__global__ __launch_bounds__(64 * kSparseWaves) void sparse_search_kernel(SparseSearchArgs a) {
+    __shared__ uint64_t s_binom[257 * 8];
     __shared__ uint8_t order[kSparseWaves][kMaxD];
     __shared__ uint8_t sbit[kSparseWaves][kMaxD];
+    __shared__ float ys[kSparseWaves][kMaxD];
+    __shared__ uint32_t s_start[kSparseWaves][64];
+    __shared__ uint32_t s_incl[kSparseWaves][64];
     const int w = threadIdx.x / 64, l = lane_id();
     const int64_t q = (int64_t)blockIdx.x * kSparseWaves + w;
-    if (q >= a.Q) return;  // no block barrier in this kernel
-    const SparseTable& t = a.t;
-    const int D = t.D;
-    for (int i = l; i < D; i += 64) {
-        order[w][i] = a.order[q * D + i];
-        sbit[w][i] = a.sbit[q * D + i];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const uint64_t nc = (uint64_t)t.n_cones, budget = (uint64_t)a.budget;
-    if ((!a.cones && budget >= (uint64_t)t.N) || (a.cones && budget >= nc)) {
-        if (l == 0) {
-            a.jstop[q] = kSparseAll;
-            if (a.ncand) a.ncand[q] = t.N;
-        }
-        return;
-    }
-    uint64_t limit = nc < kSparseWalkCap ? nc : kSparseWalkCap;
-    if (a.cones && budget < limit) limit = budget;
-    uint64_t carry = 0, stop_at = limit;
-    for (uint64_t j0 = 0; j0 < limit; j0 += 64) {
-        const uint64_t j = j0 + l;
-        uint32_t len = 0;
-        if (j < limit) {
-            const int64_t u = sparse_lookup(t, sparse_walk_cone(j, t, order[w], sbit[w]));
-            if (u >= 0) len = t.offsets[u + 1] - t.offsets[u];
-        }
-        const uint32_t incl = wave_incl_scan(len);  // distinct cones: 64 of them hold at most N rows
-        if (!a.cones) {
-            const uint64_t reached = __ballot(j < limit && carry + incl >= budget);
-            if (reached) {
-                const int st = __ffsll((unsigned long long)reached) - 1;
-                carry += shfl_u32(incl, st);
-                stop_at = j0 + st + 1;
-                break;
-            }
-        }
-        carry += shfl_u32(incl, 63);
-    }
-    if (l == 0) {
-        a.jstop[q] = stop_at;
-        if (a.ncand) a.ncand[q] = (int64_t)carry;
-    }
-}
-
-// One or four waves per query: the taken positions 64 at a time (bucket
-// starts and running row counts in LDS); lane f of the query's waves takes
-// rows f, f + 64 * wpq, ... of that chunk; FP32 distance term by term and
-// arg-min on (distance, original row).
-template <typename E>
-__global__ __launch_bounds__(256) void sparse_scan_kernel(SparseScanArgs a) {
-    __shared__ uint8_t order[4][kMaxD];
-    __shared__ uint8_t sbit[4][kMaxD];
-    __shared__ float ys[4][kMaxD];
-    __shared__ uint32_t s_start[4][64];
-    __shared__ uint32_t s_incl[4][64];
-    __shared__ float red_d[4];
-    __shared__ uint32_t red_r[4];
-    const int wpq = a.waves_per_query;
-    const int qpb = 4 / wpq;
-    const int w = threadIdx.x / 64, l = lane_id();
-    const int slot = w / wpq, sub = w % wpq;
-    const int64_t q = (int64_t)blockIdx.x * qpb + slot;
     const bool qv = q < a.Q;
-    const SparseTable& t = a.t;
+    for (int i = threadIdx.x; i < 257 * 8; i += 64 * kSparseWaves) s_binom[i] = a.t.binom[i];
+    SparseTable t = a.t;
+    t.binom = s_binom;
     const int D = t.D;
-    for (int i = sub * 64 + l; i < a.dpad; i += wpq * 64) ys[slot][i] = qv ? a.yf[q * a.dpad + i] : 0.0f;
-    for (int i = sub * 64 + l; i < D; i += wpq * 64) {
-        order[slot][i] = qv ? a.order[q * D + i] : 0;
-        sbit[slot][i] = qv ? a.sbit[q * D + i] : 0;
+    for (int i = l; i < a.dpad; i += 64) ys[w][i] = qv ? a.yf[q * a.dpad + i] : 0.0f;
+    for (int i = l; i < D; i += 64) {
+        order[w][i] = qv ? a.order[q * D + i] : 0;
+        sbit[w][i] = qv ? a.sbit[q * D + i] : 0;
     }
     __syncthreads();
-    const float* y = ys[slot];
+    if (!qv) return;  // no block barrier below this point
+    const float* y = ys[w];
     const uint4* planes = static_cast<const uint4*>(a.planes);
-    const uint64_t jstop = qv ? a.jstop[q] : 0;
     float best = __builtin_huge_valf();
     uint32_t brow = 0xFFFFFFFFu;
     auto visit = [&](int64_t p) {
@@ -270,30 +220,46 @@ __global__ __launch_bounds__(256) void sparse_scan_kernel(SparseScanArgs a) {
             }
         }
     };
-    if (jstop == kSparseAll) {
-        for (int64_t p = sub * 64 + l; p < t.N; p += wpq * 64) visit(p);
+    const uint64_t nc = (uint64_t)t.n_cones, budget = (uint64_t)a.budget;
+    uint64_t carry = 0;
+    if ((!a.cones && budget >= (uint64_t)t.N) || (a.cones && budget >= nc)) {  // every row
+        for (int64_t p = l; p < t.N; p += 64) visit(p);
+        carry = (uint64_t)t.N;
     } else {
+        uint64_t limit = nc < kSparseWalkCap ? nc : kSparseWalkCap;
+        if (a.cones && budget < limit) limit = budget;
         uint32_t* st = s_start[w];
         uint32_t* in = s_incl[w];
-        for (uint64_t j0 = 0; j0 < jstop; j0 += 64) {
+        bool done = false;
+        for (uint64_t j0 = 0; j0 < limit && !done; j0 += 64) {
             const uint64_t j = j0 + l;
             uint32_t start = 0, len = 0;
-            if (j < jstop) {
-                const int64_t u = sparse_lookup(t, sparse_walk_cone(j, t, order[slot], sbit[slot]));
+            if (j < limit) {
+                const int64_t u = sparse_lookup(t, sparse_walk_cone(j, t, order[w], sbit[w]));
                 if (u >= 0) {
                     start = t.offsets[u];
                     len = t.offsets[u + 1] - start;
                 }
             }
-            const uint32_t incl = wave_incl_scan(len);
+            uint32_t incl = wave_incl_scan(len);  // distinct cones: 64 of them hold at most N rows
+            if (!a.cones) {
+                const uint64_t reached = __ballot(j < limit && carry + incl >= budget);
+                if (reached) {  // positions after the one that meets the budget are not taken
+                    const int sl = __ffsll((unsigned long long)reached) - 1;
+                    const uint32_t at = shfl_u32(incl, sl);
+                    if (l > sl) incl = at;
+                    done = true;
+                }
+            }
             st[l] = start;
             in[l] = incl;
             const uint32_t total = shfl_u32(incl, 63);
+            carry += total;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             uint32_t k = 0;
-            for (uint32_t f = sub * 64 + l; f < total; f += wpq * 64) {
+            for (uint32_t f = l; f < total; f += 64) {
                 while (in[k] <= f) ++k;
                 const uint32_t before = k ? in[k - 1] : 0u;
                 visit((int64_t)st[k] + (f - before));
@@ -304,25 +270,10 @@ __global__ __launch_bounds__(256) void sparse_scan_kernel(SparseScanArgs a) {
         }
     }
     wave_argmin(best, brow);
-    if (wpq > 1) {
-        if (l == 0) {
-            red_d[w] = best;
-            red_r[w] = brow;
-        }
-        __syncthreads();
-        if (sub == 0 && l == 0)
-            for (int o = 1; o < wpq; ++o) {
-                const float od = red_d[w + o];
-                const uint32_t orow = red_r[w + o];
-                if (od < best || (od == best && orow < brow)) {
-                    best = od;
-                    brow = orow;
-                }
-            }
-    }
-    if (qv && sub == 0 && l == 0) {
+    if (l == 0) {
         a.out_idx[q] = brow == 0xFFFFFFFFu ? -1 : (int64_t)brow;
         a.out_dist[q] = best;
+        if (a.out_ncand) a.out_ncand[q] = (int64_t)carry;
     }
 }
 
@@ -377,23 +328,15 @@ hipError_t launch_sparse_hash(const uint64_t* keys, int64_t n, uint64_t* hkeys, 
     return hipGetLastError();
 }
 
-hipError_t launch_sparse_walk(const SparseWalkArgs& a, hipStream_t s) {
+hipError_t launch_sparse_search(const SparseSearchArgs& a, hipStream_t s) {
     if (a.Q <= 0) return hipSuccess;
-    if (a.t.D < 1 || a.t.D > kMaxD || a.t.L < 1 || a.t.L > 7 || a.budget < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(sparse_walk_kernel, grid_for(a.Q, kSparseWaves), dim3(64 * kSparseWaves), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_sparse_scan(const SparseScanArgs& a, hipStream_t s) {
-    if (a.Q <= 0) return hipSuccess;
-    if (a.waves_per_query != 1 && a.waves_per_query != 4) return hipErrorInvalidValue;
-    if (a.t.D < 1 || a.t.D > kMaxD || a.dpad > kMaxD) return hipErrorInvalidValue;
-    const int qpb = 4 / a.waves_per_query;
-    const dim3 grid = grid_for(a.Q, qpb), block(256);
+    if (a.t.D < 1 || a.t.D > kMaxD || a.t.L < 1 || a.t.L > 7 || a.dpad > kMaxD || a.budget < 1)
+        return hipErrorInvalidValue;
+    const dim3 grid = grid_for(a.Q, kSparseWaves), block(64 * kSparseWaves);
     switch (a.dtype) {
-        case kF32: hipLaunchKernelGGL(sparse_scan_kernel<F32>, grid, block, 0, s, a); break;
-        case kF16: hipLaunchKernelGGL(sparse_scan_kernel<F16>, grid, block, 0, s, a); break;
-        case kU8: hipLaunchKernelGGL(sparse_scan_kernel<U8>, grid, block, 0, s, a); break;
+        case kF32: hipLaunchKernelGGL(sparse_search_kernel<F32>, grid, block, 0, s, a); break;
+        case kF16: hipLaunchKernelGGL(sparse_search_kernel<F16>, grid, block, 0, s, a); break;
+        case kU8: hipLaunchKernelGGL(sparse_search_kernel<U8>, grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
