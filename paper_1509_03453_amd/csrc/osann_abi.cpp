@@ -323,7 +323,7 @@ struct SearchPlan {
     bool cones = false;  // fixed-C mode: the budget counts cones per walk
     size_t off_yf = 0, off_order = 0, off_sbit = 0, off_jstop = 0, off_np = 0, off_nc = 0;
     // tiled mode
-    int dk = 0, smin = 1, smax = 1, mq = 0;
+    int dk = 0, smin = 1, smax = 1, mq = 0, G = 4;  // G: MFMA B groups per wave tile
     int64_t T = 0, nw = 0;
     bool bitmap = false, fits = true;
     size_t off_ql = 0, off_qcone = 0, off_sort = 0, off_qorder = 0, off_qsorted = 0, off_part = 0,
@@ -350,7 +350,7 @@ int64_t expected_rows(const os_ann_index* ix, int64_t budget, bool cones) {
     return budget >= ix->N / mean ? ix->N : std::min<int64_t>(ix->N, budget * mean);
 }
 
-SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mode, int R, bool cones) {
+SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mode, int R, bool cones, int G = 0) {
     SearchPlan p;
     p.Q = Q;
     p.mode = mode;
@@ -402,13 +402,14 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
     if (mode == OS_ANN_MODE_TILED) {
         const int64_t ne = ix->n_nonempty > 0 ? ix->n_nonempty : 1;
         p.dk = (int)align_up((size_t)ix->D, 32);
-        p.mq = tile_queries(R);
+        p.G = G ? G : tile_groups(R);
+        p.mq = 16 * p.G;
         p.T = (Q + p.mq - 1) / p.mq;
         p.nw = (ne + 63) / 64;
         // splits only add parallelism (up to about four wave items for each
         // of the 8 waves a compute unit holds); the tuner picks the count
         p.smin = 1;
-        p.fits = tiled_screen_lds() + tiled_screen_static_lds(R) <= kLdsPerBlock;
+        p.fits = tiled_screen_lds() + tiled_screen_static_lds(R, p.G) <= kLdsPerBlock;
         const int64_t want = (32 * (int64_t)ix->num_cu + p.T - 1) / (p.T > 0 ? p.T : 1);
         p.smax = (int)std::min<int64_t>(64, pow2_ceil(std::max<int64_t>(want, 1)));
         while (p.smax > 1 && split_span(ne, p.smax) < 64 * 2) p.smax >>= 1;
@@ -768,17 +769,17 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     ta.part = reinterpret_cast<uint2*>(c.base + p.off_part);
     ta.cmin = cmin;
     const size_t lds = tiled_screen_lds();
-    int occ = tiled_screen_occupancy(p.R, ix->lp.f16, ix->lp.dk / 32, lds);
+    int occ = tiled_screen_occupancy(p.R, p.G, ix->lp.f16, ix->lp.dk / 32, lds);
     if (occ < 1) occ = 1;
     const int64_t items = p.T * S;  // one wave each, 4 waves per block
     // a multiple of kXcd blocks, so that every chiplet queue has blocks
     const int64_t cap = std::max<int64_t>(kXcd, (int64_t)occ * ix->num_cu / kXcd * kXcd);
     const int blocks = (int)std::min<int64_t>(cap, ((items + 3) / 4 + kXcd - 1) / kXcd * kXcd);
     if (std::getenv("OSANN_VERBOSE"))
-        std::fprintf(stderr, "[osann] tiled Q=%lld T=%lld S=%d span=%lld lds=%zu occ=%d blocks=%d bitmap=%d R=%d\n",
-                     (long long)c.Q, (long long)p.T, S, (long long)ta.span, lds, occ, blocks, (int)p.bitmap, p.R);
+        std::fprintf(stderr, "[osann] tiled Q=%lld T=%lld G=%d S=%d span=%lld lds=%zu occ=%d blocks=%d bitmap=%d R=%d\n",
+                     (long long)c.Q, (long long)p.T, p.G, S, (long long)ta.span, lds, occ, blocks, (int)p.bitmap, p.R);
     e = timed_launch(ix, c.timing, OS_ANN_KERNEL_SCREEN, c.s,
-                     [&] { return launch_tiled_screen(ta, p.R, ix->lp.f16, blocks, c.s); });
+                     [&] { return launch_tiled_screen(ta, p.R, p.G, ix->lp.f16, blocks, c.s); });
     if (e != hipSuccess) return e;
     FinishArgs fa{};
     fa.part = ta.part;
@@ -797,49 +798,75 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     return timed_launch(ix, c.timing, OS_ANN_KERNEL_FINISH, c.s, [&] { return launch_tiled_finish(fa, p.R, c.s); });
 }
 
-// Picks the split count of the tiled path: OSANN_TILED_SPLITS if it names a
-// valid candidate, else the cached choice, else timed over the candidates
-// (every candidate computes the same result, so the outputs of the last run
-// are valid), else (during capture) the smallest candidate.
-int choose_splits(Call& c, bool may_time, hipError_t* err) {
-    const SearchPlan& p = c.p;
+// Plans of the tiled path for every tile width: the default first.
+int tiled_plans(const os_ann_index* ix, int64_t Q, int64_t budget, int R, bool cones, SearchPlan (&plans)[2]) {
+    if (const char* env = std::getenv("OSANN_TILED_GROUPS")) {  // fixed tile width (testing)
+        const int G = std::atoi(env);
+        if (tile_groups_ok(R, G)) {
+            plans[0] = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones, G);
+            return 1;
+        }
+    }
+    plans[0] = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones);
+    int n = 1;
+    for (int G : {4, 2})
+        if (G != plans[0].G && tile_groups_ok(R, G)) plans[n++] = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones, G);
+    return n;
+}
+
+// Picks the tile width G and split count S of the tiled path and leaves c.p
+// as the plan of that G: OSANN_TILED_SPLITS (testing) fixes S with the
+// default G; else the cached choice; else both are timed over every
+// candidate pair (each computes the same result, so the outputs of the last
+// run are valid); else (during capture) the default G and the smallest S.
+int choose_tiling(Call& c, const SearchPlan* plans, int n_plans, bool may_time, hipError_t* err) {
     *err = hipSuccess;
+    c.p = plans[0];
     if (const char* env = std::getenv("OSANN_TILED_SPLITS")) {  // fixed split count (testing)
         const int v = std::atoi(env);
-        if (v >= p.smin && v <= p.smax && (v & (v - 1)) == 0) return v;
+        if (v >= c.p.smin && v <= c.p.smax && (v & (v - 1)) == 0) return v;
     }
-    if (p.smin == p.smax) return p.smin;
-    const std::string key = tune_key(c.ix, p, c.budget);
-    if (int s = g_tuner.get(key)) {
-        if (s >= p.smin && s <= p.smax) return s;
+    const std::string key = tune_key(c.ix, plans[0], c.budget) + ":GS";
+    if (int v = g_tuner.get(key)) {  // (G << 8) | S
+        for (int k = 0; k < n_plans; ++k)
+            if (plans[k].fits && plans[k].G == (v >> 8) && (v & 0xFF) >= plans[k].smin && (v & 0xFF) <= plans[k].smax) {
+                c.p = plans[k];
+                return v & 0xFF;
+            }
     }
-    if (!may_time) return p.smin;
+    if (!may_time) return c.p.smin;
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    int best_s = p.smin;
+    int best_k = 0, best_s = plans[0].smin;
     float best_ms = 1e30f;
     const bool timing = c.timing;
     c.timing = false;
-    for (int s = p.smin; s <= p.smax && e == hipSuccess; s <<= 1) {
-        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first run warms caches
-            e = hipEventRecord(a, c.s);
-            if (e == hipSuccess) e = enqueue_tiled(c, s);
-            if (e == hipSuccess) e = hipEventRecord(b, c.s);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
-            float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-            if (e == hipSuccess && rep == 1 && ms < best_ms) {
-                best_ms = ms;
-                best_s = s;
+    for (int k = 0; k < n_plans && e == hipSuccess; ++k) {
+        if (!plans[k].fits) continue;
+        c.p = plans[k];
+        for (int s = c.p.smin; s <= c.p.smax && e == hipSuccess; s <<= 1) {
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first run warms caches
+                e = hipEventRecord(a, c.s);
+                if (e == hipSuccess) e = enqueue_tiled(c, s);
+                if (e == hipSuccess) e = hipEventRecord(b, c.s);
+                if (e == hipSuccess) e = hipEventSynchronize(b);
+                float ms = 0;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                if (e == hipSuccess && rep == 1 && ms < best_ms) {
+                    best_ms = ms;
+                    best_k = k;
+                    best_s = s;
+                }
             }
         }
     }
     c.timing = timing;
+    c.p = plans[best_k];
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     *err = e;
-    if (e == hipSuccess) g_tuner.put(key, best_s, best_ms);
+    if (e == hipSuccess) g_tuner.put(key, (plans[best_k].G << 8) | best_s, best_ms);
     return best_s;
 }
 
@@ -1058,6 +1085,7 @@ int run_graph(Call& c, int S) {
     os_ann_index* ix = c.ix;
     std::vector<int64_t> key = {c.p.mode,
                                 c.p.R,
+                                c.p.G,
                                 c.p.cones,
                                 S,
                                 c.Q,
@@ -1744,6 +1772,13 @@ int64_t os_ann_workspace_bytes(const os_ann_index* idx, int64_t Q, int64_t max_c
     const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
     const bool cones = opts && (opts->flags & OS_ANN_FLAG_BUDGET_CONES);
+    if (mode == OS_ANN_MODE_TILED && !idx->sparse && idx->n_rot == 0 && !idx->proj && !idx->ivf_cent) {
+        SearchPlan plans[2];
+        const int np = tiled_plans(idx, Q, max_candidates, R, cones, plans);
+        size_t bytes = 0;
+        for (int k = 0; k < np; ++k) bytes = std::max(bytes, plans[k].bytes);
+        return (int64_t)bytes;
+    }
     return (int64_t)plan_search(idx, Q, max_candidates, mode, R, cones).bytes;
 }
 
@@ -1769,18 +1804,26 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     c.timing = opts && (opts->flags & OS_ANN_FLAG_TIME_KERNELS);
     const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
-    c.p = plan_search(ix, Q, max_candidates, mode, R, opts && (opts->flags & OS_ANN_FLAG_BUDGET_CONES));
+    const bool cones = opts && (opts->flags & OS_ANN_FLAG_BUDGET_CONES);
+    c.p = plan_search(ix, Q, max_candidates, mode, R, cones);
     if (!c.p.fits)
         return fail(OS_ANN_ENOTSUP, "tiled mode: too many non-empty cones for the LDS cone list at this D");
-    if ((rc = get_scratch(ix, opts, c.p.bytes, &c.base))) return rc;
+    SearchPlan plans[2];
+    int n_plans = 0;
+    size_t bytes = c.p.bytes;
+    if (mode == OS_ANN_MODE_TILED) {  // one scratch layout per tile width; room for the largest
+        n_plans = tiled_plans(ix, Q, max_candidates, R, cones, plans);
+        for (int k = 0; k < n_plans; ++k) bytes = std::max(bytes, plans[k].bytes);
+    }
+    if ((rc = get_scratch(ix, opts, bytes, &c.base))) return rc;
     int S = 1;
     if (mode == OS_ANN_MODE_TILED) {
         if ((rc = ensure_lowp(ix, c.s))) return rc;
         hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
         if (c.s) (void)hipStreamIsCapturing(c.s, &st);
         hipError_t e = hipSuccess;
-        S = choose_splits(c, st == hipStreamCaptureStatusNone, &e);
-        if (e != hipSuccess) return hip_fail(e, "split autotune");
+        S = choose_tiling(c, plans, n_plans, st == hipStreamCaptureStatusNone, &e);
+        if (e != hipSuccess) return hip_fail(e, "tiling autotune");
     }
     const bool graph = opts && (opts->flags & OS_ANN_FLAG_GRAPH) && c.s;
     if (graph) return run_graph(c, S);

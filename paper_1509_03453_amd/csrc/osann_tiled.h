@@ -7,10 +7,12 @@
 
 namespace osann {
 
-// A wave tile holds 16*G queries (G MFMA B operand groups); G = 4 for
-// R <= 8, G = 2 for R = 16 (LDS and register budget of the top-R lists).
-inline int tile_groups(int R) { return R <= 8 ? 4 : 2; }
-inline int tile_queries(int R) { return 16 * tile_groups(R); }
+// A wave tile holds 16*G queries (G MFMA B operand groups).  G = 4 or 2
+// for R <= 8 (wide tiles amortise each row load over more queries, narrow
+// ones stream fewer cones that only some of their queries probe; the tuner
+// picks), G = 2 for R = 16 (LDS and register budget of the top-R lists).
+inline int tile_groups(int R) { return R <= 8 ? 4 : 2; }  // default
+inline bool tile_groups_ok(int R, int G) { return G == 2 || (G == 4 && R <= 8); }
 constexpr int kChunk = 512;  // cones a screen wave lists at a time (a multiple of 64)
 constexpr int kXcd = 8;      // chiplets (each with its own L2) the blocks of a launch are dealt to in turn
 constexpr size_t kLdsPerBlock = 160 * 1024;  // LDS of one compute unit, all usable by one block
@@ -93,12 +95,12 @@ hipError_t launch_lowp_layout(const uint32_t* offsets, int64_t n_cones, uint32_t
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
                             const uint32_t* offsets, const uint32_t* poff, int dk, int to_f16, uint16_t* xl,
                             uint32_t* ppos, float* nrm, int64_t np_total, hipStream_t s);
-hipError_t launch_tiled_screen(const TiledArgs& a, int R, int f16in, int blocks, hipStream_t s);
+hipError_t launch_tiled_screen(const TiledArgs& a, int R, int G, int f16in, int blocks, hipStream_t s);
 size_t tiled_screen_lds();                      // dynamic LDS bytes of one screen block
-size_t tiled_screen_static_lds(int R);          // static LDS bytes (upper bound) of one screen block
+size_t tiled_screen_static_lds(int R, int G);          // static LDS bytes (upper bound) of one screen block
 hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s);
 hipError_t launch_tiled_seed(const SeedArgs& a, int R, int f16in, hipStream_t s);
 hipError_t tiled_screen_max_lds();
-int tiled_screen_occupancy(int R, int f16in, int ks, size_t lds);
+int tiled_screen_occupancy(int R, int G, int f16in, int ks, size_t lds);
 
 }  // namespace osann

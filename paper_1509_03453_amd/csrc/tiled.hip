@@ -578,9 +578,8 @@ __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
     }
 }
 
-template <bool F16IN, int R>
+template <bool F16IN, int R, int G>
 static hipError_t screen_ks(const TiledArgs& a, int ks, dim3 grid, size_t lds, hipStream_t s) {
-    constexpr int G = R <= 8 ? 4 : 2;
     switch (ks) {
         case 1: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 1, R, G>), grid, dim3(256), lds, s, a); break;
         case 2: hipLaunchKernelGGL((tiled_screen_kernel<F16IN, 2, R, G>), grid, dim3(256), lds, s, a); break;
@@ -595,19 +594,18 @@ static hipError_t screen_ks(const TiledArgs& a, int ks, dim3 grid, size_t lds, h
 // chunk of cones (16 B per cone).
 size_t tiled_screen_lds() { return (size_t)4 * kChunk * 16; }
 
-hipError_t launch_tiled_screen(const TiledArgs& a, int R, int f16in, int blocks, hipStream_t s) {
+hipError_t launch_tiled_screen(const TiledArgs& a, int R, int G, int f16in, int blocks, hipStream_t s) {
     const int ks = a.dk / 32;
     const size_t lds = tiled_screen_lds();
     const dim3 grid((unsigned)blocks);
-    if (f16in) {
-        if (R == 4) return screen_ks<true, 4>(a, ks, grid, lds, s);
-        if (R == 8) return screen_ks<true, 8>(a, ks, grid, lds, s);
-        if (R == 16) return screen_ks<true, 16>(a, ks, grid, lds, s);
-    } else {
-        if (R == 4) return screen_ks<false, 4>(a, ks, grid, lds, s);
-        if (R == 8) return screen_ks<false, 8>(a, ks, grid, lds, s);
-        if (R == 16) return screen_ks<false, 16>(a, ks, grid, lds, s);
-    }
+    if (!tile_groups_ok(R, G)) return hipErrorInvalidValue;
+#define OSANN_SCREEN_PICK(F16IN, RR, GG) \
+    if (f16in == (int)F16IN && R == RR && G == GG) return screen_ks<F16IN, RR, GG>(a, ks, grid, lds, s);
+    OSANN_SCREEN_PICK(true, 4, 4) OSANN_SCREEN_PICK(true, 4, 2) OSANN_SCREEN_PICK(true, 8, 4)
+    OSANN_SCREEN_PICK(true, 8, 2) OSANN_SCREEN_PICK(true, 16, 2) OSANN_SCREEN_PICK(false, 4, 4)
+    OSANN_SCREEN_PICK(false, 4, 2) OSANN_SCREEN_PICK(false, 8, 4) OSANN_SCREEN_PICK(false, 8, 2)
+    OSANN_SCREEN_PICK(false, 16, 2)
+#undef OSANN_SCREEN_PICK
     return hipErrorInvalidValue;
 }
 
@@ -643,15 +641,14 @@ hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-#define OSANN_EACH_SCREEN(X)                                                                        \
-    X(true, 1, 4, 4) X(true, 2, 4, 4) X(true, 4, 4, 4) X(true, 8, 4, 4) X(true, 1, 8, 4) X(true, 2, 8, 4)    \
-    X(true, 4, 8, 4) X(true, 8, 8, 4) X(true, 1, 16, 2) X(true, 2, 16, 2) X(true, 4, 16, 2)                  \
-    X(true, 8, 16, 2) X(false, 1, 4, 4) X(false, 2, 4, 4) X(false, 4, 4, 4) X(false, 8, 4, 4)               \
-    X(false, 1, 8, 4) X(false, 2, 8, 4) X(false, 4, 8, 4) X(false, 8, 8, 4) X(false, 1, 16, 2)              \
-    X(false, 2, 16, 2) X(false, 4, 16, 2) X(false, 8, 16, 2)
+#define OSANN_EACH_SCREEN_IN(X, F)                                                                  \
+    X(F, 1, 4, 4) X(F, 2, 4, 4) X(F, 4, 4, 4) X(F, 8, 4, 4) X(F, 1, 4, 2) X(F, 2, 4, 2) X(F, 4, 4, 2)          \
+    X(F, 8, 4, 2) X(F, 1, 8, 4) X(F, 2, 8, 4) X(F, 4, 8, 4) X(F, 8, 8, 4) X(F, 1, 8, 2) X(F, 2, 8, 2)          \
+    X(F, 4, 8, 2) X(F, 8, 8, 2) X(F, 1, 16, 2) X(F, 2, 16, 2) X(F, 4, 16, 2) X(F, 8, 16, 2)
+#define OSANN_EACH_SCREEN(X) OSANN_EACH_SCREEN_IN(X, true) OSANN_EACH_SCREEN_IN(X, false)
 
-size_t tiled_screen_static_lds(int R) {
-    const size_t qw = 16 * (size_t)tile_groups(R);
+size_t tiled_screen_static_lds(int R, int G) {
+    const size_t qw = 16 * (size_t)G;
     return 4 * qw * R * 8 + 4 * (size_t)kHitCap * 16 + 512;
 }
 
@@ -672,11 +669,11 @@ hipError_t tiled_screen_max_lds() {
     return e;
 }
 
-int tiled_screen_occupancy(int R, int f16in, int ks, size_t lds) {
+int tiled_screen_occupancy(int R, int G, int f16in, int ks, size_t lds) {
     int nb = 0;
     const void* fn = nullptr;
-#define OSANN_PICK(F16IN, KS, RR, G) \
-    if (f16in == (int)F16IN && ks == KS && R == RR) fn = (const void*)tiled_screen_kernel<F16IN, KS, RR, G>;
+#define OSANN_PICK(F16IN, KS, RR, GG) \
+    if (f16in == (int)F16IN && ks == KS && R == RR && G == GG) fn = (const void*)tiled_screen_kernel<F16IN, KS, RR, GG>;
     OSANN_EACH_SCREEN(OSANN_PICK)
 #undef OSANN_PICK
     if (!fn) return 0;

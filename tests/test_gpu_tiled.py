@@ -138,6 +138,33 @@ def test_tiled_split_and_batch_invariance(orc, monkeypatch):
     B.os_ann_free(h)
 
 
+@pytest.mark.parametrize("R", [4, 8])
+def test_tile_width_invariance(orc, monkeypatch, R):
+    # wave tiles of 32 and 64 queries (and every split count) give the same
+    # result, which is also the one the autotuner's choice gives
+    X = W.gaussian_db(30000, 64, seed=2403)
+    Y = W.gaussian_queries(700, 64, seed=2404)
+    h = B.os_ann_build_ex(dev(X), 2)
+    yd = dev(Y)
+    outs = []
+    for groups, splits in (("4", "1"), ("2", "1"), ("2", "8"), ("4", "8"), (None, None)):
+        for k, v in (("OSANN_TILED_GROUPS", groups), ("OSANN_TILED_SPLITS", splits)):
+            if v is None:
+                monkeypatch.delenv(k, raising=False)
+            else:
+                monkeypatch.setenv(k, v)
+        say(f"[tiled] R={R} groups={groups} splits={splits}")
+        i, d, n = B.os_ann_search_ex(h, yd, 3000, mode=B.OS_ANN_MODE_TILED, rerank_r=R)
+        torch.cuda.synchronize()
+        outs.append((i.cpu().numpy(), d.cpu().numpy(), n.cpu().numpy()))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+    oi, od32, od64, on, dtr, top = orc.search_tiled(X, orc.build_index(X, 2), Y, 3000, R=R)
+    assert np.array_equal(outs[0][2], on)
+    B.os_ann_free(h)
+
+
 @pytest.mark.parametrize("mode", [B.OS_ANN_MODE_FP32, B.OS_ANN_MODE_TILED])
 def test_graph_replay_matches_eager(orc, mode):
     X = W.gaussian_db(40000, 64, seed=2501)
