@@ -70,7 +70,7 @@ def lib():
             L.orc_pair_d32.argtypes = [p, i32, i32, p, i32, p, i64, p]
             L.orc_search_tiled.restype = i32
             L.orc_search_tiled.argtypes = [p, i32, i64, i32, i32, p, p, p, i32, i64, i64, i32, i32,
-                                           p, p, p, p, p, p, i32, i32]
+                                           p, p, p, p, p, p, i32, i32, p, i32]
             L.orc_pair_dtilde.restype = i32
             L.orc_pair_dtilde.argtypes = [p, i32, i32, p, i32, p, i64, i32, p]
             L.orc_round_short.restype = i32
@@ -271,7 +271,9 @@ def pair_d32(X, Y, rows) -> np.ndarray:
 def search_tiled(X, index, Y, B: int, R: int = 8, use_f16: bool | None = None, nthreads: int = 0,
                  cones: bool = False):
     """Screened search (reading R7): ``(idx, d32, d64, ncand, dt_R, top)``.
-    With ``cones`` the budget ``B`` counts cones (reading R13).
+    With ``cones`` the budget ``B`` counts cones (reading R13).  On a keyed
+    table (``index`` from build_index_proj) the walk runs on the queries'
+    keys and the screen on the full queries (reading R11).
 
     ``use_f16`` defaults to True for float16 rows (the rows are kept as
     stored) and False otherwise (bfloat16 rounding)."""
@@ -281,6 +283,11 @@ def search_tiled(X, index, Y, B: int, R: int = 8, use_f16: bool | None = None, n
         use_f16 = X.dtype == np.float16
     N, K = X.shape
     Q = Y.shape[0]
+    if index.get("P") is not None:  # keyed table: walk on the keys
+        Yk = np.ascontiguousarray(project(Y, index["mu"], index["P"]), dtype=np.float32)
+        pk, kk = Yk.ctypes.data_as(C.c_void_p), Yk.shape[1]
+    else:
+        Yk, pk, kk = None, None, K
     off, po = _arr(index["offsets"], np.int64)
     perm, pp = _arr(index["perm"], np.int64)
     idx = np.empty(Q, dtype=np.int64)
@@ -293,7 +300,7 @@ def search_tiled(X, index, Y, B: int, R: int = 8, use_f16: bool | None = None, n
                                 idx.ctypes.data_as(C.c_void_p), d32.ctypes.data_as(C.c_void_p),
                                 d64.ctypes.data_as(C.c_void_p), nca.ctypes.data_as(C.c_void_p),
                                 dtr.ctypes.data_as(C.c_void_p), top.ctypes.data_as(C.c_void_p), int(nthreads),
-                                int(bool(cones)))
+                                int(bool(cones)), pk, kk)
     if rc != 0:
         raise RuntimeError(f"orc_search_tiled failed ({rc})")
     return idx, d32, d64, nca, dtr, top

@@ -656,12 +656,15 @@ int orc_search_tiled(const void *X, int xdtype, int64_t N, int K, int G,
                      const int64_t *offsets, const int64_t *perm,
                      const void *Y, int ydtype, int64_t Q, int64_t B, int R, int use_f16,
                      int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
-                     double *out_dt_R, int64_t *out_top, int nthreads, int cones)
+                     double *out_dt_R, int64_t *out_top, int nthreads, int cones,
+                     const float *Yk, int Kk)
 {
     (void)N;
-    if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || R < 1 || R > 64)
+    if (!Yk)
+        Kk = K;
+    if (K < 1 || K > 256 || Kk < 1 || Kk > 256 || G < 1 || G > Kk || B < 1 || R < 1 || R > 64)
         return -1;
-    int64_t NC = orc_num_cones(K, G);
+    int64_t NC = orc_num_cones(Kk, G);
     set_threads(nthreads);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 4)
@@ -678,8 +681,9 @@ int orc_search_tiled(const void *X, int xdtype, int64_t N, int K, int G,
             continue;
         }
         int64_t ncand = 0;
-        int64_t np = cones ? orc_probe_cones(y, K, G, offsets, B, probes, NC, &ncand)
-                           : orc_probe(y, K, G, offsets, B, probes, NC, &ncand);
+        const float *yw = Yk ? Yk + q * Kk : y;  /* the walk runs on the keys of a keyed table (R11) */
+        int64_t np = cones ? orc_probe_cones(yw, Kk, G, offsets, B, probes, NC, &ncand)
+                           : orc_probe(yw, Kk, G, offsets, B, probes, NC, &ncand);
         struct cand top[64];
         int kept = 0;
         for (int64_t k = 0; k < np; k++) {

@@ -118,3 +118,23 @@ def test_keyed_search_brute_force():
             dd = ((X[cand].astype(np.float64) - Y[q].astype(np.float64)) ** 2).sum(1)
             assert idx[q] in cand
             assert d64[q] == pytest.approx(dd.min(), rel=1e-6)
+
+
+def test_screened_keyed_search_walks_the_keys():
+    # identity axes reproduce the plain screened search; with 12 of 32 axes
+    # the screened search takes exactly the keyed search's candidates
+    X = W.gaussian_db(4000, 16, seed=231)
+    Y = W.gaussian_queries(60, 16, seed=232)
+    eye = O.build_index_proj(X, 2, None, np.eye(16, dtype=np.float32))
+    plain = O.build_index(X, 2)
+    for u, v in zip(O.search_tiled(X, eye, Y, 300, R=8), O.search_tiled(X, plain, Y, 300, R=8)):
+        assert np.array_equal(u, v)
+    X2 = W.sift_like_db(5000, 32, seed=233)
+    Y2 = X2[:50].astype(np.float32) + W.gaussian_queries(50, 32, seed=234) * 20
+    mu, P, var = O.pca_basis(X2, 12)
+    ix = O.build_index_proj(X2, 2, mu, P)
+    for B in (50, 700):
+        t = O.search_tiled(X2, ix, Y2, B, R=8)
+        k = O.search_proj(X2, ix, Y2, B)
+        assert np.array_equal(t[3], k[3])
+        assert (t[2] >= k[2]).all()  # the screened pick is a candidate, never closer than the arg-min
