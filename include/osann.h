@@ -245,10 +245,11 @@ int os_ann_pca(const void *db, int64_t N, int32_t D, int32_t k, const os_ann_bui
  * hashes the rows' keys (L <= min(k, 7)) and holds the original rows; a
  * search projects each query the same way, walks the cones of its key and
  * compares candidates on all D components (exact FP32 distances, as for any
- * index).  Searches run in OS_ANN_MODE_FP32 only (tiled: ENOTSUP);
- * opts->want_lowp must be 0; os_ann_classify is not available (ENOTSUP).
- * Synchronous.  Errors: EINVAL, ENOMEM, EDEVICE, ENOTSUP, ENONFINITE
- * (returns NULL).
+ * index).  Both search modes apply: OS_ANN_MODE_TILED walks the keys and
+ * screens the full queries against the full rows (the low-precision copy is
+ * built on the first tiled search; opts->want_lowp must be 0 here);
+ * os_ann_classify is not available (ENOTSUP).  Synchronous.  Errors: EINVAL,
+ * ENOMEM, EDEVICE, ENOTSUP, ENONFINITE (returns NULL).
  */
 os_ann_index *os_ann_build_proj(const void *db, int64_t N, int32_t D, int32_t L, const float *mean,
                                 const float *basis, int32_t k, const os_ann_build_opts *opts);

@@ -448,8 +448,6 @@ int search_checks(const os_ann_index* ix, const void* queries, int64_t Q, int64_
             return fail(OS_ANN_ENOTSUP, "several bases: FP32 mode only");
         if (o->mode == OS_ANN_MODE_TILED && ix->sparse)
             return fail(OS_ANN_ENOTSUP, "sparse table: FP32 mode only");
-        if (o->mode == OS_ANN_MODE_TILED && ix->proj)
-            return fail(OS_ANN_ENOTSUP, "projected table: FP32 mode only");
         if (o->mode == OS_ANN_MODE_TILED && ix->ivf_cent)
             return fail(OS_ANN_ENOTSUP, "clustered table: FP32 mode only");
     }
@@ -708,8 +706,38 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     os_ann_index* ix = c.ix;
     const SearchPlan& p = c.p;
     const ProbeArgs pa = probe_args(c);
-    hipError_t e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s,
-                                [&] { return launch_walk(pa, c.p.cones, c.budget, c.s); });
+    hipError_t e;
+    if (ix->proj) {
+        // keyed table: the FP32 and low-precision copies of the full queries,
+        // their keys, then the walk on the keys
+        ProbeArgs pf{};
+        pf.Y = c.queries;
+        pf.qtype = c.qtype;
+        pf.Q = c.Q;
+        pf.D = ix->D;
+        pf.L = ix->L;
+        pf.yf = pa.yf;
+        pf.dpad = pa.dpad;
+        pf.ql = pa.ql;
+        pf.dk = pa.dk;
+        pf.ql_f16 = pa.ql_f16;
+        ProbeArgs pk = pa;
+        float* yk = reinterpret_cast<float*>(c.base + p.off_yk);
+        pk.Y = yk;
+        pk.qtype = kF32;
+        pk.yf = nullptr;
+        pk.ql = nullptr;
+        e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s, [&] {
+            hipError_t r = launch_probe(pf, c.s);
+            if (r == hipSuccess)
+                r = launch_project(c.queries, c.qtype, c.Q, ix->D, ix->proj_mu, ix->proj_P, ix->Dk, yk, c.s);
+            if (r == hipSuccess) r = launch_walk(pk, c.p.cones, c.budget, c.s);
+            return r;
+        });
+    } else {
+        e = timed_launch(ix, c.timing, OS_ANN_KERNEL_PROBE, c.s,
+                         [&] { return launch_walk(pa, c.p.cones, c.budget, c.s); });
+    }
     if (e != hipSuccess) return e;
     uint32_t* qorder = reinterpret_cast<uint32_t*>(c.base + p.off_qorder);
     e = launch_sort_by_cone(pa.q_cone, c.Q, ix->n_cones, reinterpret_cast<uint32_t*>(c.base + p.off_sort), qorder,
@@ -752,7 +780,7 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     ta.maskord = ix->maskord;
     ta.binom = ix->binom;
     ta.n_sub = ix->n_sub;
-    ta.D = ix->D;
+    ta.D = ix->Dk;  // the walk state's length (the keys' on a keyed table)
     ta.L = ix->L;
     ta.ql = pa.ql;
     ta.Q = c.Q;

@@ -39,3 +39,35 @@ def gpu_search(h, Y: np.ndarray, budget: int, mode=B.OS_ANN_MODE_FP32):
     i, d, n = B.os_ann_search_ex(h, dev(Y), budget, mode=mode)
     torch.cuda.synchronize()
     return i.cpu().numpy(), d.cpu().numpy(), n.cpu().numpy()
+
+
+def check_screened(orc, X, Y, g, o, tag, max_mismatch=0.02):
+    """Compare a tiled-mode result ``g = (idx, dist, ncand)`` with the
+    oracle's screened search ``o``: candidate counts equal, empty searches
+    give -1 / +inf, the distance is the exact FP32 distance of the returned
+    row, and a row that differs from the oracle's must be explained by a d~
+    within rounding of the R-th survivor (FP32 accumulation on the matrix
+    cores against double in the oracle); such rows must be rare."""
+    U = 2.0 ** -24
+    gi, gd, gn = g
+    oi, od32, od64, on, dtr, top = o
+    assert np.array_equal(gn, on), tag
+    empty = on == 0
+    assert (gi[empty] == -1).all() and np.isinf(gd[empty]).all(), tag
+    full = np.flatnonzero(~empty)
+    assert np.array_equal(gd[full].view(np.uint32), orc.pair_d32(X, Y[full], gi[full]).view(np.uint32)), tag
+    f16 = X.dtype == np.float16
+    D = X.shape[1]
+    bad = [q for q in full if gi[q] != oi[q]]
+    for q in bad:
+        xs = orc.round_short(X[[gi[q], oi[q], top[q][-1]]].astype(np.float32), f16).reshape(3, D)
+        ys = orc.round_short(Y[q].astype(np.float32), f16)
+        tol = 4 * (D + 2) * U * ((xs ** 2).sum(1) + 2 * np.abs(xs * ys).sum(1)).max()
+        dg = orc.pair_dtilde(X, Y[q:q + 1], [gi[q]], f16)[0]
+        do = orc.pair_dtilde(X, Y[q:q + 1], [oi[q]], f16)[0]
+        if gi[q] in top[q]:
+            assert do >= dtr[q] - tol, (tag, q)
+        else:
+            assert dg <= dtr[q] + tol, (tag, q)
+    assert len(bad) <= max_mismatch * len(full) + 1, (tag, len(bad))
+

@@ -11,7 +11,7 @@ import torch
 
 from paper_1509_03453_amd import binding as B
 from paper_1509_03453_amd import workloads as W
-from tests.gpu_util import dev, say, unpack_top
+from tests.gpu_util import check_screened, dev, say, unpack_top
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +65,11 @@ def check_proj(orc, X, Y, L, mu, P, budgets, tag):
             assert np.array_equal(gn.cpu().numpy(), on), (tag, budget)
             assert np.array_equal(gi.cpu().numpy(), oi), (tag, budget)
             assert np.array_equal(gd.cpu().numpy().view(np.uint32), od32.view(np.uint32)), (tag, budget)
+            # the screened search walks the keys and screens the full vectors
+            gi, gd, gn = B.os_ann_search_ex(h, yq, budget, mode=B.OS_ANN_MODE_TILED)
+            torch.cuda.synchronize()
+            check_screened(orc, X, Y, (gi.cpu().numpy(), gd.cpu().numpy(), gn.cpu().numpy()),
+                           orc.search_tiled(X, o, Y, budget, R=8), (tag, "tiled", budget))
     finally:
         B.os_ann_free(h)
 
@@ -118,9 +123,6 @@ def test_keyed_errors():
     assert e.value.code == B.OS_ANN_EINVAL
     h = B.os_ann_build_proj(dev(X), 2, P)
     try:
-        with pytest.raises(B.OsAnnError) as e:
-            B.os_ann_search_ex(h, dev(W.gaussian_queries(3, 8, seed=1)), 10, mode=B.OS_ANN_MODE_TILED)
-        assert e.value.code == B.OS_ANN_ENOTSUP
         with pytest.raises(B.OsAnnError) as e:
             B.os_ann_classify(h, dev(W.gaussian_queries(3, 8, seed=1)), 10)
         assert e.value.code == B.OS_ANN_ENOTSUP
