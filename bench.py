@@ -427,6 +427,20 @@ def pca_leg(budgets=(64, 256, 1024, 4096, 16384), k=16, n_q=10_000):
         out["sweep"].append(rec)
         log(f"[bench] pca {rec}")
     out["budget_recall_0.9"] = reach
+    # the keyed L=3 table in tiled mode (keys walked, full rows screened) at that budget
+    b3 = reach.get("pca16_L3")
+    if b3:
+        B.os_ann_search_ex(hp3, q, b3, mode=B.OS_ANN_MODE_TILED, rerank_r=RERANK)  # warm (and tune)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        i, d, n = B.os_ann_search_ex(hp3, q, b3, mode=B.OS_ANN_MODE_TILED, rerank_r=RERANK)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        r = float((pair_d64_torch(db.float(), q, i) <= nn).double().mean())
+        fp = [x["pca16_L3"] for x in out["sweep"] if x["budget"] == b3][0]
+        out["pca16_L3_tiled"] = {"budget": b3, "recall_at_1": round(r, 4), "search_ms": round(ms, 3),
+                                 "queries_per_s": round(n_q / ms * 1e3, 1), "fp32_search_ms": fp["search_ms"]}
+        log(f"[bench] pca tiled {out['pca16_L3_tiled']}")
     for hh in (h, hp, hp3):
         B.os_ann_free(hh)
     return out
