@@ -342,6 +342,8 @@ def os_ann_export(index: int, stream=None) -> dict:
     """Row cones (int32 view of uint32), packed top-L, offsets and perm."""
     info = os_ann_info(index)
     N, nc = info["N"], info["n_cones"]
+    if nc > (1 << 24):  # only sparse tables have more cones than dense offsets address
+        raise OsAnnError(OS_ANN_ENOTSUP, "sparse table: use os_ann_export_sparse")
     dev = torch.device("cuda", torch.cuda.current_device())
     cone = torch.empty(N, dtype=torch.int32, device=dev)
     top = torch.empty(N, dtype=torch.int64, device=dev)
