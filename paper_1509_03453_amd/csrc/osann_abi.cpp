@@ -15,6 +15,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "osann_batch.h"
 #include "osann_fixedc.h"
 #include "osann_ivf.h"
 #include "osann_sparse.h"
@@ -327,7 +328,7 @@ struct SearchPlan {
     int64_t T = 0, nw = 0;
     bool bitmap = false, fits = true;
     size_t off_ql = 0, off_qcone = 0, off_sort = 0, off_qorder = 0, off_qsorted = 0, off_part = 0,
-           off_counter = 0, off_qbits = 0, off_cmin = 0;
+           off_counter = 0, off_qbits = 0, off_cmin = 0, off_qkey = 0;
     size_t off_yr = 0;  // several bases: query coordinates [R][Q][D]
     size_t off_yk = 0;  // projected table: query keys [Q][Dk]
     // clustered table: per virtual query (query x searched cluster)
@@ -421,6 +422,7 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         p.off_qcone = take((size_t)Q * 4);
         p.off_sort = take((size_t)(4 * Q + radix_hist_words(Q)) * 4);
         p.off_qorder = take((size_t)Q * 4);
+        p.off_qkey = take((size_t)Q * 4);
         p.off_qsorted = take((size_t)Q * 4);
         p.off_part = take((size_t)Q * p.smax * R * 8);
         p.off_counter = take(256);
@@ -740,8 +742,21 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     }
     if (e != hipSuccess) return e;
     uint32_t* qorder = reinterpret_cast<uint32_t*>(c.base + p.off_qorder);
-    e = launch_sort_by_cone(pa.q_cone, c.Q, ix->n_cones, reinterpret_cast<uint32_t*>(c.base + p.off_sort), qorder,
-                            reinterpret_cast<uint32_t*>(c.base + p.off_qsorted), c.s);
+    {
+        // wave tiles of queries that share their own cone and their next
+        // largest component (and its sign) where the key fits 32 bits
+        const uint32_t* key = pa.q_cone;
+        int64_t nb = ix->n_cones;
+        if (ix->L < ix->Dk && ix->n_cones * 2 * ix->Dk <= (int64_t(1) << 32)) {
+            uint32_t* kb = reinterpret_cast<uint32_t*>(c.base + p.off_qkey);
+            e = launch_query_key(pa.q_cone, pa.order, pa.sbit, c.Q, ix->Dk, ix->L, kb, c.s);
+            if (e != hipSuccess) return e;
+            key = kb;
+            nb = ix->n_cones * 2 * ix->Dk;
+        }
+        e = launch_sort_by_cone(key, c.Q, nb, reinterpret_cast<uint32_t*>(c.base + p.off_sort), qorder,
+                                reinterpret_cast<uint32_t*>(c.base + p.off_qsorted), c.s);
+    }
     if (e != hipSuccess) return e;
     uint32_t* counter = reinterpret_cast<uint32_t*>(c.base + p.off_counter);
     e = launch_fill_u32(counter, kXcd, 0u, c.s);
