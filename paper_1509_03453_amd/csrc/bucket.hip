@@ -161,6 +161,27 @@ __global__ __launch_bounds__(256) void gather_planes_kernel(const typename E::ra
     }
 }
 
+// Rows of whole 16-byte chunks (D * element size a multiple of 16, rows
+// 16-byte aligned): each block moves 64 rows as chunks, reading every row's
+// chunks with consecutive lanes and writing every chunk plane with
+// consecutive lanes, through an LDS tile [nch][65] (the pad keeps the
+// chunks of one row in different banks).
+__global__ __launch_bounds__(256) void gather_chunks_kernel(const uint4* __restrict__ X, int64_t N, int nch,
+                                                            const uint32_t* __restrict__ perm,
+                                                            uint4* __restrict__ planes) {
+    extern __shared__ uint4 tile[];  // [nch][65]
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    for (int f = threadIdx.x; f < 64 * nch; f += blockDim.x) {
+        const int r = f / nch, k = f - r * nch;
+        if (p0 + r < N) tile[k * 65 + r] = X[(int64_t)perm[p0 + r] * nch + k];
+    }
+    __syncthreads();
+    for (int f = threadIdx.x; f < nch * 64; f += blockDim.x) {
+        const int k = f >> 6, r = f & 63;
+        if (p0 + r < N) planes[(int64_t)k * N + p0 + r] = tile[k * 65 + r];
+    }
+}
+
 hipError_t launch_gather_planes(const void* X, int dtype, int64_t N, int D, const uint32_t* perm,
                                 void* planes, hipStream_t s) {
     const int epc = chunk_elems(dtype);
@@ -168,6 +189,11 @@ hipError_t launch_gather_planes(const void* X, int dtype, int64_t N, int D, cons
     const dim3 grid((unsigned)((N + 63) / 64));
     const size_t lds = (size_t)nch * 64 * 16;
     auto out = static_cast<uint4*>(planes);
+    if (D % epc == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) {
+        hipLaunchKernelGGL(gather_chunks_kernel, grid, dim3(256), (size_t)nch * 65 * 16, s,
+                           static_cast<const uint4*>(X), N, nch, perm, out);
+        return hipGetLastError();
+    }
     switch (dtype) {
         case kF32:
             hipLaunchKernelGGL(gather_planes_kernel<F32>, grid, dim3(256), lds, s,
