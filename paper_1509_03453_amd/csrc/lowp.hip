@@ -76,63 +76,84 @@ __device__ inline uint16_t lowp_code(float x, int to_f16, float* v) {
 }
 
 // One thread per sorted position (coalesced reads of the chunk-major
-// planes): rounds the row, writes it to its padded position in 16-byte
-// units of 8 components, and stores the FP32 sum of squares of the rounded
-// values taken in ascending component order, and the position map.
+// planes): rounds the row into an LDS tile of the block's 256 rows and
+// stores the FP32 sum of squares of the rounded values taken in ascending
+// component order, and the position map; then the block writes the tile's
+// rows to their padded positions with consecutive lanes on consecutive
+// 32-bit words (rows of a cone are consecutive there).  The tile's row
+// stride is dk/2 + 1 words, so the lanes of the first phase, one row each,
+// hit different banks.
 template <typename E>
-__global__ void lowp_rows_kernel(const uint4* __restrict__ planes, int64_t N, int D, int nch,
-                                 const uint32_t* __restrict__ sorted_cone, const uint32_t* __restrict__ off,
-                                 const uint32_t* __restrict__ poff, int dk, int to_f16,
-                                 uint16_t* __restrict__ xl, uint32_t* __restrict__ ppos, float* __restrict__ nrm) {
+__global__ __launch_bounds__(256) void lowp_rows_kernel(const uint4* __restrict__ planes, int64_t N, int D, int nch,
+                                                        const uint32_t* __restrict__ sorted_cone,
+                                                        const uint32_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ poff, int dk, int to_f16,
+                                                        uint16_t* __restrict__ xl, uint32_t* __restrict__ ppos,
+                                                        float* __restrict__ nrm) {
 #pragma clang fp contract(off)
     constexpr int EPC = Unpack<E>::n;             // components per 16-byte chunk of the planes
     constexpr int CPU = EPC >= 8 ? 1 : 8 / EPC;   // chunks per step (at least one output unit)
     constexpr int NU = CPU * EPC / 8;             // output units per step
-    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= N) return;
-    const uint32_t c = sorted_cone[pos];
-    const int64_t p = (int64_t)poff[c] + (pos - (int64_t)off[c]);
-    uint4* dst = reinterpret_cast<uint4*>(xl + p * dk);
-    float acc = 0.0f;
-    for (int k0 = 0; k0 < nch; k0 += CPU) {
-        float x[CPU * EPC];
+    extern __shared__ uint32_t tile[];            // [256][dk/2 + 1]
+    __shared__ int64_t s_p[256];
+    const int words = dk / 2, stride = words + 1;
+    const int64_t pos0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t pos = pos0 + threadIdx.x;
+    uint32_t* row = tile + threadIdx.x * stride;
+    if (pos < N) {
+        const uint32_t c = sorted_cone[pos];
+        const int64_t p = (int64_t)poff[c] + (pos - (int64_t)off[c]);
+        s_p[threadIdx.x] = p;
+        for (int wd = nch * EPC / 2; wd < words; ++wd) row[wd] = 0u;  // columns past the planes' chunks
+        float acc = 0.0f;
+        for (int k0 = 0; k0 < nch; k0 += CPU) {
+            float x[CPU * EPC];
 #pragma unroll
-        for (int j = 0; j < CPU; ++j) {
-            float t[EPC];
-            if (k0 + j < nch) {
-                Unpack<E>::run(planes[(int64_t)(k0 + j) * N + pos], t);
-            } else {
+            for (int j = 0; j < CPU; ++j) {
+                float t[EPC];
+                if (k0 + j < nch) {
+                    Unpack<E>::run(planes[(int64_t)(k0 + j) * N + pos], t);
+                } else {
 #pragma unroll
-                for (int e = 0; e < EPC; ++e) t[e] = 0.0f;
-            }
-#pragma unroll
-            for (int e = 0; e < EPC; ++e) x[j * EPC + e] = t[e];
-        }
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            uint32_t w[4];
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                uint16_t code[2];
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const int e = u * 8 + 2 * h + q;
-                    const int i = k0 * EPC + e;
-                    code[q] = 0;
-                    if (i < D) {
-                        float v;
-                        code[q] = lowp_code(x[e], to_f16, &v);
-                        const float sq = v * v;
-                        acc = acc + sq;
-                    }
+                    for (int e = 0; e < EPC; ++e) t[e] = 0.0f;
                 }
-                w[h] = (uint32_t)code[0] | ((uint32_t)code[1] << 16);
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) x[j * EPC + e] = t[e];
             }
-            dst[(k0 * EPC) / 8 + u] = make_uint4(w[0], w[1], w[2], w[3]);
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    uint16_t code[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int e = u * 8 + 2 * h + q;
+                        const int i = k0 * EPC + e;
+                        code[q] = 0;
+                        if (i < D) {
+                            float v;
+                            code[q] = lowp_code(x[e], to_f16, &v);
+                            const float sq = v * v;
+                            acc = acc + sq;
+                        }
+                    }
+                    const int wd = (k0 * EPC) / 2 + u * 4 + h;
+                    if (wd < words) row[wd] = (uint32_t)code[0] | ((uint32_t)code[1] << 16);
+                }
+            }
         }
+        ppos[p] = (uint32_t)pos;
+        nrm[p] = acc;
+    } else {
+        s_p[threadIdx.x] = -1;
     }
-    ppos[p] = (uint32_t)pos;
-    nrm[p] = acc;
+    __syncthreads();
+    uint32_t* xw = reinterpret_cast<uint32_t*>(xl);
+    for (int f = threadIdx.x; f < 256 * words; f += 256) {
+        const int r = f / words, wd = f - r * words;
+        const int64_t p = s_p[r];
+        if (p >= 0) xw[p * words + wd] = tile[r * stride + wd];
+    }
 }
 
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
@@ -145,17 +166,25 @@ hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((N + 255) / 256));
     auto pl = static_cast<const uint4*>(planes);
+    const size_t lds = (size_t)256 * (dk / 2 + 1) * 4;
+    if (dk % 32 != 0 || dk < nch * chunk_elems(dtype) || lds > 150 * 1024) return hipErrorInvalidValue;
     switch (dtype) {
         case kF32:
-            hipLaunchKernelGGL(lowp_rows_kernel<F32>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
+            e = hipFuncSetAttribute((const void*)lowp_rows_kernel<F32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(lowp_rows_kernel<F32>, grid, dim3(256), lds, s, pl, N, D, nch, sorted_cone, offsets,
                                poff, dk, to_f16, xl, ppos, nrm);
             break;
         case kF16:
-            hipLaunchKernelGGL(lowp_rows_kernel<F16>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
+            e = hipFuncSetAttribute((const void*)lowp_rows_kernel<F16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(lowp_rows_kernel<F16>, grid, dim3(256), lds, s, pl, N, D, nch, sorted_cone, offsets,
                                poff, dk, to_f16, xl, ppos, nrm);
             break;
         case kU8:
-            hipLaunchKernelGGL(lowp_rows_kernel<U8>, grid, dim3(256), 0, s, pl, N, D, nch, sorted_cone, offsets,
+            e = hipFuncSetAttribute((const void*)lowp_rows_kernel<U8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(lowp_rows_kernel<U8>, grid, dim3(256), lds, s, pl, N, D, nch, sorted_cone, offsets,
                                poff, dk, to_f16, xl, ppos, nrm);
             break;
         default:
