@@ -325,6 +325,7 @@ struct SearchPlan {
     size_t off_yf = 0, off_order = 0, off_sbit = 0, off_jstop = 0, off_np = 0, off_nc = 0;
     // tiled mode
     int dk = 0, smin = 1, smax = 1, mq = 0, G = 4;  // G: MFMA B groups per wave tile
+    int qkey = 0;                                   // query order of the wave tiles (launch_query_key mode)
     int64_t T = 0, nw = 0;
     bool bitmap = false, fits = true;
     size_t off_ql = 0, off_qcone = 0, off_sort = 0, off_qorder = 0, off_qsorted = 0, off_part = 0,
@@ -743,16 +744,17 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     if (e != hipSuccess) return e;
     uint32_t* qorder = reinterpret_cast<uint32_t*>(c.base + p.off_qorder);
     {
-        // wave tiles of queries that share their own cone and their next
-        // largest component (and its sign) where the key fits 32 bits
+        // wave tiles of queries with equal keys (launch_query_key): own cone
+        // and next component (where that fits 32 bits), or sign bits
         const uint32_t* key = pa.q_cone;
         int64_t nb = ix->n_cones;
-        if (ix->L < ix->Dk && ix->n_cones * 2 * ix->Dk <= (int64_t(1) << 32)) {
+        const int64_t nb0 = ix->n_cones * 2 * ix->Dk;
+        if (ix->L < ix->Dk && (p.qkey == 1 || nb0 <= (int64_t(1) << 32))) {
             uint32_t* kb = reinterpret_cast<uint32_t*>(c.base + p.off_qkey);
-            e = launch_query_key(pa.q_cone, pa.order, pa.sbit, c.Q, ix->Dk, ix->L, kb, c.s);
+            e = launch_query_key(pa.q_cone, pa.order, pa.sbit, c.Q, ix->Dk, ix->L, p.qkey, kb, c.s);
             if (e != hipSuccess) return e;
             key = kb;
-            nb = ix->n_cones * 2 * ix->Dk;
+            nb = p.qkey == 1 ? (int64_t(1) << (ix->Dk < 32 ? ix->Dk : 32)) : nb0;
         }
         e = launch_sort_by_cone(key, c.Q, nb, reinterpret_cast<uint32_t*>(c.base + p.off_sort), qorder,
                                 reinterpret_cast<uint32_t*>(c.base + p.off_qsorted), c.s);
@@ -842,18 +844,21 @@ hipError_t enqueue_tiled(const Call& c, int S) {
 }
 
 // Plans of the tiled path for every tile width: the default first.
-int tiled_plans(const os_ann_index* ix, int64_t Q, int64_t budget, int R, bool cones, SearchPlan (&plans)[2]) {
-    if (const char* env = std::getenv("OSANN_TILED_GROUPS")) {  // fixed tile width (testing)
-        const int G = std::atoi(env);
-        if (tile_groups_ok(R, G)) {
-            plans[0] = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones, G);
-            return 1;
+int tiled_plans(const os_ann_index* ix, int64_t Q, int64_t budget, int R, bool cones, SearchPlan (&plans)[4]) {
+    int n = 0;
+    const char* genv = std::getenv("OSANN_TILED_GROUPS");  // fixed tile width (testing)
+    const char* oenv = std::getenv("OSANN_TILED_ORDER");   // fixed query order (testing)
+    const int gfix = genv && tile_groups_ok(R, std::atoi(genv)) ? std::atoi(genv) : 0;
+    const int ofix = oenv && (std::atoi(oenv) == 0 || std::atoi(oenv) == 1) ? std::atoi(oenv) + 1 : 0;
+    const SearchPlan def = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones, gfix);
+    for (int qk = 0; qk < 2; ++qk) {
+        if (ofix && qk != ofix - 1) continue;
+        for (int G : {def.G, def.G == 4 ? 2 : 4}) {
+            if (!tile_groups_ok(R, G) || (gfix && G != gfix)) continue;
+            plans[n] = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones, G);
+            plans[n++].qkey = qk;
         }
     }
-    plans[0] = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones);
-    int n = 1;
-    for (int G : {4, 2})
-        if (G != plans[0].G && tile_groups_ok(R, G)) plans[n++] = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones, G);
     return n;
 }
 
@@ -863,16 +868,18 @@ int tiled_plans(const os_ann_index* ix, int64_t Q, int64_t budget, int R, bool c
 // candidate pair (each computes the same result, so the outputs of the last
 // run are valid); else (during capture) the default G and the smallest S.
 int choose_tiling(Call& c, const SearchPlan* plans, int n_plans, bool may_time, hipError_t* err) {
+    // the choice is cached as (query order << 12) | (G << 8) | S
     *err = hipSuccess;
     c.p = plans[0];
     if (const char* env = std::getenv("OSANN_TILED_SPLITS")) {  // fixed split count (testing)
         const int v = std::atoi(env);
         if (v >= c.p.smin && v <= c.p.smax && (v & (v - 1)) == 0) return v;
     }
-    const std::string key = tune_key(c.ix, plans[0], c.budget) + ":GS";
-    if (int v = g_tuner.get(key)) {  // (G << 8) | S
+    const std::string key = tune_key(c.ix, plans[0], c.budget) + ":OGS";
+    if (int v = g_tuner.get(key)) {
         for (int k = 0; k < n_plans; ++k)
-            if (plans[k].fits && plans[k].G == (v >> 8) && (v & 0xFF) >= plans[k].smin && (v & 0xFF) <= plans[k].smax) {
+            if (plans[k].fits && plans[k].qkey == (v >> 12) && plans[k].G == ((v >> 8) & 0xF) &&
+                (v & 0xFF) >= plans[k].smin && (v & 0xFF) <= plans[k].smax) {
                 c.p = plans[k];
                 return v & 0xFF;
             }
@@ -909,7 +916,7 @@ int choose_tiling(Call& c, const SearchPlan* plans, int n_plans, bool may_time, 
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     *err = e;
-    if (e == hipSuccess) g_tuner.put(key, (plans[best_k].G << 8) | best_s, best_ms);
+    if (e == hipSuccess) g_tuner.put(key, (plans[best_k].qkey << 12) | (plans[best_k].G << 8) | best_s, best_ms);
     return best_s;
 }
 
@@ -1129,6 +1136,7 @@ int run_graph(Call& c, int S) {
     std::vector<int64_t> key = {c.p.mode,
                                 c.p.R,
                                 c.p.G,
+                                c.p.qkey,
                                 c.p.cones,
                                 S,
                                 c.Q,
@@ -1816,7 +1824,7 @@ int64_t os_ann_workspace_bytes(const os_ann_index* idx, int64_t Q, int64_t max_c
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
     const bool cones = opts && (opts->flags & OS_ANN_FLAG_BUDGET_CONES);
     if (mode == OS_ANN_MODE_TILED && !idx->sparse && idx->n_rot == 0 && !idx->proj && !idx->ivf_cent) {
-        SearchPlan plans[2];
+        SearchPlan plans[4];
         const int np = tiled_plans(idx, Q, max_candidates, R, cones, plans);
         size_t bytes = 0;
         for (int k = 0; k < np; ++k) bytes = std::max(bytes, plans[k].bytes);
@@ -1851,7 +1859,7 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     c.p = plan_search(ix, Q, max_candidates, mode, R, cones);
     if (!c.p.fits)
         return fail(OS_ANN_ENOTSUP, "tiled mode: too many non-empty cones for the LDS cone list at this D");
-    SearchPlan plans[2];
+    SearchPlan plans[4];
     int n_plans = 0;
     size_t bytes = c.p.bytes;
     if (mode == OS_ANN_MODE_TILED) {  // one scratch layout per tile width; room for the largest

@@ -140,20 +140,22 @@ def test_tiled_split_and_batch_invariance(orc, monkeypatch):
 
 @pytest.mark.parametrize("R", [4, 8])
 def test_tile_width_invariance(orc, monkeypatch, R):
-    # wave tiles of 32 and 64 queries (and every split count) give the same
-    # result, which is also the one the autotuner's choice gives
+    # wave tiles of 32 and 64 queries, either query order and every split
+    # count give the same result, which is also the one the autotuner's
+    # choice gives
     X = W.gaussian_db(30000, 64, seed=2403)
     Y = W.gaussian_queries(700, 64, seed=2404)
     h = B.os_ann_build_ex(dev(X), 2)
     yd = dev(Y)
     outs = []
-    for groups, splits in (("4", "1"), ("2", "1"), ("2", "8"), ("4", "8"), (None, None)):
-        for k, v in (("OSANN_TILED_GROUPS", groups), ("OSANN_TILED_SPLITS", splits)):
+    for groups, splits, order in (("4", "1", "0"), ("2", "1", "0"), ("2", "8", "1"), ("4", "8", "1"),
+                                  ("4", "1", "1"), (None, None, None)):
+        for k, v in (("OSANN_TILED_GROUPS", groups), ("OSANN_TILED_SPLITS", splits), ("OSANN_TILED_ORDER", order)):
             if v is None:
                 monkeypatch.delenv(k, raising=False)
             else:
                 monkeypatch.setenv(k, v)
-        say(f"[tiled] R={R} groups={groups} splits={splits}")
+        say(f"[tiled] R={R} groups={groups} splits={splits} order={order}")
         i, d, n = B.os_ann_search_ex(h, yd, 3000, mode=B.OS_ANN_MODE_TILED, rerank_r=R)
         torch.cuda.synchronize()
         outs.append((i.cpu().numpy(), d.cpu().numpy(), n.cpu().numpy()))
