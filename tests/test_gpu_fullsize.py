@@ -10,6 +10,8 @@ oracle recomputes one by one.
 * the 1e6 x 64 Gaussian workload with four bases (Section 3.A).
 * the descriptor workload through the PCA front-end (Section 4.B), k = 16.
 * the Gaussian workload in fixed-C mode (C = 16, 512, 2048 cones), both modes.
+* the Gaussian workload as a sparse table (L = 5, 2.4e8 cones) and with four
+  structured (Walsh-Hadamard) bases.
 
 The index itself (every key, bucket offset and permutation entry) is compared
 in full; searches are compared on a spread sample of queries."""
@@ -196,5 +198,61 @@ def test_descriptor_1m_pca16(orc):
             oi, od32, od64, on = orc.search_proj(X, o, Y[s], budget)
             assert np.array_equal(gn, on) and np.array_equal(gi, oi), budget
             assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), budget
+    finally:
+        B.os_ann_free(h)
+
+
+def test_sparse_1m_d64_l5(orc):
+    # the 1e6 x 64 Gaussian rows as a sparse table (L = 5: 2.4e8 cones), in
+    # the benchmark's launch shape: the whole index compared, searches sampled
+    X = W.gaussian_db(1_000_000, 64, W.SEEDS["gauss64_db"])
+    Y = W.gaussian_queries(10_000, 64, W.SEEDS["gauss64_q"])
+    say("[full] sparse L=5: building")
+    h = B.os_ann_build_ex(dev(X), 5)
+    o = orc.build_index_sparse(X, 5)
+    try:
+        ex = B.os_ann_export_sparse(h)
+        torch.cuda.synchronize()
+        assert np.array_equal(ex["cone_ids"].cpu().numpy(), o["keys"])
+        assert np.array_equal(ex["offsets"].cpu().numpy(), o["offsets"])
+        assert np.array_equal(ex["perm"].cpu().numpy(), o["perm"])
+        del ex
+        yq = dev(Y)
+        for budget, cones, n in ((1024, False, 60), (64, True, 60)):
+            s = sample_ids(len(Y), n)
+            say(f"[full] sparse L=5: budget {budget} cones={cones}")
+            gi, gd, gn = B.os_ann_search_ex(h, yq, budget, cones=cones)
+            torch.cuda.synchronize()
+            gi, gd, gn = gi.cpu().numpy()[s], gd.cpu().numpy()[s], gn.cpu().numpy()[s]
+            oi, od32, od64, on = orc.search_sparse(X, o, Y[s], budget, cones=cones)
+            assert np.array_equal(gn, on) and np.array_equal(gi, oi), budget
+            assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), budget
+    finally:
+        B.os_ann_free(h)
+
+
+def test_structured_bases_1m_d64(orc):
+    # four Walsh-Hadamard bases on the full workload at the several-bases
+    # benchmark budget
+    X = W.gaussian_db(1_000_000, 64, W.SEEDS["gauss64_db"])
+    Y = W.gaussian_queries(10_000, 64, W.SEEDS["gauss64_q"])
+    sg = W.random_signs(4, 64)
+    say("[full] structured bases: building 4 tables")
+    h = B.os_ann_build_wht(dev(X), 2, dev(sg))
+    o = orc.build_index_wht(X, 2, sg)
+    try:
+        for r in range(4):
+            ex = B.os_ann_export_basis(h, r)
+            torch.cuda.synchronize()
+            assert np.array_equal(ex["offsets"].cpu().numpy(), o["tables"][r]["offsets"]), r
+            assert np.array_equal(ex["perm"].cpu().numpy(), o["tables"][r]["perm"]), r
+            del ex
+        s = sample_ids(len(Y), 40)
+        gi, gd, gn = B.os_ann_search_ex(h, dev(Y), 131072)
+        torch.cuda.synchronize()
+        gi, gd, gn = gi.cpu().numpy()[s], gd.cpu().numpy()[s], gn.cpu().numpy()[s]
+        oi, od32, od64, on = orc.search_rot(X, o, Y[s], 131072)
+        assert np.array_equal(gn, on) and np.array_equal(gi, oi)
+        assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32))
     finally:
         B.os_ann_free(h)
