@@ -9,9 +9,10 @@
 // streams every listed cone's rows, 16 at a time, straight from memory into
 // the MFMA A operand (bucket sizes are padded to 16 rows in the
 // low-precision copy).  With the rows as the MFMA A operand and 16 queries
-// as B, lane l holds the products of query l%16 with 4 rows, from which it
-// forms d~ = ||x^||^2 - 2 q^.x^, which ranks candidates like the squared
-// distance of the rounded vectors.  No wave waits for another: a wave only
+// as B, lane l holds the products of query l%16 with 4 rows; the
+// accumulators start at -||x^||^2/2, so they end at -d~/2 with
+// d~ = ||x^||^2 - 2 q^.x^, which ranks candidates like the squared distance
+// of the rounded vectors.  No wave waits for another: a wave only
 // reads the cones its own queries probe.
 //
 // Each query keeps, per split, a top-R list of (d~, padded position) in
@@ -354,14 +355,16 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                         advance();
                     }
                 };
-                float pthr[G];  // thr, or -inf for slots that do not probe the tile's cone
+                // -thr/2 (the accumulators hold -d~/2), or +inf for slots that do
+                // not probe the tile's cone
+                float pthr[G];
                 uint32_t cmlo = 0, cmhi = 0;  // the probe mask pthr was set for
                 auto set_pthr = [&]() {
                     const uint64_t mk = ((uint64_t)cmhi << 32) | cmlo;
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
                         const bool probed = (mk >> (16 * g + (l % 16))) & 1ull;
-                        pthr[g] = probed ? thr[g] : -__builtin_huge_valf();
+                        pthr[g] = probed ? -0.5f * thr[g] : __builtin_huge_valf();
                     }
                 };
                 // One group step: issue the next group's loads into the other
@@ -385,39 +388,38 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                             cmhi = gr.mhi[u];
                             set_pthr();
                         }
+                        // the accumulators start at -||x^||^2/2, so they end at -d~/2
+                        // (the scalings by powers of two are exact)
+                        const f32x4_t c0 = {-0.5f * nv[u].x, -0.5f * nv[u].y, -0.5f * nv[u].z, -0.5f * nv[u].w};
                         f32x4_t acc[G];
 #pragma unroll
                         for (int g = 0; g < G; ++g) {
-                            acc[g] = mfma16<F16IN>(av[u][0], bq[g][0], f32x4_t{0.0f, 0.0f, 0.0f, 0.0f});
+                            acc[g] = mfma16<F16IN>(av[u][0], bq[g][0], c0);
 #pragma unroll
                             for (int ks = 1; ks < KS; ++ks) acc[g] = mfma16<F16IN>(av[u][ks], bq[g][ks], acc[g]);
                         }
-                        const float nvv[4] = {nv[u].x, nv[u].y, nv[u].z, nv[u].w};
-                        // d~ of the lane's 4 rows for each group; a NaN norm marks a
-                        // padding row: fminf drops it from the minimum and it never
-                        // passes; a -inf threshold makes the margin +inf
-                        float d[G][4];
-                        float margin = __builtin_huge_valf();
+                        // d~ <= thr  <=>  -d~/2 >= -thr/2.  A NaN norm marks a padding
+                        // row: fmaxf drops it from the maximum and it never passes; a
+                        // +inf bound (slot not probing the cone) makes the margin -inf
+                        float margin = -__builtin_huge_valf();
 #pragma unroll
                         for (int g = 0; g < G; ++g) {
-#pragma unroll
-                            for (int ii = 0; ii < 4; ++ii) d[g][ii] = nvv[ii] - 2.0f * acc[g][ii];
-                            const float m4 = fminf(fminf(d[g][0], d[g][1]), fminf(d[g][2], d[g][3]));
-                            margin = fminf(margin, m4 - pthr[g]);
+                            const float m4 = fmaxf(fmaxf(acc[g][0], acc[g][1]), fmaxf(acc[g][2], acc[g][3]));
+                            margin = fmaxf(margin, m4 - pthr[g]);
                         }
-                        if (__ballot(margin <= 0.0f) != 0) {  // rare once the bounds have settled
+                        if (__ballot(margin >= 0.0f) != 0) {  // rare once the bounds have settled
 #pragma unroll
                             for (int g = 0; g < G; ++g)
 #pragma unroll
                                 for (int ii = 0; ii < 4; ++ii) {
-                                    const bool pass = d[g][ii] <= pthr[g];
+                                    const bool pass = acc[g][ii] >= pthr[g];
                                     const uint64_t m = __ballot(pass);
                                     if (m == 0) continue;
                                     if (nhit + (uint32_t)__popcll(m) > (uint32_t)kHitCap) flush();
                                     if (pass) {
                                         const uint32_t at = nhit + (uint32_t)__popcll(m & lanemask_lt());
-                                        s_hit[w][at] = make_uint4(__float_as_uint(d[g][ii]), p + 4 * (l / 16) + ii,
-                                                                  16 * g + (l % 16), 0u);
+                                        s_hit[w][at] = make_uint4(__float_as_uint(-2.0f * acc[g][ii]),
+                                                                  p + 4 * (l / 16) + ii, 16 * g + (l % 16), 0u);
                                     }
                                     nhit += (uint32_t)__popcll(m);
                                 }
