@@ -379,6 +379,22 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                     cwn = a.cmin[(int64_t)(it & (R - 1)) * a.Q + own_slot];
                     // fold the class read one group earlier; a window of R reads starts with class 0
                     run = ((it - 1) & (R - 1)) == 0 ? cw : (cw > run ? cw : run);
+                    // products of every tile of the group first, then their bound
+                    // tests, so the matrix work of one tile overlaps the vector
+                    // work of the other
+                    f32x4_t acc[U][G];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if ((uint32_t)u >= gr.n) break;
+                        const f32x4_t c0 = {-0.5f * nv[u].x, -0.5f * nv[u].y, -0.5f * nv[u].z, -0.5f * nv[u].w};
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            acc[u][g] = mfma16<F16IN>(av[u][0], bq[g][0], c0);
+#pragma unroll
+                            for (int ks = 1; ks < KS; ++ks)
+                                acc[u][g] = mfma16<F16IN>(av[u][ks], bq[g][ks], acc[u][g]);
+                        }
+                    }
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         if ((uint32_t)u >= gr.n) break;
@@ -388,23 +404,10 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                             cmhi = gr.mhi[u];
                             set_pthr();
                         }
-                        // the accumulators start at -||x^||^2/2, so they end at -d~/2
-                        // (the scalings by powers of two are exact)
-                        const f32x4_t c0 = {-0.5f * nv[u].x, -0.5f * nv[u].y, -0.5f * nv[u].z, -0.5f * nv[u].w};
-                        f32x4_t acc[G];
-#pragma unroll
-                        for (int g = 0; g < G; ++g) {
-                            acc[g] = mfma16<F16IN>(av[u][0], bq[g][0], c0);
-#pragma unroll
-                            for (int ks = 1; ks < KS; ++ks) acc[g] = mfma16<F16IN>(av[u][ks], bq[g][ks], acc[g]);
-                        }
-                        // d~ <= thr  <=>  -d~/2 >= -thr/2.  A NaN norm marks a padding
-                        // row: fmaxf drops it from the maximum and it never passes; a
-                        // +inf bound (slot not probing the cone) makes the margin -inf
                         float margin = -__builtin_huge_valf();
 #pragma unroll
                         for (int g = 0; g < G; ++g) {
-                            const float m4 = fmaxf(fmaxf(acc[g][0], acc[g][1]), fmaxf(acc[g][2], acc[g][3]));
+                            const float m4 = fmaxf(fmaxf(acc[u][g][0], acc[u][g][1]), fmaxf(acc[u][g][2], acc[u][g][3]));
                             margin = fmaxf(margin, m4 - pthr[g]);
                         }
                         if (__ballot(margin >= 0.0f) != 0) {  // rare once the bounds have settled
@@ -412,13 +415,13 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                             for (int g = 0; g < G; ++g)
 #pragma unroll
                                 for (int ii = 0; ii < 4; ++ii) {
-                                    const bool pass = acc[g][ii] >= pthr[g];
+                                    const bool pass = acc[u][g][ii] >= pthr[g];
                                     const uint64_t m = __ballot(pass);
                                     if (m == 0) continue;
                                     if (nhit + (uint32_t)__popcll(m) > (uint32_t)kHitCap) flush();
                                     if (pass) {
                                         const uint32_t at = nhit + (uint32_t)__popcll(m & lanemask_lt());
-                                        s_hit[w][at] = make_uint4(__float_as_uint(-2.0f * acc[g][ii]),
+                                        s_hit[w][at] = make_uint4(__float_as_uint(-2.0f * acc[u][g][ii]),
                                                                   p + 4 * (l / 16) + ii, 16 * g + (l % 16), 0u);
                                     }
                                     nhit += (uint32_t)__popcll(m);
