@@ -838,6 +838,10 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     fa.perm = ix->perm;
     fa.yf = pa.yf;
     fa.dpad = p.dpad;
+    // the codes hold FP16 rows and uint8 rows exactly (FP32 rows: planes)
+    fa.xl = ix->lp.xl;
+    fa.dk = ix->lp.dk;
+    fa.xl_codes = ix->dtype == kF16 && ix->lp.f16 ? 1 : ix->dtype == kU8 && !ix->lp.f16 ? 2 : 0;
     fa.out_idx = c.out_idx;
     fa.out_dist = c.out_dist;
     return timed_launch(ix, c.timing, OS_ANN_KERNEL_FINISH, c.s, [&] { return launch_tiled_finish(fa, p.R, c.s); });

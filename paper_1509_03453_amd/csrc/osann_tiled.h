@@ -83,6 +83,13 @@ struct FinishArgs {
     const uint32_t* perm;
     const float* yf;
     int dpad;
+    // Row-major low-precision copy ([padded position][dk] codes) where it
+    // holds the table's values exactly: xl_codes 1 for FP16 codes of an FP16
+    // table, 2 for BF16 codes of a uint8 table (BF16 holds 0..255 exactly),
+    // 0 to read the chunk-major planes instead.
+    const uint16_t* xl;
+    int dk;
+    int xl_codes;
     int64_t* out_idx;
     float* out_dist;
 };

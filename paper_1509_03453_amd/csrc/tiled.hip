@@ -527,6 +527,40 @@ hipError_t launch_tiled_seed(const SeedArgs& a, int R, int f16in, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
+// The FP32 squared distance of the row at padded position p from its
+// row-major codes, where they hold the table's values exactly: the same
+// operations in the same ascending order as row_dist_fp32 over the planes
+// (the zero components past D add +0), but one contiguous read of the row
+// instead of one scattered 16-B read per plane.  dpad is a multiple of 8.
+template <bool F16CODES>
+__device__ inline float code_row_dist_fp32(const uint16_t* __restrict__ xl, int dk, int64_t p, int dpad,
+                                           const float* __restrict__ y) {
+#pragma clang fp contract(off)
+    const uint4* row = reinterpret_cast<const uint4*>(xl + p * dk);
+    const int nu = dpad / 8;  // 16-B units of 8 components
+    float acc = 0.0f;
+    for (int u0 = 0; u0 < nu; u0 += 8) {
+        uint4 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = u0 + j < nu ? row[u0 + j] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (u0 + j < nu) {
+                const uint32_t wv[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint16_t b = (uint16_t)(wv[e / 2] >> (16 * (e & 1)));
+                    const float x = F16CODES ? F16::val(b) : __uint_as_float((uint32_t)b << 16);
+                    const float d = x - y[(u0 + j) * 8 + e];
+                    const float sq = d * d;
+                    acc = acc + sq;
+                }
+            }
+        }
+    }
+    return acc;
+}
+
 // One group of G lanes per query: merge the S split lists (ordered by
 // (d~, padded position)), re-rank the R survivors with the exact FP32
 // distance, arg-min on (distance, original row).
@@ -565,7 +599,13 @@ __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
         const uint32_t pos = f.ppos[cp];
         if (pos != 0xFFFFFFFFu) {  // a padding row never enters a list; checked anyway
             cr = f.perm[pos];
-            cd = row_dist_fp32<E>(static_cast<const uint4*>(f.planes), f.N, f.nch, pos, f.yf + q * f.dpad);
+            const float* y = f.yf + q * f.dpad;
+            if (f.xl_codes == 1)
+                cd = code_row_dist_fp32<true>(f.xl, f.dk, cp, f.dpad, y);
+            else if (f.xl_codes == 2)
+                cd = code_row_dist_fp32<false>(f.xl, f.dk, cp, f.dpad, y);
+            else
+                cd = row_dist_fp32<E>(static_cast<const uint4*>(f.planes), f.N, f.nch, pos, y);
         }
     }
 #pragma unroll
@@ -638,6 +678,9 @@ static hipError_t finish_r(const FinishArgs& f, int R, hipStream_t s) {
 
 hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s) {
     if (f.Q <= 0) return hipSuccess;
+    if (f.xl_codes != 0 && (f.xl == nullptr || f.dpad % 8 != 0 || f.dpad > f.dk ||
+                            f.xl_codes != (f.dtype == kF16 ? 1 : f.dtype == kU8 ? 2 : -1)))
+        return hipErrorInvalidValue;
     switch (f.dtype) {
         case kF32: return finish_r<F32>(f, R, s);
         case kF16: return finish_r<F16>(f, R, s);
