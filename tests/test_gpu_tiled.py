@@ -96,6 +96,18 @@ def test_tiled_patches_fp16(orc):
     check_tiled(orc, X, Y, 2, (64, 1024), tag="patches f16")
 
 
+def test_tiled_ragged_fp16_uint8(orc):
+    # D not a multiple of 32: the re-rank reads FP16 and uint8 rows from the
+    # row-major low-precision copy, whose columns past D are zero
+    for D, seed in ((12, 2311), (36, 2313)):
+        X = W.gaussian_db(6000, D, seed=seed).astype(np.float16)
+        Y = W.gaussian_queries(97, D, seed=seed + 1).astype(np.float16)
+        check_tiled(orc, X, Y, 2, (40, 900), tag=f"f16 D={D} ragged")
+    Xu = W.descriptor_db(8000, 40, seed=2315)
+    Yu, _ = W.descriptor_queries(Xu, 131)
+    check_tiled(orc, Xu, Yu, 2, (64, 1500), tag="u8 D=40 ragged")
+
+
 def test_tiled_edges(orc):
     X = W.gaussian_db(3000, 8, seed=2301)
     check_tiled(orc, X, W.gaussian_queries(1, 8, seed=2302), 3, (1, 50, 3000), tag="Q=1 L3")
