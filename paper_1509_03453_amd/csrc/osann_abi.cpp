@@ -135,6 +135,8 @@ struct os_ann_index {
     uint64_t* sp_hkeys = nullptr;  // [sp_cap] hash slots
     uint32_t* sp_hval = nullptr;   // [sp_cap]
     uint64_t sp_cap = 0;
+    uint64_t* sp_filt = nullptr;   // [sp_fbits / 64] filter words
+    uint64_t sp_fbits = 0;
     uint64_t* binom64 = nullptr;   // [257][8]
     int32_t nprobe = 0;         // clusters searched per query
 };
@@ -256,7 +258,7 @@ void release(os_ann_index* ix, bool synced = false) {
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
                     ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
                     ix->planes_tab, ix->proj_mu, ix->proj_P, ix->ivf_cent, ix->rot_signs,
-                    ix->sp_keys, ix->sp_hkeys, ix->sp_hval, ix->binom64};
+                    ix->sp_keys, ix->sp_hkeys, ix->sp_hval, ix->sp_filt, ix->binom64};
     for (void* p : ptrs) dev_free(p);
     delete ix;
 }
@@ -1098,6 +1100,8 @@ hipError_t enqueue_sparse(const Call& c) {
     t.hkeys = ix->sp_hkeys;
     t.hval = ix->sp_hval;
     t.hmask = ix->sp_cap - 1;
+    t.filt = ix->sp_filt;
+    t.fmask = ix->sp_fbits - 1;
     t.offsets = ix->offsets;
     t.binom = ix->binom64;
     t.maskord = ix->maskord;
@@ -1410,14 +1414,17 @@ os_ann_index* build_sparse(const void* db, int32_t dtype, int64_t N, int32_t D, 
     uint64_t cap = 64;
     while (cap < 2 * (uint64_t)host_ne) cap <<= 1;
     ix->sp_cap = cap;
+    ix->sp_fbits = sparse_filter_bits(host_ne);
     ix->n_nonempty = host_ne;
     if (dev_alloc(ix, (void**)&ix->sp_keys, (size_t)host_ne * 8, "cone ids") ||
         dev_alloc(ix, (void**)&ix->offsets, ((size_t)host_ne + 1) * 4, "offsets") ||
         dev_alloc(ix, (void**)&ix->sp_hkeys, (size_t)cap * 8, "hash keys") ||
-        dev_alloc(ix, (void**)&ix->sp_hval, (size_t)cap * 4, "hash values"))
+        dev_alloc(ix, (void**)&ix->sp_hval, (size_t)cap * 4, "hash values") ||
+        dev_alloc(ix, (void**)&ix->sp_filt, (size_t)(ix->sp_fbits / 8), "hash filter"))
         return bail();
     if (!step(launch_sparse_compact(sorted, flag, pos, N, ix->sp_keys, ix->offsets, s), "compact") ||
-        !step(launch_sparse_hash(ix->sp_keys, host_ne, ix->sp_hkeys, ix->sp_hval, cap, s), "hash table") ||
+        !step(launch_sparse_hash(ix->sp_keys, host_ne, ix->sp_hkeys, ix->sp_hval, cap, ix->sp_filt, ix->sp_fbits,
+                                 s), "hash table") ||
         !step(launch_gather_planes(db, dtype, N, D, ix->perm, ix->planes, s), "gather") ||
         !step(hipStreamSynchronize(s), "build sync"))
         return bail();

@@ -19,6 +19,11 @@ struct SparseTable {
     const uint64_t* hkeys;    // [hmask + 1] cone id per slot (kSparseEmpty: free)
     const uint32_t* hval;     // [hmask + 1] bucket number per slot
     uint64_t hmask;
+    // One-hash bit filter in front of the table (no false negatives): bit
+    // (mix(id) >> 32) & fmask is set for every non-empty cone id.  At 16 or
+    // more bits per key it stays in L2 and answers most probes of empty cones.
+    const uint64_t* filt;     // [(fmask + 1) / 64] words
+    uint64_t fmask;
     const uint32_t* offsets;  // [n_ne + 1] first row position of each bucket
     const uint64_t* binom;    // [257][8] C(n, k)
     const uint8_t* maskord;   // [128] flip masks by popcount, then value
@@ -42,9 +47,12 @@ hipError_t launch_sparse_heads(const uint64_t* sorted, int64_t N, uint32_t* flag
 // offsets[pos[i]] = i at every head, offsets[pos[N]] = N.
 hipError_t launch_sparse_compact(const uint64_t* sorted, const uint32_t* flag, const uint32_t* pos, int64_t N,
                                  uint64_t* keys, uint32_t* offsets, hipStream_t s);
-// Hash table of n distinct keys in cap (a power of two >= 2n) slots.
+// Hash table of n distinct keys in cap (a power of two >= 2n) slots, and
+// their filter of fbits bits (a power of two, 64 to 2^32).
 hipError_t launch_sparse_hash(const uint64_t* keys, int64_t n, uint64_t* hkeys, uint32_t* hval, uint64_t cap,
-                              hipStream_t s);
+                              uint64_t* filt, uint64_t fbits, hipStream_t s);
+// Filter size for n keys: a power of two >= 16 n bits, from 2^12 to 2^25.
+uint64_t sparse_filter_bits(int64_t n);
 
 // Search: walk (row budget, the first C cones, or at most kSparseWalkCap
 // positions) and FP32 scan with arg-min in one pass per query, from the

@@ -33,7 +33,10 @@ __device__ inline uint64_t sparse_mix(uint64_t z) {
 // Bucket number of a cone id, or -1 for an empty cone.  At least half the
 // slots are free, so every probe sequence ends at a free slot.
 __device__ inline int64_t sparse_lookup(const SparseTable& t, uint64_t key) {
-    uint64_t h = sparse_mix(key) & t.hmask;
+    const uint64_t m = sparse_mix(key);
+    const uint64_t b = (m >> 32) & t.fmask;
+    if (!((t.filt[b >> 6] >> (b & 63)) & 1ull)) return -1;  // not in the filter: an empty cone
+    uint64_t h = m & t.hmask;
     for (uint64_t step = 0; step <= t.hmask; ++step) {
         const uint64_t k = t.hkeys[h];
         if (k == key) return t.hval[h];
@@ -158,11 +161,14 @@ __global__ void sparse_fill_kernel(uint64_t* __restrict__ p, uint64_t n, uint64_
 }
 
 __global__ void sparse_insert_kernel(const uint64_t* __restrict__ keys, int64_t n, uint64_t* hkeys,
-                                     uint32_t* __restrict__ hval, uint64_t mask) {
+                                     uint32_t* __restrict__ hval, uint64_t mask, uint64_t* filt, uint64_t fmask) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     const uint64_t key = keys[u];
-    uint64_t h = sparse_mix(key) & mask;
+    const uint64_t m = sparse_mix(key);
+    const uint64_t b = (m >> 32) & fmask;
+    atomicOr(reinterpret_cast<unsigned long long*>(filt + (b >> 6)), 1ull << (b & 63));
+    uint64_t h = m & mask;
     for (uint64_t step = 0; step <= mask; ++step) {
         const unsigned long long prev =
             atomicCAS(reinterpret_cast<unsigned long long*>(hkeys + h), (unsigned long long)kSparseEmpty,
@@ -318,13 +324,26 @@ hipError_t launch_sparse_compact(const uint64_t* sorted, const uint32_t* flag, c
     return hipGetLastError();
 }
 
+uint64_t sparse_filter_bits(int64_t n) {
+    uint64_t bits = uint64_t(1) << 12;
+    while (bits < 16 * (uint64_t)(n > 0 ? n : 0) && bits < (uint64_t(1) << 25)) bits <<= 1;
+    return bits;
+}
+
 hipError_t launch_sparse_hash(const uint64_t* keys, int64_t n, uint64_t* hkeys, uint32_t* hval, uint64_t cap,
-                              hipStream_t s) {
+                              uint64_t* filt, uint64_t fbits, hipStream_t s) {
     if (cap == 0 || (cap & (cap - 1)) || cap < 2 * (uint64_t)n) return hipErrorInvalidValue;
+    if (fbits < 64 || (fbits & (fbits - 1)) || fbits > (uint64_t(1) << 32) || filt == nullptr)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(sparse_fill_kernel, grid_for((int64_t)cap, 256), dim3(256), 0, s, hkeys, cap, kSparseEmpty);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sparse_fill_kernel, grid_for((int64_t)(fbits / 64), 256), dim3(256), 0, s, filt, fbits / 64,
+                       uint64_t(0));
+    e = hipGetLastError();
     if (e != hipSuccess || n <= 0) return e;
-    hipLaunchKernelGGL(sparse_insert_kernel, grid_for(n, 256), dim3(256), 0, s, keys, n, hkeys, hval, cap - 1);
+    hipLaunchKernelGGL(sparse_insert_kernel, grid_for(n, 256), dim3(256), 0, s, keys, n, hkeys, hval, cap - 1, filt,
+                       fbits - 1);
     return hipGetLastError();
 }
 
