@@ -50,18 +50,23 @@ __device__ inline int64_t sparse_lookup(const SparseTable& t, uint64_t key) {
 // index 0x7FFF so that they sort last.  Colex rank of the ascending index
 // set times 2^L, plus the sign bits in ascending index order, the lowest
 // index most significant.
+// LT > 0: L is LT, known at compile time, and only the first LT entries
+// are sorted (the rest hold 0x7FFF and stay last); LT = 0: L at run time.
+template <int LT = 0>
 __device__ inline uint64_t sparse_cone_id(int L, int (&idx)[7], int (&sg)[7], const uint64_t* __restrict__ binom) {
+    constexpr int NS = LT > 0 ? LT : 7;
+    if (LT > 0) L = LT;
 #pragma unroll
-    for (int a = 1; a < 7; ++a)
+    for (int a = 1; a < NS; ++a)
 #pragma unroll
-        for (int b = 6; b >= a; --b)
+        for (int b = NS - 1; b >= a; --b)
             if (idx[b - 1] > idx[b]) {
                 int u = idx[b]; idx[b] = idx[b - 1]; idx[b - 1] = u;
                 u = sg[b]; sg[b] = sg[b - 1]; sg[b - 1] = u;
             }
     uint64_t rank = 0, bits = 0;
 #pragma unroll
-    for (int j = 0; j < 7; ++j)
+    for (int j = 0; j < NS; ++j)
         if (j < L) {
             rank += binom[idx[j] * 8 + j + 1];
             bits = (bits << 1) | (uint64_t)sg[j];
@@ -75,9 +80,10 @@ __device__ inline uint64_t sparse_cone_id(int L, int (&idx)[7], int (&sg)[7], co
 // k-th largest element s_k is the largest s with C(s, k) <= the remaining
 // rank.  T_b = D-1-s_{L-b}, and mask bit L-1-b (= k-1) flips the sign of
 // component order[T_b].
+template <int LT>
 __device__ inline uint64_t sparse_walk_cone(uint64_t j, const SparseTable& t, const uint8_t* order,
                                             const uint8_t* sbit) {
-    const int L = t.L, D = t.D;
+    const int L = LT > 0 ? LT : t.L, D = t.D;
     const uint64_t nsub = (uint64_t)t.n_sub;
     uint64_t tt = j;
     int mask = 0;
@@ -116,7 +122,7 @@ __device__ inline uint64_t sparse_walk_cone(uint64_t j, const SparseTable& t, co
             sg[k - 1] = sbit[c] ^ ((mask >> (k - 1)) & 1);
         }
     }
-    return sparse_cone_id(L, idx, sg, t.binom);
+    return sparse_cone_id<LT>(L, idx, sg, t.binom);
 }
 
 __global__ void sparse_keys_kernel(const uint64_t* __restrict__ row_top, int64_t N, int L,
@@ -190,7 +196,7 @@ constexpr int kSparseWaves = 4;
 // lanes through a cursor over the running counts; FP32 distance term by
 // term and arg-min on (distance, original row).  The binomials and the walk
 // state sit in LDS.
-template <typename E>
+template <typename E, int LT>
 __global__ __launch_bounds__(64 * kSparseWaves) void sparse_search_kernel(SparseSearchArgs a) {
     __shared__ uint64_t s_binom[257 * 8];
     __shared__ uint8_t order[kSparseWaves][kMaxD];
@@ -241,7 +247,7 @@ __global__ __launch_bounds__(64 * kSparseWaves) void sparse_search_kernel(Sparse
             const uint64_t j = j0 + l;
             uint32_t start = 0, len = 0;
             if (j < limit) {
-                const int64_t u = sparse_lookup(t, sparse_walk_cone(j, t, order[w], sbit[w]));
+                const int64_t u = sparse_lookup(t, sparse_walk_cone<LT>(j, t, order[w], sbit[w]));
                 if (u >= 0) {
                     start = t.offsets[u];
                     len = t.offsets[u + 1] - start;
@@ -347,18 +353,33 @@ hipError_t launch_sparse_hash(const uint64_t* keys, int64_t n, uint64_t* hkeys, 
     return hipGetLastError();
 }
 
+// The walk compiled for each L (1 to 7).
+template <typename E>
+static hipError_t search_l(const SparseSearchArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    switch (a.t.L) {
+        case 1: hipLaunchKernelGGL((sparse_search_kernel<E, 1>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((sparse_search_kernel<E, 2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((sparse_search_kernel<E, 3>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((sparse_search_kernel<E, 4>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((sparse_search_kernel<E, 5>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((sparse_search_kernel<E, 6>), grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((sparse_search_kernel<E, 7>), grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_sparse_search(const SparseSearchArgs& a, hipStream_t s) {
     if (a.Q <= 0) return hipSuccess;
     if (a.t.D < 1 || a.t.D > kMaxD || a.t.L < 1 || a.t.L > 7 || a.dpad > kMaxD || a.budget < 1)
         return hipErrorInvalidValue;
     const dim3 grid = grid_for(a.Q, kSparseWaves), block(64 * kSparseWaves);
     switch (a.dtype) {
-        case kF32: hipLaunchKernelGGL(sparse_search_kernel<F32>, grid, block, 0, s, a); break;
-        case kF16: hipLaunchKernelGGL(sparse_search_kernel<F16>, grid, block, 0, s, a); break;
-        case kU8: hipLaunchKernelGGL(sparse_search_kernel<U8>, grid, block, 0, s, a); break;
-        default: return hipErrorInvalidValue;
+        case kF32: return search_l<F32>(a, grid, block, s);
+        case kF16: return search_l<F16>(a, grid, block, s);
+        case kU8: return search_l<U8>(a, grid, block, s);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 }  // namespace osann
