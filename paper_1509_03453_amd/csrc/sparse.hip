@@ -52,8 +52,10 @@ __device__ inline int64_t sparse_lookup(const SparseTable& t, uint64_t key) {
 // index most significant.
 // LT > 0: L is LT, known at compile time, and only the first LT entries
 // are sorted (the rest hold 0x7FFF and stay last); LT = 0: L at run time.
-template <int LT = 0>
-__device__ inline uint64_t sparse_cone_id(int L, int (&idx)[7], int (&sg)[7], const uint64_t* __restrict__ binom) {
+// BT: element type of the binomial table (uint32_t where every binomial
+// read is below 2^32).
+template <int LT = 0, typename BT = uint64_t>
+__device__ inline uint64_t sparse_cone_id(int L, int (&idx)[7], int (&sg)[7], const BT* __restrict__ binom) {
     constexpr int NS = LT > 0 ? LT : 7;
     if (LT > 0) L = LT;
 #pragma unroll
@@ -64,14 +66,15 @@ __device__ inline uint64_t sparse_cone_id(int L, int (&idx)[7], int (&sg)[7], co
                 int u = idx[b]; idx[b] = idx[b - 1]; idx[b - 1] = u;
                 u = sg[b]; sg[b] = sg[b - 1]; sg[b - 1] = u;
             }
-    uint64_t rank = 0, bits = 0;
+    BT rank = 0;
+    uint64_t bits = 0;
 #pragma unroll
     for (int j = 0; j < NS; ++j)
         if (j < L) {
             rank += binom[idx[j] * 8 + j + 1];
             bits = (bits << 1) | (uint64_t)sg[j];
         }
-    return (rank << L) | bits;
+    return ((uint64_t)rank << L) | bits;
 }
 
 // Cone at walk position j: block h of C(D,L) C(L,h) positions (flipped
@@ -80,9 +83,9 @@ __device__ inline uint64_t sparse_cone_id(int L, int (&idx)[7], int (&sg)[7], co
 // k-th largest element s_k is the largest s with C(s, k) <= the remaining
 // rank.  T_b = D-1-s_{L-b}, and mask bit L-1-b (= k-1) flips the sign of
 // component order[T_b].
-template <int LT>
-__device__ inline uint64_t sparse_walk_cone(uint64_t j, const SparseTable& t, const uint8_t* order,
-                                            const uint8_t* sbit) {
+template <int LT, typename BT>
+__device__ inline uint64_t sparse_walk_cone(uint64_t j, const SparseTable& t, const BT* __restrict__ bn,
+                                            const uint8_t* order, const uint8_t* sbit) {
     const int L = LT > 0 ? LT : t.L, D = t.D;
     const uint64_t nsub = (uint64_t)t.n_sub;
     uint64_t tt = j;
@@ -91,7 +94,7 @@ __device__ inline uint64_t sparse_walk_cone(uint64_t j, const SparseTable& t, co
         uint64_t base = nsub, cl = 1;
         int mstart = 1;
         for (int h = 1; h <= L; ++h) {
-            cl = t.binom[L * 8 + h];
+            cl = (uint64_t)bn[L * 8 + h];
             const uint64_t sz = nsub * cl;
             if (j < base + sz) break;
             base += sz;
@@ -101,7 +104,7 @@ __device__ inline uint64_t sparse_walk_cone(uint64_t j, const SparseTable& t, co
         tt = jj / cl;
         mask = t.maskord[mstart + (int)(jj % cl)];
     }
-    uint64_t r = nsub - 1 - tt;
+    BT r = (BT)(nsub - 1 - tt);
     int idx[7], sg[7];
 #pragma unroll
     for (int k = 7; k >= 1; --k) {
@@ -111,18 +114,18 @@ __device__ inline uint64_t sparse_walk_cone(uint64_t j, const SparseTable& t, co
             int lo = k - 1, hi = D - 1;  // C(k-1, k) = 0 <= r
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (t.binom[mid * 8 + k] <= r)
+                if (bn[mid * 8 + k] <= r)
                     lo = mid;
                 else
                     hi = mid - 1;
             }
-            r -= t.binom[lo * 8 + k];
+            r -= bn[lo * 8 + k];
             const int c = order[D - 1 - lo];
             idx[k - 1] = c;
             sg[k - 1] = sbit[c] ^ ((mask >> (k - 1)) & 1);
         }
     }
-    return sparse_cone_id<LT>(L, idx, sg, t.binom);
+    return sparse_cone_id<LT, BT>(L, idx, sg, bn);
 }
 
 __global__ void sparse_keys_kernel(const uint64_t* __restrict__ row_top, int64_t N, int L,
@@ -196,9 +199,9 @@ constexpr int kSparseWaves = 4;
 // lanes through a cursor over the running counts; FP32 distance term by
 // term and arg-min on (distance, original row).  The binomials and the walk
 // state sit in LDS.
-template <typename E, int LT>
+template <typename E, int LT, typename BT>
 __global__ __launch_bounds__(64 * kSparseWaves) void sparse_search_kernel(SparseSearchArgs a) {
-    __shared__ uint64_t s_binom[257 * 8];
+    __shared__ BT s_binom[257 * 8];
     __shared__ uint8_t order[kSparseWaves][kMaxD];
     __shared__ uint8_t sbit[kSparseWaves][kMaxD];
     __shared__ float ys[kSparseWaves][kMaxD];
@@ -207,9 +210,8 @@ __global__ __launch_bounds__(64 * kSparseWaves) void sparse_search_kernel(Sparse
     const int w = threadIdx.x / 64, l = lane_id();
     const int64_t q = (int64_t)blockIdx.x * kSparseWaves + w;
     const bool qv = q < a.Q;
-    for (int i = threadIdx.x; i < 257 * 8; i += 64 * kSparseWaves) s_binom[i] = a.t.binom[i];
-    SparseTable t = a.t;
-    t.binom = s_binom;
+    for (int i = threadIdx.x; i < 257 * 8; i += 64 * kSparseWaves) s_binom[i] = (BT)a.t.binom[i];
+    const SparseTable t = a.t;
     const int D = t.D;
     for (int i = l; i < a.dpad; i += 64) ys[w][i] = qv ? a.yf[q * a.dpad + i] : 0.0f;
     for (int i = l; i < D; i += 64) {
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(64 * kSparseWaves) void sparse_search_kernel(Sparse
             const uint64_t j = j0 + l;
             uint32_t start = 0, len = 0;
             if (j < limit) {
-                const int64_t u = sparse_lookup(t, sparse_walk_cone<LT>(j, t, order[w], sbit[w]));
+                const int64_t u = sparse_lookup(t, sparse_walk_cone<LT, BT>(j, t, s_binom, order[w], sbit[w]));
                 if (u >= 0) {
                     start = t.offsets[u];
                     len = t.offsets[u + 1] - start;
@@ -353,20 +355,39 @@ hipError_t launch_sparse_hash(const uint64_t* keys, int64_t n, uint64_t* hkeys, 
     return hipGetLastError();
 }
 
-// The walk compiled for each L (1 to 7).
-template <typename E>
-static hipError_t search_l(const SparseSearchArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+// Whether every binomial the walk reads (C(n, k), n < D, k <= L) and the
+// subset ranks (< C(D, L)) are below 2^32.
+static bool binom_fits_32(int D, int L) {
+    uint64_t c = 1, top = 0;
+    for (int k = 1; k <= L; ++k) {  // C(D-1, k) from C(D-1, k-1); exact in 64 bits for D <= 256, k <= 7
+        c = c * (uint64_t)(D - k) / (uint64_t)k;
+        if (c > top) top = c;
+    }
+    uint64_t nsub = 1;
+    for (int k = 1; k <= L; ++k) nsub = nsub * (uint64_t)(D - k + 1) / (uint64_t)k;
+    return top < (uint64_t(1) << 32) && nsub < (uint64_t(1) << 32);
+}
+
+// The walk compiled for each L (1 to 7) and binomial width.
+template <typename E, typename BT>
+static hipError_t search_lb(const SparseSearchArgs& a, dim3 grid, dim3 block, hipStream_t s) {
     switch (a.t.L) {
-        case 1: hipLaunchKernelGGL((sparse_search_kernel<E, 1>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((sparse_search_kernel<E, 2>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((sparse_search_kernel<E, 3>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((sparse_search_kernel<E, 4>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((sparse_search_kernel<E, 5>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((sparse_search_kernel<E, 6>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((sparse_search_kernel<E, 7>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((sparse_search_kernel<E, 1, BT>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((sparse_search_kernel<E, 2, BT>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((sparse_search_kernel<E, 3, BT>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((sparse_search_kernel<E, 4, BT>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((sparse_search_kernel<E, 5, BT>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((sparse_search_kernel<E, 6, BT>), grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((sparse_search_kernel<E, 7, BT>), grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename E>
+static hipError_t search_l(const SparseSearchArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+    return binom_fits_32(a.t.D, a.t.L) ? search_lb<E, uint32_t>(a, grid, block, s)
+                                       : search_lb<E, uint64_t>(a, grid, block, s);
 }
 
 hipError_t launch_sparse_search(const SparseSearchArgs& a, hipStream_t s) {
