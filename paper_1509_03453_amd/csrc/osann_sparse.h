@@ -20,8 +20,9 @@ struct SparseTable {
     const uint32_t* hval;     // [hmask + 1] bucket number per slot
     uint64_t hmask;
     // One-hash bit filter in front of the table (no false negatives): bit
-    // (mix(id) >> 32) & fmask is set for every non-empty cone id.  At 16 or
-    // more bits per key it stays in L2 and answers most probes of empty cones.
+    // (mix(id) >> 32) & fmask is set for every non-empty cone id.  At 32 bits
+    // per key (at most 4 MB) it stays in L2 and answers most probes of empty
+    // cones (about 3% of them pass it).
     const uint64_t* filt;     // [(fmask + 1) / 64] words
     uint64_t fmask;
     const uint32_t* offsets;  // [n_ne + 1] first row position of each bucket
@@ -51,7 +52,7 @@ hipError_t launch_sparse_compact(const uint64_t* sorted, const uint32_t* flag, c
 // their filter of fbits bits (a power of two, 64 to 2^32).
 hipError_t launch_sparse_hash(const uint64_t* keys, int64_t n, uint64_t* hkeys, uint32_t* hval, uint64_t cap,
                               uint64_t* filt, uint64_t fbits, hipStream_t s);
-// Filter size for n keys: a power of two >= 16 n bits, from 2^12 to 2^25.
+// Filter size for n keys: a power of two >= 32 n bits, from 2^12 to 2^25.
 uint64_t sparse_filter_bits(int64_t n);
 
 // Search: walk (row budget, the first C cones, or at most kSparseWalkCap

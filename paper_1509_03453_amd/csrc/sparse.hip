@@ -334,7 +334,7 @@ hipError_t launch_sparse_compact(const uint64_t* sorted, const uint32_t* flag, c
 
 uint64_t sparse_filter_bits(int64_t n) {
     uint64_t bits = uint64_t(1) << 12;
-    while (bits < 16 * (uint64_t)(n > 0 ? n : 0) && bits < (uint64_t(1) << 25)) bits <<= 1;
+    while (bits < 32 * (uint64_t)(n > 0 ? n : 0) && bits < (uint64_t(1) << 25)) bits <<= 1;
     return bits;
 }
 
