@@ -21,7 +21,7 @@ struct SparseTable {
     uint64_t hmask;
     // One-hash bit filter in front of the table (no false negatives): bit
     // (mix(id) >> 32) & fmask is set for every non-empty cone id.  At 32 bits
-    // per key (at most 4 MB) it stays in L2 and answers most probes of empty
+    // per key (at most 4 MB) it stays in the caches and answers most probes of empty
     // cones (about 3% of them pass it).
     const uint64_t* filt;     // [(fmask + 1) / 64] words
     uint64_t fmask;
