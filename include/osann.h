@@ -365,6 +365,38 @@ void os_ann_free(os_ann_index *idx);
  * are not touched.  Never fails: returns OS_ANN_OK. */
 int os_ann_trim(void);
 
+/*
+ * Device memory from the caller's allocator.  The north star of this library
+ * has PyTorch supply device memory; the paper's problem statement (Section 2,
+ * eq. (1)) puts no constraint on where the index lives.
+ *
+ * alloc(bytes, stream, ctx) must return a block of at least `bytes` bytes of
+ * device memory on the current device, aligned to 256 bytes, usable by work
+ * enqueued on `stream` (the stream of the library call that asks; NULL is the
+ * null stream), or NULL when it can not.  free(ptr, stream, ctx) takes back a
+ * block with the stream it was asked for; the library calls it only once the
+ * device has finished every use of the block.
+ *
+ * Once set, every device allocation of the library goes through alloc:
+ * index memory (os_ann_free returns it), the index's own search scratch and
+ * low-precision copy, and the temporaries of builds, PCA and k-means.  A NULL
+ * from alloc makes the call fail with OS_ANN_ENOMEM after it has returned
+ * every block it obtained; an index built earlier stays usable.  A block not
+ * aligned to 256 bytes is handed back at once and the call fails with
+ * OS_ANN_ENOMEM.  Blocks always go back to the allocator that made them, even
+ * after the hook changes.  Passing NULL for both functions restores the
+ * library's own allocation (the HIP runtime behind an idle-block cache); one
+ * NULL and one function is EINVAL.  Setting a hook also returns the idle
+ * blocks of the library's own cache to the runtime.  Process-wide; not to be
+ * called while another library call is running.
+ *
+ * Caller-owned workspaces (os_ann_search_opts.workspace) never come from the
+ * hook: the caller allocates them.
+ */
+typedef void *(*os_ann_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*os_ann_free_fn)(void *ptr, void *stream, void *ctx);
+int os_ann_set_allocator(os_ann_alloc_fn alloc, os_ann_free_fn free, void *ctx);
+
 /* Last error code / message of the calling thread (OS_ANN_OK / "" if none). */
 int os_ann_last_error(void);
 const char *os_ann_last_error_message(void);

@@ -10,6 +10,7 @@ hashed, ``N_C = C(K,G) 2^G`` cones.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
 import os
 import subprocess
 import threading
@@ -18,18 +19,49 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "osann_oracle.c")
-_LIB = os.path.join(_HERE, "libosann_oracle.so")
 _lock = threading.Lock()
 _lib = None
 
 DTYPES = {np.dtype(np.float32): 0, np.dtype(np.float16): 1, np.dtype(np.uint8): 2}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def _host_tag() -> str:
+    # the library is compiled for the CPU it runs on (-march=native), so it
+    # is kept per CPU model and instruction-set flags
+    flags = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("flags"):
+                    flags = line
+                    break
+    except OSError:
+        pass
+    return hashlib.sha1((cpu_model() + flags).encode()).hexdigest()[:12]
+
+
+_LIB = os.path.join(_HERE, f"libosann_oracle.{_host_tag()}.so")
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (no fused or re-associated FP arithmetic)."""
+    """Compile the oracle with gcc for this host's CPU: -O3 -march=native,
+    no fused or re-associated FP arithmetic (-ffp-contract=off, no fast math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+        cmd = ["gcc", "-std=c11", "-O3", "-march=native", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)

@@ -43,6 +43,10 @@ class os_ann_search_opts(C.Structure):
                 ("workspace_bytes", C.c_int64)]
 
 
+# os_ann_alloc_fn / os_ann_free_fn of os_ann_set_allocator
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
 # name -> (restype, argtypes); every symbol include/osann.h declares.
 SIGNATURES = {
     "os_ann_build": (C.c_void_p, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32]),
@@ -77,6 +81,7 @@ SIGNATURES = {
                               C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "os_ann_free": (None, [C.c_void_p]),
     "os_ann_trim": (C.c_int, []),
+    "os_ann_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, C.c_void_p]),
     "os_ann_last_error": (C.c_int, []),
     "os_ann_last_error_message": (C.c_char_p, []),
     "os_ann_version": (C.c_char_p, []),
@@ -408,6 +413,53 @@ def os_ann_free(index: int) -> None:
 def os_ann_trim() -> None:
     """Hand the library's idle device blocks back to the HIP runtime."""
     lib().os_ann_trim()
+
+
+_hooks = None  # the ctypes callbacks in use (kept alive while the library holds them)
+
+
+def os_ann_set_allocator(alloc=None, free=None) -> None:
+    """Route the library's device allocations through ``alloc(nbytes,
+    stream_ptr) -> device pointer (int, 0 when out of memory)`` and
+    ``free(ptr, stream_ptr)``; ``None, None`` restores the library's own."""
+    global _hooks
+    if (alloc is None) != (free is None):
+        raise ValueError("give both functions or neither")
+    if alloc is None:
+        rc = lib().os_ann_set_allocator(C.cast(None, ALLOC_FN), C.cast(None, FREE_FN), None)
+        if rc:
+            _raise(rc)
+        _hooks = None
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0))) or None
+        except Exception:  # an exception must not cross the C boundary: report no memory
+            return None
+
+    def _free(ptr, stream, ctx):
+        try:
+            free(int(ptr), int(stream or 0))
+        except Exception:
+            pass
+
+    hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
+    rc = lib().os_ann_set_allocator(hooks[0], hooks[1], None)
+    if rc:
+        _raise(rc)
+    _hooks = hooks
+
+
+def use_torch_allocator() -> None:
+    """Let PyTorch's caching allocator own the library's device memory."""
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, torch.cuda.current_device(), stream)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    os_ann_set_allocator(alloc, free)
 
 
 def os_ann_last_error() -> int:

@@ -9,7 +9,10 @@
 //   nrm[p]         FP32 sum of squares of the rounded row (ascending component
 //                  order), NaN on padding rows
 //   ppos[p]        sorted position of the row (exact FP32 re-rank from the
-//                  planes; original id via perm), 0xFFFFFFFF on padding rows
+//                  planes), 0xFFFFFFFF on padding rows
+//   prow[p]        original row at padded position p, 0xFFFFFFFF on padding
+//                  rows (the screen orders equal d~ by original row)
+//   ipos[r]        padded position of original row r (inverse of prow)
 //   ne_id[c]       rank of cone c among the non-empty cones; ne_cone is its inverse
 #include "osann_device.h"
 #include "osann_kernels.h"
@@ -87,8 +90,10 @@ template <typename E>
 __global__ __launch_bounds__(256) void lowp_rows_kernel(const uint4* __restrict__ planes, int64_t N, int D, int nch,
                                                         const uint32_t* __restrict__ sorted_cone,
                                                         const uint32_t* __restrict__ off,
-                                                        const uint32_t* __restrict__ poff, int dk, int to_f16,
+                                                        const uint32_t* __restrict__ poff,
+                                                        const uint32_t* __restrict__ perm, int dk, int to_f16,
                                                         uint16_t* __restrict__ xl, uint32_t* __restrict__ ppos,
+                                                        uint32_t* __restrict__ prow, uint32_t* __restrict__ ipos,
                                                         float* __restrict__ nrm) {
 #pragma clang fp contract(off)
     constexpr int EPC = Unpack<E>::n;             // components per 16-byte chunk of the planes
@@ -142,7 +147,10 @@ __global__ __launch_bounds__(256) void lowp_rows_kernel(const uint4* __restrict_
                 }
             }
         }
+        const uint32_t r = perm[pos];
         ppos[p] = (uint32_t)pos;
+        prow[p] = r;
+        ipos[r] = (uint32_t)p;
         nrm[p] = acc;
     } else {
         s_p[threadIdx.x] = -1;
@@ -157,11 +165,13 @@ __global__ __launch_bounds__(256) void lowp_rows_kernel(const uint4* __restrict_
 }
 
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
-                            const uint32_t* offsets, const uint32_t* poff, int dk, int to_f16, uint16_t* xl,
-                            uint32_t* ppos, float* nrm, int64_t np_total, hipStream_t s) {
+                            const uint32_t* offsets, const uint32_t* poff, const uint32_t* perm, int dk, int to_f16,
+                            uint16_t* xl, uint32_t* ppos, uint32_t* prow, uint32_t* ipos, float* nrm,
+                            int64_t np_total, hipStream_t s) {
     // padding rows: zero components, no position, NaN norm (fails every comparison)
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(xl), np_total * dk / 2, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32(ppos, np_total, 0xFFFFFFFFu, s);
+    if (e == hipSuccess) e = launch_fill_u32(prow, np_total, 0xFFFFFFFFu, s);
     if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(nrm), np_total, 0x7FC00000u, s);
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((N + 255) / 256));
@@ -173,19 +183,19 @@ hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int
             e = hipFuncSetAttribute((const void*)lowp_rows_kernel<F32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(lowp_rows_kernel<F32>, grid, dim3(256), lds, s, pl, N, D, nch, sorted_cone, offsets,
-                               poff, dk, to_f16, xl, ppos, nrm);
+                               poff, perm, dk, to_f16, xl, ppos, prow, ipos, nrm);
             break;
         case kF16:
             e = hipFuncSetAttribute((const void*)lowp_rows_kernel<F16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(lowp_rows_kernel<F16>, grid, dim3(256), lds, s, pl, N, D, nch, sorted_cone, offsets,
-                               poff, dk, to_f16, xl, ppos, nrm);
+                               poff, perm, dk, to_f16, xl, ppos, prow, ipos, nrm);
             break;
         case kU8:
             e = hipFuncSetAttribute((const void*)lowp_rows_kernel<U8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(lowp_rows_kernel<U8>, grid, dim3(256), lds, s, pl, N, D, nch, sorted_cone, offsets,
-                               poff, dk, to_f16, xl, ppos, nrm);
+                               poff, perm, dk, to_f16, xl, ppos, prow, ipos, nrm);
             break;
         default:
             return hipErrorInvalidValue;

@@ -70,6 +70,8 @@ struct LowpCopy {
     uint16_t* xl = nullptr;
     float* nrm = nullptr;
     uint32_t* ppos = nullptr;
+    uint32_t* prow = nullptr;  // original row of each padded row
+    uint32_t* ipos = nullptr;  // padded position of each original row
 };
 
 struct GraphEntry {
@@ -161,6 +163,29 @@ BlockCache& block_cache() {
     static BlockCache* c = new BlockCache;  // never destroyed: blocks live until the process ends
     return *c;
 }
+
+// Caller-supplied allocator (os_ann_set_allocator).  Blocks it hands out are
+// recorded with the hook that made them and the stream they were asked for,
+// and go back to that hook, never to the idle cache.
+struct Hook {
+    os_ann_alloc_fn alloc = nullptr;
+    os_ann_free_fn free = nullptr;
+    void* ctx = nullptr;
+};
+struct HookedBlock {
+    Hook hook;
+    void* stream;
+};
+Hook g_hook;                                         // guarded by block_cache().mu
+std::unordered_map<void*, HookedBlock> g_hooked;     // guarded by block_cache().mu
+thread_local hipStream_t t_stream = nullptr;         // stream of the calling entry point
+
+// Sets the stream an entry point's allocations are made for, for its scope.
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s) : prev(t_stream) { t_stream = s; }
+    ~StreamScope() { t_stream = prev; }
+};
 constexpr size_t kIdleMax = size_t(8) << 30;  // idle bytes kept at most (all devices)
 
 size_t block_size(size_t bytes) { return bytes > (size_t(1) << 20) ? align_up(bytes, size_t(2) << 20) : align_up(bytes, 256); }
@@ -207,7 +232,15 @@ hipError_t cached_malloc(void** p, size_t bytes) {
 void dev_free(void* p) {
     if (!p) return;
     BlockCache& c = block_cache();
-    std::lock_guard<std::mutex> g(c.mu);
+    std::unique_lock<std::mutex> g(c.mu);
+    auto hk = g_hooked.find(p);
+    if (hk != g_hooked.end()) {
+        const HookedBlock b = hk->second;
+        g_hooked.erase(hk);
+        g.unlock();  // the hook may call back into the runtime
+        b.hook.free(p, b.stream, b.hook.ctx);
+        return;
+    }
     auto it = c.owned.find(p);
     if (it == c.owned.end()) {
         (void)hipFree(p);
@@ -226,6 +259,26 @@ void dev_free(void* p) {
 int dev_alloc(os_ann_index* ix, void** p, size_t bytes, const char* what) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
+    Hook h;
+    {
+        std::lock_guard<std::mutex> g(block_cache().mu);
+        h = g_hook;
+    }
+    if (h.alloc) {
+        void* q = h.alloc(bytes, static_cast<void*>(t_stream), h.ctx);
+        if (!q) return fail(OS_ANN_ENOMEM, std::string(what) + ": the allocator hook returned NULL");
+        if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {
+            h.free(q, static_cast<void*>(t_stream), h.ctx);
+            return fail(OS_ANN_ENOMEM, std::string(what) + ": the allocator hook returned a block not aligned to 256 bytes");
+        }
+        {
+            std::lock_guard<std::mutex> g(block_cache().mu);
+            g_hooked[q] = {h, static_cast<void*>(t_stream)};
+        }
+        *p = q;
+        if (ix) ix->device_bytes += bytes;
+        return OS_ANN_OK;
+    }
     hipError_t e = cached_malloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
@@ -256,7 +309,7 @@ void release(os_ann_index* ix, bool synced = false) {
     void* ptrs[] = {ix->row_cone, ix->row_top,  ix->perm,       ix->sorted_cone, ix->offsets,
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
-                    ix->lp.ppos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
+                    ix->lp.ppos,  ix->lp.prow,  ix->lp.ipos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
                     ix->planes_tab, ix->proj_mu, ix->proj_P, ix->ivf_cent, ix->rot_signs,
                     ix->sp_keys, ix->sp_hkeys, ix->sp_hval, ix->sp_filt, ix->binom64};
     for (void* p : ptrs) dev_free(p);
@@ -285,17 +338,27 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
     lp.dk = (int)align_up((size_t)ix->D, 32);
     lp.f16 = ix->dtype == kF16;
     uint32_t* tmp = nullptr;
+    const size_t bytes0 = ix->device_bytes;
+    // on failure every block of the copy goes back, so a later call starts afresh
+    auto done = [&](int code) {
+        if (code != OS_ANN_OK) {
+            (void)hipDeviceSynchronize();
+            for (void** q : {(void**)&lp.poff, (void**)&lp.ne_id, (void**)&lp.ne_cone, (void**)&lp.xl,
+                             (void**)&lp.nrm, (void**)&lp.ppos, (void**)&lp.prow, (void**)&lp.ipos}) {
+                dev_free(*q);
+                *q = nullptr;
+            }
+            ix->device_bytes = bytes0;
+        }
+        dev_free(tmp);
+        return code;
+    };
     const int64_t scan_words = exclusive_scan_tmp_words(nc);
     int rc = dev_alloc(ix, (void**)&lp.poff, (size_t)(nc + 1) * 4, "poff");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.ne_id, (size_t)(nc + 1) * 4, "ne_id");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.ne_cone, (size_t)nc * 4, "ne_cone");
     if (!rc) rc = dev_alloc(nullptr, (void**)&tmp, (size_t)(2 * nc + scan_words) * 4, "lowp scratch");
-    if (rc) return rc;
-    auto done = [&](int code) {
-        if (code != OS_ANN_OK) (void)hipDeviceSynchronize();
-        dev_free(tmp);
-        return code;
-    };
+    if (rc) return done(rc);
     hipError_t e = launch_lowp_layout(ix->offsets, nc, tmp, tmp + nc, tmp + 2 * nc, lp.poff, lp.ne_id,
                                       lp.ne_cone, s);
     uint32_t np32 = 0;
@@ -307,9 +370,11 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
     rc = dev_alloc(ix, (void**)&lp.xl, (size_t)rows * lp.dk * 2, "xl");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.nrm, (size_t)rows * 4, "nrm");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.ppos, (size_t)rows * 4, "ppos");
+    if (!rc) rc = dev_alloc(ix, (void**)&lp.prow, (size_t)rows * 4, "prow");
+    if (!rc) rc = dev_alloc(ix, (void**)&lp.ipos, (size_t)ix->N * 4, "ipos");
     if (rc) return done(rc);
     e = launch_lowp_rows(ix->planes, ix->dtype, ix->N, ix->D, ix->nch, ix->sorted_cone, ix->offsets, lp.poff,
-                             lp.dk, lp.f16, lp.xl, lp.ppos, lp.nrm, rows, s);
+                         ix->perm, lp.dk, lp.f16, lp.xl, lp.ppos, lp.prow, lp.ipos, lp.nrm, rows, s);
     if (e == hipSuccess) e = tiled_screen_max_lds();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return done(hip_fail(e, "low-precision copy"));
@@ -789,7 +854,7 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     ta.xl = ix->lp.xl;
     ta.dk = ix->lp.dk;
     ta.nrm = ix->lp.nrm;
-    ta.ppos = ix->lp.ppos;
+    ta.prow = ix->lp.prow;
     ta.poff = ix->lp.poff;
     ta.offsets = ix->offsets;
     ta.ne_id = ix->lp.ne_id;
@@ -837,7 +902,7 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     fa.N = ix->N;
     fa.nch = ix->nch;
     fa.ppos = ix->lp.ppos;
-    fa.perm = ix->perm;
+    fa.ipos = ix->lp.ipos;
     fa.yf = pa.yf;
     fa.dpad = p.dpad;
     // the codes hold FP16 rows and uint8 rows exactly (FP32 rows: planes)
@@ -1445,6 +1510,7 @@ os_ann_index* build_bases(const void* db, int64_t N, int32_t D, int32_t L, const
     clear_error();
     const int32_t dtype = opts ? opts->dtype : kF32;
     hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    StreamScope ss(s);
     int64_t nc = 0;
     if (!db || !basis) {
         fail(OS_ANN_EINVAL, "null db or bases");
@@ -1550,6 +1616,7 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L, c
     clear_error();
     const int32_t dtype = opts ? opts->dtype : kF32;
     hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    StreamScope ss(s);
     int64_t nc = 0;
     if (!db) {
         fail(OS_ANN_EINVAL, "null db");
@@ -1590,6 +1657,7 @@ int os_ann_pca(const void* db, int64_t N, int32_t D, int32_t k, const os_ann_bui
     clear_error();
     const int32_t dtype = opts ? opts->dtype : kF32;
     hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    StreamScope ss(s);
     if (!db || !mean_out || !basis_out) return fail(OS_ANN_EINVAL, "null db or output");
     if (!dtype_ok(dtype)) return fail(OS_ANN_EINVAL, "bad db dtype");
     if (N < 1 || N >= (int64_t(1) << 31)) return fail(OS_ANN_EINVAL, "N must be in [1, 2^31)");
@@ -1641,6 +1709,7 @@ os_ann_index* os_ann_build_proj(const void* db, int64_t N, int32_t D, int32_t L,
     clear_error();
     const int32_t dtype = opts ? opts->dtype : kF32;
     hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    StreamScope ss(s);
     int64_t nc = 0, nc_rows = 0;
     if (!db || !basis) {
         fail(OS_ANN_EINVAL, "null db or basis");
@@ -1695,6 +1764,7 @@ int os_ann_kmeans(const void* db, int64_t N, int32_t D, int32_t C, int32_t iters
     clear_error();
     const int32_t dtype = opts ? opts->dtype : kF32;
     hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    StreamScope ss(s);
     if (!db || !init || !out) return fail(OS_ANN_EINVAL, "null db, init or out");
     if (!dtype_ok(dtype)) return fail(OS_ANN_EINVAL, "bad db dtype");
     if (N < 1 || N >= (int64_t(1) << 31)) return fail(OS_ANN_EINVAL, "N must be in [1, 2^31)");
@@ -1737,6 +1807,7 @@ os_ann_index* os_ann_build_ivf(const void* db, int64_t N, int32_t D, int32_t L, 
     clear_error();
     const int32_t dtype = opts ? opts->dtype : kF32;
     hipStream_t s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    StreamScope ss(s);
     int64_t nc = 0;
     if (!db || !centroids) {
         fail(OS_ANN_EINVAL, "null db or centroids");
@@ -1826,6 +1897,20 @@ int os_ann_trim(void) {
     return OS_ANN_OK;
 }
 
+int os_ann_set_allocator(os_ann_alloc_fn alloc, os_ann_free_fn free_fn, void* ctx) {
+    clear_error();
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(OS_ANN_EINVAL, "set_allocator: give both functions or neither");
+    {
+        std::lock_guard<std::mutex> g(block_cache().mu);
+        g_hook.alloc = alloc;
+        g_hook.free = free_fn;
+        g_hook.ctx = alloc ? ctx : nullptr;
+    }
+    if (alloc) trim_blocks();  // idle blocks of the library's own are not needed any more
+    return OS_ANN_OK;
+}
+
 int64_t os_ann_workspace_bytes(const os_ann_index* idx, int64_t Q, int64_t max_candidates,
                                const os_ann_search_opts* opts) {
     clear_error();
@@ -1863,6 +1948,7 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     c.out_dist = out_dist;
     c.out_ncand = out_ncand;
     c.s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    StreamScope ss(c.s);
     c.timing = opts && (opts->flags & OS_ANN_FLAG_TIME_KERNELS);
     const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;

@@ -22,7 +22,7 @@ struct TiledArgs {
     const uint16_t* xl;
     int dk;
     const float* nrm;
-    const uint32_t* ppos;   // sorted position of each padded row (0xFFFFFFFF: padding)
+    const uint32_t* prow;   // original row of each padded row (0xFFFFFFFF: padding)
     const uint32_t* poff;
     const uint32_t* offsets;
     const uint32_t* ne_id;
@@ -51,7 +51,7 @@ struct TiledArgs {
     int64_t span;           // non-empty cones per split (multiple of 64)
     uint32_t* counter;      // [kXcd] work-queue heads, zero before the launch
     // output
-    uint2* part;            // [Q][S][R] (FP32 bits of d~, padded position)
+    uint2* part;            // [Q][S][R] (FP32 bits of d~, original row), ascending
     uint32_t* cmin;         // [R][Q] by tile slot: smallest order-preserving d~ bits kept per class
                             // (padded position mod R), 0xFFFFFFFF before the launch
 };
@@ -79,8 +79,8 @@ struct FinishArgs {
     int dtype;
     int64_t N;
     int nch;
-    const uint32_t* ppos;
-    const uint32_t* perm;
+    const uint32_t* ppos;   // sorted position of each padded row
+    const uint32_t* ipos;   // padded position of each original row
     const float* yf;
     int dpad;
     // Row-major low-precision copy ([padded position][dk] codes) where it
@@ -100,8 +100,9 @@ hipError_t launch_lowp_layout(const uint32_t* offsets, int64_t n_cones, uint32_t
                               uint32_t* scan_tmp, uint32_t* poff, uint32_t* ne_id, uint32_t* ne_cone,
                               hipStream_t s);
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
-                            const uint32_t* offsets, const uint32_t* poff, int dk, int to_f16, uint16_t* xl,
-                            uint32_t* ppos, float* nrm, int64_t np_total, hipStream_t s);
+                            const uint32_t* offsets, const uint32_t* poff, const uint32_t* perm, int dk, int to_f16,
+                            uint16_t* xl, uint32_t* ppos, uint32_t* prow, uint32_t* ipos, float* nrm,
+                            int64_t np_total, hipStream_t s);
 hipError_t launch_tiled_screen(const TiledArgs& a, int R, int G, int f16in, int blocks, hipStream_t s);
 size_t tiled_screen_lds();                      // dynamic LDS bytes of one screen block
 size_t tiled_screen_static_lds(int R, int G);          // static LDS bytes (upper bound) of one screen block

@@ -15,11 +15,12 @@
 // of the rounded vectors.  No wave waits for another: a wave only
 // reads the cones its own queries probe.
 //
-// Each query keeps, per split, a top-R list of (d~, padded position) in
-// LDS.  The tile loop only compares d~ with a per-query bound; the few
-// candidates at or below it go to a per-wave hit buffer, which is merged
-// into the lists (one lane per query) when it fills and at the end of the
-// item.
+// Each query keeps, per split, a top-R list of (d~, original row) in LDS,
+// the order the exact definition of the screen uses, so equal d~ resolve to
+// the lower original row.  The tile loop only compares d~ with a per-query
+// bound; the few candidates at or below it go to a per-wave hit buffer,
+// which is merged into the lists (one lane per query) when it fills and at
+// the end of the item.
 //
 // Pruning: a candidate whose d~ exceeds an upper bound of the query's final
 // R-th value can never be kept.  Two bounds are used: the R-th entry of the
@@ -33,7 +34,7 @@
 //
 // A finishing pass merges the S split lists, recomputes the exact FP32
 // distance of the R survivors and keeps the arg-min on (distance, row).
-// Lists are kept in the total order (d~, position), so results do not
+// Lists are kept in the total order (d~, original row), so results do not
 // depend on the order of the tiles or on the split.
 #include "osann_device.h"
 #include "osann_kernels.h"
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
     constexpr int U = KS <= 2 ? 2 : 1;      // row tiles per load group
     extern __shared__ uint64_t dyn[];
     __shared__ uint2 s_list[4][QW * R];     // per wave: top-R list of each query slot
-    __shared__ uint4 s_hit[4][kHitCap];     // per wave: (d~ bits, padded position, slot) hits
+    __shared__ uint4 s_hit[4][kHitCap];     // per wave: (d~ bits, padded position, slot, original row) hits
     const int w = threadIdx.x / 64, l = lane_id();
     // Work queue of this block's chiplet (blocks are dealt to the kXcd chiplets
     // in turn, and each has its own L2): with 8 splits or more, chiplet x
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                                        : make_uint4(0, 0, 0, 0);
         }
         // The split's top-R list of every query of the tile lives in LDS
-        // (wl[slot][k], ascending (d~, padded position)); lane l owns slot l
+        // (wl[slot][k], ascending (d~, original row)); lane l owns slot l
         // when lists are updated.  Candidates that pass the bound go to a hit
         // buffer first and are merged in bulk, which keeps the tile loop free
         // of list code.
@@ -217,8 +218,12 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
             for (int g = 0; g < G; ++g) thr[g] = __shfl(ob, 16 * g + (l % 16), 64);
         };
         refresh_thr();
-        // merge the hit buffer into the lists: lane l takes the hits of slot l
+        // merge the hit buffer into the lists: first every lane looks up the
+        // original rows of up to one hit (one parallel gather), then lane l
+        // takes the hits of slot l
         auto flush = [&]() {
+            wave_sync();
+            if ((uint32_t)l < nhit) s_hit[w][l].w = a.prow[s_hit[w][l].y];
             wave_sync();
             float ld[R];
             uint32_t lr[R];
@@ -232,8 +237,8 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
             for (uint32_t h = 0; h < nhit; ++h) {
                 const uint4 e = s_hit[w][h];
                 const float d = __uint_as_float(e.x);
-                if (e.z == (uint32_t)l && pair_less(d, e.y, ld[R - 1], lr[R - 1])) {
-                    list_insert<R>(ld, lr, d, e.y);
+                if (e.z == (uint32_t)l && pair_less(d, e.w, ld[R - 1], lr[R - 1])) {
+                    list_insert<R>(ld, lr, d, e.w);
                     changed = true;
                     __hip_atomic_fetch_min(a.cmin + (int64_t)(e.y & (R - 1)) * a.Q + own_slot, ord_bits(d),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -562,7 +567,7 @@ __device__ inline float code_row_dist_fp32(const uint16_t* __restrict__ xl, int 
 }
 
 // One group of G lanes per query: merge the S split lists (ordered by
-// (d~, padded position)), re-rank the R survivors with the exact FP32
+// (d~, original row)), re-rank the R survivors with the exact FP32
 // distance, arg-min on (distance, original row).
 template <typename E, int R, int G>
 __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
@@ -589,16 +594,17 @@ __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
     }
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) merge_with<R>(ld, lr, m);
-    uint32_t cp = 0xFFFFFFFFu;
+    uint32_t row = 0xFFFFFFFFu;
 #pragma unroll
     for (int k = 0; k < R; ++k)
-        if (k == g) cp = lr[k];
+        if (k == g) row = lr[k];
     float cd = __builtin_huge_valf();
     uint32_t cr = 0xFFFFFFFFu;
-    if (qv && cp != 0xFFFFFFFFu) {
+    if (qv && row != 0xFFFFFFFFu) {
+        const uint32_t cp = f.ipos[row];
         const uint32_t pos = f.ppos[cp];
         if (pos != 0xFFFFFFFFu) {  // a padding row never enters a list; checked anyway
-            cr = f.perm[pos];
+            cr = row;
             const float* y = f.yf + q * f.dpad;
             if (f.xl_codes == 1)
                 cd = code_row_dist_fp32<true>(f.xl, f.dk, cp, f.dpad, y);

@@ -18,3 +18,17 @@ def orc():
     from oracle import oracle
     oracle.build()
     return oracle
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Mismatch rates of the screened (tiled) comparisons against the oracle."""
+    mod = sys.modules.get("tests.gpu_util")
+    rows = getattr(mod, "MISMATCHES", None) if mod else None
+    if not rows:
+        return
+    bad = sum(r[1] for r in rows)
+    tot = sum(r[2] for r in rows)
+    terminalreporter.write_line(f"screened comparisons: {len(rows)}, rows differing from the oracle "
+                                f"{bad}/{tot} ({bad / max(tot, 1):.4%}); worst:")
+    for tag, b, t in sorted(rows, key=lambda r: -r[1] / max(r[2], 1))[:8]:
+        terminalreporter.write_line(f"  {tag}: {b}/{t}")

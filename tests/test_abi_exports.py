@@ -48,3 +48,17 @@ def test_version_and_error_state_without_gpu():
     assert binding.lib().os_ann_build(None, 10, 4, 1) is None
     assert binding.os_ann_last_error() == binding.OS_ANN_EINVAL
     assert binding.lib().os_ann_workspace_bytes(None, 1, 1, None) == binding.OS_ANN_EINVAL
+
+
+def test_set_allocator_host_checks():
+    # argument checks of os_ann_set_allocator happen on the host
+    from paper_1509_03453_amd import binding as B
+    L = B.lib()
+    alloc = B.ALLOC_FN(lambda n, s, c: None)
+    free = B.FREE_FN(lambda p, s, c: None)
+    assert L.os_ann_set_allocator(alloc, ctypes.cast(None, B.FREE_FN), None) == B.OS_ANN_EINVAL
+    assert L.os_ann_set_allocator(ctypes.cast(None, B.ALLOC_FN), free, None) == B.OS_ANN_EINVAL
+    assert L.os_ann_set_allocator(alloc, free, None) == B.OS_ANN_OK
+    assert L.os_ann_set_allocator(ctypes.cast(None, B.ALLOC_FN), ctypes.cast(None, B.FREE_FN), None) == B.OS_ANN_OK
+    with pytest.raises(ValueError):
+        B.os_ann_set_allocator(lambda n, s: 0, None)

@@ -15,7 +15,7 @@ import torch
 
 from paper_1509_03453_amd import binding as B
 from paper_1509_03453_amd import workloads as W
-from tests.gpu_util import dev, say
+from tests.gpu_util import check_screened, dev, say
 
 pytestmark = pytest.mark.gpu
 U = 2.0 ** -24
@@ -42,27 +42,7 @@ def same_fp32(g, o, tag):
 
 
 def same_tiled(orc, X, Y, g, o, tag, max_mismatch=0.02):
-    gi, gd, gn = g
-    oi, od32, od64, on, dtr, top = o
-    assert np.array_equal(gn, on), tag
-    empty = on == 0
-    assert (gi[empty] == -1).all() and np.isinf(gd[empty]).all(), tag
-    full = np.flatnonzero(~empty)
-    assert np.array_equal(gd[full].view(np.uint32), orc.pair_d32(X, Y[full], gi[full]).view(np.uint32)), tag
-    f16 = X.dtype == np.float16
-    D = X.shape[1]
-    bad = [q for q in full if gi[q] != oi[q]]
-    for q in bad:
-        xs = orc.round_short(X[[gi[q], oi[q], top[q][-1]]].astype(np.float32), f16).reshape(3, D)
-        ys = orc.round_short(Y[q].astype(np.float32), f16)
-        tol = 4 * (D + 2) * U * ((xs ** 2).sum(1) + 2 * np.abs(xs * ys).sum(1)).max()
-        dg = orc.pair_dtilde(X, Y[q:q + 1], [gi[q]], f16)[0]
-        do = orc.pair_dtilde(X, Y[q:q + 1], [oi[q]], f16)[0]
-        if gi[q] in top[q]:
-            assert do >= dtr[q] - tol, (tag, q)
-        else:
-            assert dg <= dtr[q] + tol, (tag, q)
-    assert len(bad) <= max_mismatch * len(full) + 1, (tag, len(bad))
+    check_screened(orc, X, Y, g, o, tag, max_mismatch=max_mismatch)
 
 
 @pytest.mark.parametrize("kind", ["gauss", "desc", "patch"])

@@ -15,7 +15,7 @@ import torch
 
 from paper_1509_03453_amd import binding as B
 from paper_1509_03453_amd import workloads as W
-from tests.gpu_util import dev, gpu_search, say
+from tests.gpu_util import check_screened, dev, gpu_search, say
 
 pytestmark = pytest.mark.gpu
 U = 2.0 ** -24
@@ -31,8 +31,6 @@ def check_tiled(orc, X, Y, L, budgets, R=8, tag="", max_mismatch=0.02):
     say(f"[tiled] {tag} N={X.shape[0]} D={X.shape[1]} L={L} Q={Y.shape[0]} R={R} dtype={X.dtype}")
     h = B.os_ann_build_ex(dev(X), L)
     o = orc.build_index(X, L)
-    f16 = X.dtype == np.float16
-    D = X.shape[1]
     try:
         for budget in budgets:
             say(f"[tiled] {tag} budget={budget}")
@@ -40,25 +38,8 @@ def check_tiled(orc, X, Y, L, budgets, R=8, tag="", max_mismatch=0.02):
             torch.cuda.synchronize()
             gi, gd, gn = gi.cpu().numpy(), gd.cpu().numpy(), gn.cpu().numpy()
             oi, od32, od64, on, dtr, top = orc.search_tiled(X, o, Y, budget, R=R)
-            assert np.array_equal(gn, on), tag
-            assert (gi >= 0).all() and (gi < X.shape[0]).all()
-            # the reported distance is the exact FP32 distance of the reported row
-            assert np.array_equal(gd.view(np.uint32), orc.pair_d32(X, Y, gi).view(np.uint32)), tag
-            bad = np.flatnonzero(gi != oi)
-            for q in bad:
-                xs = orc.round_short(X[[gi[q], oi[q], top[q][-1]]].astype(np.float32), f16).reshape(3, D)
-                ys = orc.round_short(Y[q].astype(np.float32), f16)
-                scale = ((xs ** 2).sum(1) + 2 * np.abs(xs * ys).sum(1)).max()
-                tol = 4 * (D + 2) * U * scale
-                t = dtr[q]
-                dg = orc.pair_dtilde(X, Y[q:q + 1], [gi[q]], f16)[0]
-                do = orc.pair_dtilde(X, Y[q:q + 1], [oi[q]], f16)[0]
-                if gi[q] in top[q]:
-                    assert do >= t - tol, (tag, q, "oracle's pick dropped without a near tie")
-                else:
-                    assert dg <= t + tol, (tag, q, "GPU kept a row beyond the R-th d~")
-            assert len(bad) <= max_mismatch * len(gi) + 1, (tag, len(bad))
-            say(f"[tiled] {tag} budget={budget} mismatches={len(bad)}/{len(gi)}")
+            check_screened(orc, X, Y, (gi, gd, gn), (oi, od32, od64, on, dtr, top), (tag, budget),
+                           max_mismatch=max_mismatch)
     finally:
         B.os_ann_free(h)
 
