@@ -118,6 +118,10 @@ typedef struct os_ann_search_opts {
     void *workspace;      /* optional caller-owned device scratch, >= os_ann_workspace_bytes;
                              NULL: the index's own scratch (not for concurrent calls) */
     int64_t workspace_bytes;
+    int64_t *walks_capped;  /* optional device int64: sparse tables only, set to the number of
+                               walks the 2^22-position cap stopped (a row budget not met
+                               although cones remained, or a C beyond the cap); ignored
+                               (left untouched) for other tables */
 } os_ann_search_opts;
 
 /*

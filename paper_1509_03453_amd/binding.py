@@ -40,7 +40,7 @@ class os_ann_build_opts(C.Structure):
 class os_ann_search_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("rerank_r", C.c_int32), ("query_dtype", C.c_int32),
                 ("flags", C.c_int32), ("stream", C.c_void_p), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_int64)]
+                ("workspace_bytes", C.c_int64), ("walks_capped", C.c_void_p)]
 
 
 # os_ann_alloc_fn / os_ann_free_fn of os_ann_set_allocator
@@ -251,11 +251,13 @@ def os_ann_set_nprobe(index: int, nprobe: int) -> None:
         _raise(rc)
 
 
-def _search_opts(queries, mode, stream, workspace, rerank_r=8, flags=0):
+def _search_opts(queries, mode, stream, workspace, rerank_r=8, flags=0, walks_capped=None):
     qt = _check_rows(queries, "queries") if queries is not None else OS_ANN_F32
     ws = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    if walks_capped is not None and (walks_capped.dtype != torch.int64 or not walks_capped.is_cuda):
+        raise ValueError("walks_capped must be a GPU int64 tensor")
     return os_ann_search_opts(int(mode), int(rerank_r), qt, int(flags), _stream_ptr(stream),
-                              _ptr(workspace), int(ws))
+                              _ptr(workspace), int(ws), _ptr(walks_capped))
 
 
 def os_ann_search(index: int, queries: torch.Tensor, max_candidates: int,
@@ -279,13 +281,14 @@ def os_ann_search(index: int, queries: torch.Tensor, max_candidates: int,
 def os_ann_search_ex(index: int, queries: torch.Tensor, max_candidates: int, mode: int = OS_ANN_MODE_FP32,
                      stream=None, workspace: torch.Tensor | None = None, rerank_r: int = 8,
                      out_idx=None, out_dist=None, out_ncand=None, want_ncand: bool = True,
-                     flags: int = 0, cones: bool = False):
+                     flags: int = 0, cones: bool = False, walks_capped: torch.Tensor | None = None):
     """As os_ann_search with options; returns ``(idx, dist, ncand or None)``.
     ``cones``: max_candidates is the number C of cones each walk takes
-    (OS_ANN_FLAG_BUDGET_CONES)."""
+    (OS_ANN_FLAG_BUDGET_CONES).  ``walks_capped`` (one GPU int64, sparse
+    tables): receives the number of walks the position cap stopped."""
     if cones:
         flags |= OS_ANN_FLAG_BUDGET_CONES
-    o = _search_opts(queries, mode, stream, workspace, rerank_r, flags)
+    o = _search_opts(queries, mode, stream, workspace, rerank_r, flags, walks_capped)
     Q = queries.shape[0]
     dev = queries.device
     out_idx = torch.empty(Q, dtype=torch.int64, device=dev) if out_idx is None else out_idx

@@ -376,6 +376,7 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
     e = launch_lowp_rows(ix->planes, ix->dtype, ix->N, ix->D, ix->nch, ix->sorted_cone, ix->offsets, lp.poff,
                          ix->perm, lp.dk, lp.f16, lp.xl, lp.ppos, lp.prow, lp.ipos, lp.nrm, rows, s);
     if (e == hipSuccess) e = tiled_screen_max_lds();
+    if (e == hipSuccess) e = cone_screen_max_lds();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return done(hip_fail(e, "low-precision copy"));
     lp.ready = true;
@@ -393,6 +394,8 @@ struct SearchPlan {
     // tiled mode
     int dk = 0, smin = 1, smax = 1, mq = 0, G = 4;  // G: MFMA B groups per wave tile
     int qkey = 0;                                   // query order of the wave tiles (launch_query_key mode)
+    int kern = 0;                                   // screen kernel: 0 query tiles x cone splits, 1 cone-major
+    bool cone_ok = false;                           // the cone-major screen applies (bitmaps, dk, list memory)
     int64_t T = 0, nw = 0;
     bool bitmap = false, fits = true;
     size_t off_ql = 0, off_qcone = 0, off_sort = 0, off_qorder = 0, off_qsorted = 0, off_part = 0,
@@ -486,13 +489,15 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         const int64_t mean_bucket = std::max<int64_t>(1, ix->N / ne);
         const int64_t probes = cones ? std::min<int64_t>(budget, ne) : std::min<int64_t>(budget, ix->N) / mean_bucket + 1;
         p.bitmap = probes >= 32 && p.nw <= 512 && (size_t)Q * p.nw * 8 <= ((size_t)1 << 30);
+        // the cone-major screen keeps one top-R list per (query, 64-cone word)
+        p.cone_ok = p.bitmap && cone_screen_ok(p.dk, R) && (size_t)Q * p.nw * R * 8 <= ((size_t)1 << 30);
         p.off_ql = take((size_t)Q * p.dk * 2);
         p.off_qcone = take((size_t)Q * 4);
         p.off_sort = take((size_t)(4 * Q + radix_hist_words(Q)) * 4);
         p.off_qorder = take((size_t)Q * 4);
         p.off_qkey = take((size_t)Q * 4);
         p.off_qsorted = take((size_t)Q * 4);
-        p.off_part = take((size_t)Q * p.smax * R * 8);
+        p.off_part = take((size_t)Q * (p.cone_ok ? std::max<int64_t>(p.smax, p.nw) : p.smax) * R * 8);
         p.off_counter = take(256);
         p.off_cmin = take((size_t)Q * R * 4);
         if (p.bitmap) p.off_qbits = take((size_t)Q * p.nw * 8);
@@ -636,6 +641,7 @@ struct Call {
     int64_t* out_idx;
     float* out_dist;
     int64_t* out_ncand;
+    int64_t* walks_capped;  // sparse tables: capped walks counted here (may be null)
     char* base;
     SearchPlan p;
     bool timing;
@@ -839,15 +845,24 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     sd.poff = ix->lp.poff;
     sd.dk = ix->lp.dk;
     sd.ql = pa.ql;
-    sd.q_cone = pa.q_cone;
     sd.qorder = qorder;
     sd.Q = c.Q;
     sd.cmin = cmin;
-    // The seed reads up to sd.rows rows of each query's own cone; keep that
-    // near a sixteenth of the budget (16 .. 256 rows), a small share of what
-    // the screen then reads per query.
+    sd.order = pa.order;
+    sd.sbit = pa.sbit;
+    sd.jstop = pa.jstop;
+    sd.lexsub = ix->lexsub;
+    sd.maskord = ix->maskord;
+    sd.binom = ix->binom;
+    sd.n_sub = ix->n_sub;
+    sd.n_cones = ix->n_cones;
+    sd.D = ix->Dk;  // the walk state's length
+    sd.L = ix->L;
+    // The seed reads up to sd.rows padded rows from the first cones of each
+    // query's walk; keep that near a sixteenth of the budget (64 .. 1024
+    // rows), a small share of what the screen then reads per query.
     const int64_t rows = expected_rows(ix, c.budget, p.cones);
-    sd.rows = (int)std::min<int64_t>(256, std::max<int64_t>(16, pow2_ceil(std::max<int64_t>(rows / 16, 1))));
+    sd.rows = (int)std::min<int64_t>(1024, std::max<int64_t>(64, pow2_ceil(std::max<int64_t>(rows / 16, 1))));
     e = launch_tiled_seed(sd, p.R, ix->lp.f16, c.s);
     if (e != hipSuccess) return e;
     TiledArgs ta{};
@@ -890,12 +905,18 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     if (std::getenv("OSANN_VERBOSE"))
         std::fprintf(stderr, "[osann] tiled Q=%lld T=%lld G=%d S=%d span=%lld lds=%zu occ=%d blocks=%d bitmap=%d R=%d\n",
                      (long long)c.Q, (long long)p.T, p.G, S, (long long)ta.span, lds, occ, blocks, (int)p.bitmap, p.R);
-    e = timed_launch(ix, c.timing, OS_ANN_KERNEL_SCREEN, c.s,
-                     [&] { return launch_tiled_screen(ta, p.R, p.G, ix->lp.f16, blocks, c.s); });
+    if (p.kern == 1) {
+        ta.S = (int)p.nw;  // one list per (query, 64-cone word)
+        e = timed_launch(ix, c.timing, OS_ANN_KERNEL_SCREEN, c.s,
+                         [&] { return launch_cone_screen(ta, p.R, ix->lp.f16, c.s); });
+    } else {
+        e = timed_launch(ix, c.timing, OS_ANN_KERNEL_SCREEN, c.s,
+                         [&] { return launch_tiled_screen(ta, p.R, p.G, ix->lp.f16, blocks, c.s); });
+    }
     if (e != hipSuccess) return e;
     FinishArgs fa{};
     fa.part = ta.part;
-    fa.S = S;
+    fa.S = ta.S;
     fa.Q = c.Q;
     fa.planes = ix->planes;
     fa.dtype = ix->dtype;
@@ -914,16 +935,28 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     return timed_launch(ix, c.timing, OS_ANN_KERNEL_FINISH, c.s, [&] { return launch_tiled_finish(fa, p.R, c.s); });
 }
 
-// Plans of the tiled path for every tile width: the default first.
-int tiled_plans(const os_ann_index* ix, int64_t Q, int64_t budget, int R, bool cones, SearchPlan (&plans)[4]) {
+// Plans of the tiled path: the query-tile screen for every tile width and
+// the cone-major screen (where the probe bitmaps exist), each for both query
+// orders; the default first.
+constexpr int kMaxPlans = 8;
+int tiled_plans(const os_ann_index* ix, int64_t Q, int64_t budget, int R, bool cones, SearchPlan (&plans)[kMaxPlans]) {
     int n = 0;
     const char* genv = std::getenv("OSANN_TILED_GROUPS");  // fixed tile width (testing)
     const char* oenv = std::getenv("OSANN_TILED_ORDER");   // fixed query order (testing)
+    const char* kenv = std::getenv("OSANN_TILED_KERNEL");  // fixed screen kernel (testing): tile | cone
     const int gfix = genv && tile_groups_ok(R, std::atoi(genv)) ? std::atoi(genv) : 0;
     const int ofix = oenv && (std::atoi(oenv) == 0 || std::atoi(oenv) == 1) ? std::atoi(oenv) + 1 : 0;
+    const int kfix = kenv ? (std::string(kenv) == "cone" ? 2 : std::string(kenv) == "tile" ? 1 : 0) : 0;
     const SearchPlan def = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones, gfix);
     for (int qk = 0; qk < 2; ++qk) {
         if (ofix && qk != ofix - 1) continue;
+        if (def.cone_ok && kfix != 1) {
+            plans[n] = def;
+            plans[n].qkey = qk;
+            plans[n].fits = true;  // its LDS use depends on dk only (at most 32 KB of queries)
+            plans[n++].kern = 1;
+        }
+        if (kfix == 2 && def.cone_ok) continue;
         for (int G : {def.G, def.G == 4 ? 2 : 4}) {
             if (!tile_groups_ok(R, G) || (gfix && G != gfix)) continue;
             plans[n] = plan_search(ix, Q, budget, OS_ANN_MODE_TILED, R, cones, G);
@@ -939,34 +972,46 @@ int tiled_plans(const os_ann_index* ix, int64_t Q, int64_t budget, int R, bool c
 // candidate pair (each computes the same result, so the outputs of the last
 // run are valid); else (during capture) the default G and the smallest S.
 int choose_tiling(Call& c, const SearchPlan* plans, int n_plans, bool may_time, hipError_t* err) {
-    // the choice is cached as (query order << 12) | (G << 8) | S
+    // the choice is cached as (kernel << 20) | (query order << 16) | (G << 12) | S
     *err = hipSuccess;
     c.p = plans[0];
     if (const char* env = std::getenv("OSANN_TILED_SPLITS")) {  // fixed split count (testing)
         const int v = std::atoi(env);
-        if (v >= c.p.smin && v <= c.p.smax && (v & (v - 1)) == 0) return v;
-    }
-    const std::string key = tune_key(c.ix, plans[0], c.budget) + ":OGS";
-    if (int v = g_tuner.get(key)) {
         for (int k = 0; k < n_plans; ++k)
-            if (plans[k].fits && plans[k].qkey == (v >> 12) && plans[k].G == ((v >> 8) & 0xF) &&
-                (v & 0xFF) >= plans[k].smin && (v & 0xFF) <= plans[k].smax) {
+            if (plans[k].kern == 0 && v >= plans[k].smin && v <= plans[k].smax && (v & (v - 1)) == 0) {
                 c.p = plans[k];
-                return v & 0xFF;
+                return v;
             }
     }
-    if (!may_time) return c.p.smin;
+    const std::string key = tune_key(c.ix, plans[0], c.budget) + ":KOGS";
+    if (int v = g_tuner.get(key)) {
+        for (int k = 0; k < n_plans; ++k) {
+            const SearchPlan& pk = plans[k];
+            if (!pk.fits || pk.kern != (v >> 20) || pk.qkey != ((v >> 16) & 0xF)) continue;
+            if (pk.kern == 1) {
+                c.p = pk;
+                return (int)pk.nw;
+            }
+            if (pk.G == ((v >> 12) & 0xF) && (v & 0xFFF) >= pk.smin && (v & 0xFFF) <= pk.smax) {
+                c.p = pk;
+                return v & 0xFFF;
+            }
+        }
+    }
+    if (!may_time) return c.p.kern == 1 ? (int)c.p.nw : c.p.smin;
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    int best_k = 0, best_s = plans[0].smin;
+    int best_k = 0, best_s = plans[0].kern == 1 ? (int)plans[0].nw : plans[0].smin;
     float best_ms = 1e30f;
     const bool timing = c.timing;
     c.timing = false;
     for (int k = 0; k < n_plans && e == hipSuccess; ++k) {
         if (!plans[k].fits) continue;
         c.p = plans[k];
-        for (int s = c.p.smin; s <= c.p.smax && e == hipSuccess; s <<= 1) {
+        const int s_lo = c.p.kern == 1 ? (int)c.p.nw : c.p.smin;
+        const int s_hi = c.p.kern == 1 ? (int)c.p.nw : c.p.smax;
+        for (int s = s_lo; s <= s_hi && e == hipSuccess; s = c.p.kern == 1 ? s_hi + 1 : s << 1) {
             for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first run warms caches
                 e = hipEventRecord(a, c.s);
                 if (e == hipSuccess) e = enqueue_tiled(c, s);
@@ -987,7 +1032,9 @@ int choose_tiling(Call& c, const SearchPlan* plans, int n_plans, bool may_time, 
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
     *err = e;
-    if (e == hipSuccess) g_tuner.put(key, (plans[best_k].qkey << 12) | (plans[best_k].G << 8) | best_s, best_ms);
+    if (e == hipSuccess)
+        g_tuner.put(key, (plans[best_k].kern << 20) | (plans[best_k].qkey << 16) | (plans[best_k].G << 12) | best_s,
+                    best_ms);
     return best_s;
 }
 
@@ -1193,6 +1240,11 @@ hipError_t enqueue_sparse(const Call& c) {
     sa.out_idx = c.out_idx;
     sa.out_dist = c.out_dist;
     sa.out_ncand = c.out_ncand;
+    sa.out_capped = reinterpret_cast<unsigned long long*>(c.walks_capped);
+    if (c.walks_capped) {  // zeroed by a fill kernel (the sequence stays graph-capturable)
+        e = launch_fill_u32(reinterpret_cast<uint32_t*>(c.walks_capped), 2, 0u, c.s);
+        if (e != hipSuccess) return e;
+    }
     return timed_launch(ix, c.timing, OS_ANN_KERNEL_SCAN, c.s, [&] { return launch_sparse_search(sa, c.s); });
 }
 
@@ -1210,6 +1262,7 @@ int run_graph(Call& c, int S) {
                                 c.p.R,
                                 c.p.G,
                                 c.p.qkey,
+                                c.p.kern,
                                 c.p.cones,
                                 S,
                                 c.Q,
@@ -1920,7 +1973,7 @@ int64_t os_ann_workspace_bytes(const os_ann_index* idx, int64_t Q, int64_t max_c
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
     const bool cones = opts && (opts->flags & OS_ANN_FLAG_BUDGET_CONES);
     if (mode == OS_ANN_MODE_TILED && !idx->sparse && idx->n_rot == 0 && !idx->proj && !idx->ivf_cent) {
-        SearchPlan plans[4];
+        SearchPlan plans[kMaxPlans];
         const int np = tiled_plans(idx, Q, max_candidates, R, cones, plans);
         size_t bytes = 0;
         for (int k = 0; k < np; ++k) bytes = std::max(bytes, plans[k].bytes);
@@ -1947,6 +2000,7 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     c.out_idx = out_idx;
     c.out_dist = out_dist;
     c.out_ncand = out_ncand;
+    c.walks_capped = opts ? opts->walks_capped : nullptr;
     c.s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
     StreamScope ss(c.s);
     c.timing = opts && (opts->flags & OS_ANN_FLAG_TIME_KERNELS);
@@ -1956,7 +2010,7 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     c.p = plan_search(ix, Q, max_candidates, mode, R, cones);
     if (!c.p.fits)
         return fail(OS_ANN_ENOTSUP, "tiled mode: too many non-empty cones for the LDS cone list at this D");
-    SearchPlan plans[4];
+    SearchPlan plans[kMaxPlans];
     int n_plans = 0;
     size_t bytes = c.p.bytes;
     if (mode == OS_ANN_MODE_TILED) {  // one scratch layout per tile width; room for the largest

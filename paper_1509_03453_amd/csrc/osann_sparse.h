@@ -72,6 +72,7 @@ struct SparseSearchArgs {
     int64_t* out_idx;
     float* out_dist;
     int64_t* out_ncand;    // rows compared (may be null)
+    unsigned long long* out_capped;  // walks stopped by the kSparseWalkCap limit: added to (may be null)
 };
 hipError_t launch_sparse_search(const SparseSearchArgs& a, hipStream_t s);
 

@@ -56,19 +56,28 @@ struct TiledArgs {
                             // (padded position mod R), 0xFFFFFFFF before the launch
 };
 
-// Bound seeding before the screen: d~ of (part of) each query's own cone on
-// the vector units, raised by an accumulation-order error bound.
+// Bound seeding before the screen: d~ of the rows of the first cones of each
+// query's walk (its own cone first) on the vector units, raised by an
+// accumulation-order error bound; the R-th smallest goes into every class.
 struct SeedArgs {
     const uint16_t* xl;
     const float* nrm;
     const uint32_t* poff;
     int dk;
     const uint16_t* ql;      // [Q][dk]
-    const uint32_t* q_cone;  // [Q] own cone
     const uint32_t* qorder;  // tile slot -> query
     int64_t Q;
     uint32_t* cmin;          // [R][Q] by tile slot, as in the screen
-    int rows;                // rows of the own cone seeded per query (at most)
+    int rows;                // padded rows seeded per query (at most; a multiple of 64, <= 1024)
+    // walk state and tables (the walk's first positions are the cones seeded)
+    const uint8_t* order;    // [Q][D]
+    const uint8_t* sbit;     // [Q][D]
+    const uint32_t* jstop;   // [Q] walk positions taken (kWalkAll: every cone)
+    const uint8_t* lexsub;
+    const uint8_t* maskord;
+    const uint32_t* binom;
+    int64_t n_sub, n_cones;
+    int D, L;
 };
 
 struct FinishArgs {
@@ -107,6 +116,12 @@ hipError_t launch_tiled_screen(const TiledArgs& a, int R, int G, int f16in, int 
 size_t tiled_screen_lds();                      // dynamic LDS bytes of one screen block
 size_t tiled_screen_static_lds(int R, int G);          // static LDS bytes (upper bound) of one screen block
 hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s);
+// Cone-major screen (needs the probe bitmaps; a.S must equal a.nw: one list
+// per (query, 64-cone word)); dk of 32, 64 or 128.
+bool cone_screen_ok(int dk, int R);
+size_t cone_screen_lds(int dk);
+hipError_t launch_cone_screen(const TiledArgs& a, int R, int f16in, hipStream_t s);
+hipError_t cone_screen_max_lds();
 hipError_t launch_tiled_seed(const SeedArgs& a, int R, int f16in, hipStream_t s);
 hipError_t tiled_screen_max_lds();
 int tiled_screen_occupancy(int R, int G, int f16in, int ks, size_t lds);

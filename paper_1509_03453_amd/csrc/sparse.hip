@@ -236,6 +236,7 @@ __global__ __launch_bounds__(64 * kSparseWaves) void sparse_search_kernel(Sparse
     };
     const uint64_t nc = (uint64_t)t.n_cones, budget = (uint64_t)a.budget;
     uint64_t carry = 0;
+    bool capped = false;
     if ((!a.cones && budget >= (uint64_t)t.N) || (a.cones && budget >= nc)) {  // every row
         for (int64_t p = l; p < t.N; p += 64) visit(p);
         carry = (uint64_t)t.N;
@@ -282,12 +283,16 @@ __global__ __launch_bounds__(64 * kSparseWaves) void sparse_search_kernel(Sparse
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
+        // stopped by the position cap: a row budget not met although cones
+        // remained, or a C beyond the cap
+        capped = a.cones ? limit == kSparseWalkCap && budget > limit && nc > limit : !done && limit < nc;
     }
     wave_argmin(best, brow);
     if (l == 0) {
         a.out_idx[q] = brow == 0xFFFFFFFFu ? -1 : (int64_t)brow;
         a.out_dist[q] = best;
         if (a.out_ncand) a.out_ncand[q] = (int64_t)carry;
+        if (capped && a.out_capped) atomicAdd(a.out_capped, 1ull);
     }
 }
 

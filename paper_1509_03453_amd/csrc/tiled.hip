@@ -39,96 +39,10 @@
 #include "osann_device.h"
 #include "osann_kernels.h"
 #include "osann_tiled.h"
+#include "osann_screen.h"
 
 namespace osann {
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8_t;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
-
-__device__ inline bool pair_less(float d, uint32_t r, float e, uint32_t s) {
-    return d < e || (d == e && r < s);
-}
-
-// Merge this lane's sorted list with lane^m's into the R smallest, sorted.
-template <int R>
-__device__ inline void merge_with(float (&d)[R], uint32_t (&r)[R], int m) {
-    float pd[R];
-    uint32_t pr[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        pd[k] = __shfl_xor(d[k], m, 64);
-        pr[k] = (uint32_t)__shfl_xor((int)r[k], m, 64);
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k)
-        if (pair_less(pd[R - 1 - k], pr[R - 1 - k], d[k], r[k])) {
-            d[k] = pd[R - 1 - k];
-            r[k] = pr[R - 1 - k];
-        }
-#pragma unroll
-    for (int j = R / 2; j > 0; j >>= 1)
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            if ((k & j) == 0 && pair_less(d[k + j], r[k + j], d[k], r[k])) {
-                const float td = d[k];
-                d[k] = d[k + j];
-                d[k + j] = td;
-                const uint32_t tr = r[k];
-                r[k] = r[k + j];
-                r[k + j] = tr;
-            }
-}
-
-template <int R>
-__device__ inline void list_insert(float (&d)[R], uint32_t (&r)[R], float nd, uint32_t nr) {
-    bool placed = false;
-#pragma unroll
-    for (int k = R - 1; k >= 1; --k) {
-        if (!placed) {
-            if (pair_less(nd, nr, d[k - 1], r[k - 1])) {
-                d[k] = d[k - 1];
-                r[k] = r[k - 1];
-            } else {
-                d[k] = nd;
-                r[k] = nr;
-                placed = true;
-            }
-        }
-    }
-    if (!placed) {
-        d[0] = nd;
-        r[0] = nr;
-    }
-}
-
-// Order-preserving map of a non-NaN float to 32 bits (and back); 0xFFFFFFFF
-// (above every float) stands for "no candidate yet".
-__device__ inline uint32_t ord_bits(float f) {
-    const uint32_t b = __float_as_uint(f);
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-__device__ inline float ord_float(uint32_t u) {
-    if (u == 0xFFFFFFFFu) return __builtin_huge_valf();
-    return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
-}
-
-// A value every lane of the wave holds alike, moved to scalar registers.
-__device__ inline uint4 uni4(uint4 v) {
-    return make_uint4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
-                      __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
-}
-
-template <bool F16IN>
-__device__ inline f32x4_t mfma16(const uint4& a, const uint4& b, f32x4_t acc) {
-    if (F16IN)
-        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, b),
-                                                      acc, 0, 0, 0);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
-                                                   acc, 0, 0, 0);
-}
-
-constexpr int kHitCap = 64;   // hit buffer entries per wave (one full ballot)
 
 // One wave works on one item at a time: (wave tile of 16G queries, split),
 // taking the split's cones kChunk at a time.  Dynamic LDS holds, per wave,
@@ -468,36 +382,70 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
     }
 }
 
-// Seeds the shared class minima before the screen, so that no split starts
-// without a bound.  One wave per query; each lane takes one row of the
-// query's own cone (the first a.rows rows at most), computes d~ on the
-// vector units and raises it by a bound on the difference to any FP32
-// accumulation of the same products (the matrix cores add them in another
-// order): each of the two sums is off by at most dk*u*S with S the sum of
-// |products|, and the final subtraction by u*(|n| + 2|q.x|), so
-// (4dk + 8)*u*(n + 2S) covers both (u = 2^-24), with a margin.  The raised
-// value is at least the screen's d~ of a real candidate of its class, so the
-// largest-class-minimum rule stays a valid bound.
+// Seeds the shared class minima before the screen, so that no split or word
+// starts without a bound.  One wave per query takes the rows of the first
+// cones of its walk (its own cone, then the next positions of Section 3.B's
+// order: the most promising candidates), at most a.rows padded rows, each
+// lane a row at a time; computes d~ on the vector units and raises it by a
+// bound on the difference to any FP32 accumulation of the same products (the
+// matrix cores add them in another order): each of the two sums is off by at
+// most dk*u*S with S the sum of |products|, and the final subtraction by
+// u*(|n| + 2|q.x|), so (4dk + 8)*u*(n + 2S) covers both (u = 2^-24), with a
+// margin.  The R-th smallest raised value T is at least the screen's d~ of
+// R distinct candidates, so it bounds the query's final R-th d~; it is put
+// into every class, where it stays valid: the largest class minimum is at
+// least T while any class keeps it, else every class holds a real candidate
+// of its own.
+constexpr int kSeedMaxRows = 1024;  // 16 rows per lane
 
 template <bool F16IN, int R>
 __global__ __launch_bounds__(256) void tiled_seed_kernel(SeedArgs a) {
 #pragma clang fp contract(off)
-    const int64_t slot = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-    const int l = lane_id();
-    if (slot >= a.Q) return;
+    __shared__ uint32_t s_start[4][64], s_incl[4][64];
+    const int w = threadIdx.x / 64, l = lane_id();
+    const int64_t slot = (int64_t)blockIdx.x * 4 + w;
+    if (slot >= a.Q) return;  // the whole wave; no block barrier below
     const int64_t q = a.qorder[slot];
-    const uint32_t c = a.q_cone[q];
-    const uint32_t p0 = a.poff[c], p1 = a.poff[c + 1];
-    const uint32_t pend = p1 - p0 > (uint32_t)a.rows ? p0 + (uint32_t)a.rows : p1;
+    // the walk's first positions (at most 64) while their rows stay within a.rows
+    const uint32_t js = a.jstop[q];
+    const int64_t walk = js == kWalkAll ? a.n_cones : (int64_t)js;
+    const int npos = (int)(walk < 64 ? walk : 64);
+    uint32_t start = 0, len = 0;
+    if (l < npos) {
+        const uint32_t c = probe_cone(l, a.L, a.order + q * a.D, a.sbit + q * a.D, a.n_sub, a.lexsub, a.maskord,
+                                      a.binom);
+        start = a.poff[c];
+        len = a.poff[c + 1] - start;
+    }
+    const uint32_t incl = wave_incl_scan(len);
+    const bool take = l < npos && incl - len < (uint32_t)a.rows;  // the first position always
+    s_start[w][l] = start;
+    s_incl[w][l] = take ? incl : 0xFFFFFFFFu;
+    const uint64_t tk = __ballot(take);
+    const uint32_t last = tk ? shfl_u32(incl, 63 - __clzll((unsigned long long)tk)) : 0u;
+    const uint32_t total = last < (uint32_t)a.rows ? last : (uint32_t)a.rows;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const float gamma = (float)(4 * a.dk + 8) * 5.9604645e-08f * 1.01f;
-    for (uint32_t p = p0 + l; p < pend; p += 64) {
+    constexpr int PER = kSeedMaxRows / 64;
+    float raised[PER];  // this lane's raised values
+    uint32_t k = 0;     // position of the lane's current row (rows ascend with i)
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        raised[i] = __builtin_huge_valf();
+        const uint32_t r = (uint32_t)l + 64u * i;
+        if (r >= total) continue;
+        while (s_incl[w][k] <= r) ++k;
+        const uint32_t before = k ? s_incl[w][k - 1] : 0u;
+        const uint32_t p = s_start[w][k] + (r - before);
         const float n = a.nrm[p];
         if (!(n < __builtin_huge_valf())) continue;  // padding row (NaN norm)
         const uint4* xr = reinterpret_cast<const uint4*>(a.xl + (int64_t)p * a.dk);
         const uint4* qr = reinterpret_cast<const uint4*>(a.ql + q * a.dk);
         float dot = 0.0f, sabs = 0.0f;
-        for (int k = 0; k < a.dk / 8; ++k) {
-            const uint4 xv = xr[k], qv = qr[k];
+        for (int u = 0; u < a.dk / 8; ++u) {
+            const uint4 xv = xr[u], qv = qr[u];
             const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w}, qw[4] = {qv.x, qv.y, qv.z, qv.w};
 #pragma unroll
             for (int h = 0; h < 4; ++h)
@@ -513,13 +461,41 @@ __global__ __launch_bounds__(256) void tiled_seed_kernel(SeedArgs a) {
         }
         const float d = n - 2.0f * dot;
         const float tol = gamma * (n + 2.0f * sabs);
-        __hip_atomic_fetch_min(a.cmin + (int64_t)(p & (R - 1)) * a.Q + slot, ord_bits(d + tol), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        raised[i] = d + tol;
     }
+    // the R-th smallest: R rounds of a wave minimum, each removing one occurrence
+    float T = __builtin_huge_valf();
+    for (int rr = 0; rr < R; ++rr) {
+        float lm = raised[0];
+#pragma unroll
+        for (int i = 1; i < PER; ++i) lm = fminf(lm, raised[i]);
+        float m = lm;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
+        if (!(m < __builtin_huge_valf())) {  // fewer than R seeded rows
+            T = __builtin_huge_valf();
+            break;
+        }
+        const uint64_t who = __ballot(lm == m);
+        if (l == __ffsll((unsigned long long)who) - 1) {
+            bool done = false;
+#pragma unroll
+            for (int i = 0; i < PER; ++i)
+                if (!done && raised[i] == m) {
+                    raised[i] = __builtin_huge_valf();
+                    done = true;
+                }
+        }
+        T = m;
+    }
+    if (T < __builtin_huge_valf() && l < R)
+        __hip_atomic_fetch_min(a.cmin + (int64_t)l * a.Q + slot, ord_bits(T), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
 hipError_t launch_tiled_seed(const SeedArgs& a, int R, int f16in, hipStream_t s) {
     if (a.Q <= 0) return hipSuccess;
+    if (a.rows < 64 || a.rows > kSeedMaxRows || a.rows % 64 != 0 || a.L < 1 || a.L > 7) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((a.Q + 3) / 4));
 #define OSANN_SEED(F, RR)                                                                     \
     if ((f16in != 0) == F && R == RR) {                                                       \
@@ -662,7 +638,9 @@ hipError_t launch_tiled_screen(const TiledArgs& a, int R, int G, int f16in, int 
 
 template <typename E, int R>
 static hipError_t finish_g(const FinishArgs& f, hipStream_t s) {
-    const int G = f.S > R ? (f.S < 16 ? f.S : 16) : R;
+    // lanes per query: a power of two (the lists are merged over xor partners);
+    // lanes past the S lists fold nothing
+    const int G = f.S > R ? 16 : R;
     const int64_t threads = f.Q * G;
     const dim3 grid((unsigned)((threads + 255) / 256));
     switch (G) {

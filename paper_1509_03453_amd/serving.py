@@ -15,9 +15,12 @@ loop that
   goes alone) and launches one ``os_ann_search_ex`` on that slot's stream.
 
 So requests arriving while others are on the GPU start as soon as a slot and
-memory free up, and their kernels overlap on the device.  Latency is measured
-on the device clock: completion event time minus the request's arrival time,
-both relative to a start event recorded when the run begins.
+memory free up, and their kernels overlap on the device.  Latency is the
+completion event of a request's batch (device clock) minus its scheduled
+arrival (host clock) moved onto the device clock: while the device is idle,
+before and after the run, events are recorded at known host times and their
+device times give the offset between the two clocks; the run reports that
+offset's spread and drift, which bound the error of every latency.
 
 The search itself (hash, probe, screen, re-rank) is entirely in the HIP
 library: this module only schedules calls to it.  A query's result does not
@@ -37,7 +40,8 @@ import torch
 
 from . import binding as B
 
-__all__ = ["Request", "ResidentIndex", "Server", "pack_batch", "admissible", "latency_stats", "choose_mode"]
+__all__ = ["Request", "ResidentIndex", "Server", "pack_batch", "admissible", "latency_stats", "choose_mode",
+           "load_sweep"]
 
 
 @dataclasses.dataclass
@@ -52,6 +56,8 @@ class Request:
     launched: float | None = None        # host seconds when its batch was launched
     done: float | None = None            # device seconds of its batch's completion event
     batch_id: int | None = None
+    lag: float | None = None             # host seconds from scheduled arrival to queueing
+    offset: float | None = None          # device minus host clock (seconds) of the run
 
     @property
     def n(self) -> int:
@@ -59,7 +65,7 @@ class Request:
 
     @property
     def latency(self) -> float | None:
-        return None if self.done is None else self.done - self.arrival
+        return None if self.done is None else self.done - (self.arrival + self.offset)
 
 
 @dataclasses.dataclass
@@ -129,6 +135,23 @@ def latency_stats(lat: Sequence[float]) -> dict:
             "mean_ms": float(a.mean()), "max_ms": float(a.max())}
 
 
+def clock_offsets(base, t0: float, device, n: int = 16) -> np.ndarray:
+    """Device-minus-host clock offsets (seconds): with the device idle, an
+    event is recorded at a known host time (seconds after ``t0``) and its
+    device time read relative to ``base``; the event completes a little
+    after the host enqueues it, so each sample is the offset plus that
+    submission delay, and their spread shows the delay's variation."""
+    stream = torch.cuda.current_stream(device)
+    out = []
+    for _ in range(n):
+        ev = torch.cuda.Event(enable_timing=True)
+        h = time.perf_counter() - t0
+        ev.record(stream)
+        ev.synchronize()
+        out.append(base.elapsed_time(ev) * 1e-3 - h)
+    return np.asarray(out)
+
+
 def pick_index(queues: dict[str, collections.deque]) -> str | None:
     """The index whose oldest queued request arrived first (first come, first served)."""
     best, t = None, None
@@ -149,6 +172,7 @@ class _Slot:
         self.hold: tuple = ()
         self.bytes = 0
         self.busy = False
+        self.ws = None  # the slot's search workspace; grows to the largest launch, then is reused
 
 
 class Server:
@@ -197,13 +221,22 @@ class Server:
                 if q >= min(self.max_batch, x.shape[0]):
                     break
                 q *= 2
+        # every slot's workspace sized for the largest launch, so timed launches allocate none
+        need = max(ix.workspace(self.max_batch) for ix in self.indexes.values())
+        for s in self.slots:
+            with torch.cuda.stream(s.stream):
+                s.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         torch.cuda.synchronize(self.device)
 
     def _launch(self, slot: _Slot, ix: ResidentIndex, reqs: list[Request], need: int, now: float) -> None:
         q_total = sum(r.n for r in reqs)
         with torch.cuda.stream(slot.stream):
             qs = reqs[0].queries if len(reqs) == 1 else torch.cat([r.queries for r in reqs])
-            ws = torch.empty(ix.workspace(q_total), dtype=torch.uint8, device=self.device)
+            wsb = ix.workspace(q_total)
+            if slot.ws is None or slot.ws.numel() < wsb:
+                slot.ws = None  # the old buffer is idle: this slot's previous launch has retired
+                slot.ws = torch.empty(wsb, dtype=torch.uint8, device=self.device)
+            ws = slot.ws
             oi = torch.empty(q_total, dtype=torch.int64, device=self.device)
             od = torch.empty(q_total, dtype=torch.float32, device=self.device)
             B.os_ann_search_ex(ix.index.handle, qs, ix.budget, mode=ix.mode, stream=slot.stream,
@@ -233,6 +266,7 @@ class Server:
         base.record(torch.cuda.current_stream(self.device))
         base.synchronize()
         t0 = time.perf_counter()
+        before = clock_offsets(base, t0, self.device)
         finished: list[Request] = []
         while pending or any(queues.values()) or any(s.busy for s in self.slots):
             now = time.perf_counter() - t0
@@ -240,6 +274,7 @@ class Server:
                 raise TimeoutError(f"serving run exceeded {max_seconds} s")
             while pending and pending[0].arrival <= now:
                 r = pending.popleft()
+                r.lag = now - r.arrival
                 queues[r.index].append(r)
             for s in self.slots:  # retire
                 if s.busy and s.event.query():
@@ -272,10 +307,51 @@ class Server:
             if not progressed:
                 time.sleep(5e-5)
         wall = time.perf_counter() - t0
+        torch.cuda.synchronize(self.device)
+        after = clock_offsets(base, t0, self.device)
+        offset = float(np.median(before))
+        for r in finished:
+            r.offset = offset
         n_q = sum(r.n for r in finished)
         span = max(r.done for r in finished) - min(r.arrival for r in finished) if finished else 0.0
         out = {"requests": len(finished), "queries": n_q, "batches": self.n_batches,
                "qps": n_q / span if span > 0 else None, "span_s": span, "wall_s": wall,
                "max_concurrent_launches": self.max_concurrent, "peak_in_flight_bytes": self.peak_in_flight}
         out.update(latency_stats([r.latency for r in finished]))
+        lag = np.asarray([r.lag for r in finished]) * 1e3
+        out["arrival_lag_ms"] = {"p50": float(np.percentile(lag, 50)), "max": float(lag.max())} if lag.size else None
+        out["clock_offset_us"] = {"before_median": offset * 1e6,
+                                  "before_spread": float(np.ptp(before)) * 1e6,
+                                  "after_median": float(np.median(after)) * 1e6,
+                                  "drift": float(np.median(after) - offset) * 1e6}
         return out
+
+
+def load_sweep(server: "Server", make_requests: Callable[[float], list], fractions=(0.5, 0.8, 0.95),
+               warmup_requests: int = 100, saturation_requests: int = 600, max_seconds: float = 300.0) -> dict:
+    """Saturation rate, then Poisson load points at fractions of it.
+
+    ``make_requests(rate)`` returns a fresh request list with arrivals at
+    ``rate`` requests/s (rate = inf: every request at time 0).  The
+    saturation rate is the request rate the server sustains with the first
+    ``saturation_requests`` requests queued at once.  Each load point runs
+    the whole list and reports throughput and latency over the requests
+    after the first ``warmup_requests``.  Returns the summary and the
+    requests of the last load point (with their results)."""
+    sat_reqs = make_requests(float("inf"))[:saturation_requests]
+    st = server.run(sat_reqs, max_seconds=max_seconds)
+    sat_rate = st["requests"] / st["span_s"]
+    out = {"saturation": {"req_per_s": sat_rate, "qps": st["qps"], "requests": st["requests"]}, "points": []}
+    reqs = []
+    for f in fractions:
+        reqs = make_requests(f * sat_rate)
+        server.run(reqs, max_seconds=max_seconds)
+        meas = reqs[warmup_requests:]
+        t_first = min(r.arrival for r in meas)
+        t_last = max(r.done for r in meas)
+        pt = {"fraction": f, "offered_req_per_s": f * sat_rate, "measured_requests": len(meas),
+              "qps": sum(r.n for r in meas) / (t_last - t_first),
+              "req_per_s": len(meas) / (t_last - t_first)}
+        pt.update(latency_stats([r.latency for r in meas]))
+        out["points"].append(pt)
+    return out, reqs

@@ -200,3 +200,19 @@ def random_signs(n: int, d: int, seed: int = SEEDS["wht_signs"]) -> np.ndarray:
     diagonal of the structured bases H diag(s)."""
     return np.where(_rng(seed).random((int(n), int(d))) < 0.5, -1.0, 1.0).astype(np.float32)
 
+
+
+def prototype_rows(n_proto: int, per: int, d: int, n_big: int, noise: float = 0.3,
+                   seed: int = 7301) -> np.ndarray:
+    """Clustered FP32 rows: ``n_proto`` prototypes, each with ``n_big``
+    components of magnitude 8..12 (random indices and signs) over N(0, 0.5^2)
+    background, and ``per`` copies of each plus N(0, noise^2).  Copies of one
+    prototype mostly share their largest components, so a table with very
+    many cones still has populated neighbourhoods."""
+    r = _rng(seed)
+    protos = r.normal(0.0, 0.5, size=(n_proto, d))
+    for p in range(n_proto):
+        idx = r.choice(d, size=n_big, replace=False)
+        protos[p, idx] = r.uniform(8.0, 12.0, size=n_big) * r.choice([-1.0, 1.0], size=n_big)
+    rows = np.repeat(protos, per, axis=0) + r.normal(0.0, noise, size=(n_proto * per, d))
+    return rows.astype(np.float32)

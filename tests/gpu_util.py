@@ -46,7 +46,24 @@ def gpu_search(h, Y: np.ndarray, budget: int, mode=B.OS_ANN_MODE_FP32):
 MISMATCHES = []
 
 
-def check_screened(orc, X, Y, g, o, tag, max_mismatch=0.02):
+def candidates_of(orc, index, Y, budget, cones=False, Yk=None):
+    """``is_candidate(q, row)``: row lies in one of the cones query q's walk
+    takes within the budget (reading R5; R13 with ``cones``).  ``Yk``: the
+    keys a keyed table's walk runs on."""
+    walk_rows = Y if Yk is None else Yk
+    seen = {}
+
+    def is_candidate(q, row):
+        if q not in seen:
+            y = np.asarray(walk_rows[q], dtype=np.float32)
+            pr = (orc.probe_cones(y, index["G"], index["offsets"], budget) if cones
+                  else orc.probe(y, index["G"], index["offsets"], budget))
+            seen[q] = set(pr[0].tolist())
+        return int(index["cone"][row]) in seen[q]
+    return is_candidate
+
+
+def check_screened(orc, X, Y, g, o, tag, max_mismatch=0.02, is_candidate=None):
     """Compare a tiled-mode result ``g = (idx, dist, ncand)`` with the
     oracle's screened search ``o = (idx, d32, d64, ncand, dtilde_R, top)``.
 
@@ -62,7 +79,9 @@ def check_screened(orc, X, Y, g, o, tag, max_mismatch=0.02):
         GPU dropped the oracle's pick, so that pick's d~ lies within
         rounding of the R-th d~; if it is better, it can not be among the
         oracle's survivors (the oracle would have returned it).
-    Such queries must be rare; their count is recorded and printed."""
+    With ``is_candidate`` a differing row must also be a candidate of its
+    query (in one of the cones its walk takes).  Such queries must be rare;
+    their count is recorded and printed."""
     U = 2.0 ** -24
     gi, gd, gn = g
     oi, od32, od64, on, dtr, top = o
@@ -76,6 +95,8 @@ def check_screened(orc, X, Y, g, o, tag, max_mismatch=0.02):
     D = X.shape[1]
     bad = [q for q in full if gi[q] != oi[q]]
     for q in bad:
+        if is_candidate is not None:
+            assert is_candidate(q, int(gi[q])), (tag, q, "the returned row is not a candidate of the query")
         xs = orc.round_short(X[[gi[q], oi[q], top[q][-1]]].astype(np.float32), f16).reshape(3, D)
         ys = orc.round_short(Y[q].astype(np.float32), f16)
         tol = 4 * (D + 2) * U * ((xs ** 2).sum(1) + 2 * np.abs(xs * ys).sum(1)).max()

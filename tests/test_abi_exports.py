@@ -62,3 +62,19 @@ def test_set_allocator_host_checks():
     assert L.os_ann_set_allocator(ctypes.cast(None, B.ALLOC_FN), ctypes.cast(None, B.FREE_FN), None) == B.OS_ANN_OK
     with pytest.raises(ValueError):
         B.os_ann_set_allocator(lambda n, s: 0, None)
+
+
+def _header_struct_fields(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, flags=re.S).group(1)
+    return [re.findall(r"(\w+)\s*;", decl)[0] for decl in body.split(";") if decl.strip() for decl in [decl + ";"]]
+
+
+@pytest.mark.parametrize("name", ["os_ann_build_opts", "os_ann_search_opts"])
+def test_binding_structs_match_header(name):
+    # the ctypes structures the binding passes have exactly the header's
+    # fields in the header's order (a missing trailing field would make the
+    # library read past the end of the caller's structure)
+    from paper_1509_03453_amd import binding
+    ctype_fields = [f for f, _ in getattr(binding, name)._fields_]
+    assert ctype_fields == _header_struct_fields(name)

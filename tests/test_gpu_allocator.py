@@ -16,7 +16,7 @@ import torch
 
 from paper_1509_03453_amd import binding as B
 from paper_1509_03453_amd import workloads as W
-from tests.gpu_util import check_screened, dev, say
+from tests.gpu_util import candidates_of, check_screened, dev, say
 
 pytestmark = pytest.mark.gpu
 
@@ -129,7 +129,8 @@ def test_hook_owns_every_block_and_enomem_leaks_nothing(orc):
             break
         assert refused >= 4, refused  # scratch and several blocks of the copy were refused
         hook.fail_from = None
-        check_screened(orc, Xb, Y, g, orc.search_tiled(Xb, o, Y, 1000, R=8), "tiled after refusals")
+        check_screened(orc, Xb, Y, g, orc.search_tiled(Xb, o, Y, 1000, R=8), "tiled after refusals",
+                       is_candidate=candidates_of(orc, o, Y, 1000))
         gi, gd, gn = _search(hb, Y, 1000)
         oi, od32, od64, on = orc.search(Xb, o, Y, 1000)
         assert np.array_equal(gi, oi) and np.array_equal(gn, on)

@@ -15,7 +15,7 @@ import torch
 
 from paper_1509_03453_amd import binding as B
 from paper_1509_03453_amd import workloads as W
-from tests.gpu_util import check_screened, dev, say
+from tests.gpu_util import candidates_of, check_screened, dev, say
 
 pytestmark = pytest.mark.gpu
 U = 2.0 ** -24
@@ -41,8 +41,9 @@ def same_fp32(g, o, tag):
     assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), tag
 
 
-def same_tiled(orc, X, Y, g, o, tag, max_mismatch=0.02):
-    check_screened(orc, X, Y, g, o, tag, max_mismatch=max_mismatch)
+def same_tiled(orc, X, Y, g, o, tag, max_mismatch=0.02, index=None, C=None):
+    cand = candidates_of(orc, index, Y, C, cones=True) if index is not None else None
+    check_screened(orc, X, Y, g, o, tag, max_mismatch=max_mismatch, is_candidate=cand)
 
 
 @pytest.mark.parametrize("kind", ["gauss", "desc", "patch"])
@@ -71,7 +72,7 @@ def test_cones_one_basis(orc, kind):
         for C in (1, 5, 64, 500):
             say(f"[cones] {kind} tiled C={C}")
             same_tiled(orc, X, Y, run(h, yq, C, B.OS_ANN_MODE_TILED),
-                       orc.search_tiled(X, o, Y, C, R=8, cones=True), (kind, "tiled", C))
+                       orc.search_tiled(X, o, Y, C, R=8, cones=True), (kind, "tiled", C), index=o, C=C)
     finally:
         B.os_ann_free(h)
 
@@ -90,7 +91,7 @@ def test_cones_empty_walks(orc):
             assert (g[2] == 0).any()
             same_fp32(g, orc.search(X, o, Y, C, cones=True), ("empty", C))
             same_tiled(orc, X, Y, run(h, yq, C, B.OS_ANN_MODE_TILED),
-                       orc.search_tiled(X, o, Y, C, R=8, cones=True), ("empty tiled", C))
+                       orc.search_tiled(X, o, Y, C, R=8, cones=True), ("empty tiled", C), index=o, C=C)
     finally:
         B.os_ann_free(h)
 

@@ -21,7 +21,7 @@ import torch
 
 from paper_1509_03453_amd import binding as B
 from paper_1509_03453_amd import workloads as W
-from tests.gpu_util import check_screened, dev, say, unpack_top
+from tests.gpu_util import candidates_of, check_screened, dev, say, unpack_top
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 RTOL = 1e-5
@@ -71,8 +71,9 @@ def tiled_sampled(orc, X, o, h, Y, yq, budget, sample, tag, R=8, max_mismatch=0.
     torch.cuda.synchronize()
     gi, gd, gn = gi.cpu().numpy()[sample], gd.cpu().numpy()[sample], gn.cpu().numpy()[sample]
     Ys = Y[sample]
-    o = orc.search_tiled(X, o, Ys, budget, R=R, cones=cones)
-    check_screened(orc, X, Ys, (gi, gd, gn), o, (tag, "tiled", budget), max_mismatch=max_mismatch)
+    ot = orc.search_tiled(X, o, Ys, budget, R=R, cones=cones)
+    check_screened(orc, X, Ys, (gi, gd, gn), ot, (tag, "tiled", budget), max_mismatch=max_mismatch,
+                   is_candidate=candidates_of(orc, o, Ys, budget, cones=cones))
 
 
 @pytest.fixture(scope="module")

@@ -37,13 +37,24 @@ def check_sparse(orc, X, Y, L, budgets, cones, tag):
         ti, ts = unpack_top(ex["top"].cpu().numpy().view(np.uint64), L)
         assert np.array_equal(ti, o["top"]) and np.array_equal(ts, o["sign"]), tag
         yq = dev(Y)
+        capped = torch.full((1,), -5, dtype=torch.int64, device="cuda")
+        cap = 1 << 22
         for budget, c in [(b, False) for b in budgets] + [(b, True) for b in cones]:
             say(f"[sparse] {tag} budget={budget} cones={c}")
-            gi, gd, gn = B.os_ann_search_ex(h, yq, budget, cones=c)
+            gi, gd, gn = B.os_ann_search_ex(h, yq, budget, cones=c, walks_capped=capped)
             torch.cuda.synchronize()
             gi, gd, gn = gi.cpu().numpy(), gd.cpu().numpy(), gn.cpu().numpy()
             oi, od32, od64, on = orc.search_sparse(X, o, Y, budget, cones=c)
             assert np.array_equal(gn, on), (tag, budget, c)
+            # walks the position cap stopped (reading R15): with a row budget
+            # below N those whose candidates fall short of it; with C cones,
+            # every walk when C and N_C both exceed the cap
+            nc = o["n_cones"]
+            if c:
+                want = len(Y) if (budget < nc and budget > cap and nc > cap) else 0
+            else:
+                want = int((on < budget).sum()) if budget < X.shape[0] else 0
+            assert int(capped.item()) == want, (tag, budget, c, int(capped.item()), want)
             assert np.array_equal(gi, oi), (tag, budget, c)
             assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), (tag, budget, c)
     finally:
@@ -96,3 +107,24 @@ def test_sparse_errors():
         assert B.lib().os_ann_export(h, cone.data_ptr(), None, None, None, None) == B.OS_ANN_ENOTSUP
     finally:
         B.os_ann_free(h)
+
+
+def _binoms_fit_32(D, L):
+    # every binomial the walk decode reads (C(D-1, k), k <= L) and the
+    # subset count C(D, L) below 2^32 (exact integers)
+    from math import comb
+    return max(comb(D - 1, k) for k in range(1, L + 1)) < 2 ** 32 and comb(D, L) < 2 ** 32
+
+
+def test_sparse_wide_binomials(orc):
+    # shapes whose walk decode needs 64-bit binomials (C(127, 6) and
+    # C(255, 5) exceed 2^32), with row budgets below N and walks of hundreds
+    # to thousands of positions, on clustered rows whose cones have
+    # populated neighbourhoods; the 32-bit shapes of the tests above stay
+    # on the other side of the switch
+    assert not _binoms_fit_32(128, 6) and not _binoms_fit_32(256, 5)
+    assert _binoms_fit_32(64, 5) and _binoms_fit_32(128, 4) and _binoms_fit_32(256, 3) and _binoms_fit_32(32, 6)
+    for D, L, seed in ((128, 6, 7311), (256, 5, 7313)):
+        X = W.prototype_rows(40, 100, D, L + 2, seed=seed)
+        Y = W.prototype_rows(40, 100, D, L + 2, noise=0.45, seed=seed)[::53].copy()  # the same prototypes
+        check_sparse(orc, X, Y, L, (1, 20, 50), (1, 300, 2500, 30000), f"clustered d{D} L{L}")

@@ -15,7 +15,7 @@ import torch
 
 from paper_1509_03453_amd import binding as B
 from paper_1509_03453_amd import workloads as W
-from tests.gpu_util import check_screened, dev, gpu_search, say
+from tests.gpu_util import candidates_of, check_screened, dev, gpu_search, say
 
 pytestmark = pytest.mark.gpu
 U = 2.0 ** -24
@@ -39,7 +39,7 @@ def check_tiled(orc, X, Y, L, budgets, R=8, tag="", max_mismatch=0.02):
             gi, gd, gn = gi.cpu().numpy(), gd.cpu().numpy(), gn.cpu().numpy()
             oi, od32, od64, on, dtr, top = orc.search_tiled(X, o, Y, budget, R=R)
             check_screened(orc, X, Y, (gi, gd, gn), (oi, od32, od64, on, dtr, top), (tag, budget),
-                           max_mismatch=max_mismatch)
+                           max_mismatch=max_mismatch, is_candidate=candidates_of(orc, o, Y, budget))
     finally:
         B.os_ann_free(h)
 
@@ -193,3 +193,48 @@ def test_graph_replay_matches_eager(orc, mode):
         assert np.array_equal(on.cpu().numpy(), eager[2])
         del junk
     B.os_ann_free(h)
+
+
+@pytest.mark.parametrize("case", ["gauss64", "gauss32_r16", "desc128_u8", "patch_f16", "gauss64_r4_q1"])
+def test_screen_kernels_agree(orc, monkeypatch, case):
+    # the cone-major screen (one list per (query, 64-cone word), queries
+    # compacted per cone) and the query-tile screen give the same result,
+    # which passes the screened comparison with the oracle; budgets are large
+    # enough that queries probe many cones (the cone-major screen's regime),
+    # query counts ragged against its 128-query blocks
+    R = 8
+    if case == "gauss64":
+        X, Y, L, budget = W.gaussian_db(60000, 64, seed=2601), W.gaussian_queries(1000, 64, seed=2602), 2, 9000
+    elif case == "gauss32_r16":
+        X, Y, L, budget, R = W.gaussian_db(30000, 32, seed=2603), W.gaussian_queries(301, 32, seed=2604), 2, 6000, 16
+    elif case == "desc128_u8":
+        X = W.descriptor_db(30000, 128, seed=2605)
+        Y, _ = W.descriptor_queries(X, 257)
+        L, budget = 2, 3000
+    elif case == "patch_f16":
+        img = W.patch_field(192)
+        X = W.patch_rows(img)
+        Y = W.patch_rows(np.roll(img, (3, 5), axis=(0, 1)) + np.random.default_rng(11).normal(0, 0.05, img.shape))[::37]
+        L, budget = 2, 8000
+    else:
+        X, Y, L, budget, R = W.gaussian_db(20000, 64, seed=2606), W.gaussian_queries(1, 64, seed=2607), 2, 4000, 4
+    h = B.os_ann_build_ex(dev(X), L)
+    yd = dev(Y)
+    outs = {}
+    try:
+        for kern in ("cone", "tile"):
+            monkeypatch.setenv("OSANN_TILED_KERNEL", kern)
+            say(f"[tiled] {case} kernel={kern} Q={len(Y)} budget={budget} R={R}")
+            i, d, n = B.os_ann_search_ex(h, yd, budget, mode=B.OS_ANN_MODE_TILED, rerank_r=R)
+            torch.cuda.synchronize()
+            outs[kern] = (i.cpu().numpy(), d.cpu().numpy(), n.cpu().numpy())
+        monkeypatch.delenv("OSANN_TILED_KERNEL")
+        ix = orc.build_index(X, L)
+        o = orc.search_tiled(X, ix, Y, budget, R=R)
+        cand = candidates_of(orc, ix, Y, budget)
+        check_screened(orc, X, Y, outs["tile"], o, (case, "query-tile"), is_candidate=cand)
+        check_screened(orc, X, Y, outs["cone"], o, (case, "cone-major"), is_candidate=cand)
+        for a, b in zip(outs["cone"], outs["tile"]):
+            assert np.array_equal(a, b), case
+    finally:
+        B.os_ann_free(h)

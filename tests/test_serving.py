@@ -65,12 +65,13 @@ def test_poisson_arrivals():
 def _make_mix(n_req, rate, max_q):
     import torch
     from paper_1509_03453_amd import binding as B
-    from gpu_util import dev, say
+    from tests.gpu_util import dev, say
 
     say("[serving] building three resident indexes")
     g16 = W.gaussian_db(16384, 16, W.SEEDS["gauss16_db"])
     g64 = W.gaussian_db(60000, 64, W.SEEDS["gauss64_db"])
     d128 = W.descriptor_db(30000, 128)
+    host = {"gauss16": (g16, 1), "gauss64": (g64, 2), "desc128": (d128, 2)}
     ixs = [S.ResidentIndex("gauss16", B.Index(dev(g16), 1, want_lowp=True), budget=512),
            S.ResidentIndex("gauss64", B.Index(dev(g64), 2, want_lowp=True), budget=2048),
            S.ResidentIndex("desc128", B.Index(dev(d128), 2, want_lowp=True), budget=1024)]
@@ -86,17 +87,17 @@ def _make_mix(n_req, rate, max_q):
     reqs = [S.Request(i, names[w], queries(names[w], n, s), a)
             for i, (a, w, n, s) in enumerate(W.serving_requests(n_req, rate, 3, max_q=max_q, seed=77))]
     torch.cuda.synchronize()
-    return ixs, reqs, queries
+    return ixs, reqs, queries, host
 
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("mode", ["tiled", "fp32"])
-def test_serving_mix_equals_alone(mode):
+def test_serving_mix_equals_alone(orc, mode):
     import torch
     from paper_1509_03453_amd import binding as B
-    from gpu_util import say
+    from tests.gpu_util import candidates_of, check_screened, say
 
-    ixs, reqs, queries = _make_mix(n_req=60, rate=3000.0, max_q=700)
+    ixs, reqs, queries, host = _make_mix(n_req=60, rate=3000.0, max_q=700)
     m = B.OS_ANN_MODE_TILED if mode == "tiled" else B.OS_ANN_MODE_FP32
     for ix in ixs:
         ix.mode = m
@@ -110,14 +111,59 @@ def test_serving_mix_equals_alone(mode):
     assert st["batches"] < len(reqs)           # requests were packed together
     assert st["max_concurrent_launches"] >= 2  # launches overlapped on several streams
     assert st["p99_ms"] >= st["p50_ms"] > 0
+    # the two clocks are tied to within tens of microseconds, steadily
+    assert abs(st["clock_offset_us"]["drift"]) < 200 and st["clock_offset_us"]["before_spread"] < 500
     byname = {ix.name: ix for ix in ixs}
     for r in reqs:
-        assert r.done is not None and r.done >= r.arrival
+        assert r.done is not None and r.latency > 0 and r.lag >= 0
         ix = byname[r.index]
         i1, d1, _ = B.os_ann_search_ex(ix.index.handle, r.queries, ix.budget, mode=m, rerank_r=ix.rerank_r)
         torch.cuda.synchronize()
         assert torch.equal(i1, r.out_idx), f"request {r.rid} ({r.index}, {r.n} queries): indices differ"
         assert torch.equal(d1, r.out_dist), f"request {r.rid}: distances differ"
+    # what the server returned, against the oracle: every fifth request of each index
+    oidx = {name: orc.build_index(X, L) for name, (X, L) in host.items()}
+    for name, (X, L) in host.items():
+        rr = [r for r in reqs if r.index == name][::5]
+        Y = np.concatenate([r.queries.cpu().numpy() for r in rr])
+        gi = torch.cat([r.out_idx for r in rr]).cpu().numpy()
+        gd = torch.cat([r.out_dist for r in rr]).cpu().numpy()
+        budget = byname[name].budget
+        say(f"[serving] {mode} {name}: {len(rr)} served requests ({len(Y)} queries) against the oracle")
+        if m == B.OS_ANN_MODE_FP32:
+            oi, od32, od64, on = orc.search(X, oidx[name], Y, budget)
+            assert np.array_equal(gi, oi), name
+            assert np.array_equal(gd.view(np.uint32), od32.view(np.uint32)), name
+        else:
+            o = orc.search_tiled(X, oidx[name], Y, budget, R=8)
+            check_screened(orc, X, Y, (gi, gd, o[3]), o, ("serving", name),
+                           is_candidate=candidates_of(orc, oidx[name], Y, budget))
+    for ix in ixs:
+        ix.index.close()
+
+
+@pytest.mark.gpu
+def test_serving_load_sweep():
+    # saturation, then load points below it: every request is served, latency
+    # parts are positive, and throughput does not exceed what was offered by
+    # more than the arrival noise
+    ixs, reqs, queries, host = _make_mix(n_req=8, rate=1.0, max_q=400)
+    srv = S.Server(ixs, slots=4, max_batch=1024, pool_cap_bytes=1 << 30, reserve_bytes=256 << 20)
+    srv.warmup({ix.name: queries(ix.name, 1024, 99) for ix in ixs})
+    arrivals = W.serving_requests(260, 1.0, 3, max_q=400, seed=78)
+    qs = [queries(ixs[w].name, n, sd) for (_, w, n, sd) in arrivals]
+
+    def make(rate):
+        t = [0.0 if rate == float("inf") else a / rate for (a, _, _, _) in arrivals]
+        return [S.Request(i, ixs[w].name, qs[i], t[i]) for i, (_, w, _, _) in enumerate(arrivals)]
+
+    out, last = S.load_sweep(srv, make, fractions=(0.5, 0.9), warmup_requests=20, saturation_requests=200)
+    assert len(last) == 260 and all(r.out_idx is not None for r in last)
+    assert out["saturation"]["req_per_s"] > 0
+    for pt in out["points"]:
+        assert pt["measured_requests"] == 240
+        assert pt["p99_ms"] >= pt["p50_ms"] > 0
+        assert pt["req_per_s"] <= 1.5 * pt["offered_req_per_s"]
     for ix in ixs:
         ix.index.close()
 
@@ -127,7 +173,7 @@ def test_serving_pool_cap_serialises_and_rejects():
     import torch
     from paper_1509_03453_amd import binding as B
 
-    ixs, reqs, queries = _make_mix(n_req=12, rate=5000.0, max_q=300)
+    ixs, reqs, queries, host = _make_mix(n_req=12, rate=5000.0, max_q=300)
     need = max(S.Server(ixs).need_bytes(byn, 300, 128 * 4) for byn in ixs)
     srv = S.Server(ixs, slots=4, max_batch=300, pool_cap_bytes=need, reserve_bytes=0)
     st = srv.run(reqs, max_seconds=120)
@@ -149,7 +195,7 @@ def test_serving_pool_cap_serialises_and_rejects():
 def test_choose_mode_returns_the_faster_valid_mode():
     import torch
     from paper_1509_03453_amd import binding as B
-    from gpu_util import dev
+    from tests.gpu_util import dev
 
     X = W.gaussian_db(50000, 64, seed=5101)
     Y = dev(W.gaussian_queries(2048, 64, seed=5102))
