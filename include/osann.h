@@ -224,6 +224,31 @@ int os_ann_search_ex(const os_ann_index *idx, const void *queries, int64_t Q,
                      int64_t *out_idx, float *out_dist, int64_t *out_ncand);
 
 /*
+ * For callers that can not allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP32
+ * search of os_ann_search_ex, allocating nothing.  Its scratch (the queries'
+ * FP32 copies and walk state, O(D) bytes per query) is a fixed 64 MiB device
+ * array inside the library, one copy per GPU, held until the process ends;
+ * the call makes no hipMalloc, hipFree or other allocating call.  The caller
+ * still passes the queries and the outputs (device memory, as for
+ * os_ann_search_ex; out_ncand may be NULL).
+ * opts may be NULL; its mode must be OS_ANN_MODE_FP32 (tiled: ENOTSUP), its
+ * workspace NULL and its flags at most OS_ANN_FLAG_BUDGET_CONES (EINVAL
+ * otherwise).  Any index kind searchable in FP32 mode works.  A batch whose
+ * scratch exceeds 64 MiB (about 160,000 queries at D = 64, 43,000 at
+ * D = 256; os_ann_workspace_bytes in FP32 mode gives the need) is rejected
+ * with EINVAL: split it.  Asynchronous on opts->stream.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads, or one issued before the previous one's stream has
+ * finished reading it) race and give wrong results; serialise them.  No
+ * part of the array needs to start at zero.
+ * Errors: EINVAL, ENOTSUP, EDEVICE.
+ */
+int os_ann_search_static(const os_ann_index *idx, const void *queries, int64_t Q,
+                         int64_t max_candidates, const os_ann_search_opts *opts,
+                         int64_t *out_idx, float *out_dist, int64_t *out_ncand);
+
+/*
  * Principal axes of the database, for the PCA front-end of Section 4.B
  * (classify on the first principal components, compare on all of them).
  * The float64 mean and covariance (sum of the centred outer products divided

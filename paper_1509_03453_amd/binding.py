@@ -68,6 +68,8 @@ SIGNATURES = {
     "os_ann_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]),
     "os_ann_search_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                    C.POINTER(os_ann_search_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "os_ann_search_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                       C.POINTER(os_ann_search_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
     "os_ann_workspace_bytes": (C.c_int64, [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(os_ann_search_opts)]),
     "os_ann_classify": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int64,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -300,6 +302,23 @@ def os_ann_search_ex(index: int, queries: torch.Tensor, max_candidates: int, mod
     if rc:
         _raise(rc)
     return out_idx, out_dist, out_ncand
+
+
+def os_ann_search_static(index: int, queries: torch.Tensor, max_candidates: int, out_idx: torch.Tensor,
+                         out_dist: torch.Tensor, out_ncand: torch.Tensor | None = None, stream=None,
+                         cones: bool = False) -> None:
+    """FP32 search into caller-owned outputs with the library's fixed device
+    scratch (no allocation by the library)."""
+    o = _search_opts(queries, OS_ANN_MODE_FP32, stream, None, 8, OS_ANN_FLAG_BUDGET_CONES if cones else 0)
+    Q = queries.shape[0]
+    for t, dt, what in ((out_idx, torch.int64, "out_idx"), (out_dist, torch.float32, "out_dist"),
+                        (out_ncand, torch.int64, "out_ncand")):
+        if t is not None and (t.dtype != dt or t.numel() < Q or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{what} must be a contiguous GPU {dt} tensor of at least {Q} elements")
+    rc = lib().os_ann_search_static(index, _ptr(queries), Q, int(max_candidates), C.byref(o),
+                                    _ptr(out_idx), _ptr(out_dist), _ptr(out_ncand))
+    if rc:
+        _raise(rc)
 
 
 def os_ann_workspace_bytes(index: int, Q: int, max_candidates: int, mode: int = OS_ANN_MODE_FP32,

@@ -25,6 +25,14 @@
 
 using namespace osann;
 
+// Scratch of os_ann_search_static: a fixed device array, one copy per GPU the
+// library runs on, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): it takes the device address from hipGetSymbolAddress once per
+// device and uses that.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 thread_local int g_err = OS_ANN_OK;
@@ -2030,6 +2038,59 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     const bool graph = opts && (opts->flags & OS_ANN_FLAG_GRAPH) && c.s;
     if (graph) return run_graph(c, S);
     OSANN_HIP(enqueue(c, S), mode == OS_ANN_MODE_TILED ? "tiled search" : "fp32 search");
+    return OS_ANN_OK;
+}
+
+int os_ann_search_static(const os_ann_index* cidx, const void* queries, int64_t Q, int64_t max_candidates,
+                         const os_ann_search_opts* opts, int64_t* out_idx, float* out_dist, int64_t* out_ncand) {
+    clear_error();
+    int rc = search_checks(cidx, queries, Q, max_candidates, opts);
+    if (rc) return rc;
+    if (opts && opts->mode != OS_ANN_MODE_FP32)
+        return fail(OS_ANN_ENOTSUP, "search_static: FP32 mode only (tiled mode builds its low-precision copy on first use)");
+    if (opts && opts->workspace) return fail(OS_ANN_EINVAL, "search_static: takes no workspace");
+    if (opts && (opts->flags & ~OS_ANN_FLAG_BUDGET_CONES))
+        return fail(OS_ANN_EINVAL, "search_static: only OS_ANN_FLAG_BUDGET_CONES applies");
+    if (Q == 0) return OS_ANN_OK;
+    if (!out_idx || !out_dist) return fail(OS_ANN_EINVAL, "null output");
+    auto* ix = const_cast<os_ann_index*>(cidx);
+    const bool cones = opts && (opts->flags & OS_ANN_FLAG_BUDGET_CONES);
+    Call c{};
+    c.ix = ix;
+    c.queries = queries;
+    c.qtype = opts ? opts->query_dtype : kF32;
+    c.Q = Q;
+    c.budget = max_candidates;
+    c.out_idx = out_idx;
+    c.out_dist = out_dist;
+    c.out_ncand = out_ncand;
+    c.walks_capped = opts ? opts->walks_capped : nullptr;
+    c.s = opts ? static_cast<hipStream_t>(opts->stream) : nullptr;
+    c.timing = false;
+    c.p = plan_search(ix, Q, max_candidates, OS_ANN_MODE_FP32, 8, cones);
+    if (c.p.bytes > kStaticScratchBytes) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "search_static: %lld queries need %zu bytes of scratch, the static scratch holds %zu "
+                      "(split the batch)", (long long)Q, c.p.bytes, kStaticScratchBytes);
+        return fail(OS_ANN_EINVAL, msg);
+    }
+    // the device address of this GPU's copy of the array, looked up once
+    static std::mutex mu;
+    static std::unordered_map<int, void*> addr;
+    int dev = 0;
+    OSANN_HIP(hipGetDevice(&dev), "search_static: current device");
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = addr.find(dev);
+        if (it == addr.end()) {
+            void* p = nullptr;
+            OSANN_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "search_static: scratch address");
+            it = addr.emplace(dev, p).first;
+        }
+        c.base = static_cast<char*>(it->second);
+    }
+    OSANN_HIP(enqueue(c, 1), "search_static");
     return OS_ANN_OK;
 }
 
