@@ -20,7 +20,7 @@ and against the achievable peaks the probes in calibrate.hip measure.
 Prints ONE JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                     [--mode fp32|tiled|both] [--budget B] [--no-<leg> ...]
-    python bench.py --only descriptor|out-of-cache|serving|patches
+    python bench.py --only descriptor|out-of-cache|serving|patches|bases|sparse
     python bench.py --calibrate
 """
 from __future__ import annotations
@@ -765,7 +765,8 @@ def main():
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-table leg")
     ap.add_argument("--no-descriptor", action="store_true", help="skip the 1e6 x 128 uint8 descriptor leg")
     ap.add_argument("--no-out-of-cache", action="store_true", help="skip the 4e6 x 64 FP32 scan leg")
-    ap.add_argument("--only", choices=("descriptor", "out-of-cache", "serving", "patches"), default=None,
+    ap.add_argument("--only", choices=("descriptor", "out-of-cache", "serving", "patches", "bases", "sparse"),
+                    default=None,
                     help="run one leg alone (with calibration) and print its JSON")
     ap.add_argument("--calibrate", action="store_true",
                     help="print the achievable peaks (and a 2 GiB device copy for PMC byte counters) and exit")
@@ -792,6 +793,13 @@ def main():
         if args.only == "serving":
             X = W.gaussian_db(N_DB, DIM, W.SEEDS["gauss64_db"])
             leg["serving"] = lambda: serving_leg(X, torch.from_numpy(X).cuda(), args.budget or 327680)
+        if args.only in ("bases", "sparse"):
+            X = W.gaussian_db(N_DB, DIM, W.SEEDS["gauss64_db"])
+            db = torch.from_numpy(X).cuda()
+            q = torch.from_numpy(W.gaussian_queries(N_Q, DIM, W.SEEDS["gauss64_q"])).cuda()
+            _, nn_d64 = exact_nn_torch(db, q)
+            leg["bases"] = lambda: bases_leg(X, db, q, nn_d64)
+            leg["sparse"] = lambda: sparse_leg(db, q, nn_d64)
         print(json.dumps({args.only: leg[args.only](), "calibration": calib}), flush=True)
         return
 

@@ -1,6 +1,7 @@
 // Bucket build: one cone-bucketed table of the database (Section 4).
 //
-//  * sort_by_cone   stable LSD radix sort of row ids by cone, 8-bit digits.
+//  * sort_by_cone   stable LSD radix sort of row ids by cone, 8-bit digits
+//                   (also on 64-bit keys, for the sparse second-level table).
 //                   Each block owns a contiguous chunk of the input; the rank
 //                   of an element inside its block comes from wave ballots
 //                   (lanes of equal digit below it) plus per-wave counts in
@@ -26,26 +27,25 @@ int64_t radix_hist_words(int64_t N) {
     return 2 * h + 1 + exclusive_scan_tmp_words(h);  // counts, scanned counts, scan scratch
 }
 
-__global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                                   int64_t N, int shift,
-                                                                   uint32_t* __restrict__ hist,
-                                                                   int64_t nb) {
+template <typename K>
+__global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const K* __restrict__ keys, int64_t N, int shift,
+                                                                   uint32_t* __restrict__ hist, int64_t nb) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixChunk;
     for (int t = 0; t < kRadixChunk; t += kRadixThreads) {
         int64_t i = base + t + threadIdx.x;
-        if (i < N) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);  // counts only
+        if (i < N) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);  // counts only
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+template <typename K>
 __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, int64_t N, int shift,
-    const uint32_t* __restrict__ hist, int64_t nb, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out) {
+    const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, int64_t N, int shift,
+    const uint32_t* __restrict__ hist, int64_t nb, K* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
     constexpr int kWaves = kRadixThreads / 64;
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[kWaves][256];
@@ -58,9 +58,9 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
         __syncthreads();
         const int64_t i = base + t + tid;
         const bool valid = i < N;
-        const uint32_t key = valid ? keys_in[i] : 0u;
+        const K key = valid ? keys_in[i] : K(0);
         const uint32_t val = valid ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
-        const uint32_t dig = (key >> shift) & 255u;
+        const uint32_t dig = (uint32_t)(key >> shift) & 255u;
         // lanes of this wave holding the same digit
         uint64_t same = __ballot(valid);
 #pragma unroll
@@ -106,11 +106,50 @@ hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_co
         const bool last = p == passes - 1;
         uint32_t* kout = last ? sorted_cone_out : ((p & 1) ? kb : ka);
         uint32_t* vout = last ? perm_out : ((p & 1) ? vb : va);
-        hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin, N,
+        hipLaunchKernelGGL(radix_hist_kernel<uint32_t>, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin, N,
                            8 * p, hist, nb);
         hipError_t e = launch_exclusive_scan(hist, hw, hscan, stmp, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin,
+        hipLaunchKernelGGL(radix_scatter_kernel<uint32_t>, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin,
+                           vin, N, 8 * p, hscan, nb, kout, vout);
+        kin = kout;
+        vin = vout;
+    }
+    return hipGetLastError();
+}
+
+// The same sort on 64-bit keys (bits [0, end_bit) decide the order): row
+// ids by key, ties in ascending row id.  tmp layout, in bytes: two key
+// arrays of N u64, two id arrays of N u32, then the digit counts.
+size_t radix_sort_u64_tmp_bytes(int64_t N) {
+    return (size_t)N * 24 + (size_t)radix_hist_words(N) * 4;
+}
+
+hipError_t launch_radix_sort_u64(const uint64_t* key_in, int64_t N, int end_bit, void* tmp, uint64_t* key_out,
+                                 uint32_t* perm_out, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    if (end_bit < 1 || end_bit > 64 || N > 0xFFFFFFFFll) return hipErrorInvalidValue;
+    const int passes = (end_bit + 7) / 8;
+    const int64_t nb = radix_blocks(N);
+    uint64_t* ka = static_cast<uint64_t*>(tmp);
+    uint64_t* kb = ka + N;
+    uint32_t* va = reinterpret_cast<uint32_t*>(kb + N);
+    uint32_t* vb = va + N;
+    const int64_t hw = 256 * nb;
+    uint32_t* hist = vb + N;
+    uint32_t* hscan = hist + hw;
+    uint32_t* stmp = hscan + hw + 1;
+    const uint64_t* kin = key_in;
+    const uint32_t* vin = nullptr;  // identity on the first pass
+    for (int p = 0; p < passes; ++p) {
+        const bool last = p == passes - 1;
+        uint64_t* kout = last ? key_out : ((p & 1) ? kb : ka);
+        uint32_t* vout = last ? perm_out : ((p & 1) ? vb : va);
+        hipLaunchKernelGGL(radix_hist_kernel<uint64_t>, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin, N,
+                           8 * p, hist, nb);
+        hipError_t e = launch_exclusive_scan(hist, hw, hscan, stmp, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(radix_scatter_kernel<uint64_t>, dim3((unsigned)nb), dim3(kRadixThreads), 0, s, kin,
                            vin, N, 8 * p, hscan, nb, kout, vout);
         kin = kout;
         vin = vout;

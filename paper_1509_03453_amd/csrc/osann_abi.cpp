@@ -867,10 +867,17 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     sd.D = ix->Dk;  // the walk state's length
     sd.L = ix->L;
     // The seed reads up to sd.rows padded rows from the first cones of each
-    // query's walk; keep that near a sixteenth of the budget (64 .. 1024
-    // rows), a small share of what the screen then reads per query.
+    // query's walk, one query at a time (no row is shared between queries):
+    // keep that near a sixteenth of the budget, 64 .. 512 rows.  Past 512 the
+    // seed costs more than the tighter bound saves the screen (1e6 x 64
+    // Gaussian rows, 1e4 queries: 2.83 ms per search at 512 rows against
+    // 3.00 ms at 1024).
     const int64_t rows = expected_rows(ix, c.budget, p.cones);
-    sd.rows = (int)std::min<int64_t>(1024, std::max<int64_t>(64, pow2_ceil(std::max<int64_t>(rows / 16, 1))));
+    sd.rows = (int)std::min<int64_t>(512, std::max<int64_t>(64, pow2_ceil(std::max<int64_t>(rows / 16, 1))));
+    if (const char* env = std::getenv("OSANN_TILED_SEED_ROWS")) {  // fixed seed size (testing)
+        const int v = std::atoi(env);
+        if (v >= 64 && v <= 1024 && v % 64 == 0) sd.rows = v;
+    }
     e = launch_tiled_seed(sd, p.R, ix->lp.f16, c.s);
     if (e != hipSuccess) return e;
     TiledArgs ta{};

@@ -54,6 +54,13 @@ hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_co
                                uint32_t* tmp, uint32_t* perm_out, uint32_t* sorted_cone_out,
                                hipStream_t s);
 
+// The same stable sort on 64-bit keys, by bits [0, end_bit) (1..64): row ids
+// (0..N-1) by key to perm_out, sorted keys to key_out.  tmp holds
+// radix_sort_u64_tmp_bytes(N) bytes.
+size_t radix_sort_u64_tmp_bytes(int64_t N);
+hipError_t launch_radix_sort_u64(const uint64_t* key_in, int64_t N, int end_bit, void* tmp, uint64_t* key_out,
+                                 uint32_t* perm_out, hipStream_t s);
+
 // Bucket offsets from the sorted cones.
 hipError_t launch_offsets(const uint32_t* sorted_cone, int64_t N, int64_t n_cones,
                           uint32_t* offsets, hipStream_t s);

@@ -19,29 +19,73 @@
 namespace osann {
 
 // out[n][i] = sum_j M[i][j] x[n][j] in FP32, ascending j, each product and
-// sum rounded separately; one thread per (row, output component).
+// sum rounded separately.  A block of 256 threads takes 64 rows and 64
+// output components; for each chunk of 32 j it stages the chunk of the 64
+// rows and of the 64 matrix rows in LDS (each element read from memory
+// once per block), and thread (tr, ti) adds the chunk's terms, in ascending
+// j, to its 4 x 4 sums: rows tr + 16a, components ti + 16b.  Only j < D
+// terms are added, so every sum is the same sequence of roundings as the
+// plain loop.
+constexpr int kRotTile = 64;
+constexpr int kRotChunk = 32;
+
 template <typename E>
-__global__ void rotate_kernel(const void* __restrict__ X, int64_t N, int D, const float* __restrict__ M,
-                              float* __restrict__ out) {
+__global__ __launch_bounds__(256) void rotate_kernel(const void* __restrict__ X, int64_t N, int D,
+                                                     const float* __restrict__ M, float* __restrict__ out) {
 #pragma clang fp contract(off)
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * D) return;
-    const int64_t n = t / D;
-    const int i = (int)(t % D);
-    auto x = static_cast<const typename E::raw*>(X) + n * D;
-    const float* m = M + (int64_t)i * D;
-    float acc = 0.0f;
-    for (int j = 0; j < D; ++j) {
-        const float pr = m[j] * E::val(x[j]);
-        acc = acc + pr;
+    __shared__ float sx[kRotTile][kRotChunk + 1];  // +1: rows fall in different banks
+    __shared__ float sm[kRotTile][kRotChunk + 1];
+    const int t = threadIdx.x, ti = t % 16, tr = t / 16;
+    const int64_t n0 = (int64_t)blockIdx.x * kRotTile;
+    const int i0 = (int)blockIdx.y * kRotTile;
+    auto x = static_cast<const typename E::raw*>(X);
+    float acc[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[q][b] = 0.0f;
+    for (int j0 = 0; j0 < D; j0 += kRotChunk) {
+        const int jn = D - j0 < kRotChunk ? D - j0 : kRotChunk;
+        for (int e = t; e < kRotTile * kRotChunk; e += 256) {
+            const int r = e / kRotChunk, jj = e % kRotChunk;
+            const int64_t n = n0 + r;
+            const int i = i0 + r;
+            sx[r][jj] = n < N && jj < jn ? E::val(x[n * D + j0 + jj]) : 0.0f;
+            sm[r][jj] = i < D && jj < jn ? M[(int64_t)i * D + j0 + jj] : 0.0f;
+        }
+        __syncthreads();
+        for (int jj = 0; jj < jn; ++jj) {
+            float xv[4], mv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[q] = sx[tr + 16 * q][jj];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) mv[b] = sm[ti + 16 * b][jj];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const float pr = mv[b] * xv[q];
+                    acc[q][b] = acc[q][b] + pr;
+                }
+        }
+        __syncthreads();
     }
-    out[t] = acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t n = n0 + tr + 16 * q;
+        if (n >= N) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + ti + 16 * b;
+            if (i < D) out[n * D + i] = acc[q][b];
+        }
+    }
 }
 
 hipError_t launch_rotate(const void* X, int dtype, int64_t N, int D, const float* M, float* out, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    const int64_t n = N * D;
-    const dim3 grid((unsigned)((n + 255) / 256));
+    if (D <= 0 || (N + kRotTile - 1) / kRotTile > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((N + kRotTile - 1) / kRotTile), (unsigned)((D + kRotTile - 1) / kRotTile));
     switch (dtype) {
         case kF32: hipLaunchKernelGGL(rotate_kernel<F32>, grid, dim3(256), 0, s, X, N, D, M, out); break;
         case kF16: hipLaunchKernelGGL(rotate_kernel<F16>, grid, dim3(256), 0, s, X, N, D, M, out); break;

@@ -12,8 +12,6 @@
 // element), then the cone id is looked up; a missing id is an empty cone.
 // Walk and scan run in one pass, since the cones of a sparse table hold few
 // rows and a second walk would cost as much as the first.
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/iterator/counting_iterator.hpp>
 
 #include "osann_device.h"
 #include "osann_kernels.h"
@@ -309,19 +307,15 @@ hipError_t launch_sparse_keys(const uint64_t* row_top, int64_t N, int L, const u
 }
 
 size_t sparse_sort_tmp_bytes(int64_t N, int end_bit) {
-    size_t bytes = 0;
-    (void)rocprim::radix_sort_pairs(nullptr, bytes, static_cast<const uint64_t*>(nullptr),
-                                    static_cast<uint64_t*>(nullptr), rocprim::counting_iterator<uint32_t>(0u),
-                                    static_cast<uint32_t*>(nullptr), (unsigned)N, 0u, (unsigned)end_bit);
-    return bytes;
+    (void)end_bit;
+    return radix_sort_u64_tmp_bytes(N);
 }
 
 hipError_t launch_sparse_sort(const uint64_t* key_in, uint64_t* key_out, uint32_t* perm, int64_t N, int end_bit,
                               void* tmp, size_t tmp_bytes, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    size_t bytes = tmp_bytes;
-    return rocprim::radix_sort_pairs(tmp, bytes, key_in, key_out, rocprim::counting_iterator<uint32_t>(0u), perm,
-                                     (unsigned)N, 0u, (unsigned)end_bit, s);
+    if (tmp_bytes < radix_sort_u64_tmp_bytes(N)) return hipErrorInvalidValue;
+    return launch_radix_sort_u64(key_in, N, end_bit, tmp, key_out, perm, s);
 }
 
 hipError_t launch_sparse_heads(const uint64_t* sorted, int64_t N, uint32_t* flag, hipStream_t s) {
