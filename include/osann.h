@@ -78,10 +78,15 @@ extern "C" {
 
 /* Search flags. */
 #define OS_ANN_FLAG_TIME_KERNELS 1  /* record HIP events around each kernel launch */
-#define OS_ANN_FLAG_GRAPH        2  /* capture the launch sequence in a hipGraph on the
-                                       first call with these exact arguments (pointers,
-                                       sizes, stream; non-null stream only) and replay it
-                                       on later identical calls */
+#define OS_ANN_FLAG_GRAPH        2  /* run the search as a hipGraph of its shape class
+                                       (stream, Q rounded up to one of 8 steps per
+                                       octave, query type, mode, R, cone budget, budget),
+                                       captured on the class's first call and replayed on
+                                       later calls with any buffers: the queries are
+                                       copied into buffers the index keeps per stream,
+                                       the results out of them; `workspace` is not used.
+                                       Needs a non-null stream that is not being
+                                       captured (else OS_ANN_EINVAL) */
 #define OS_ANN_FLAG_BUDGET_CONES 4  /* fixed-C mode (Section 3, Table III): max_candidates
                                        is the number C of cones each walk takes, empty
                                        ones included, not a number of rows; with several
@@ -382,6 +387,12 @@ int os_ann_kernel_time(const os_ann_index *idx, int32_t kernel, int64_t *launche
  * N, D, L, number of cones, number of non-empty cones, device bytes held. */
 int os_ann_info(const os_ann_index *idx, int64_t *N, int32_t *D, int32_t *L,
                 int64_t *n_cones, int64_t *n_nonempty, int64_t *device_bytes);
+
+/* Graph replay statistics of an index (OS_ANN_FLAG_GRAPH): graphs captured
+ * so far, graph replays so far, and graphs currently kept (at most 512 per
+ * index; the least recently replayed is dropped first).  Any output may be
+ * NULL.  Host-side counters; no device work. */
+int os_ann_graph_stats(const os_ann_index *idx, int64_t *captured, int64_t *replayed, int64_t *cached);
 
 /* Release the index.  The caller makes sure no search on it is in flight.
  * Waits for the device to finish its work (as hipFree does); the index's

@@ -83,6 +83,8 @@ SIGNATURES = {
                               C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "os_ann_free": (None, [C.c_void_p]),
     "os_ann_trim": (C.c_int, []),
+    "os_ann_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]),
     "os_ann_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, C.c_void_p]),
     "os_ann_last_error": (C.c_int, []),
     "os_ann_last_error_message": (C.c_char_p, []),
@@ -363,6 +365,15 @@ def os_ann_info(index: int) -> dict:
         _raise(rc)
     return {"N": N.value, "D": D.value, "L": L.value, "n_cones": nc.value, "n_nonempty": ne.value,
             "device_bytes": nb.value}
+
+
+def os_ann_graph_stats(index: int) -> dict:
+    """Graphs captured, graph replays and graphs kept by an index."""
+    cap, rep, kept = C.c_int64(), C.c_int64(), C.c_int64()
+    rc = lib().os_ann_graph_stats(index, C.byref(cap), C.byref(rep), C.byref(kept))
+    if rc:
+        _raise(rc)
+    return {"captured": cap.value, "replayed": rep.value, "cached": kept.value}
 
 
 def os_ann_export(index: int, stream=None) -> dict:

@@ -82,11 +82,29 @@ struct LowpCopy {
     uint32_t* ipos = nullptr;  // padded position of each original row
 };
 
+// Graph replay by shape class.  The graphs captured on one stream read and
+// write that stream's arena: the search scratch, the staged queries and the
+// outputs, sized for the largest class captured there so far.  Calls on one
+// stream run in order, so its graphs can share the arena.
+struct GraphArena {
+    hipStream_t s = nullptr;
+    int64_t cap_q = 0;     // query rows the staging and output buffers hold
+    int qtype = -1;        // element type the staged rows were last written in
+    size_t ws_bytes = 0;
+    char* ws = nullptr;
+    void* q = nullptr;     // [cap_q][D] elements of up to 4 bytes
+    int64_t* oidx = nullptr;
+    float* odist = nullptr;
+    int64_t* oncand = nullptr;
+    int64_t* capped = nullptr;
+};
 struct GraphEntry {
-    std::vector<int64_t> key;
+    std::vector<int64_t> key;  // stream, query class, query type, mode, R, cone budget, budget, capped count
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;         // last replay (the least recently used goes first)
 };
+constexpr size_t kMaxGraphs = 512;  // per index: a few streams times the classes up to 8192 queries
 
 struct os_ann_index {
     int64_t N = 0;
@@ -118,9 +136,12 @@ struct os_ann_index {
     };
     std::mutex time_mu;
     std::vector<Timed> timed;
-    // captured search sequences
+    // captured search sequences, by shape class, and their per-stream arenas
     std::mutex graph_mu;
     std::vector<GraphEntry> graphs;
+    std::vector<GraphArena> arenas;
+    uint64_t graph_tick = 0;
+    int64_t graph_captures = 0, graph_replays = 0;
     // several bases (Section 3.A): one table per basis; this index then owns
     // the tables, the bases and their gathered copies
     int n_rot = 0;
@@ -297,12 +318,23 @@ int dev_alloc(os_ann_index* ix, void** p, size_t bytes, const char* what) {
     return OS_ANN_OK;
 }
 
+void destroy_graph(GraphEntry& g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
+}
+
 void drop_graphs(os_ann_index* ix) {
-    for (auto& g : ix->graphs) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        if (g.graph) (void)hipGraphDestroy(g.graph);
-    }
+    for (auto& g : ix->graphs) destroy_graph(g);
     ix->graphs.clear();
+}
+
+void free_arena(os_ann_index* ix, GraphArena& a) {
+    void* ptrs[] = {a.ws, a.q, a.oidx, a.odist, a.oncand, a.capped};
+    for (void* p : ptrs) dev_free(p);
+    ix->device_bytes -= a.ws_bytes + (size_t)a.cap_q * (ix->D * 4 + 20) + 8;
+    a = GraphArena{a.s};
 }
 
 void release(os_ann_index* ix, bool synced = false) {
@@ -313,6 +345,7 @@ void release(os_ann_index* ix, bool synced = false) {
         (void)hipEventDestroy(t.stop);
     }
     drop_graphs(ix);
+    for (auto& a : ix->arenas) free_arena(ix, a);
     for (auto* t : ix->sub) release(t, true);
     void* ptrs[] = {ix->row_cone, ix->row_top,  ix->perm,       ix->sorted_cone, ix->offsets,
                     ix->planes,   ix->lexsub,   ix->maskord,    ix->binom,       ix->scratch,
@@ -553,8 +586,6 @@ int get_scratch(os_ann_index* ix, const os_ann_search_opts* o, size_t bytes, cha
             ix->device_bytes -= ix->scratch_bytes;
             ix->scratch = nullptr;
             ix->scratch_bytes = 0;
-            std::lock_guard<std::mutex> gg(ix->graph_mu);  // graphs captured the old scratch
-            drop_graphs(ix);
         }
         const size_t want = align_up(bytes + bytes / 4, 1 << 20);
         int rc = dev_alloc(ix, &ix->scratch, want, "search scratch");
@@ -1270,36 +1301,127 @@ hipError_t enqueue(const Call& c, int S) {
     return c.p.mode == OS_ANN_MODE_TILED ? enqueue_tiled(c, S) : enqueue_fp32(c);
 }
 
-// Replays (or captures, then replays) the whole launch sequence of a call.
-int run_graph(Call& c, int S) {
+// Query count of a graph class: Q rounded up to one of eight steps per
+// octave (at most 1/8 of padding rows), 8 and 16 below that.
+int64_t graph_class(int64_t Q) {
+    if (Q <= 8) return 8;
+    if (Q <= 16) return 16;
+    int k = 0;
+    while ((int64_t(1) << (k + 1)) < Q) ++k;  // 2^k < Q <= 2^(k+1)
+    const int64_t step = (int64_t(1) << k) / 8;
+    return (Q + step - 1) / step * step;
+}
+
+// The arena of stream s, grown to hold Qc query rows and `bytes` of scratch.
+// Growing it frees the old buffers (after the stream has drained) and drops
+// the stream's graphs, which point into them.
+int graph_arena(os_ann_index* ix, hipStream_t s, int64_t Qc, size_t bytes, GraphArena** out) {
+    GraphArena* a = nullptr;
+    for (auto& e : ix->arenas)
+        if (e.s == s) a = &e;
+    if (!a) {
+        ix->arenas.push_back(GraphArena{s});
+        a = &ix->arenas.back();
+    }
+    if (a->cap_q >= Qc && a->ws_bytes >= bytes) {
+        *out = a;
+        return OS_ANN_OK;
+    }
+    OSANN_HIP(hipStreamSynchronize(s), "graph arena resize");
+    for (auto it = ix->graphs.begin(); it != ix->graphs.end();) {
+        if (it->key[0] == (int64_t)(intptr_t)s) {
+            destroy_graph(*it);
+            it = ix->graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    const int64_t cap = std::max(Qc, a->cap_q);
+    const size_t ws = std::max(align_up(bytes + bytes / 4, 1 << 20), a->ws_bytes);
+    free_arena(ix, *a);
+    int rc = OS_ANN_OK;
+    if ((rc = dev_alloc(nullptr, (void**)&a->ws, ws, "graph scratch")) ||
+        (rc = dev_alloc(nullptr, &a->q, (size_t)cap * ix->D * 4, "graph queries")) ||
+        (rc = dev_alloc(nullptr, (void**)&a->oidx, (size_t)cap * 8, "graph rows")) ||
+        (rc = dev_alloc(nullptr, (void**)&a->odist, (size_t)cap * 4, "graph distances")) ||
+        (rc = dev_alloc(nullptr, (void**)&a->oncand, (size_t)cap * 8, "graph counts")) ||
+        (rc = dev_alloc(nullptr, (void**)&a->capped, 8, "graph capped count"))) {
+        free_arena(ix, *a);  // nothing counted yet: the sizes are still zero
+        return rc;
+    }
+    a->cap_q = cap;
+    a->ws_bytes = ws;
+    ix->device_bytes += a->ws_bytes + (size_t)cap * (ix->D * 4 + 20) + 8;
+    // staged rows past a call's Q are searched and thrown away: start them
+    // as zero vectors (a fill kernel; the stream is not being captured)
+    OSANN_HIP(launch_fill_u32(static_cast<uint32_t*>(a->q), cap * ix->D, 0u, s), "graph queries");
+    a->qtype = kF32;
+    *out = a;
+    return OS_ANN_OK;
+}
+
+// A search through the graph of its shape class (stream, Q class, query
+// type, mode, R, cone budget, budget): the queries are staged into the
+// stream's arena, the class's graph (captured on first use, with the tiling
+// the tuner picks for the class) runs on the arena, and the first Q results
+// are copied to the caller's buffers.  Rows past Q in the class are earlier
+// calls' queries (or zero vectors); each query's result is independent of
+// the others in its batch, so they change nothing.
+int search_graph(Call& c, int mode, int R, bool cones) {
     os_ann_index* ix = c.ix;
-    std::vector<int64_t> key = {c.p.mode,
-                                c.p.R,
-                                c.p.G,
-                                c.p.qkey,
-                                c.p.kern,
-                                c.p.cones,
-                                S,
-                                c.Q,
-                                c.budget,
-                                c.qtype,
-                                (int64_t)(intptr_t)c.queries,
-                                (int64_t)(intptr_t)c.out_idx,
-                                (int64_t)(intptr_t)c.out_dist,
-                                (int64_t)(intptr_t)c.out_ncand,
-                                (int64_t)(intptr_t)c.base,
-                                (int64_t)(intptr_t)c.s};
-    std::lock_guard<std::mutex> g(ix->graph_mu);
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    OSANN_HIP(hipStreamIsCapturing(c.s, &st), "graph search");
+    if (st != hipStreamCaptureStatusNone)
+        return fail(OS_ANN_EINVAL, "OS_ANN_FLAG_GRAPH on a stream that is being captured");
+    const int64_t Qc = graph_class(c.Q);
+    Call g = c;
+    g.Q = Qc;
+    g.timing = false;
+    g.p = plan_search(ix, Qc, c.budget, mode, R, cones);
+    if (!g.p.fits)
+        return fail(OS_ANN_ENOTSUP, "tiled mode: too many non-empty cones for the LDS cone list at this D");
+    SearchPlan plans[kMaxPlans];
+    int n_plans = 0;
+    size_t bytes = g.p.bytes;
+    if (mode == OS_ANN_MODE_TILED) {
+        n_plans = tiled_plans(ix, Qc, c.budget, R, cones, plans);
+        for (int k = 0; k < n_plans; ++k) bytes = std::max(bytes, plans[k].bytes);
+        int rc = ensure_lowp(ix, c.s);
+        if (rc) return rc;
+    }
+    std::lock_guard<std::mutex> lk(ix->graph_mu);
+    GraphArena* a = nullptr;
+    int rc = graph_arena(ix, c.s, Qc, bytes, &a);
+    if (rc) return rc;
+    const size_t row_bytes = (size_t)ix->D * elem_bytes(c.qtype);
+    if (a->qtype != c.qtype) {  // rows staged in another type may not be valid in this one
+        OSANN_HIP(launch_fill_u32(static_cast<uint32_t*>(a->q), a->cap_q * ix->D, 0u, c.s), "graph queries");
+        a->qtype = c.qtype;
+    }
+    OSANN_HIP(hipMemcpyAsync(a->q, c.queries, (size_t)c.Q * row_bytes, hipMemcpyDeviceToDevice, c.s),
+              "graph queries");
+    g.queries = a->q;
+    g.out_idx = a->oidx;
+    g.out_dist = a->odist;
+    g.out_ncand = a->oncand;
+    g.walks_capped = c.walks_capped ? a->capped : nullptr;
+    g.base = a->ws;
+    const std::vector<int64_t> key = {(int64_t)(intptr_t)c.s, Qc, c.qtype, mode, R, cones ? 1 : 0, c.budget,
+                                      c.walks_capped ? 1 : 0};
     GraphEntry* hit = nullptr;
     for (auto& e : ix->graphs)
         if (e.key == key) hit = &e;
     if (!hit) {
+        int S = 1;
+        if (mode == OS_ANN_MODE_TILED) {
+            hipError_t e = hipSuccess;
+            S = choose_tiling(g, plans, n_plans, true, &e);  // may time candidates on the arena
+            if (e != hipSuccess) return hip_fail(e, "tiling autotune");
+        }
         GraphEntry ne;
         ne.key = key;
-        Call cc = c;
-        cc.timing = false;
         OSANN_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal), "graph capture");
-        hipError_t e = enqueue(cc, S);
+        hipError_t e = enqueue(g, S);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(c.s, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -1312,17 +1434,28 @@ int run_graph(Call& c, int S) {
             (void)hipGraphDestroy(graph);
             return hip_fail(e, "graph instantiate");
         }
-        if (ix->graphs.size() >= 8) {
-            (void)hipGraphExecDestroy(ix->graphs.front().exec);
-            (void)hipGraphDestroy(ix->graphs.front().graph);
-            ix->graphs.erase(ix->graphs.begin());
+        if (ix->graphs.size() >= kMaxGraphs) {  // replays in flight keep their own references
+            auto lru = std::min_element(ix->graphs.begin(), ix->graphs.end(),
+                                        [](const GraphEntry& x, const GraphEntry& y) { return x.used < y.used; });
+            destroy_graph(*lru);
+            ix->graphs.erase(lru);
         }
         ix->graphs.push_back(ne);
         hit = &ix->graphs.back();
+        ++ix->graph_captures;
     }
+    hit->used = ++ix->graph_tick;
     hipGraphExec_t exec = hit->exec;
     OSANN_HIP(timed_launch(ix, c.timing, OS_ANN_KERNEL_GRAPH, c.s, [&] { return hipGraphLaunch(exec, c.s); }),
               "graph launch");
+    ++ix->graph_replays;
+    OSANN_HIP(hipMemcpyAsync(c.out_idx, a->oidx, (size_t)c.Q * 8, hipMemcpyDeviceToDevice, c.s), "graph rows");
+    OSANN_HIP(hipMemcpyAsync(c.out_dist, a->odist, (size_t)c.Q * 4, hipMemcpyDeviceToDevice, c.s), "graph distances");
+    if (c.out_ncand)
+        OSANN_HIP(hipMemcpyAsync(c.out_ncand, a->oncand, (size_t)c.Q * 8, hipMemcpyDeviceToDevice, c.s),
+                  "graph counts");
+    if (c.walks_capped)
+        OSANN_HIP(hipMemcpyAsync(c.walks_capped, a->capped, 8, hipMemcpyDeviceToDevice, c.s), "graph capped count");
     return OS_ANN_OK;
 }
 
@@ -1959,6 +2092,17 @@ os_ann_index* os_ann_build(const float* db, int64_t N, int32_t D, int32_t L) {
 
 void os_ann_free(os_ann_index* idx) { release(idx); }
 
+int os_ann_graph_stats(const os_ann_index* cidx, int64_t* captured, int64_t* replayed, int64_t* cached) {
+    clear_error();
+    if (!cidx) return fail(OS_ANN_EINVAL, "null index");
+    auto* ix = const_cast<os_ann_index*>(cidx);
+    std::lock_guard<std::mutex> g(ix->graph_mu);
+    if (captured) *captured = ix->graph_captures;
+    if (replayed) *replayed = ix->graph_replays;
+    if (cached) *cached = (int64_t)ix->graphs.size();
+    return OS_ANN_OK;
+}
+
 int os_ann_trim(void) {
     clear_error();
     trim_blocks();
@@ -2022,6 +2166,10 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
     const int mode = opts ? opts->mode : OS_ANN_MODE_FP32;
     const int R = opts && opts->rerank_r ? opts->rerank_r : 8;
     const bool cones = opts && (opts->flags & OS_ANN_FLAG_BUDGET_CONES);
+    if (opts && (opts->flags & OS_ANN_FLAG_GRAPH)) {
+        if (!c.s) return fail(OS_ANN_EINVAL, "OS_ANN_FLAG_GRAPH needs a non-null stream");
+        return search_graph(c, mode, R, cones);
+    }
     c.p = plan_search(ix, Q, max_candidates, mode, R, cones);
     if (!c.p.fits)
         return fail(OS_ANN_ENOTSUP, "tiled mode: too many non-empty cones for the LDS cone list at this D");
@@ -2042,8 +2190,6 @@ int os_ann_search_ex(const os_ann_index* cidx, const void* queries, int64_t Q, i
         S = choose_tiling(c, plans, n_plans, st == hipStreamCaptureStatusNone, &e);
         if (e != hipSuccess) return hip_fail(e, "tiling autotune");
     }
-    const bool graph = opts && (opts->flags & OS_ANN_FLAG_GRAPH) && c.s;
-    if (graph) return run_graph(c, S);
     OSANN_HIP(enqueue(c, S), mode == OS_ANN_MODE_TILED ? "tiled search" : "fp32 search");
     return OS_ANN_OK;
 }

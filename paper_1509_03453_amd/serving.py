@@ -12,7 +12,10 @@ loop that
   outputs) fits both in the free HBM above a reserve and in the pool cap;
 * packs the oldest queued requests of one index into a micro-batch of at most
   ``max_batch`` queries (whole requests only; one request larger than the cap
-  goes alone) and launches one ``os_ann_search_ex`` on that slot's stream.
+  goes alone) and launches one ``os_ann_search_ex`` on that slot's stream,
+  by default as a replay of the library's hipGraph for the batch's shape
+  class (``OS_ANN_FLAG_GRAPH``: one graph per slot stream and class, all
+  captured during ``warmup``).
 
 So requests arriving while others are on the GPU start as soon as a slot and
 memory free up, and their kernels overlap on the device.  Latency is the
@@ -41,7 +44,7 @@ import torch
 from . import binding as B
 
 __all__ = ["Request", "ResidentIndex", "Server", "pack_batch", "admissible", "latency_stats", "choose_mode",
-           "load_sweep"]
+           "load_sweep", "graph_classes"]
 
 
 @dataclasses.dataclass
@@ -161,6 +164,26 @@ def pick_index(queues: dict[str, collections.deque]) -> str | None:
     return best
 
 
+def graph_classes(max_q: int) -> list[int]:
+    """The query counts of the library's graph shape classes up to ``max_q``
+    (OS_ANN_FLAG_GRAPH: Q rounded up to one of eight steps per octave; 8 and
+    16 below that), ascending; the last one covers ``max_q``."""
+    out, q = [], 1
+    while True:
+        if q <= 8:
+            c = 8
+        elif q <= 16:
+            c = 16
+        else:
+            k = (q - 1).bit_length() - 1  # 2^k < q <= 2^(k+1)
+            step = (1 << k) // 8
+            c = (q + step - 1) // step * step
+        out.append(c)
+        if c >= max_q:
+            return out
+        q = c + 1
+
+
 # ---------------------------------------------------------------------------
 # the server
 # ---------------------------------------------------------------------------
@@ -184,7 +207,7 @@ class Server:
     def __init__(self, indexes: Sequence[ResidentIndex], slots: int = 4, max_batch: int = 8192,
                  pool_cap_bytes: int = 4 << 30, reserve_bytes: int = 1 << 30,
                  device: torch.device | str = "cuda:0",
-                 free_hbm: Callable[[], int] | None = None):
+                 free_hbm: Callable[[], int] | None = None, graphs: bool = True):
         if slots < 1 or max_batch < 1:
             raise ValueError("slots and max_batch must be positive")
         self.indexes = {r.name: r for r in indexes}
@@ -198,6 +221,7 @@ class Server:
         self.n_batches = 0
         self.peak_in_flight = 0
         self.max_concurrent = 0
+        self.graphs = bool(graphs)
 
     def _device_free(self) -> int:
         free, _ = torch.cuda.mem_get_info(self.device)
@@ -221,6 +245,18 @@ class Server:
                 if q >= min(self.max_batch, x.shape[0]):
                     break
                 q *= 2
+        if self.graphs:
+            # every (slot, shape class) graph captured now, largest class first so that each
+            # slot's graph buffers are sized once
+            for name, ix in self.indexes.items():
+                x = samples[name]
+                for q in reversed(graph_classes(min(self.max_batch, x.shape[0]))):
+                    for s in self.slots:
+                        with torch.cuda.stream(s.stream):
+                            B.os_ann_search_ex(ix.index.handle, x[:q], ix.budget, mode=ix.mode, stream=s.stream,
+                                               rerank_r=ix.rerank_r, want_ncand=False, flags=B.OS_ANN_FLAG_GRAPH)
+            torch.cuda.synchronize(self.device)
+            return
         # every slot's workspace sized for the largest launch, so timed launches allocate none
         need = max(ix.workspace(self.max_batch) for ix in self.indexes.values())
         for s in self.slots:
@@ -232,16 +268,22 @@ class Server:
         q_total = sum(r.n for r in reqs)
         with torch.cuda.stream(slot.stream):
             qs = reqs[0].queries if len(reqs) == 1 else torch.cat([r.queries for r in reqs])
-            wsb = ix.workspace(q_total)
-            if slot.ws is None or slot.ws.numel() < wsb:
-                slot.ws = None  # the old buffer is idle: this slot's previous launch has retired
-                slot.ws = torch.empty(wsb, dtype=torch.uint8, device=self.device)
-            ws = slot.ws
             oi = torch.empty(q_total, dtype=torch.int64, device=self.device)
             od = torch.empty(q_total, dtype=torch.float32, device=self.device)
-            B.os_ann_search_ex(ix.index.handle, qs, ix.budget, mode=ix.mode, stream=slot.stream,
-                               workspace=ws, rerank_r=ix.rerank_r, out_idx=oi, out_dist=od,
-                               want_ncand=False)
+            if self.graphs:  # the library keeps the graph's buffers per slot stream
+                ws = None
+                B.os_ann_search_ex(ix.index.handle, qs, ix.budget, mode=ix.mode, stream=slot.stream,
+                                   rerank_r=ix.rerank_r, out_idx=oi, out_dist=od, want_ncand=False,
+                                   flags=B.OS_ANN_FLAG_GRAPH)
+            else:
+                wsb = ix.workspace(q_total)
+                if slot.ws is None or slot.ws.numel() < wsb:
+                    slot.ws = None  # the old buffer is idle: this slot's previous launch has retired
+                    slot.ws = torch.empty(wsb, dtype=torch.uint8, device=self.device)
+                ws = slot.ws
+                B.os_ann_search_ex(ix.index.handle, qs, ix.budget, mode=ix.mode, stream=slot.stream,
+                                   workspace=ws, rerank_r=ix.rerank_r, out_idx=oi, out_dist=od,
+                                   want_ncand=False)
             slot.event.record(slot.stream)
         off = 0
         for r in reqs:

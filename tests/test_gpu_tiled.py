@@ -195,6 +195,54 @@ def test_graph_replay_matches_eager(orc, mode):
     B.os_ann_free(h)
 
 
+@pytest.mark.parametrize("mode", [B.OS_ANN_MODE_FP32, B.OS_ANN_MODE_TILED])
+def test_graph_shape_class_new_buffers(orc, mode):
+    # 300 and 290 queries fall in one class (320 rows): one capture, then
+    # replays with fresh query and output buffers each time, every result
+    # checked against the oracle (the class's padding rows change nothing)
+    X = W.gaussian_db(40000, 64, seed=2511)
+    Ys = {"a": W.gaussian_queries(300, 64, seed=2512), "b": W.gaussian_queries(290, 64, seed=2513)}
+    budget = 1500
+    h = B.os_ann_build_ex(dev(X), 2)
+    o = orc.build_index(X, 2)
+    s = torch.cuda.Stream()
+    try:
+        with pytest.raises(B.OsAnnError):  # a graph needs a stream of the caller's
+            B.os_ann_search_ex(h, dev(Ys["a"]), budget, mode=mode, flags=B.OS_ANN_FLAG_GRAPH)
+        st0 = B.os_ann_graph_stats(h)
+        for tag in ("a", "b", "a"):
+            Y = Ys[tag]
+            say(f"[graph] class replay mode={mode} set={tag} Q={Y.shape[0]}")
+            yq = dev(Y)
+            oi = torch.full((Y.shape[0],), -7, dtype=torch.int64, device="cuda")
+            od = torch.full((Y.shape[0],), -1.0, dtype=torch.float32, device="cuda")
+            on = torch.full((Y.shape[0],), -1, dtype=torch.int64, device="cuda")
+            torch.cuda.synchronize()
+            with torch.cuda.stream(s):
+                B.os_ann_search_ex(h, yq, budget, mode=mode, stream=s, out_idx=oi, out_dist=od, out_ncand=on,
+                                   flags=B.OS_ANN_FLAG_GRAPH)
+            s.synchronize()
+            junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+            torch.cuda.synchronize()
+            del junk
+            g = (oi.cpu().numpy(), od.cpu().numpy(), on.cpu().numpy())
+            if mode == B.OS_ANN_MODE_FP32:
+                ri, rd32, rd64, rn = orc.search(X, o, Y, budget)
+                assert np.array_equal(g[2], rn)
+                assert np.array_equal(g[0], ri)
+                assert np.array_equal(g[1].view(np.uint32), rd32.view(np.uint32))
+            else:
+                check_screened(orc, X, Y, g, orc.search_tiled(X, o, Y, budget, R=8), ("graph class", tag),
+                               is_candidate=candidates_of(orc, o, Y, budget))
+        st = B.os_ann_graph_stats(h)
+        assert st["captured"] - st0["captured"] == 1, st
+        assert st["replayed"] - st0["replayed"] == 3, st
+        assert 1 <= st["cached"] <= 512, st
+    finally:
+        torch.cuda.synchronize()
+        B.os_ann_free(h)
+
+
 @pytest.mark.parametrize("case", ["gauss64", "gauss32_r16", "desc128_u8", "patch_f16", "gauss64_r4_q1"])
 def test_screen_kernels_agree(orc, monkeypatch, case):
     # the cone-major screen (one list per (query, 64-cone word), queries

@@ -44,6 +44,20 @@ def test_pick_index_is_first_come_first_served():
     assert S.pick_index({"a": collections.deque()}) is None
 
 
+def test_graph_classes_pad_at_most_an_eighth():
+    # one class per count the server can launch; a class covers every count
+    # from the previous class + 1 up to itself, with at most 1/8 padding above 16
+    c = S.graph_classes(8192)
+    assert c[0] == 8 and c[1] == 16 and c[-1] == 8192
+    assert all(a < b for a, b in zip(c, c[1:]))
+    lo = 1
+    for hi in c:
+        for q in (lo, hi):
+            assert q <= hi and (q <= 16 or 8 * (hi - q) < q), (q, hi)
+        lo = hi + 1
+    assert len(S.graph_classes(4096)) == 66 and S.graph_classes(10000)[-1] == 10240
+
+
 def test_poisson_arrivals():
     reqs = W.serving_requests(20000, rate=500.0, n_indexes=3, max_q=4096)
     t = np.array([r[0] for r in reqs])
