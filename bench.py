@@ -756,6 +756,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--mode", choices=("fp32", "tiled", "both"), default="both")
     ap.add_argument("--budget", type=int, default=0, help="fixed budget instead of the recall sweep")
+    ap.add_argument("--trace", default=None,
+                    help="append one JSON line per timed headline step (mode, step, wall and kernel times) to this file")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix leg")
     ap.add_argument("--no-bases", action="store_true", help="skip the several-bases leg")
     ap.add_argument("--no-patches", action="store_true", help="skip the 4.2e6-patch batching leg")
@@ -902,6 +904,12 @@ def main():
             probe_ms.append(msp / max(npb, 1))
             extra_ms.append(msf / max(nf, 1) if nf else 0.0)
             ncand_sum.append(float(n.double().sum()))
+            if args.trace:
+                with open(args.trace, "a") as tf:
+                    tf.write(json.dumps({"mode": m, "step": len(step_ms) - 1, "budget": budget,
+                                         "wall_ms": round(step_ms[-1], 4), "main_kernel_ms": round(kern_ms[-1], 4),
+                                         "probe_ms": round(probe_ms[-1], 4), "finish_ms": round(extra_ms[-1], 4),
+                                         "candidates": ncand_sum[-1]}) + "\n")
             B.os_ann_free(hh)
         torch.cuda.synchronize()
         total_s = time.perf_counter() - t_all

@@ -54,6 +54,8 @@ def _host_tag() -> str:
 
 
 _LIB = os.path.join(_HERE, f"libosann_oracle.{_host_tag()}.so")
+# A separately built copy (the sanitizer build of the tests) may stand in.
+_LIB_OVERRIDE = os.environ.get("OSANN_ORACLE_LIB")
 
 
 def build(force: bool = False) -> str:
@@ -68,12 +70,25 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_sanitized(out: str) -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every finding aborts) into ``out``, for the host sanitizer test."""
+    cmd = ["gcc", "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fPIC", "-shared",
+           "-o", out, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 def lib():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            L = C.CDLL(_LIB)
+            if _LIB_OVERRIDE:
+                L = C.CDLL(_LIB_OVERRIDE)
+            else:
+                build()
+                L = C.CDLL(_LIB)
             p = C.c_void_p
             i64, i32 = C.c_int64, C.c_int
             L.orc_binom.restype = i64

@@ -13,7 +13,8 @@ import threading
 
 import torch
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libosann.so")
+# OSANN_LIB names another build of the same library (the host sanitizer build of the tests)
+LIB_PATH = os.environ.get("OSANN_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libosann.so")
 
 OS_ANN_OK, OS_ANN_EINVAL, OS_ANN_ENOMEM, OS_ANN_EDEVICE, OS_ANN_ENOTSUP, OS_ANN_ENONFINITE = 0, -1, -2, -3, -4, -5
 OS_ANN_F32, OS_ANN_F16, OS_ANN_U8 = 0, 1, 2
