@@ -394,6 +394,16 @@ int os_ann_info(const os_ann_index *idx, int64_t *N, int32_t *D, int32_t *L,
  * NULL.  Host-side counters; no device work. */
 int os_ann_graph_stats(const os_ann_index *idx, int64_t *captured, int64_t *replayed, int64_t *cached);
 
+/* Tiling of the last tiled-mode search enqueued on the index (Section
+ * 3.D's short-list scan as matrix-core tiles, as the autotuner chose it):
+ * kernel 0 = query-tile screen, 1 = cone-major screen; order 0 = queries by
+ * own cone, 1 = by their walk's first cones; groups = 16-query MFMA groups
+ * per tile (per pass for the cone-major screen); splits = lists per query.
+ * -1 / 0 before any tiled search.  Any output may be NULL.  Host-side; no
+ * device work. */
+int os_ann_last_tiling(const os_ann_index *idx, int32_t *kernel, int32_t *order, int32_t *groups,
+                       int32_t *splits);
+
 /* Release the index.  The caller makes sure no search on it is in flight.
  * Waits for the device to finish its work (as hipFree does); the index's
  * device blocks then stay with the library, idle, for later builds and

@@ -86,6 +86,8 @@ SIGNATURES = {
     "os_ann_trim": (C.c_int, []),
     "os_ann_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64)]),
+    "os_ann_last_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "os_ann_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, C.c_void_p]),
     "os_ann_last_error": (C.c_int, []),
     "os_ann_last_error_message": (C.c_char_p, []),
@@ -375,6 +377,15 @@ def os_ann_graph_stats(index: int) -> dict:
     if rc:
         _raise(rc)
     return {"captured": cap.value, "replayed": rep.value, "cached": kept.value}
+
+
+def os_ann_last_tiling(index: int) -> dict:
+    """Kernel (0 query-tile, 1 cone-major), query order, groups and splits of the last tiled search."""
+    k, o, g, sp = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    rc = lib().os_ann_last_tiling(index, C.byref(k), C.byref(o), C.byref(g), C.byref(sp))
+    if rc:
+        _raise(rc)
+    return {"kernel": k.value, "order": o.value, "groups": g.value, "splits": sp.value}
 
 
 def os_ann_export(index: int, stream=None) -> dict:

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -142,6 +143,8 @@ struct os_ann_index {
     std::vector<GraphArena> arenas;
     uint64_t graph_tick = 0;
     int64_t graph_captures = 0, graph_replays = 0;
+    // the tiling of the last tiled search enqueued (kernel 0 query-tile, 1 cone-major)
+    std::atomic<int32_t> last_kern{-1}, last_order{-1}, last_groups{0}, last_splits{0};
     // several bases (Section 3.A): one table per basis; this index then owns
     // the tables, the bases and their gathered copies
     int n_rot = 0;
@@ -822,6 +825,10 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     const SearchPlan& p = c.p;
     const ProbeArgs pa = probe_args(c);
     hipError_t e;
+    ix->last_kern = p.kern;
+    ix->last_order = p.qkey;
+    ix->last_groups = p.kern == 1 ? 4 : p.G;
+    ix->last_splits = p.kern == 1 ? (int32_t)p.nw : S;
     if (ix->proj) {
         // keyed table: the FP32 and low-precision copies of the full queries,
         // their keys, then the walk on the keys
@@ -900,9 +907,9 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     // The seed reads up to sd.rows padded rows from the first cones of each
     // query's walk, one query at a time (no row is shared between queries):
     // keep that near a sixteenth of the budget, 64 .. 512 rows.  Past 512 the
-    // seed costs more than the tighter bound saves the screen (1e6 x 64
-    // Gaussian rows, 1e4 queries: 2.83 ms per search at 512 rows against
-    // 3.00 ms at 1024).
+    // seed costs about what the tighter bound saves the screen (1e6 x 64
+    // Gaussian rows, 1e4 queries, budget 327,680: 2.73 / 2.62 / 2.59 ms per
+    // search at 256 / 512 / 1024 rows).
     const int64_t rows = expected_rows(ix, c.budget, p.cones);
     sd.rows = (int)std::min<int64_t>(512, std::max<int64_t>(64, pow2_ceil(std::max<int64_t>(rows / 16, 1))));
     if (const char* env = std::getenv("OSANN_TILED_SEED_ROWS")) {  // fixed seed size (testing)
@@ -2100,6 +2107,17 @@ int os_ann_graph_stats(const os_ann_index* cidx, int64_t* captured, int64_t* rep
     if (captured) *captured = ix->graph_captures;
     if (replayed) *replayed = ix->graph_replays;
     if (cached) *cached = (int64_t)ix->graphs.size();
+    return OS_ANN_OK;
+}
+
+int os_ann_last_tiling(const os_ann_index* idx, int32_t* kernel, int32_t* order, int32_t* groups,
+                       int32_t* splits) {
+    clear_error();
+    if (!idx) return fail(OS_ANN_EINVAL, "null index");
+    if (kernel) *kernel = idx->last_kern;
+    if (order) *order = idx->last_order;
+    if (groups) *groups = idx->last_groups;
+    if (splits) *splits = idx->last_splits;
     return OS_ANN_OK;
 }
 

@@ -385,11 +385,14 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
 // Seeds the shared class minima before the screen, so that no split or word
 // starts without a bound.  One wave per query takes the rows of the first
 // cones of its walk (its own cone, then the next positions of Section 3.B's
-// order: the most promising candidates), at most a.rows padded rows, each
-// lane a row at a time; computes d~ on the vector units and raises it by a
+// order: the most promising candidates), at most a.rows padded rows; a group
+// of dk/8 lanes (rounded up to a power of two) reads one row in one
+// coalesced load, 8 components per lane, and several rows' loads are issued
+// before their products; it computes d~ on the vector units and raises it by a
 // bound on the difference to any FP32 accumulation of the same products (the
 // matrix cores add them in another order): each of the two sums is off by at
-// most dk*u*S with S the sum of |products|, and the final subtraction by
+// most dk*u*S with S the sum of |products| (in any order of the additions),
+// and the final subtraction by
 // u*(|n| + 2|q.x|), so (4dk + 8)*u*(n + 2S) covers both (u = 2^-24), with a
 // margin.  The R-th smallest raised value T is at least the screen's d~ of
 // R distinct candidates, so it bounds the query's final R-th d~; it is put
@@ -402,6 +405,7 @@ template <bool F16IN, int R>
 __global__ __launch_bounds__(256) void tiled_seed_kernel(SeedArgs a) {
 #pragma clang fp contract(off)
     __shared__ uint32_t s_start[4][64], s_incl[4][64];
+    __shared__ float s_raised[4][kSeedMaxRows];  // per wave: raised d~ of each seeded row
     const int w = threadIdx.x / 64, l = lane_id();
     const int64_t slot = (int64_t)blockIdx.x * 4 + w;
     if (slot >= a.Q) return;  // the whole wave; no block barrier below
@@ -428,40 +432,79 @@ __global__ __launch_bounds__(256) void tiled_seed_kernel(SeedArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     const float gamma = (float)(4 * a.dk + 8) * 5.9604645e-08f * 1.01f;
-    constexpr int PER = kSeedMaxRows / 64;
-    float raised[PER];  // this lane's raised values
-    uint32_t k = 0;     // position of the lane's current row (rows ascend with i)
+    const int units = a.dk / 8;  // 16-byte units of a row
+    int gs = 4;                  // lanes per row
+    while (gs < units) gs *= 2;
+    const int rps = 64 / gs;     // rows per step
+    const int sub = l % gs, grp = l / gs;
+    float qf[8];
+    {
+        const uint4 qv = sub < units ? reinterpret_cast<const uint4*>(a.ql + q * a.dk)[sub] : make_uint4(0, 0, 0, 0);
+        const uint32_t qw[4] = {qv.x, qv.y, qv.z, qv.w};
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        raised[i] = __builtin_huge_valf();
-        const uint32_t r = (uint32_t)l + 64u * i;
-        if (r >= total) continue;
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const uint16_t qb = (uint16_t)(qw[h] >> (16 * e));
+                qf[2 * h + e] = F16IN ? F16::val(qb) : __uint_as_float((uint32_t)qb << 16);
+            }
+    }
+    float* raised_rows = s_raised[w];
+    uint32_t k = 0;  // walk position of the lane's current row (the lane's rows ascend)
+    auto locate = [&](uint32_t r) {
         while (s_incl[w][k] <= r) ++k;
         const uint32_t before = k ? s_incl[w][k - 1] : 0u;
-        const uint32_t p = s_start[w][k] + (r - before);
-        const float n = a.nrm[p];
-        if (!(n < __builtin_huge_valf())) continue;  // padding row (NaN norm)
-        const uint4* xr = reinterpret_cast<const uint4*>(a.xl + (int64_t)p * a.dk);
-        const uint4* qr = reinterpret_cast<const uint4*>(a.ql + q * a.dk);
-        float dot = 0.0f, sabs = 0.0f;
-        for (int u = 0; u < a.dk / 8; ++u) {
-            const uint4 xv = xr[u], qv = qr[u];
-            const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w}, qw[4] = {qv.x, qv.y, qv.z, qv.w};
+        return s_start[w][k] + (r - before);
+    };
+    constexpr int U = 4;  // steps whose loads are in flight together
+    for (uint32_t r0 = 0; r0 < total; r0 += (uint32_t)(rps * U)) {
+        uint4 xv[U];
+        float nv[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const uint32_t r = r0 + (uint32_t)(i * rps + grp);
+            const bool ok = r < total;
+            const uint32_t p = ok ? locate(r) : 0u;
+            xv[i] = ok && sub < units ? reinterpret_cast<const uint4*>(a.xl + (int64_t)p * a.dk)[sub]
+                                      : make_uint4(0, 0, 0, 0);
+            nv[i] = ok ? a.nrm[p] : __builtin_nanf("");
+        }
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const uint32_t xw[4] = {xv[i].x, xv[i].y, xv[i].z, xv[i].w};
+            float dot = 0.0f, sabs = 0.0f;
 #pragma unroll
             for (int h = 0; h < 4; ++h)
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
-                    const uint16_t xb = (uint16_t)(xw[h] >> (16 * e)), qb = (uint16_t)(qw[h] >> (16 * e));
+                    const uint16_t xb = (uint16_t)(xw[h] >> (16 * e));
                     const float xf = F16IN ? F16::val(xb) : __uint_as_float((uint32_t)xb << 16);
-                    const float qf = F16IN ? F16::val(qb) : __uint_as_float((uint32_t)qb << 16);
-                    const float pr = xf * qf;
+                    const float pr = xf * qf[2 * h + e];
                     dot = dot + pr;
                     sabs = sabs + fabsf(pr);
                 }
+            for (int o = gs / 2; o > 0; o >>= 1) {  // the row's lanes: the same sums in every one
+                dot = dot + __shfl_xor(dot, o, 64);
+                sabs = sabs + __shfl_xor(sabs, o, 64);
+            }
+            const uint32_t r = r0 + (uint32_t)(i * rps + grp);
+            if (sub == 0 && r < total) {
+                const float n = nv[i];
+                // padding rows (NaN norm) never count
+                raised_rows[r] = n < __builtin_huge_valf() ? (n - 2.0f * dot) + gamma * (n + 2.0f * sabs)
+                                                           : __builtin_huge_valf();
+            }
         }
-        const float d = n - 2.0f * dot;
-        const float tol = gamma * (n + 2.0f * sabs);
-        raised[i] = d + tol;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    constexpr int PER = kSeedMaxRows / 64;
+    float raised[PER];  // this lane's share of the raised values
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const uint32_t r = (uint32_t)l + 64u * i;
+        raised[i] = r < total ? raised_rows[r] : __builtin_huge_valf();
     }
     // the R-th smallest: R rounds of a wave minimum, each removing one occurrence
     float T = __builtin_huge_valf();
