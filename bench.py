@@ -111,25 +111,26 @@ def cpu_baseline(X, Y, budget, target_s=15.0):
 def calibrate(copy_mib=0):
     """Achievable peaks on this GPU from the probes in calibrate.hip: HBM read
     bandwidth (one pass over 4 GiB, far beyond the 256 MB last-level cache),
-    the last-level cache's read bandwidth (64 MiB), and the dense BF16 / FP16
+    the last-level cache's read bandwidth (32 passes over 64 MiB in one
+    launch), and the dense BF16 / FP16
     matrix-core rate (back-to-back 16x16x32 and 32x32x16 instructions, no
     memory traffic).  Each figure is the best over launch shapes and
     repetitions.  With ``copy_mib`` also a plain device copy of that size
     (torch), the reference kernel for scaling PMC byte counters."""
     import ctypes as C
     lib = C.CDLL(os.path.join(ROOT, "libcalibrate.so"))
-    lib.calib_read_stream.argtypes = [C.c_size_t, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    lib.calib_read_stream.argtypes = [C.c_size_t, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
     lib.calib_mfma.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                                C.POINTER(C.c_double)]
     ms, fl = C.c_double(), C.c_double()
     out = {}
-    for name, nbytes in (("hbm_read", 4 << 30), ("llc_read", 64 << 20)):
+    for name, nbytes, passes in (("hbm_read", 4 << 30, 1), ("llc_read", 64 << 20, 32)):
         best = 0.0
         for bpc in (4, 8, 16):
-            rc = lib.calib_read_stream(nbytes, 5, bpc, C.byref(ms))
+            rc = lib.calib_read_stream(nbytes, passes, 5, bpc, C.byref(ms))
             if rc:
                 raise RuntimeError(f"calib_read_stream failed ({rc})")
-            best = max(best, nbytes / (ms.value / 1e3) / 1e9)
+            best = max(best, nbytes * passes / (ms.value / 1e3) / 1e9)
         out[name + "_GBps"] = round(best, 1)
     for name, shape, f16 in (("bf16_16x16x32", 16, 0), ("bf16_32x32x16", 32, 0), ("f16_16x16x32", 16, 1)):
         best = 0.0

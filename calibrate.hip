@@ -1,10 +1,11 @@
 // Roofline calibration probes for bench.py (measurement only; not part of
 // the search library).
 //
-//   calib_read_stream  reads a device buffer once per repetition with 16-byte
-//                      loads spread over the whole chip: the achievable read
-//                      bandwidth of HBM (buffer far above the 256 MB
-//                      last-level cache) or of that cache (buffer well below).
+//   calib_read_stream  reads a device buffer (several times per launch if
+//                      asked) with 16-byte loads spread over the whole chip:
+//                      the achievable read bandwidth of HBM (buffer far above
+//                      the 256 MB last-level cache) or of that cache (buffer
+//                      well below, read many times).
 //   calib_mfma         every wave issues back-to-back BF16/FP16 matrix
 //                      instructions into independent accumulators, with no
 //                      memory traffic: the achievable dense matrix-core rate.
@@ -19,21 +20,29 @@ typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 
-__global__ __launch_bounds__(256) void read_stream_kernel(const uint4* __restrict__ p, size_t n16,
+// `passes` passes over the buffer in one launch (a small buffer is read
+// many times, so the timed interval is long next to the launch); pass k
+// starts k threads' worth of elements further on, so no load repeats the
+// previous pass's address in the same thread.
+__global__ __launch_bounds__(256) void read_stream_kernel(const uint4* __restrict__ p, size_t n16, int passes,
                                                           uint32_t* __restrict__ sink) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint4 a = make_uint4(0, 0, 0, 0), b = a, c = a, d = a;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        const uint4 x0 = p[i], x1 = p[i + stride], x2 = p[i + 2 * stride], x3 = p[i + 3 * stride];
-        a.x ^= x0.x; a.y ^= x0.y; a.z ^= x0.z; a.w ^= x0.w;
-        b.x ^= x1.x; b.y ^= x1.y; b.z ^= x1.z; b.w ^= x1.w;
-        c.x ^= x2.x; c.y ^= x2.y; c.z ^= x2.z; c.w ^= x2.w;
-        d.x ^= x3.x; d.y ^= x3.y; d.z ^= x3.z; d.w ^= x3.w;
-    }
-    for (; i < n16; i += stride) {
-        const uint4 x = p[i];
-        a.x ^= x.x; a.y ^= x.y; a.z ^= x.z; a.w ^= x.w;
+    for (int k = 0; k < passes; ++k) {
+        const size_t shift = ((size_t)k * 256) % n16;
+        auto at = [&](size_t j) { j += shift; return j < n16 ? j : j - n16; };
+        size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+        for (; i + 3 * stride < n16; i += 4 * stride) {
+            const uint4 x0 = p[at(i)], x1 = p[at(i + stride)], x2 = p[at(i + 2 * stride)], x3 = p[at(i + 3 * stride)];
+            a.x ^= x0.x; a.y ^= x0.y; a.z ^= x0.z; a.w ^= x0.w;
+            b.x ^= x1.x; b.y ^= x1.y; b.z ^= x1.z; b.w ^= x1.w;
+            c.x ^= x2.x; c.y ^= x2.y; c.z ^= x2.z; c.w ^= x2.w;
+            d.x ^= x3.x; d.y ^= x3.y; d.z ^= x3.z; d.w ^= x3.w;
+        }
+        for (; i < n16; i += stride) {
+            const uint4 x = p[at(i)];
+            a.x ^= x.x; a.y ^= x.y; a.z ^= x.z; a.w ^= x.w;
+        }
     }
     const uint32_t v = a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
     if (v == 0x9E3779B9u) sink[blockIdx.x % 1024] = v;  // keeps the loads; the buffer's pattern never folds to it
@@ -119,11 +128,11 @@ static int best_time(int reps, F&& launch, double* best_ms) {
 
 extern "C" {
 
-// Best time of one pass over `bytes` (a multiple of 16) with
-// blocks_per_cu * CUs blocks of 256 threads.
-int calib_read_stream(size_t bytes, int reps, int blocks_per_cu, double* best_ms) {
+// Best time of `passes` passes over `bytes` (a multiple of 16) in one
+// launch of blocks_per_cu * CUs blocks of 256 threads.
+int calib_read_stream(size_t bytes, int passes, int reps, int blocks_per_cu, double* best_ms) {
     const int ncu = num_cu();
-    if (!best_ms || bytes < 16 || bytes % 16 || reps < 1 || blocks_per_cu < 1 || ncu < 1) return -1;
+    if (!best_ms || bytes < 16 || bytes % 16 || passes < 1 || reps < 1 || blocks_per_cu < 1 || ncu < 1) return -1;
     void* buf = nullptr;
     uint32_t* sink = nullptr;
     if (hipMalloc(&buf, bytes) != hipSuccess) return -2;
@@ -135,7 +144,8 @@ int calib_read_stream(size_t bytes, int reps, int blocks_per_cu, double* best_ms
     const unsigned blocks = (unsigned)(blocks_per_cu * ncu);
     if (!rc)
         rc = best_time(reps, [&](hipStream_t s) {
-            hipLaunchKernelGGL(read_stream_kernel, dim3(blocks), dim3(256), 0, s, (const uint4*)buf, bytes / 16, sink);
+            hipLaunchKernelGGL(read_stream_kernel, dim3(blocks), dim3(256), 0, s, (const uint4*)buf, bytes / 16, passes,
+                               sink);
             return hipGetLastError();
         }, best_ms);
     (void)hipFree(buf);
