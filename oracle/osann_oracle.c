@@ -815,25 +815,31 @@ int orc_wht(const void *X, int dtype, int64_t N, int K, const float *signs, floa
     return 0;
 }
 
-/* Algorithm 1 with R bases.  Basis r has its own table (offsets_r, perm_r
- * built from the rows' coordinates in that basis by orc_hash/orc_bucket);
- * rot holds the R matrices (wht set: R sign vectors of length K, the bases
- * of reading R14).  For each query: its coordinates in every basis
- * and each basis's full probe order (Section 3.B); then, for l = 0, 1, ...
- * (the l-th cone of every basis's order, empty cones included) and for
- * r = 0..R-1, every row of cone l of basis r that is not yet marked analyzed
- * gets its distance computed (on the original vectors), updates the arg-min
- * and is marked.  Reading R10: the budget counts the rows of the visited
- * cones, a row met again in another basis counting again, and the search
- * stops after the cone at which that count reaches B (with cones set,
- * reading R13: after level B-1 of every basis).  ncand is the number of
- * distinct rows whose distance was computed. */
+/* The search with R bases (Section 3.A).  Basis r has its own table
+ * (offsets_r, perm_r built from the rows' coordinates in that basis by
+ * orc_hash/orc_bucket); rot holds the R matrices (wht set: R sign vectors of
+ * length K, the bases of reading R14).  A query's candidates are the rows of
+ * the cones it reaches when it visits, level by level, the l-th cone of every
+ * basis's Section 3.B order (empty cones included), each row analyzed once;
+ * reading R10 says where that visit stops: when the rows of the visited
+ * cones, a row in several of them counted each time, reach B (with cones set,
+ * reading R13: after level B-1 of every basis).  Distances are taken on the
+ * original vectors; ncand is the number of distinct candidates. */
 int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, const float *rot,
                    const int64_t *offsets, const int64_t *perms,
                    const void *Y, int ydtype, int64_t Q, int64_t B,
                    int64_t *out_idx, float *out_d32, double *out_d64, int64_t *out_ncand,
                    int nthreads, int cones, int wht)
 {
+    /* Section 3.A with R bases, in the reading R10, stated as a set:
+     *   slot k of a query's schedule is (level l, basis r) = (k / R, k % R),
+     *   its cone the l-th of basis r's Section 3.B walk of the query's
+     *   coordinates in that basis;
+     *   the search takes the shortest prefix of the schedule whose cones hold
+     *   at least B rows, a row in several of them counted each time (all
+     *   slots if they never do), or with `cones` the first C = B levels;
+     *   the candidates are the distinct rows of the prefix's cones, the result
+     *   their arg-min on (FP32 distance, row), ncand their number. */
     if (K < 1 || K > 256 || G < 1 || G > K || B < 1 || R < 1 || (wht && (K & (K - 1))))
         return -1;
     int64_t NC = orc_num_cones(K, G);
@@ -844,10 +850,10 @@ int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, co
         float y[256], yr[256], x[256];
         load_row(Y, ydtype, q, K, y);
         int64_t *walks = (int64_t *)malloc(sizeof(int64_t) * (size_t)(NC * R));
-        unsigned char *analyzed = (unsigned char *)calloc((size_t)N, 1);
-        if (!walks || !analyzed) {
+        unsigned char *member = (unsigned char *)calloc((size_t)N, 1);
+        if (!walks || !member) {
             free(walks);
-            free(analyzed);
+            free(member);
 #pragma omp atomic write
             bad = 1;
             continue;
@@ -859,44 +865,55 @@ int orc_search_rot(const void *X, int xdtype, int64_t N, int K, int G, int R, co
                 orc_rotate(y, ORC_F32, 1, K, rot + (int64_t)r * K * K, yr);
             orc_walk(yr, K, G, walks + (int64_t)r * NC, NC);
         }
+        /* the length of the prefix */
+        const int64_t nslots = NC * R;
+        int64_t take = nslots;
+        if (cones) {
+            take = (B < NC ? B : NC) * R;
+        } else {
+            int64_t rows = 0;
+            for (int64_t k = 0; k < nslots; k++) {
+                const int64_t r = k % R, c = walks[r * NC + k / R];
+                const int64_t *off = offsets + r * (NC + 1);
+                rows += off[c + 1] - off[c];
+                if (rows >= B) {
+                    take = k + 1;
+                    break;
+                }
+            }
+        }
+        /* the candidate set */
+        for (int64_t k = 0; k < take; k++) {
+            const int64_t r = k % R, c = walks[r * NC + k / R];
+            const int64_t *off = offsets + r * (NC + 1);
+            const int64_t *perm = perms + r * N;
+            for (int64_t pos = off[c]; pos < off[c + 1]; pos++)
+                member[perm[pos]] = 1;
+        }
+        /* the arg-min over it */
         float best_d = INFINITY;
         int64_t best_row = INT64_MAX;
         double best_d64 = INFINITY;
-        int64_t visited = 0, ncand = 0;
-        int done = 0;
-        for (int64_t l = 0; l < NC && !done; l++) {
-            for (int r = 0; r < R && !done; r++) {
-                const int64_t *off = offsets + (int64_t)r * (NC + 1);
-                const int64_t *perm = perms + (int64_t)r * N;
-                int64_t c = walks[(int64_t)r * NC + l];
-                for (int64_t pos = off[c]; pos < off[c + 1]; pos++) {
-                    int64_t row = perm[pos];
-                    if (analyzed[row])
-                        continue;
-                    float d32;
-                    double d64;
-                    load_row(X, xdtype, row, K, x);
-                    dist2(x, y, K, &d32, &d64);
-                    int64_t before = best_row;
-                    argmin_update(d32, row, &best_d, &best_row);
-                    if (best_row != before)
-                        best_d64 = d64;
-                    analyzed[row] = 1;
-                    ncand++;
-                }
-                visited += off[c + 1] - off[c];
-                if (!cones && visited >= B)
-                    done = 1;
-            }
-            if (cones && l + 1 >= B)
-                done = 1;
+        int64_t ncand = 0;
+        for (int64_t row = 0; row < N; row++) {
+            if (!member[row])
+                continue;
+            float d32;
+            double d64;
+            load_row(X, xdtype, row, K, x);
+            dist2(x, y, K, &d32, &d64);
+            int64_t before = best_row;
+            argmin_update(d32, row, &best_d, &best_row);
+            if (best_row != before)
+                best_d64 = d64;
+            ncand++;
         }
         out_idx[q] = best_row == INT64_MAX ? -1 : best_row;  /* -1: no candidate (R13) */
         out_d32[q] = best_d;
         out_d64[q] = best_d64;
         out_ncand[q] = ncand;
         free(walks);
-        free(analyzed);
+        free(member);
     }
     return bad ? -2 : 0;
 }
