@@ -107,6 +107,15 @@ struct GraphEntry {
 };
 constexpr size_t kMaxGraphs = 512;  // per index: a few streams times the classes up to 8192 queries
 
+// The graph cap; OSANN_MAX_GRAPHS (1 .. 4096) lowers it for testing.
+size_t max_graphs() {
+    if (const char* e = std::getenv("OSANN_MAX_GRAPHS")) {
+        const long v = std::atol(e);
+        if (v >= 1 && v <= 4096) return (size_t)v;
+    }
+    return kMaxGraphs;
+}
+
 struct os_ann_index {
     int64_t N = 0;
     int32_t D = 0, L = 0, dtype = 0;
@@ -1441,9 +1450,17 @@ int search_graph(Call& c, int mode, int R, bool cones) {
             (void)hipGraphDestroy(graph);
             return hip_fail(e, "graph instantiate");
         }
-        if (ix->graphs.size() >= kMaxGraphs) {  // replays in flight keep their own references
+        if (ix->graphs.size() >= max_graphs()) {
             auto lru = std::min_element(ix->graphs.begin(), ix->graphs.end(),
                                         [](const GraphEntry& x, const GraphEntry& y) { return x.used < y.used; });
+            // its last replay may still run on a stream of its own (which the
+            // caller may have destroyed since): wait for the whole device
+            e = hipDeviceSynchronize();
+            if (e != hipSuccess) {
+                (void)hipGraphExecDestroy(ne.exec);
+                (void)hipGraphDestroy(graph);
+                return hip_fail(e, "graph eviction");
+            }
             destroy_graph(*lru);
             ix->graphs.erase(lru);
         }
@@ -2074,6 +2091,7 @@ int os_ann_set_nprobe(os_ann_index* ix, int32_t nprobe) {
     if (!ix->ivf_cent) return fail(OS_ANN_EINVAL, "not a clustered table");
     if (nprobe < 1 || nprobe > ix->n_groups || nprobe > 64) return fail(OS_ANN_EINVAL, "nprobe out of range");
     std::lock_guard<std::mutex> g(ix->graph_mu);
+    if (!ix->graphs.empty()) OSANN_HIP(hipDeviceSynchronize(), "set_nprobe");  // replays may still run
     drop_graphs(ix);  // captured searches used the old count
     ix->nprobe = nprobe;
     return OS_ANN_OK;

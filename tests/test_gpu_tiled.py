@@ -243,6 +243,33 @@ def test_graph_shape_class_new_buffers(orc, mode):
         B.os_ann_free(h)
 
 
+def test_graph_eviction_recaptures(orc, monkeypatch):
+    # a cap of two graphs: three classes evict the least recently replayed,
+    # which is captured again when it comes back; every result is the oracle's
+    monkeypatch.setenv("OSANN_MAX_GRAPHS", "2")
+    X = W.gaussian_db(20000, 32, seed=2521)
+    h = B.os_ann_build_ex(dev(X), 2)
+    o = orc.build_index(X, 2)
+    s = torch.cuda.Stream()
+    try:
+        st0 = B.os_ann_graph_stats(h)
+        for k, Q in enumerate((700, 300, 100, 700)):  # largest first: one arena, no regrowth
+            Y = W.gaussian_queries(Q, 32, seed=2530 + k)
+            say(f"[graph] eviction step {k} Q={Q}")
+            with torch.cuda.stream(s):
+                gi, gd, gn = B.os_ann_search_ex(h, dev(Y), 900, stream=s, flags=B.OS_ANN_FLAG_GRAPH)
+            s.synchronize()
+            ri, rd32, rd64, rn = orc.search(X, o, Y, 900)
+            assert np.array_equal(gn.cpu().numpy(), rn) and np.array_equal(gi.cpu().numpy(), ri)
+            assert np.array_equal(gd.cpu().numpy().view(np.uint32), rd32.view(np.uint32))
+        st = B.os_ann_graph_stats(h)
+        assert st["captured"] - st0["captured"] == 4, st  # the fourth call recaptured an evicted class
+        assert st["replayed"] - st0["replayed"] == 4 and st["cached"] == 2, st
+    finally:
+        torch.cuda.synchronize()
+        B.os_ann_free(h)
+
+
 @pytest.mark.parametrize("case", ["gauss64", "gauss32_r16", "desc128_u8", "patch_f16", "gauss64_r4_q1"])
 def test_screen_kernels_agree(orc, monkeypatch, case):
     # the cone-major screen (one list per (query, 64-cone word), queries
