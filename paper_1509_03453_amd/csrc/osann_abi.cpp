@@ -541,9 +541,14 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         // probed-cone bitmaps pay off once a query probes many cones and stay small
         const int64_t mean_bucket = std::max<int64_t>(1, ix->N / ne);
         const int64_t probes = cones ? std::min<int64_t>(budget, ne) : std::min<int64_t>(budget, ix->N) / mean_bucket + 1;
-        p.bitmap = probes >= 32 && p.nw <= 512 && (size_t)Q * p.nw * 8 <= ((size_t)1 << 30);
-        // the cone-major screen keeps one top-R list per (query, 64-cone word)
-        p.cone_ok = p.bitmap && cone_screen_ok(p.dk, R) && (size_t)Q * p.nw * R * 8 <= ((size_t)1 << 30);
+        const bool bitmap_fits = p.nw <= 512 && (size_t)Q * p.nw * 8 <= ((size_t)1 << 30);
+        p.bitmap = probes >= 32 && bitmap_fits;
+        // the cone-major screen keeps one top-R list per (query, 64-cone word);
+        // OSANN_TILED_KERNEL=cone (testing) takes it at any probe count
+        const char* kenv = std::getenv("OSANN_TILED_KERNEL");
+        const bool force_cone = kenv && std::string(kenv) == "cone";
+        p.cone_ok = (p.bitmap || (force_cone && bitmap_fits)) && cone_screen_ok(p.dk, R) &&
+                    (size_t)Q * p.nw * R * 8 <= ((size_t)1 << 30);
         p.off_ql = take((size_t)Q * p.dk * 2);
         p.off_qcone = take((size_t)Q * 4);
         p.off_sort = take((size_t)(4 * Q + radix_hist_words(Q)) * 4);
@@ -553,7 +558,7 @@ SearchPlan plan_search(const os_ann_index* ix, int64_t Q, int64_t budget, int mo
         p.off_part = take((size_t)Q * (p.cone_ok ? std::max<int64_t>(p.smax, p.nw) : p.smax) * R * 8);
         p.off_counter = take(256);
         p.off_cmin = take((size_t)Q * R * 4);
-        if (p.bitmap) p.off_qbits = take((size_t)Q * p.nw * 8);
+        if (p.bitmap || p.cone_ok) p.off_qbits = take((size_t)Q * p.nw * 8);
     }
     p.bytes = at;
     return p;
@@ -1016,6 +1021,7 @@ int tiled_plans(const os_ann_index* ix, int64_t Q, int64_t budget, int R, bool c
             plans[n] = def;
             plans[n].qkey = qk;
             plans[n].fits = true;  // its LDS use depends on dk only (at most 32 KB of queries)
+            plans[n].bitmap = true;    // it finds each cone's queries in the bitmaps
             plans[n++].kern = 1;
         }
         if (kfix == 2 && def.cone_ok) continue;
