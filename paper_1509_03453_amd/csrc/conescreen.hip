@@ -62,6 +62,8 @@ __global__ __launch_bounds__(256, 2) void cone_screen_kernel(TiledArgs a, int64_
     __shared__ uint4 s_hit[4][kHitCap];   // per wave: (d~ bits, padded position, slot, original row)
     __shared__ uint8_t s_sel[4][QB];      // per wave: slots probing the cone being screened
     __shared__ float s_thr[4][QB];        // per wave: bound of each slot
+    __shared__ uint32_t s_head[4][QB];    // per wave, during a flush: last hit of each slot (~0: none)
+    __shared__ uint32_t s_next[4][kHitCap];  // the hit chained before it for the same slot
     const int w = threadIdx.x / 64, l = lane_id();
     const int64_t ncg = (a.nw + 3) / 4;
     const int64_t xq = blockIdx.x % kXcd, jj = blockIdx.x / kXcd;
@@ -137,10 +139,22 @@ __global__ __launch_bounds__(256, 2) void cone_screen_kernel(TiledArgs a, int64_
     wave_sync();
 
     // ---- hits -> lists: lane l owns slots l and 64 + l ----
+    // A flush chains each buffered hit into its slot's list in LDS (one
+    // exchange per hit), so each lane then walks only its own slots' hits
+    // (a few) instead of the whole buffer; the merge keeps the R smallest
+    // (d~, row) and the class minima, neither of which depends on the order.
+    uint32_t* head = s_head[w];
+    uint32_t* nxt = s_next[w];
+    head[l] = ~0u;
+    head[64 + l] = ~0u;
     uint32_t nhit = 0;
     auto flush = [&]() {
         wave_sync();
-        if ((uint32_t)l < nhit) hit[l].w = a.prow[hit[l].y];
+        if ((uint32_t)l < nhit) {
+            const uint4 en = hit[l];
+            hit[l].w = a.prow[en.y];
+            nxt[l] = atomicExch(&head[en.z], (uint32_t)l);
+        }
         wave_sync();
         float ld0[R], ld1[R];
         uint32_t lr0[R], lr1[R];
@@ -152,22 +166,23 @@ __global__ __launch_bounds__(256, 2) void cone_screen_kernel(TiledArgs a, int64_
             ld1[r] = __uint_as_float(e1.x);
             lr1[r] = e1.y;
         }
-        bool ch0 = false, ch1 = false;
-        for (uint32_t h = 0; h < nhit; ++h) {
-            const uint4 en = hit[h];
-            const float d = __uint_as_float(en.x);
-            if (en.z == (uint32_t)l && pair_less(d, en.w, ld0[R - 1], lr0[R - 1])) {
-                list_insert<R>(ld0, lr0, d, en.w);
-                ch0 = true;
-                __hip_atomic_fetch_min(a.cmin + (int64_t)(en.y & (R - 1)) * a.Q + slot0 + l, ord_bits(d),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else if (en.z == (uint32_t)(64 + l) && pair_less(d, en.w, ld1[R - 1], lr1[R - 1])) {
-                list_insert<R>(ld1, lr1, d, en.w);
-                ch1 = true;
-                __hip_atomic_fetch_min(a.cmin + (int64_t)(en.y & (R - 1)) * a.Q + slot0 + 64 + l, ord_bits(d),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        auto merge = [&](int s, float (&ld)[R], uint32_t (&lr)[R]) {
+            bool ch = false;
+            for (uint32_t j = head[s]; j != ~0u; j = nxt[j]) {
+                const uint4 en = hit[j];
+                const float d = __uint_as_float(en.x);
+                if (pair_less(d, en.w, ld[R - 1], lr[R - 1])) {
+                    list_insert<R>(ld, lr, d, en.w);
+                    ch = true;
+                    __hip_atomic_fetch_min(a.cmin + (int64_t)(en.y & (R - 1)) * a.Q + slot0 + s, ord_bits(d),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
-        }
+            head[s] = ~0u;  // empty for the next flush
+            return ch;
+        };
+        const bool ch0 = merge(l, ld0, lr0);
+        const bool ch1 = merge(64 + l, ld1, lr1);
         if (ch0) {
 #pragma unroll
             for (int r = 0; r < R; ++r) wl[l * R + r] = make_uint2(__float_as_uint(ld0[r]), lr0[r]);
