@@ -59,7 +59,10 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
     extern __shared__ uint64_t dyn[];
     __shared__ uint2 s_list[4][QW * R];     // per wave: top-R list of each query slot
     __shared__ uint4 s_hit[4][kHitCap];     // per wave: (d~ bits, padded position, slot, original row) hits
+    __shared__ uint32_t s_head[4][64];      // per wave, during a flush: last hit of each slot (~0: none)
+    __shared__ uint32_t s_next[4][kHitCap];  // the hit chained before it for the same slot
     const int w = threadIdx.x / 64, l = lane_id();
+    s_head[w][l] = ~0u;
     // Work queue of this block's chiplet (blocks are dealt to the kXcd chiplets
     // in turn, and each has its own L2): with 8 splits or more, chiplet x
     // takes the splits x, x + kXcd, ... one after the other, so the waves
@@ -133,11 +136,16 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
         };
         refresh_thr();
         // merge the hit buffer into the lists: first every lane looks up the
-        // original rows of up to one hit (one parallel gather), then lane l
-        // takes the hits of slot l
+        // original row of up to one hit (one parallel gather) and chains the
+        // hit into its slot's list in LDS (one exchange), then lane l walks
+        // the hits of slot l only (the merge does not depend on their order)
         auto flush = [&]() {
             wave_sync();
-            if ((uint32_t)l < nhit) s_hit[w][l].w = a.prow[s_hit[w][l].y];
+            if ((uint32_t)l < nhit) {
+                const uint4 e = s_hit[w][l];
+                s_hit[w][l].w = a.prow[e.y];
+                s_next[w][l] = atomicExch(&s_head[w][e.z], (uint32_t)l);
+            }
             wave_sync();
             float ld[R];
             uint32_t lr[R];
@@ -148,15 +156,18 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
                 lr[k] = e.y;
             }
             bool changed = false;
-            for (uint32_t h = 0; h < nhit; ++h) {
-                const uint4 e = s_hit[w][h];
-                const float d = __uint_as_float(e.x);
-                if (e.z == (uint32_t)l && pair_less(d, e.w, ld[R - 1], lr[R - 1])) {
-                    list_insert<R>(ld, lr, d, e.w);
-                    changed = true;
-                    __hip_atomic_fetch_min(a.cmin + (int64_t)(e.y & (R - 1)) * a.Q + own_slot, ord_bits(d),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (l < QW) {
+                for (uint32_t h = s_head[w][l]; h != ~0u; h = s_next[w][h]) {
+                    const uint4 e = s_hit[w][h];
+                    const float d = __uint_as_float(e.x);
+                    if (pair_less(d, e.w, ld[R - 1], lr[R - 1])) {
+                        list_insert<R>(ld, lr, d, e.w);
+                        changed = true;
+                        __hip_atomic_fetch_min(a.cmin + (int64_t)(e.y & (R - 1)) * a.Q + own_slot, ord_bits(d),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
+                s_head[w][l] = ~0u;  // empty for the next flush
             }
             if (changed && l < QW)
 #pragma unroll
