@@ -14,6 +14,7 @@ namespace osann {
 inline int tile_groups(int R) { return R <= 8 ? 4 : 2; }  // default
 inline bool tile_groups_ok(int R, int G) { return G == 2 || (G == 4 && R <= 8); }
 constexpr int kChunk = 512;  // cones a screen wave lists at a time (a multiple of 64)
+constexpr int kWalkCache = 16;  // probed non-empty cones a query lane keeps from one walk decode (no bitmaps)
 constexpr int kXcd = 8;      // chiplets (each with its own L2) the blocks of a launch are dealt to in turn
 constexpr size_t kLdsPerBlock = 160 * 1024;  // LDS of one compute unit, all usable by one block
 

@@ -61,6 +61,7 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
     __shared__ uint4 s_hit[4][kHitCap];     // per wave: (d~ bits, padded position, slot, original row) hits
     __shared__ uint32_t s_head[4][64];      // per wave, during a flush: last hit of each slot (~0: none)
     __shared__ uint32_t s_next[4][kHitCap];  // the hit chained before it for the same slot
+    __shared__ uint32_t s_walk[4][64 * kWalkCache];  // per wave, lane l: ranks of the non-empty cones its query probes
     const int w = threadIdx.x / 64, l = lane_id();
     s_head[w][l] = ~0u;
     // Work queue of this block's chiplet (blocks are dealt to the kXcd chiplets
@@ -97,6 +98,26 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
         const bool own_ok = l < QW && slot0 + l < a.Q;
         const uint32_t own_q = own_ok ? a.qorder[slot0 + l] : 0u;
         const int64_t own_slot = own_ok ? slot0 + l : 0;  // class minima are stored by tile slot
+        // Without bitmaps, each query lane decodes its walk once per item and
+        // keeps the ranks of the non-empty cones it probes (up to kWalkCache;
+        // a lane with more decodes its walk again for every chunk of cones).
+        uint32_t* wc = s_walk[w] + l * kWalkCache;
+        uint32_t nwc = 0;
+        bool wover = false;
+        const uint32_t walk_len = !a.qbits && own_ok ? a.jstop[own_q] : 0u;
+        if (!a.qbits && own_ok && walk_len != kWalkAll) {
+            const uint8_t* qo = a.order + (int64_t)own_q * a.D;
+            const uint8_t* qs = a.sbit + (int64_t)own_q * a.D;
+            for (uint32_t j = 0; j < walk_len; ++j) {
+                const uint32_t cone = probe_cone(j, a.L, qo, qs, a.n_sub, a.lexsub, a.maskord, a.binom);
+                if (a.offsets[cone + 1] <= a.offsets[cone]) continue;
+                if (nwc == (uint32_t)kWalkCache) {
+                    wover = true;
+                    break;
+                }
+                wc[nwc++] = a.ne_id[cone];
+            }
+        }
 
         // 1. B operands: group g = query slots 16g .. 16g+15 of the tile;
         //    lane l works on slot 16g + l%16 of every group
@@ -225,11 +246,17 @@ __global__ __launch_bounds__(256, 2) void tiled_screen_kernel(TiledArgs a) {
             } else {
                 // one lane per query regenerates its walk; a query that probes
                 // every cone sets its bit everywhere
-                const uint32_t js = own_ok ? a.jstop[own_q] : 0u;
+                const uint32_t js = walk_len;
                 const uint64_t all = __ballot(own_ok && js == kWalkAll);
                 for (int i = l; i < nchunk; i += 64) tab[i] = all;
                 wave_sync();
-                if (own_ok && js != kWalkAll) {
+                if (own_ok && js != kWalkAll && !wover) {
+                    const unsigned long long bit = 1ull << l;
+                    for (uint32_t k = 0; k < nwc; ++k) {
+                        const int64_t e = wc[k];
+                        if (e >= c0 && e < c1) atomicOr((unsigned long long*)&tab[e - c0], bit);
+                    }
+                } else if (own_ok && js != kWalkAll) {
                     const uint8_t* qo = a.order + (int64_t)own_q * a.D;
                     const uint8_t* qs = a.sbit + (int64_t)own_q * a.D;
                     const unsigned long long bit = 1ull << l;
@@ -735,7 +762,7 @@ hipError_t launch_tiled_finish(const FinishArgs& f, int R, hipStream_t s) {
 
 size_t tiled_screen_static_lds(int R, int G) {
     const size_t qw = 16 * (size_t)G;
-    return 4 * qw * R * 8 + 4 * (size_t)kHitCap * 16 + 512;
+    return 4 * qw * R * 8 + 4 * (size_t)kHitCap * 16 + 4 * (64 + (size_t)kHitCap) * 4 + 4 * 64 * kWalkCache * 4 + 512;
 }
 
 // Lets every screen kernel take all the LDS its static arrays leave free.
