@@ -52,18 +52,23 @@ __device__ inline uint64_t readlane_u64(uint64_t v, int lane) {
 }
 constexpr int kConeG = 4;     // MFMA B groups (16 queries each) per pass over a cone's rows
 
+// Waves per SIMD the kernel is register-capped for: three where the block's
+// LDS (short rows) lets three blocks share a compute unit, else two.
+template <int KS>
+constexpr int cone_waves_per_simd() { return KS <= 2 ? 3 : 2; }
+
 template <bool F16IN, int KS, int R>
-__global__ __launch_bounds__(256, 2) void cone_screen_kernel(TiledArgs a, int64_t nqb) {
+__global__ __launch_bounds__(256, cone_waves_per_simd<KS>()) void cone_screen_kernel(TiledArgs a, int64_t nqb) {
     constexpr int QB = kConeQB;
     constexpr int G = kConeG;
     constexpr int UNITS = 4 * KS;         // 16-byte units of one query's codes (dk = 32 KS)
     extern __shared__ uint4 s_q[];        // [QB][UNITS] the block's queries
     __shared__ uint2 s_list[4][QB * R];   // per wave: top-R list per slot, ascending (d~, original row)
-    __shared__ uint4 s_hit[4][kHitCap];   // per wave: (d~ bits, padded position, slot, original row)
+    __shared__ uint3 s_hit[4][kHitCap];   // per wave: (d~ bits, padded position, slot); a flush
+                                          // rewrites .y as the original row and .z as
+                                          // slot | class << 8 | previous hit << 16
     __shared__ uint8_t s_sel[4][QB];      // per wave: slots probing the cone being screened
-    __shared__ float s_thr[4][QB];        // per wave: bound of each slot
-    __shared__ uint32_t s_head[4][QB];    // per wave, during a flush: last hit of each slot (~0: none)
-    __shared__ uint32_t s_next[4][kHitCap];  // the hit chained before it for the same slot
+    __shared__ uint8_t s_head[4][QB];     // per wave, during a flush: last hit of each slot (0xFF: none)
     const int w = threadIdx.x / 64, l = lane_id();
     const int64_t ncg = (a.nw + 3) / 4;
     const int64_t xq = blockIdx.x % kXcd, jj = blockIdx.x / kXcd;
@@ -87,9 +92,10 @@ __global__ __launch_bounds__(256, 2) void cone_screen_kernel(TiledArgs a, int64_
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     };
     uint2* wl = s_list[w];
-    uint4* hit = s_hit[w];
+    uint3* hit = s_hit[w];
     uint8_t* sel = s_sel[w];
-    float* thr = s_thr[w];
+    // bound of slots l and 64 + l (lane l's own); other lanes read them by shuffle
+    float thr[2] = {__builtin_huge_valf(), __builtin_huge_valf()};
     for (int t = l; t < QB * R; t += 64) wl[t] = make_uint2(0x7F800000u, 0xFFFFFFFFu);
     // bound of each slot: the largest of its R class minima (+inf while a class is empty)
     auto shared_bounds = [&]() {
@@ -106,11 +112,9 @@ __global__ __launch_bounds__(256, 2) void cone_screen_kernel(TiledArgs a, int64_
                     b = v > b ? v : b;
                 }
             }
-            thr[s] = fminf(thr[s], ord_float(b));
+            thr[h] = fminf(thr[h], ord_float(b));
         }
     };
-#pragma unroll
-    for (int h = 0; h < 2; ++h) thr[64 * h + l] = __builtin_huge_valf();
     shared_bounds();
 
     // lane c: masks over the block's 128 slots of the queries that probe
@@ -139,60 +143,67 @@ __global__ __launch_bounds__(256, 2) void cone_screen_kernel(TiledArgs a, int64_
     wave_sync();
 
     // ---- hits -> lists: lane l owns slots l and 64 + l ----
-    // A flush chains each buffered hit into its slot's list in LDS (one
-    // exchange per hit), so each lane then walks only its own slots' hits
-    // (a few) instead of the whole buffer; the merge keeps the R smallest
-    // (d~, row) and the class minima, neither of which depends on the order.
-    uint32_t* head = s_head[w];
-    uint32_t* nxt = s_next[w];
-    head[l] = ~0u;
-    head[64 + l] = ~0u;
+    // A flush chains each buffered hit to the previous hit of the same slot
+    // (found by matching slot bits across the wave: the last hit of a slot
+    // becomes its head), so each lane then walks only its own slots' hits (a
+    // few) instead of the whole buffer; the merge keeps the R smallest (d~,
+    // row) and the class minima, neither of which depends on the order.
+    uint8_t* head = s_head[w];
+    head[l] = 0xFFu;
+    head[64 + l] = 0xFFu;
     uint32_t nhit = 0;
     auto flush = [&]() {
         wave_sync();
-        if ((uint32_t)l < nhit) {
-            const uint4 en = hit[l];
-            hit[l].w = a.prow[en.y];
-            nxt[l] = atomicExch(&head[en.z], (uint32_t)l);
+        const bool mine = (uint32_t)l < nhit;
+        const uint3 en = hit[l];  // entries past nhit are stale but never used
+        const uint32_t sl = en.z & 0xFFu;
+        uint64_t same = __ballot(mine);
+#pragma unroll
+        for (int b = 0; b < 7; ++b) {
+            const bool bit = (sl >> b) & 1u;
+            const uint64_t ones = __ballot(bit);
+            same &= bit ? ones : ~ones;
+        }
+        if (mine) {
+            const uint64_t before = same & lanemask_lt();
+            const uint32_t prev = before ? 63u - (uint32_t)__clzll((unsigned long long)before) : 0xFFu;
+            hit[l] = make_uint3(en.x, a.prow[en.y], sl | ((en.y & (uint32_t)(R - 1)) << 8) | (prev << 16));
+            if ((same >> l) == 1ull) head[sl] = (uint8_t)l;  // no later hit of this slot
         }
         wave_sync();
-        float ld0[R], ld1[R];
-        uint32_t lr0[R], lr1[R];
+        auto merge = [&](int h) __attribute__((always_inline)) {
+            const int s = 64 * h + l;
+            uint32_t j = head[s];
+            if (j == 0xFFu) return;
+            float ld[R];
+            uint32_t lr[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint2 e0 = wl[l * R + r], e1 = wl[(64 + l) * R + r];
-            ld0[r] = __uint_as_float(e0.x);
-            lr0[r] = e0.y;
-            ld1[r] = __uint_as_float(e1.x);
-            lr1[r] = e1.y;
-        }
-        auto merge = [&](int s, float (&ld)[R], uint32_t (&lr)[R]) {
+            for (int r = 0; r < R; ++r) {
+                const uint2 e = wl[s * R + r];
+                ld[r] = __uint_as_float(e.x);
+                lr[r] = e.y;
+            }
             bool ch = false;
-            for (uint32_t j = head[s]; j != ~0u; j = nxt[j]) {
-                const uint4 en = hit[j];
-                const float d = __uint_as_float(en.x);
-                if (pair_less(d, en.w, ld[R - 1], lr[R - 1])) {
-                    list_insert<R>(ld, lr, d, en.w);
+            for (; j != 0xFFu;) {
+                const uint3 he = hit[j];
+                const float d = __uint_as_float(he.x);
+                if (pair_less(d, he.y, ld[R - 1], lr[R - 1])) {
+                    list_insert<R>(ld, lr, d, he.y);
                     ch = true;
-                    __hip_atomic_fetch_min(a.cmin + (int64_t)(en.y & (R - 1)) * a.Q + slot0 + s, ord_bits(d),
+                    __hip_atomic_fetch_min(a.cmin + (int64_t)((he.z >> 8) & 0xFFu) * a.Q + slot0 + s, ord_bits(d),
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
+                j = (he.z >> 16) & 0xFFu;
             }
-            head[s] = ~0u;  // empty for the next flush
-            return ch;
+            head[s] = 0xFFu;  // empty for the next flush
+            if (ch) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) wl[s * R + r] = make_uint2(__float_as_uint(ld[r]), lr[r]);
+                thr[h] = fminf(thr[h], ld[R - 1]);
+            }
         };
-        const bool ch0 = merge(l, ld0, lr0);
-        const bool ch1 = merge(64 + l, ld1, lr1);
-        if (ch0) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) wl[l * R + r] = make_uint2(__float_as_uint(ld0[r]), lr0[r]);
-            thr[l] = fminf(thr[l], ld0[R - 1]);
-        }
-        if (ch1) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) wl[(64 + l) * R + r] = make_uint2(__float_as_uint(ld1[r]), lr1[r]);
-            thr[64 + l] = fminf(thr[64 + l], ld1[R - 1]);
-        }
+        merge(0);
+        merge(1);
         nhit = 0;
         wave_sync();
     };
@@ -243,7 +254,11 @@ __global__ __launch_bounds__(256, 2) void cone_screen_kernel(TiledArgs a, int64_
     uint32_t bslot[G];  // its slot, 0xFF: none
     auto set_pthr = [&]() {
 #pragma unroll
-        for (int g = 0; g < G; ++g) pthr[g] = bslot[g] != 0xFFu ? -0.5f * thr[bslot[g]] : __builtin_huge_valf();
+        for (int g = 0; g < G; ++g) {
+            const int src = (int)(bslot[g] & 63u);
+            const float t0 = __shfl(thr[0], src, 64), t1 = __shfl(thr[1], src, 64);
+            pthr[g] = bslot[g] != 0xFFu ? -0.5f * (bslot[g] < 64u ? t0 : t1) : __builtin_huge_valf();
+        }
     };
     auto setup = [&](int c, int base) __attribute__((always_inline)) {
         if (c != unit_c) {
@@ -307,7 +322,7 @@ __global__ __launch_bounds__(256, 2) void cone_screen_kernel(TiledArgs a, int64_
                     }
                     if (pass) {
                         const uint32_t at = nhit + (uint32_t)__popcll(m & lanemask_lt());
-                        hit[at] = make_uint4(__float_as_uint(-2.0f * acc[g][ii]), t.p + 4 * (l / 16) + ii, bslot[g], 0u);
+                        hit[at] = make_uint3(__float_as_uint(-2.0f * acc[g][ii]), t.p + 4 * (l / 16) + ii, bslot[g]);
                     }
                     nhit += (uint32_t)__popcll(m);
                 }
