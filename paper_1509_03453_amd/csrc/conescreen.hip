@@ -63,7 +63,8 @@ __global__ __launch_bounds__(256, cone_waves_per_simd<KS>()) void cone_screen_ke
     constexpr int G = kConeG;
     constexpr int UNITS = 4 * KS;         // 16-byte units of one query's codes (dk = 32 KS)
     extern __shared__ uint4 s_q[];        // [QB][UNITS] the block's queries
-    __shared__ uint2 s_list[4][QB * R];   // per wave: top-R list per slot, ascending (d~, original row)
+    __shared__ uint2 s_list[4][R * QB];   // per wave: top-R list per slot, ascending (d~, original row);
+                                          // entry r of slot s at r * QB + s
     __shared__ uint3 s_hit[4][kHitCap];   // per wave: (d~ bits, padded position, slot); a flush
                                           // rewrites .y as the original row and .z as
                                           // slot | class << 8 | previous hit << 16
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(256, cone_waves_per_simd<KS>()) void cone_screen_ke
             uint32_t lr[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const uint2 e = wl[s * R + r];
+                const uint2 e = wl[r * QB + s];
                 ld[r] = __uint_as_float(e.x);
                 lr[r] = e.y;
             }
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256, cone_waves_per_simd<KS>()) void cone_screen_ke
             head[s] = 0xFFu;  // empty for the next flush
             if (ch) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) wl[s * R + r] = make_uint2(__float_as_uint(ld[r]), lr[r]);
+                for (int r = 0; r < R; ++r) wl[r * QB + s] = make_uint2(__float_as_uint(ld[r]), lr[r]);
                 thr[h] = fminf(thr[h], ld[R - 1]);
             }
         };
@@ -290,22 +291,21 @@ __global__ __launch_bounds__(256, cone_waves_per_simd<KS>()) void cone_screen_ke
     auto screen = [&](const Tile& t, const uint4 (&av)[KS], const float4& nv) __attribute__((always_inline)) {
         if (t.c != unit_c || t.base != unit_base) setup(t.c, t.base);
         const f32x4_t c0 = {-0.5f * nv.x, -0.5f * nv.y, -0.5f * nv.z, -0.5f * nv.w};
+        // every group, used or not: straight-line code (a group past the
+        // pass's queries holds zero operands and a +inf bound, so it never
+        // passes the test)
         f32x4_t acc[G];
         float margin = -__builtin_huge_valf();
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            if (g < ng) {
-                acc[g] = mfma16<F16IN>(av[0], bq[g][0], c0);
+        for (int g = 0; g < G; ++g) acc[g] = mfma16<F16IN>(av[0], bq[g][0], c0);
 #pragma unroll
-                for (int ks = 1; ks < KS; ++ks) acc[g] = mfma16<F16IN>(av[ks], bq[g][ks], acc[g]);
-            }
-        }
+        for (int ks = 1; ks < KS; ++ks)
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = mfma16<F16IN>(av[ks], bq[g][ks], acc[g]);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (g < ng) {
-                const float m4 = fmaxf(fmaxf(acc[g][0], acc[g][1]), fmaxf(acc[g][2], acc[g][3]));
-                margin = fmaxf(margin, m4 - pthr[g]);
-            }
+            const float m4 = fmaxf(fmaxf(acc[g][0], acc[g][1]), fmaxf(acc[g][2], acc[g][3]));
+            margin = fmaxf(margin, m4 - pthr[g]);
         }
         if (__ballot(margin >= 0.0f) != 0) {  // rare once the bounds have settled
 #pragma unroll
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(256, cone_waves_per_simd<KS>()) void cone_screen_ke
         if (s < nq) {
             uint2* dst = a.part + ((int64_t)a.qorder[slot0 + s] * a.S + k) * R;
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r] = wl[s * R + r];
+            for (int r = 0; r < R; ++r) dst[r] = wl[r * QB + s];
         }
     }
 }
