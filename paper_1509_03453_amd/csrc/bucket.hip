@@ -86,6 +86,93 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
     }
 }
 
+// The same sort for short inputs (a search's queries) in one block of 1024
+// threads and one launch: every pass counts the digits of the whole input
+// (LDS counts), scans them, then takes the input in order, 1024 elements at
+// a time, ranking each element among the equal digits before it exactly as
+// radix_scatter_kernel does (wave ballots, then the earlier waves' counts).
+// The ping-pong arrays stay in the L2; the block barrier between passes
+// makes one pass's writes visible to the next (one compute unit, one L1).
+constexpr int kSmallSortThreads = 1024;
+constexpr int64_t kSmallSortMax = 32768;
+
+__global__ __launch_bounds__(kSmallSortThreads) void radix_small_kernel(const uint32_t* __restrict__ keys_in,
+                                                                        int64_t N, int passes, uint32_t* ka,
+                                                                        uint32_t* va, uint32_t* kb, uint32_t* vb,
+                                                                        uint32_t* keys_out, uint32_t* vals_out) {
+    constexpr int kWaves = kSmallSortThreads / 64;
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kWaves][256];
+    const int tid = threadIdx.x, w = tid / 64, l = tid % 64;
+    const uint32_t* kin = keys_in;
+    const uint32_t* vin = nullptr;  // identity on the first pass
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        const bool last = p == passes - 1;
+        uint32_t* kout = last ? keys_out : ((p & 1) ? kb : ka);
+        uint32_t* vout = last ? vals_out : ((p & 1) ? vb : va);
+        if (tid < 256) run[tid] = 0;
+        __syncthreads();
+        for (int64_t i = tid; i < N; i += kSmallSortThreads) atomicAdd(&run[(kin[i] >> shift) & 255u], 1u);  // counts only
+        __syncthreads();
+        if (w == 0) {  // exclusive scan of the 256 counts: 4 per lane, then across the wave
+            uint32_t c[4], sum = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                c[j] = run[4 * l + j];
+                sum += c[j];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t up = (uint32_t)__shfl_up((int)incl, d, 64);
+                if (l >= d) incl += up;
+            }
+            uint32_t at = incl - sum;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                run[4 * l + j] = at;
+                at += c[j];
+            }
+        }
+        __syncthreads();
+        for (int64_t t = 0; t < N; t += kSmallSortThreads) {
+            for (int j = tid; j < kWaves * 256; j += kSmallSortThreads) (&wcnt[0][0])[j] = 0;
+            __syncthreads();
+            const int64_t i = t + tid;
+            const bool valid = i < N;
+            const uint32_t key = valid ? kin[i] : 0u;
+            const uint32_t val = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+            const uint32_t dig = (key >> shift) & 255u;
+            uint64_t same = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t ones = __ballot((dig >> b) & 1u);
+                same &= ((dig >> b) & 1u) ? ones : ~ones;
+            }
+            const uint32_t below = (uint32_t)__popcll(same & lanemask_lt());
+            if (valid && below == 0) wcnt[w][dig] = (uint32_t)__popcll(same);
+            __syncthreads();
+            if (valid) {
+                uint32_t off = run[dig] + below;
+                for (int a = 0; a < w; ++a) off += wcnt[a][dig];
+                kout[off] = key;
+                vout[off] = val;
+            }
+            __syncthreads();
+            if (tid < 256) {
+                uint32_t add = 0;
+#pragma unroll
+                for (int a = 0; a < kWaves; ++a) add += wcnt[a][tid];
+                run[tid] += add;
+            }
+            __syncthreads();
+        }
+        kin = kout;
+        vin = vout;
+    }
+}
+
 hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_cones, uint32_t* tmp,
                                uint32_t* perm_out, uint32_t* sorted_cone_out, hipStream_t s) {
     int bits = 1;
@@ -96,6 +183,11 @@ hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_co
     uint32_t* va = tmp + N;
     uint32_t* kb = tmp + 2 * N;
     uint32_t* vb = tmp + 3 * N;
+    if (N > 0 && N <= kSmallSortMax) {
+        hipLaunchKernelGGL(radix_small_kernel, dim3(1), dim3(kSmallSortThreads), 0, s, row_cone, N, passes, ka, va,
+                           kb, vb, sorted_cone_out, perm_out);
+        return hipGetLastError();
+    }
     const int64_t hw = 256 * nb;
     uint32_t* hist = tmp + 4 * N;        // per (digit, block) counts
     uint32_t* hscan = hist + hw;         // their exclusive scan (hw + 1 words)

@@ -29,15 +29,25 @@ __global__ __launch_bounds__(256) void row_keys_kernel(const typename E::raw* __
     bool bad = false;
     if (valid) {
         const typename E::raw* xr = X + row * (int64_t)D;
-        for (int i = t; i < D; i += S) {
-            typename E::raw b = xr[i];
-            bad |= E::nonfinite(b);
-            uint64_t k = comp_key(E::mag(b), i, E::neg(b));
-            // insert into the descending list
+        // four components per step, loaded before any is inserted (keys
+        // carry the component index, so they are distinct and the insertion
+        // order does not matter)
+        constexpr int U = 4;
+        for (int i0 = t; i0 < D; i0 += U * S) {
+            typename E::raw b[U];
 #pragma unroll
-            for (int j = L - 1; j >= 0; --j) {
-                uint64_t above = j > 0 ? top[j - 1] : ~0ull;
-                if (k > top[j]) top[j] = (k > above) ? above : k;
+            for (int u = 0; u < U; ++u) b[u] = i0 + u * S < D ? xr[i0 + u * S] : typename E::raw(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i0 + u * S >= D) break;
+                bad |= E::nonfinite(b[u]);
+                const uint64_t k = comp_key(E::mag(b[u]), i0 + u * S, E::neg(b[u]));
+                // insert into the descending list
+#pragma unroll
+                for (int j = L - 1; j >= 0; --j) {
+                    const uint64_t above = j > 0 ? top[j - 1] : ~0ull;
+                    if (k > top[j]) top[j] = (k > above) ? above : k;
+                }
             }
         }
     }

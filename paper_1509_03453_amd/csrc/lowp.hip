@@ -71,6 +71,31 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The padding rows of the copy (the slots past a cone's rows up to its
+// multiple of 16, and every row from the last cone's end to np_total): zero
+// components, no position, NaN norm.  Thread g < 16 nc takes slot g % 16 of
+// cone g / 16; the others take the tail, which starts at or after N.
+__global__ void lowp_pad_kernel(const uint32_t* __restrict__ off, const uint32_t* __restrict__ poff, int64_t nc,
+                                int dk, uint16_t* __restrict__ xl, uint32_t* __restrict__ ppos,
+                                uint32_t* __restrict__ prow, float* __restrict__ nrm, int64_t np_total) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = -1;
+    if (g < 16 * nc) {
+        const int64_t c = g / 16;
+        const int64_t q = (int64_t)poff[c] + (int64_t)(off[c + 1] - off[c]) + g % 16;
+        if (q < (int64_t)poff[c + 1]) p = q;
+    } else {
+        const int64_t q = (int64_t)poff[nc] + (g - 16 * nc);
+        if (q < np_total) p = q;
+    }
+    if (p < 0) return;
+    uint4* xr = reinterpret_cast<uint4*>(xl + p * dk);
+    for (int k = 0; k < dk / 8; ++k) xr[k] = make_uint4(0u, 0u, 0u, 0u);
+    ppos[p] = 0xFFFFFFFFu;
+    prow[p] = 0xFFFFFFFFu;
+    nrm[p] = __uint_as_float(0x7FC00000u);
+}
+
 // Rounded value of one component and its 16-bit code.
 __device__ inline uint16_t lowp_code(float x, int to_f16, float* v) {
     const uint16_t b = to_f16 ? f16_rne(x) : bf16_rne(x);
@@ -165,14 +190,23 @@ __global__ __launch_bounds__(256) void lowp_rows_kernel(const uint4* __restrict_
 }
 
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
-                            const uint32_t* offsets, const uint32_t* poff, const uint32_t* perm, int dk, int to_f16,
-                            uint16_t* xl, uint32_t* ppos, uint32_t* prow, uint32_t* ipos, float* nrm,
-                            int64_t np_total, hipStream_t s) {
-    // padding rows: zero components, no position, NaN norm (fails every comparison)
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(xl), np_total * dk / 2, 0u, s);
-    if (e == hipSuccess) e = launch_fill_u32(ppos, np_total, 0xFFFFFFFFu, s);
-    if (e == hipSuccess) e = launch_fill_u32(prow, np_total, 0xFFFFFFFFu, s);
-    if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(nrm), np_total, 0x7FC00000u, s);
+                            const uint32_t* offsets, int64_t n_cones, const uint32_t* poff, const uint32_t* perm,
+                            int dk, int to_f16, uint16_t* xl, uint32_t* ppos, uint32_t* prow, uint32_t* ipos,
+                            float* nrm, int64_t np_total, hipStream_t s) {
+    // padding rows: zero components, no position, NaN norm (fails every
+    // comparison); the real rows are written whole below
+    hipError_t e = hipSuccess;
+    if (16 * n_cones <= np_total) {
+        const int64_t threads = 16 * n_cones + (np_total - N);
+        hipLaunchKernelGGL(lowp_pad_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, offsets, poff,
+                           n_cones, dk, xl, ppos, prow, nrm, np_total);
+        e = hipGetLastError();
+    } else {
+        e = launch_fill_u32(reinterpret_cast<uint32_t*>(xl), np_total * dk / 2, 0u, s);
+        if (e == hipSuccess) e = launch_fill_u32(ppos, np_total, 0xFFFFFFFFu, s);
+        if (e == hipSuccess) e = launch_fill_u32(prow, np_total, 0xFFFFFFFFu, s);
+        if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(nrm), np_total, 0x7FC00000u, s);
+    }
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((N + 255) / 256));
     auto pl = static_cast<const uint4*>(planes);

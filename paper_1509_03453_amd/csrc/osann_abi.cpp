@@ -12,6 +12,7 @@
 #include <map>
 #include <atomic>
 #include <mutex>
+#include <set>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -133,6 +134,11 @@ struct os_ann_index {
     uint8_t* lexsub = nullptr;
     uint8_t* maskord = nullptr;
     uint32_t* binom = nullptr;
+    // a build whose closing check is left to the low-precision copy's end:
+    // its flags ([0] non-finite, [1] non-empty count) and sort scratch, kept
+    // until that synchronisation
+    uint32_t* pending_small = nullptr;
+    uint32_t* pending_tmp = nullptr;
     std::mutex lowp_mu;
     LowpCopy lp;
     // scratch owned by the index, used when the caller brings no workspace
@@ -364,7 +370,8 @@ void release(os_ann_index* ix, bool synced = false) {
                     ix->lp.poff,  ix->lp.ne_id, ix->lp.ne_cone, ix->lp.xl,       ix->lp.nrm,
                     ix->lp.ppos,  ix->lp.prow,  ix->lp.ipos,  ix->rot,      ix->rot_offsets, ix->rot_perm,   ix->xtop,
                     ix->planes_tab, ix->proj_mu, ix->proj_P, ix->ivf_cent, ix->rot_signs,
-                    ix->sp_keys, ix->sp_hkeys, ix->sp_hval, ix->sp_filt, ix->binom64};
+                    ix->sp_keys, ix->sp_hkeys, ix->sp_hval, ix->sp_filt, ix->binom64,
+                    ix->pending_small, ix->pending_tmp};
     for (void* p : ptrs) dev_free(p);
     delete ix;
 }
@@ -381,6 +388,22 @@ int check_shape(int64_t N, int32_t D, int32_t L, int64_t* n_cones, bool allow_sp
 
 bool dtype_ok(int32_t t) { return t == kF32 || t == kF16 || t == kU8; }
 bool rerank_ok(int32_t r) { return r == 4 || r == 8 || r == 16; }
+
+// The screens' dynamic LDS limits: set once per device (the attribute
+// belongs to the device, not to an index).
+hipError_t screen_lds_once() {
+    static std::mutex mu;
+    static std::set<int> set_on;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> g(mu);
+    if (set_on.count(dev)) return hipSuccess;
+    e = tiled_screen_max_lds();
+    if (e == hipSuccess) e = cone_screen_max_lds();
+    if (e == hipSuccess) set_on.insert(dev);
+    return e;
+}
 
 // Builds the low-precision copy once per index.
 int ensure_lowp(os_ann_index* ix, hipStream_t s) {
@@ -414,24 +437,45 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
     if (rc) return done(rc);
     hipError_t e = launch_lowp_layout(ix->offsets, nc, tmp, tmp + nc, tmp + 2 * nc, lp.poff, lp.ne_id,
                                       lp.ne_cone, s);
-    uint32_t np32 = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&np32, lp.poff + nc, 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return done(hip_fail(e, "low-precision layout"));
-    lp.np = np32;
-    const int64_t rows = lp.np + 16;  // 16 zero rows past the end
+    // Each non-empty cone rounds up to a multiple of 16 rows, so the copy
+    // holds at most N + 15 min(cones, N) rows.  Where that bound is within a
+    // quarter of N it sizes the copy (no wait for the exact count); else the
+    // count is read first.
+    const int64_t ne_max = std::min<int64_t>(nc, ix->N);
+    if (15 * ne_max <= ix->N / 4) {
+        lp.np = ix->N + 15 * ne_max;
+    } else {
+        uint32_t np32 = 0;
+        e = hipMemcpyAsync(&np32, lp.poff + nc, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return done(hip_fail(e, "low-precision layout"));
+        lp.np = np32;
+    }
+    const int64_t rows = lp.np + 16;  // at least 16 zero rows past the end
     rc = dev_alloc(ix, (void**)&lp.xl, (size_t)rows * lp.dk * 2, "xl");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.nrm, (size_t)rows * 4, "nrm");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.ppos, (size_t)rows * 4, "ppos");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.prow, (size_t)rows * 4, "prow");
     if (!rc) rc = dev_alloc(ix, (void**)&lp.ipos, (size_t)ix->N * 4, "ipos");
     if (rc) return done(rc);
-    e = launch_lowp_rows(ix->planes, ix->dtype, ix->N, ix->D, ix->nch, ix->sorted_cone, ix->offsets, lp.poff,
+    e = launch_lowp_rows(ix->planes, ix->dtype, ix->N, ix->D, ix->nch, ix->sorted_cone, ix->offsets, nc, lp.poff,
                          ix->perm, lp.dk, lp.f16, lp.xl, lp.ppos, lp.prow, lp.ipos, lp.nrm, rows, s);
-    if (e == hipSuccess) e = tiled_screen_max_lds();
-    if (e == hipSuccess) e = cone_screen_max_lds();
+    if (e == hipSuccess) e = screen_lds_once();
+    // a build that left its closing check here: its flags come back with
+    // this one synchronisation
+    uint32_t host_small[2] = {0, 0};
+    if (e == hipSuccess && ix->pending_small)
+        e = hipMemcpyAsync(host_small, ix->pending_small, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return done(hip_fail(e, "low-precision copy"));
+    if (ix->pending_small) {
+        dev_free(ix->pending_small);
+        dev_free(ix->pending_tmp);
+        ix->pending_small = ix->pending_tmp = nullptr;
+        if (host_small[0]) return done(fail(OS_ANN_ENONFINITE, "database holds NaN or infinity"));
+        ix->n_nonempty = host_small[1];
+    }
     lp.ready = true;
     return done(OS_ANN_OK);
 }
@@ -1545,9 +1589,13 @@ void jacobi_eigen(std::vector<double>& A, int n, std::vector<double>& V) {
 // table stores the rows `db` (type dtype) in that bucket order.  For one
 // basis both are the database; for basis r of several, keys holds the
 // database's coordinates in that basis.
+//
+// defer: the closing check (non-finite rows, non-empty count) is not taken
+// here but by ensure_lowp's one synchronisation at its end, which the caller
+// runs next; until then the index holds the flags and the sort scratch.
 os_ann_index* build_table(const void* keys, int32_t key_dtype, int32_t Dk, const void* db, int32_t dtype, int64_t N,
                           int32_t D, int32_t L, int64_t nc, hipStream_t s, const uint32_t* group = nullptr,
-                          int32_t n_groups = 1) {
+                          int32_t n_groups = 1, bool defer = false) {
 
     auto* ix = new os_ann_index();
     ix->N = N;
@@ -1606,6 +1654,11 @@ os_ann_index* build_table(const void* keys, int32_t key_dtype, int32_t Dk, const
         !step(launch_binom_table(ix->binom, s), "binomial table") ||
         !step(launch_count_nonempty(ix->offsets, nb, small + 1, s), "count"))
         return bail(0);
+    if (defer) {
+        ix->pending_small = small;
+        ix->pending_tmp = tmp;
+        return ix;
+    }
     uint32_t host_small[2] = {0, 0};
     if (!step(hipMemcpyAsync(host_small, small, 8, hipMemcpyDeviceToHost, s), "copy flags") ||
         !step(hipStreamSynchronize(s), "build sync"))
@@ -1865,8 +1918,9 @@ os_ann_index* os_ann_build_ex(const void* db, int64_t N, int32_t D, int32_t L, c
         }
         return build_sparse(db, dtype, N, D, L, nc, s);
     }
-    os_ann_index* ix = build_table(db, dtype, D, db, dtype, N, D, L, nc, s);
-    if (ix && opts && opts->want_lowp && ensure_lowp(ix, s)) {
+    const bool lowp = opts && opts->want_lowp;
+    os_ann_index* ix = build_table(db, dtype, D, db, dtype, N, D, L, nc, s, nullptr, 1, lowp);
+    if (ix && lowp && ensure_lowp(ix, s)) {
         release(ix);
         return nullptr;
     }

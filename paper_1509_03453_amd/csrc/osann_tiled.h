@@ -110,9 +110,9 @@ hipError_t launch_lowp_layout(const uint32_t* offsets, int64_t n_cones, uint32_t
                               uint32_t* scan_tmp, uint32_t* poff, uint32_t* ne_id, uint32_t* ne_cone,
                               hipStream_t s);
 hipError_t launch_lowp_rows(const void* planes, int dtype, int64_t N, int D, int nch, const uint32_t* sorted_cone,
-                            const uint32_t* offsets, const uint32_t* poff, const uint32_t* perm, int dk, int to_f16,
-                            uint16_t* xl, uint32_t* ppos, uint32_t* prow, uint32_t* ipos, float* nrm,
-                            int64_t np_total, hipStream_t s);
+                            const uint32_t* offsets, int64_t n_cones, const uint32_t* poff, const uint32_t* perm,
+                            int dk, int to_f16, uint16_t* xl, uint32_t* ppos, uint32_t* prow, uint32_t* ipos,
+                            float* nrm, int64_t np_total, hipStream_t s);
 hipError_t launch_tiled_screen(const TiledArgs& a, int R, int G, int f16in, int blocks, hipStream_t s);
 size_t tiled_screen_lds();                      // dynamic LDS bytes of one screen block
 size_t tiled_screen_static_lds(int R, int G);          // static LDS bytes (upper bound) of one screen block
