@@ -86,41 +86,87 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
     }
 }
 
-// The same sort for short inputs (a search's queries) in one block of 1024
-// threads and one launch: every pass counts the digits of the whole input
-// (LDS counts), scans them, then takes the input in order, 1024 elements at
-// a time, ranking each element among the equal digits before it exactly as
-// radix_scatter_kernel does (wave ballots, then the earlier waves' counts).
-// The ping-pong arrays stay in the L2; the block barrier between passes
-// makes one pass's writes visible to the next (one compute unit, one L1).
+// The same sort for short inputs (a search's queries, small tables) in one
+// block of 1024 threads and one launch, held in LDS.  Wave w owns the
+// contiguous segment [w S, (w + 1) S) of the positions (S a multiple of 64),
+// its lane l the items w S + 64 j + l, in registers.  Every pass:
+//   1. each wave counts its segment's digits, 64 items at a time, into its
+//      own LDS counts (one add per distinct digit, by the lowest lane
+//      holding it: no atomics, no order taken from timing);
+//   2. the counts are scanned digit-major, wave-minor, into each wave's
+//      start per digit (earlier segments first: the sort stays stable);
+//   3. each wave walks its segment again in order, each item's place being
+//      its wave's running start for its digit plus the lanes of equal digit
+//      below it (wave ballots), and scatters it into the LDS arrays;
+// then the items are reloaded from there.  Only block barriers separate
+// the steps; inside a step each wave works alone.
 constexpr int kSmallSortThreads = 1024;
-constexpr int64_t kSmallSortMax = 32768;
+constexpr int kSmallSortItems = 16;  // per thread
+constexpr int64_t kSmallSortMax = (int64_t)kSmallSortThreads * kSmallSortItems;
 
 __global__ __launch_bounds__(kSmallSortThreads) void radix_small_kernel(const uint32_t* __restrict__ keys_in,
-                                                                        int64_t N, int passes, uint32_t* ka,
-                                                                        uint32_t* va, uint32_t* kb, uint32_t* vb,
-                                                                        uint32_t* keys_out, uint32_t* vals_out) {
+                                                                        int64_t N, int passes,
+                                                                        uint32_t* __restrict__ keys_out,
+                                                                        uint32_t* __restrict__ vals_out) {
     constexpr int kWaves = kSmallSortThreads / 64;
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t s_key[kSmallSortMax];
+    __shared__ uint32_t s_val[kSmallSortMax];
+    __shared__ uint32_t cnt[kWaves][256];  // per wave: digit counts, then running starts
+    __shared__ uint32_t tot[256];
     const int tid = threadIdx.x, w = tid / 64, l = tid % 64;
-    const uint32_t* kin = keys_in;
-    const uint32_t* vin = nullptr;  // identity on the first pass
+    const int64_t seg = ((N + kWaves * 64 - 1) / (kWaves * 64)) * 64;  // positions per wave
+    const int groups = (int)(seg / 64);                                  // <= kSmallSortItems
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    };
+    uint32_t key[kSmallSortItems], val[kSmallSortItems];
+#pragma unroll
+    for (int j = 0; j < kSmallSortItems; ++j) {
+        const int64_t e = w * seg + 64 * j + l;
+        const bool v = j < groups && e < N;
+        key[j] = v ? keys_in[e] : 0u;
+        val[j] = (uint32_t)e;
+    }
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        const bool last = p == passes - 1;
-        uint32_t* kout = last ? keys_out : ((p & 1) ? kb : ka);
-        uint32_t* vout = last ? vals_out : ((p & 1) ? vb : va);
-        if (tid < 256) run[tid] = 0;
+        for (int q = l; q < 256; q += 64) cnt[w][q] = 0;
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < kSmallSortItems; ++j) {
+            if (j >= groups) break;
+            const int64_t e = w * seg + 64 * j + l;
+            const bool valid = e < N;
+            const uint32_t dig = (key[j] >> shift) & 255u;
+            uint64_t same = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t ones = __ballot((dig >> b) & 1u);
+                same &= ((dig >> b) & 1u) ? ones : ~ones;
+            }
+            if (valid && (same & lanemask_lt()) == 0) cnt[w][dig] += (uint32_t)__popcll(same);
+            wave_sync();
+        }
         __syncthreads();
-        for (int64_t i = tid; i < N; i += kSmallSortThreads) atomicAdd(&run[(kin[i] >> shift) & 255u], 1u);  // counts only
+        if (tid < 256) {  // digit tid: prefix over the waves, then the total
+            uint32_t c[kWaves], sum = 0;
+#pragma unroll
+            for (int a = 0; a < kWaves; ++a) c[a] = cnt[a][tid];
+#pragma unroll
+            for (int a = 0; a < kWaves; ++a) {
+                cnt[a][tid] = sum;
+                sum += c[a];
+            }
+            tot[tid] = sum;
+        }
         __syncthreads();
-        if (w == 0) {  // exclusive scan of the 256 counts: 4 per lane, then across the wave
+        if (w == 0) {  // exclusive scan of the 256 totals: 4 per lane, then across the wave
             uint32_t c[4], sum = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                c[j] = run[4 * l + j];
-                sum += c[j];
+            for (int q = 0; q < 4; ++q) {
+                c[q] = tot[4 * l + q];
+                sum += c[q];
             }
             uint32_t incl = sum;
 #pragma unroll
@@ -130,46 +176,54 @@ __global__ __launch_bounds__(kSmallSortThreads) void radix_small_kernel(const ui
             }
             uint32_t at = incl - sum;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                run[4 * l + j] = at;
-                at += c[j];
+            for (int q = 0; q < 4; ++q) {
+                tot[4 * l + q] = at;
+                at += c[q];
             }
         }
         __syncthreads();
-        for (int64_t t = 0; t < N; t += kSmallSortThreads) {
-            for (int j = tid; j < kWaves * 256; j += kSmallSortThreads) (&wcnt[0][0])[j] = 0;
-            __syncthreads();
-            const int64_t i = t + tid;
-            const bool valid = i < N;
-            const uint32_t key = valid ? kin[i] : 0u;
-            const uint32_t val = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
-            const uint32_t dig = (key >> shift) & 255u;
+        for (int q = l; q < 256; q += 64) cnt[w][q] += tot[q];  // this wave's start per digit
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < kSmallSortItems; ++j) {
+            if (j >= groups) break;
+            const int64_t e = w * seg + 64 * j + l;
+            const bool valid = e < N;
+            const uint32_t dig = (key[j] >> shift) & 255u;
             uint64_t same = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
                 const uint64_t ones = __ballot((dig >> b) & 1u);
                 same &= ((dig >> b) & 1u) ? ones : ~ones;
             }
-            const uint32_t below = (uint32_t)__popcll(same & lanemask_lt());
-            if (valid && below == 0) wcnt[w][dig] = (uint32_t)__popcll(same);
-            __syncthreads();
+            const uint64_t below = same & lanemask_lt();
             if (valid) {
-                uint32_t off = run[dig] + below;
-                for (int a = 0; a < w; ++a) off += wcnt[a][dig];
-                kout[off] = key;
-                vout[off] = val;
+                const uint32_t off = cnt[w][dig] + (uint32_t)__popcll(below);
+                s_key[off] = key[j];
+                s_val[off] = val[j];
             }
-            __syncthreads();
-            if (tid < 256) {
-                uint32_t add = 0;
-#pragma unroll
-                for (int a = 0; a < kWaves; ++a) add += wcnt[a][tid];
-                run[tid] += add;
-            }
-            __syncthreads();
+            wave_sync();
+            if (valid && below == 0) cnt[w][dig] += (uint32_t)__popcll(same);
+            wave_sync();
         }
-        kin = kout;
-        vin = vout;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSmallSortItems; ++j) {
+            const int64_t e = w * seg + 64 * j + l;
+            if (j < groups && e < N) {
+                key[j] = s_key[e];
+                val[j] = s_val[e];
+            }
+        }
+        __syncthreads();  // every item read before the next pass scatters
+    }
+#pragma unroll
+    for (int j = 0; j < kSmallSortItems; ++j) {
+        const int64_t e = w * seg + 64 * j + l;
+        if (j < groups && e < N) {
+            keys_out[e] = key[j];
+            vals_out[e] = val[j];
+        }
     }
 }
 
@@ -184,8 +238,8 @@ hipError_t launch_sort_by_cone(const uint32_t* row_cone, int64_t N, int64_t n_co
     uint32_t* kb = tmp + 2 * N;
     uint32_t* vb = tmp + 3 * N;
     if (N > 0 && N <= kSmallSortMax) {
-        hipLaunchKernelGGL(radix_small_kernel, dim3(1), dim3(kSmallSortThreads), 0, s, row_cone, N, passes, ka, va,
-                           kb, vb, sorted_cone_out, perm_out);
+        hipLaunchKernelGGL(radix_small_kernel, dim3(1), dim3(kSmallSortThreads), 0, s, row_cone, N, passes,
+                           sorted_cone_out, perm_out);
         return hipGetLastError();
     }
     const int64_t hw = 256 * nb;

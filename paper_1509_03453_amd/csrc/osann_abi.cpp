@@ -389,6 +389,14 @@ int check_shape(int64_t N, int32_t D, int32_t L, int64_t* n_cones, bool allow_sp
 bool dtype_ok(int32_t t) { return t == kF32 || t == kF16 || t == kU8; }
 bool rerank_ok(int32_t r) { return r == 4 || r == 8 || r == 16; }
 
+// Two words of pinned host memory per calling thread, for the flags a build
+// reads back (allocated on first use, held until the process ends).
+uint32_t* pinned_flags() {
+    thread_local uint32_t* p = nullptr;
+    if (!p && hipHostMalloc((void**)&p, 16, hipHostMallocDefault) != hipSuccess) p = nullptr;
+    return p;
+}
+
 // The screens' dynamic LDS limits: set once per device (the attribute
 // belongs to the device, not to an index).
 hipError_t screen_lds_once() {
@@ -463,8 +471,10 @@ int ensure_lowp(os_ann_index* ix, hipStream_t s) {
                          ix->perm, lp.dk, lp.f16, lp.xl, lp.ppos, lp.prow, lp.ipos, lp.nrm, rows, s);
     if (e == hipSuccess) e = screen_lds_once();
     // a build that left its closing check here: its flags come back with
-    // this one synchronisation
-    uint32_t host_small[2] = {0, 0};
+    // this one synchronisation (into pinned memory: the copy is queued
+    // behind the build, not staged by the calling thread)
+    uint32_t* host_small = pinned_flags();
+    if (e == hipSuccess && ix->pending_small && !host_small) e = hipErrorOutOfMemory;
     if (e == hipSuccess && ix->pending_small)
         e = hipMemcpyAsync(host_small, ix->pending_small, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -124,8 +124,16 @@ __device__ inline uint32_t probe_cone(int64_t j, int L, const uint8_t* order, co
             mstart += (int)cl;
         }
         const int64_t jj = j - base;
-        t = jj / (int64_t)cl;
-        mask = maskord[mstart + (int)(jj % (int64_t)cl)];
+        int64_t r;
+        if (jj < (int64_t(1) << 32)) {  // 32-bit division (a short sequence; 64-bit is a long one)
+            const uint32_t q32 = (uint32_t)jj / (uint32_t)cl;
+            t = q32;
+            r = (uint32_t)jj - q32 * (uint32_t)cl;
+        } else {
+            t = jj / (int64_t)cl;
+            r = jj - t * (int64_t)cl;
+        }
+        mask = maskord[mstart + (int)r];
     }
     int idx[7], sg[7];
 #pragma unroll

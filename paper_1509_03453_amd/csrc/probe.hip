@@ -108,35 +108,48 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
 
-    // 5. walk the probe sequence 64 positions at a time until the budget is met
+    // 5. walk the probe sequence 64 positions at a time until the budget is
+    // met; two steps' cones are generated and their bucket bounds (and
+    // non-empty ids) loaded before either is scanned, so their loads are in
+    // flight together
     const uint64_t budget = (uint64_t)a.budget;
     const uint32_t* offs = a.offsets + (a.cone_base ? a.cone_base[q] : 0u);  // this query's buckets
     uint64_t carry = 0;
     uint32_t np = 0, stop_at = 0;
-    for (int64_t j0 = 0; j0 < a.n_cones; j0 += 64) {
+    // one step at j0: false once the budget is met
+    auto step = [&](int64_t j0, uint32_t len, uint32_t e) __attribute__((always_inline)) {
         const int64_t j = j0 + l;
-        uint32_t len = 0, c = 0;
-        if (j < a.n_cones) {
-            c = probe_cone(j, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
-            len = offs[c + 1] - offs[c];
-        }
         const uint32_t incl = wave_incl_scan(len);
         const uint64_t tot = carry + incl;
         const uint64_t reached = __ballot(j < a.n_cones && tot >= budget);
         const int stop = reached ? __ffsll((unsigned long long)reached) - 1 : 63;
         const bool taken = j < a.n_cones && l <= stop && len > 0;
         const uint64_t tm = __ballot(taken);
-        if (a.qbits && taken) {
-            const uint32_t e = a.ne_id[c];
-            atomicOr(&qb[e >> 6], 1ull << (e & 63));
-        }
+        if (a.qbits && taken) atomicOr(&qb[e >> 6], 1ull << (e & 63));
         np += (uint32_t)__popcll(tm);
         carry += shfl_u32(incl, stop);
         if (reached) {
             stop_at = (uint32_t)(j0 + stop + 1);
-            break;
+            return false;
         }
         stop_at = (uint32_t)(j0 + 64 < a.n_cones ? j0 + 64 : a.n_cones);
+        return true;
+    };
+    for (int64_t j0 = 0; j0 < a.n_cones; j0 += 128) {
+        const int64_t ja = j0 + l, jb = j0 + 64 + l;
+        uint32_t ca = 0, cb = 0, lena = 0, lenb = 0, ea = 0, eb = 0;
+        if (ja < a.n_cones) ca = probe_cone(ja, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
+        if (jb < a.n_cones) cb = probe_cone(jb, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
+        if (ja < a.n_cones) {
+            lena = offs[ca + 1] - offs[ca];
+            if (a.qbits) ea = a.ne_id[ca];
+        }
+        if (jb < a.n_cones) {
+            lenb = offs[cb + 1] - offs[cb];
+            if (a.qbits) eb = a.ne_id[cb];
+        }
+        if (!step(j0, lena, ea)) break;
+        if (j0 + 64 >= a.n_cones || !step(j0 + 64, lenb, eb)) break;
     }
     if (l == 0) {
         if (a.jstop) a.jstop[q] = stop_at;

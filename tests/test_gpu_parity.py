@@ -156,6 +156,12 @@ def test_edge_cases(orc):
     with pytest.raises(B.OsAnnError) as e:
         B.os_ann_build_ex(dev(bad.astype(np.float16)), 2)
     assert e.value.code == B.OS_ANN_ENONFINITE
+    # with the low-precision copy the table's check is taken at the copy's end
+    for dt in (np.float32, np.float16):
+        bad[7, 2] = np.nan if dt == np.float32 else np.inf
+        with pytest.raises(B.OsAnnError) as e:
+            B.os_ann_build_ex(dev(bad.astype(dt)), 2, want_lowp=True)
+        assert e.value.code == B.OS_ANN_ENONFINITE
     # C(256,7) 2^7 = 1.7e15 cones: a sparse table (reading R15) of 10 rows
     Xs = W.gaussian_db(10, 256, seed=4)
     Ys = W.gaussian_queries(3, 256, seed=5)
