@@ -1105,7 +1105,11 @@ int choose_tiling(Call& c, const SearchPlan* plans, int n_plans, bool may_time, 
                 return v;
             }
     }
-    const std::string key = tune_key(c.ix, plans[0], c.budget) + ":KOGS";
+    // testing overrides narrow the candidates: their choices are cached
+    // under keys of their own, never as the unrestricted choice
+    std::string key = tune_key(c.ix, plans[0], c.budget) + ":KOGS";
+    for (const char* var : {"OSANN_TILED_GROUPS", "OSANN_TILED_ORDER", "OSANN_TILED_KERNEL"})
+        if (const char* v = std::getenv(var)) key += std::string(":") + var + "=" + v;
     if (int v = g_tuner.get(key)) {
         for (int k = 0; k < n_plans; ++k) {
             const SearchPlan& pk = plans[k];
