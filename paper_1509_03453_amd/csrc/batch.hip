@@ -10,7 +10,7 @@ __global__ void query_key_kernel(const uint32_t* __restrict__ q_cone, const uint
     if (q >= Q) return;
     if (mode == 1) {
         uint32_t k = 0;
-        const int nb = D < 32 ? D : 32;
+        const int nb = query_sign_bits(D, Q);
         for (int i = 0; i < nb; ++i) k = (k << 1) | sbit[q * D + i];
         key[q] = k;
         return;

@@ -47,9 +47,74 @@ __global__ void ne_cone_kernel(const uint32_t* __restrict__ off, int64_t nc, con
     if (c < nc && off[c + 1] > off[c]) ne_cone[ne_id[c]] = (uint32_t)c;
 }
 
+// The same layout for up to 65,536 cones in one block and one launch:
+// thread t takes a run of consecutive cones, sums their padded sizes and
+// non-empty flags, the block scans the 1024 sums (wave scans, then the
+// waves' totals), and each thread walks its run again writing the starts.
+constexpr int kLayoutThreads = 1024;
+constexpr int64_t kLayoutSmallMax = 65536;
+
+__global__ __launch_bounds__(kLayoutThreads) void lowp_layout_small_kernel(const uint32_t* __restrict__ off,
+                                                                           int64_t nc, uint32_t* __restrict__ poff,
+                                                                           uint32_t* __restrict__ ne_id,
+                                                                           uint32_t* __restrict__ ne_cone) {
+    __shared__ uint32_t wsum_p[kLayoutThreads / 64], wsum_n[kLayoutThreads / 64];
+    const int t = threadIdx.x, w = t / 64, l = t % 64;
+    const int64_t per = (nc + kLayoutThreads - 1) / kLayoutThreads;
+    const int64_t c0 = (int64_t)t * per, c1 = c0 + per < nc ? c0 + per : nc;
+    uint32_t sp = 0, sn = 0;
+    for (int64_t c = c0; c < c1; ++c) {
+        const uint32_t len = off[c + 1] - off[c];
+        sp += (len + 15u) & ~15u;
+        sn += len > 0;
+    }
+    // inclusive wave scans, then the waves' totals
+    uint32_t ip = sp, in = sn;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t up = (uint32_t)__shfl_up((int)ip, d, 64), un = (uint32_t)__shfl_up((int)in, d, 64);
+        if (l >= d) {
+            ip += up;
+            in += un;
+        }
+    }
+    if (l == 63) {
+        wsum_p[w] = ip;
+        wsum_n[w] = in;
+    }
+    __syncthreads();
+    uint32_t bp = 0, bn = 0, tp = 0, tn = 0;
+    for (int a = 0; a < kLayoutThreads / 64; ++a) {
+        if (a < w) {
+            bp += wsum_p[a];
+            bn += wsum_n[a];
+        }
+        tp += wsum_p[a];
+        tn += wsum_n[a];
+    }
+    uint32_t rp = bp + ip - sp, rn = bn + in - sn;  // exclusive starts of this thread's run
+    for (int64_t c = c0; c < c1; ++c) {
+        const uint32_t len = off[c + 1] - off[c];
+        poff[c] = rp;
+        ne_id[c] = rn;
+        if (len > 0) ne_cone[rn] = (uint32_t)c;
+        rp += (len + 15u) & ~15u;
+        rn += len > 0;
+    }
+    if (t == 0) {
+        poff[nc] = tp;
+        ne_id[nc] = tn;
+    }
+}
+
 hipError_t launch_lowp_layout(const uint32_t* offsets, int64_t n_cones, uint32_t* psz_tmp, uint32_t* nef_tmp,
                               uint32_t* scan_tmp, uint32_t* poff, uint32_t* ne_id, uint32_t* ne_cone,
                               hipStream_t s) {
+    if (n_cones > 0 && n_cones <= kLayoutSmallMax) {
+        hipLaunchKernelGGL(lowp_layout_small_kernel, dim3(1), dim3(kLayoutThreads), 0, s, offsets, n_cones, poff, ne_id,
+                           ne_cone);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((n_cones + 255) / 256));
     hipLaunchKernelGGL(lowp_sizes_kernel, grid, dim3(256), 0, s, offsets, n_cones, psz_tmp, nef_tmp);
     hipError_t e = launch_exclusive_scan(psz_tmp, n_cones, poff, scan_tmp, s);

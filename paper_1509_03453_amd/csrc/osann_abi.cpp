@@ -941,7 +941,7 @@ hipError_t enqueue_tiled(const Call& c, int S) {
             e = launch_query_key(pa.q_cone, pa.order, pa.sbit, c.Q, ix->Dk, ix->L, p.qkey, kb, c.s);
             if (e != hipSuccess) return e;
             key = kb;
-            nb = p.qkey == 1 ? (int64_t(1) << (ix->Dk < 32 ? ix->Dk : 32)) : nb0;
+            nb = p.qkey == 1 ? (int64_t(1) << query_sign_bits(ix->Dk, c.Q)) : nb0;
         }
         e = launch_sort_by_cone(key, c.Q, nb, reinterpret_cast<uint32_t*>(c.base + p.off_sort), qorder,
                                 reinterpret_cast<uint32_t*>(c.base + p.off_qsorted), c.s);
