@@ -974,12 +974,13 @@ hipError_t enqueue_tiled(const Call& c, int S) {
     sd.L = ix->L;
     // The seed reads up to sd.rows padded rows from the first cones of each
     // query's walk, one query at a time (no row is shared between queries):
-    // keep that near a sixteenth of the budget, 64 .. 512 rows.  Past 512 the
-    // seed costs about what the tighter bound saves the screen (1e6 x 64
-    // Gaussian rows, 1e4 queries, budget 327,680: 2.73 / 2.62 / 2.59 ms per
-    // search at 256 / 512 / 1024 rows).
+    // keep that near a sixteenth of the budget, 64 .. 192 rows.  Past 192
+    // the seed costs more than its tighter bound saves the screen (1e6 x 64
+    // Gaussian rows, 1e4 queries, budget 327,680, cone-major screen: 2.01 /
+    // 1.98 / 1.98 / 2.00 / 2.04 ms per search at 64 / 128 / 192 / 256 / 512
+    // rows).
     const int64_t rows = expected_rows(ix, c.budget, p.cones);
-    sd.rows = (int)std::min<int64_t>(512, std::max<int64_t>(64, pow2_ceil(std::max<int64_t>(rows / 16, 1))));
+    sd.rows = (int)std::min<int64_t>(192, std::max<int64_t>(64, pow2_ceil(std::max<int64_t>(rows / 16, 1))));
     if (const char* env = std::getenv("OSANN_TILED_SEED_ROWS")) {  // fixed seed size (testing)
         const int v = std::atoi(env);
         if (v >= 64 && v <= 1024 && v % 64 == 0) sd.rows = v;
