@@ -19,9 +19,23 @@ namespace osann {
 
 constexpr int kProbeWaves = 4;
 
+// The walk's tables are read from LDS: the binomial rows it uses (0 ..
+// max(D - 1, L)), the flip-mask order and, where it takes at most 16 KB, the
+// lexicographic L-subsets.  Dynamic LDS layout: the probe bitmaps of the
+// block's waves (when kept), then those tables.
+__host__ __device__ inline int probe_binom_rows(int D, int L) { return D > L + 1 ? D : L + 1; }
+__host__ __device__ inline bool probe_lex_in_lds(int64_t n_sub, int L) { return n_sub * L <= 16384; }
+__host__ __device__ inline int64_t probe_qb_bytes(const ProbeArgs& a) {
+    return a.qbits ? (int64_t)kProbeWaves * a.nw * 8 : 0;
+}
+
 template <typename E, int L>
 __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
-    extern __shared__ unsigned long long qb_all[];  // [kProbeWaves][nw] when a.qbits
+    extern __shared__ __align__(16) unsigned char probe_lds[];
+    unsigned long long* qb_all = reinterpret_cast<unsigned long long*>(probe_lds);  // [kProbeWaves][nw] when a.qbits
+    uint32_t* s_binom = reinterpret_cast<uint32_t*>(probe_lds + probe_qb_bytes(a));
+    uint8_t* s_mask = reinterpret_cast<uint8_t*>(s_binom + probe_binom_rows(a.D, L) * 8);
+    uint8_t* s_lex = s_mask + 128;
     __shared__ uint64_t keys[kProbeWaves][kMaxD];
     __shared__ uint8_t order[kProbeWaves][kMaxD];
     __shared__ uint8_t sbit[kProbeWaves][kMaxD];
@@ -30,6 +44,15 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
     const bool qv = q < a.Q;
     const int D = a.D;
     auto Y = static_cast<const typename E::raw*>(a.Y);
+    // the same for every thread of the launch: whether the walk runs
+    const bool walk = (a.jstop || a.ncand || a.nprobe) && a.budget < a.N;
+    const bool lex_lds = probe_lex_in_lds(a.n_sub, L);
+    if (walk) {
+        for (int i = threadIdx.x; i < probe_binom_rows(D, L) * 8; i += blockDim.x) s_binom[i] = a.binom[i];
+        for (int i = threadIdx.x; i < 128; i += blockDim.x) s_mask[i] = a.maskord[i];
+        if (lex_lds)
+            for (int64_t i = threadIdx.x; i < a.n_sub * L; i += blockDim.x) s_lex[i] = a.lexsub[i];
+    }
 
     // 1. load the query, keep FP32 and low-precision copies, stage the keys
     uint64_t mine[kMaxD / 64];
@@ -138,8 +161,9 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
     for (int64_t j0 = 0; j0 < a.n_cones; j0 += 128) {
         const int64_t ja = j0 + l, jb = j0 + 64 + l;
         uint32_t ca = 0, cb = 0, lena = 0, lenb = 0, ea = 0, eb = 0;
-        if (ja < a.n_cones) ca = probe_cone(ja, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
-        if (jb < a.n_cones) cb = probe_cone(jb, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
+        const uint8_t* lex = lex_lds ? s_lex : a.lexsub;
+        if (ja < a.n_cones) ca = probe_cone(ja, L, order[w], sbit[w], a.n_sub, lex, s_mask, s_binom);
+        if (jb < a.n_cones) cb = probe_cone(jb, L, order[w], sbit[w], a.n_sub, lex, s_mask, s_binom);
         if (ja < a.n_cones) {
             lena = offs[ca + 1] - offs[ca];
             if (a.qbits) ea = a.ne_id[ca];
@@ -167,7 +191,9 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
 template <typename E>
 static hipError_t dispatch_probe(const ProbeArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.Q + kProbeWaves - 1) / kProbeWaves)), block(64 * kProbeWaves);
-    const size_t lds = a.qbits ? (size_t)kProbeWaves * a.nw * 8 : 0;
+    const size_t lds = (size_t)probe_qb_bytes(a) + (size_t)probe_binom_rows(a.D, a.L) * 8 * 4 + 128 +
+                       (probe_lex_in_lds(a.n_sub, a.L) ? (size_t)(a.n_sub * a.L) : 0);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     switch (a.L) {
 #define OSANN_PROBE_CASE(LL)                                                  \
     case LL:                                                                  \
