@@ -62,11 +62,24 @@ __global__ __launch_bounds__(kLayoutThreads) void lowp_layout_small_kernel(const
     const int t = threadIdx.x, w = t / 64, l = t % 64;
     const int64_t per = (nc + kLayoutThreads - 1) / kLayoutThreads;
     const int64_t c0 = (int64_t)t * per, c1 = c0 + per < nc ? c0 + per : nc;
+    // a thread's bucket lengths, 8 at a time, the 9 offsets of a batch
+    // loaded together
+    auto lengths = [&](int64_t c, uint32_t (&len)[8]) __attribute__((always_inline)) {
+        uint32_t o[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) o[i] = c + i <= c1 ? off[c + i] : 0u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) len[i] = c + i < c1 ? o[i + 1] - o[i] : 0u;
+    };
     uint32_t sp = 0, sn = 0;
-    for (int64_t c = c0; c < c1; ++c) {
-        const uint32_t len = off[c + 1] - off[c];
-        sp += (len + 15u) & ~15u;
-        sn += len > 0;
+    for (int64_t c = c0; c < c1; c += 8) {
+        uint32_t len[8];
+        lengths(c, len);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            sp += (len[i] + 15u) & ~15u;
+            sn += len[i] > 0;
+        }
     }
     // inclusive wave scans, then the waves' totals
     uint32_t ip = sp, in = sn;
@@ -93,13 +106,18 @@ __global__ __launch_bounds__(kLayoutThreads) void lowp_layout_small_kernel(const
         tn += wsum_n[a];
     }
     uint32_t rp = bp + ip - sp, rn = bn + in - sn;  // exclusive starts of this thread's run
-    for (int64_t c = c0; c < c1; ++c) {
-        const uint32_t len = off[c + 1] - off[c];
-        poff[c] = rp;
-        ne_id[c] = rn;
-        if (len > 0) ne_cone[rn] = (uint32_t)c;
-        rp += (len + 15u) & ~15u;
-        rn += len > 0;
+    for (int64_t c = c0; c < c1; c += 8) {
+        uint32_t len[8];
+        lengths(c, len);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (c + i >= c1) break;
+            poff[c + i] = rp;
+            ne_id[c + i] = rn;
+            if (len[i] > 0) ne_cone[rn] = (uint32_t)(c + i);
+            rp += (len[i] + 15u) & ~15u;
+            rn += len[i] > 0;
+        }
     }
     if (t == 0) {
         poff[nc] = tp;

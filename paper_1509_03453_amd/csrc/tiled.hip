@@ -639,15 +639,29 @@ __global__ __launch_bounds__(256) void tiled_finish_kernel(FinishArgs f) {
         ld[k] = __builtin_huge_valf();
         lr[k] = 0xFFFFFFFFu;
     }
-    // lane g takes the split lists g, g + G, ... into its own list
-    for (int sp = g; qv && sp < f.S; sp += G) {
-        const uint2* src = f.part + (q * f.S + sp) * R;
+    // lane g takes the split lists g, g + G, ... into its own list, two at
+    // a time, each list's R entries in 16-byte loads issued together
+    auto load_list = [&](int sp, uint4 (&v)[R / 2]) __attribute__((always_inline)) {
+        const uint4* src = reinterpret_cast<const uint4*>(f.part + (q * f.S + sp) * R);
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) v[i] = src[i];
+    };
+    auto fold_list = [&](const uint4 (&v)[R / 2]) __attribute__((always_inline)) {
+#pragma unroll
         for (int k = 0; k < R; ++k) {
-            const uint2 e = src[k];
-            const float d = __uint_as_float(e.x);
-            if (!pair_less(d, e.y, ld[R - 1], lr[R - 1])) break;  // the list is sorted
-            list_insert<R>(ld, lr, d, e.y);
+            const uint32_t db = (k & 1) ? v[k / 2].z : v[k / 2].x, r = (k & 1) ? v[k / 2].w : v[k / 2].y;
+            const float d = __uint_as_float(db);
+            if (!pair_less(d, r, ld[R - 1], lr[R - 1])) break;  // the list is sorted
+            list_insert<R>(ld, lr, d, r);
         }
+    };
+    for (int sp = g; qv && sp < f.S; sp += 2 * G) {
+        uint4 va[R / 2], vb[R / 2];
+        const bool two = sp + G < f.S;
+        load_list(sp, va);
+        if (two) load_list(sp + G, vb);
+        fold_list(va);
+        if (two) fold_list(vb);
     }
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) merge_with<R>(ld, lr, m);
