@@ -401,13 +401,18 @@ hipError_t launch_gather_planes(const void* X, int dtype, int64_t N, int D, cons
 // lexsub[j] = j-th L-subset of {0..D-1} in lexicographic order (unranked by
 // counting the subsets that start with each candidate value).
 __global__ void lexsub_kernel(int D, int L, int64_t count, uint8_t* __restrict__ lexsub) {
+    // C(n, k) for n < D, k < L, computed once per block (the walk below
+    // would otherwise redo each with k divisions)
+    __shared__ uint64_t cb[kMaxD * 8];
+    for (int i = threadIdx.x; i < D * L; i += blockDim.x) cb[(i / L) * 8 + i % L] = binom_dev(i / L, i % L);
+    __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= count) return;
     uint64_t rem = (uint64_t)j;
     int prev = -1;
     for (int a = 0; a < L; ++a) {
         for (int v = prev + 1; v < D; ++v) {
-            const uint64_t cnt = binom_dev(D - 1 - v, L - 1 - a);
+            const uint64_t cnt = cb[(D - 1 - v) * 8 + (L - 1 - a)];
             if (rem < cnt) {
                 lexsub[j * L + a] = (uint8_t)v;
                 prev = v;

@@ -15,7 +15,7 @@ namespace osann {
 
 template <typename E, int L>
 __global__ __launch_bounds__(256) void row_keys_kernel(const typename E::raw* __restrict__ X,
-                                                       int64_t N, int D, int S,
+                                                       int64_t N, int D, int S, int vec,
                                                        uint32_t* __restrict__ row_cone,
                                                        uint64_t* __restrict__ row_top,
                                                        uint32_t* __restrict__ nonfinite) {
@@ -27,11 +27,39 @@ __global__ __launch_bounds__(256) void row_keys_kernel(const typename E::raw* __
 #pragma unroll
     for (int j = 0; j < L; ++j) top[j] = 0;  // every real key is >= 1
     bool bad = false;
-    if (valid) {
+    // keys carry the component index, so they are distinct and the
+    // insertion order does not matter
+    auto insert = [&](typename E::raw b, int i) __attribute__((always_inline)) {
+        bad |= E::nonfinite(b);
+        const uint64_t k = comp_key(E::mag(b), i, E::neg(b));
+#pragma unroll
+        for (int j = L - 1; j >= 0; --j) {  // into the descending list
+            const uint64_t above = j > 0 ? top[j - 1] : ~0ull;
+            if (k > top[j]) top[j] = (k > above) ? above : k;
+        }
+    };
+    struct alignas(4 * sizeof(typename E::raw)) Raw4 {
+        typename E::raw v[4];
+    };
+    if (valid && vec) {
+        // D a multiple of 4, rows aligned: components 4t .. 4t + 3 and
+        // 4t + 4S .. 4t + 4S + 3 (then 8S further ...), two loads per lane
+        // issued before either is inserted
         const typename E::raw* xr = X + row * (int64_t)D;
-        // four components per step, loaded before any is inserted (keys
-        // carry the component index, so they are distinct and the insertion
-        // order does not matter)
+        for (int i0 = 4 * t; i0 < D; i0 += 8 * S) {
+            const bool two = i0 + 4 * S < D;
+            const Raw4 v0 = *reinterpret_cast<const Raw4*>(xr + i0);
+            Raw4 v1{};
+            if (two) v1 = *reinterpret_cast<const Raw4*>(xr + i0 + 4 * S);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) insert(v0.v[u], i0 + u);
+            if (two)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) insert(v1.v[u], i0 + 4 * S + u);
+        }
+    } else if (valid) {
+        const typename E::raw* xr = X + row * (int64_t)D;
+        // four components per step, loaded before any is inserted
         constexpr int U = 4;
         for (int i0 = t; i0 < D; i0 += U * S) {
             typename E::raw b[U];
@@ -40,14 +68,7 @@ __global__ __launch_bounds__(256) void row_keys_kernel(const typename E::raw* __
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (i0 + u * S >= D) break;
-                bad |= E::nonfinite(b[u]);
-                const uint64_t k = comp_key(E::mag(b[u]), i0 + u * S, E::neg(b[u]));
-                // insert into the descending list
-#pragma unroll
-                for (int j = L - 1; j >= 0; --j) {
-                    const uint64_t above = j > 0 ? top[j - 1] : ~0ull;
-                    if (k > top[j]) top[j] = (k > above) ? above : k;
-                }
+                insert(b[u], i0 + u * S);
             }
         }
     }
@@ -86,17 +107,19 @@ __global__ __launch_bounds__(256) void row_keys_kernel(const typename E::raw* __
 template <typename E>
 static hipError_t dispatch_keys(const void* X, int64_t N, int D, int L, uint32_t* cone,
                                 uint64_t* top, uint32_t* flag, hipStream_t s) {
+    auto x = static_cast<const typename E::raw*>(X);
+    const int vec = D % 4 == 0 && reinterpret_cast<uintptr_t>(X) % (4 * sizeof(typename E::raw)) == 0;
     int S = 1;
-    while (S * 2 <= D / 4 && S < 64) S *= 2;  // about four components per lane
+    // about four components per lane, eight with the vector loads
+    while (S * 2 <= D / (vec ? 8 : 4) && S < 64) S *= 2;
     const int threads = 256;
     const int64_t rows_per_block = threads / S;
     const dim3 grid((unsigned)((N + rows_per_block - 1) / rows_per_block));
-    auto x = static_cast<const typename E::raw*>(X);
     switch (L) {
-#define OSANN_KEY_CASE(LL)                                                                   \
-    case LL:                                                                                 \
-        hipLaunchKernelGGL((row_keys_kernel<E, LL>), grid, dim3(threads), 0, s, x, N, D, S, \
-                           cone, top, flag);                                                 \
+#define OSANN_KEY_CASE(LL)                                                                        \
+    case LL:                                                                                      \
+        hipLaunchKernelGGL((row_keys_kernel<E, LL>), grid, dim3(threads), 0, s, x, N, D, S, vec, \
+                           cone, top, flag);                                                      \
         break;
         OSANN_KEY_CASE(1) OSANN_KEY_CASE(2) OSANN_KEY_CASE(3) OSANN_KEY_CASE(4)
         OSANN_KEY_CASE(5) OSANN_KEY_CASE(6) OSANN_KEY_CASE(7)
