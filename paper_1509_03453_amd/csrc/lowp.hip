@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void lowp_rows_kernel(const uint4* __restrict_
                                                         float* __restrict__ nrm) {
 #pragma clang fp contract(off)
     constexpr int EPC = Unpack<E>::n;             // components per 16-byte chunk of the planes
-    constexpr int CPU = EPC >= 8 ? 1 : 8 / EPC;   // chunks per step (at least one output unit)
+    constexpr int CPU = (EPC >= 8 ? 1 : 8 / EPC) * 4;  // chunks per step (32 or 64 components, loaded together)
     constexpr int NU = CPU * EPC / 8;             // output units per step
     extern __shared__ uint32_t tile[];            // [256][dk/2 + 1]
     __shared__ int64_t s_p[256];
