@@ -19,12 +19,18 @@ namespace osann {
 
 constexpr int kProbeWaves = 4;
 
-// The walk's tables are read from LDS: the binomial rows it uses (0 ..
-// max(D - 1, L)), the flip-mask order and, where it takes at most 16 KB, the
-// lexicographic L-subsets.  Dynamic LDS layout: the probe bitmaps of the
-// block's waves (when kept), then those tables.
+// Long walks read the walk's tables from LDS: the binomial rows it uses (0
+// .. max(D - 1, L)), the flip-mask order and, where it takes at most 16 KB,
+// the lexicographic L-subsets.  A walk is long when a query is expected to
+// take at least 256 positions (budget x cones / rows: the walk passes empty
+// cones too); a block of short walks would spend more copying the tables than
+// reading them.  Dynamic LDS layout: the probe bitmaps of the block's waves
+// (when kept), then those tables.
 __host__ __device__ inline int probe_binom_rows(int D, int L) { return D > L + 1 ? D : L + 1; }
 __host__ __device__ inline bool probe_lex_in_lds(int64_t n_sub, int L) { return n_sub * L <= 16384; }
+__host__ __device__ inline bool probe_tables_in_lds(const ProbeArgs& a) {
+    return (a.jstop || a.ncand || a.nprobe) && a.budget < a.N && a.budget * a.n_cones >= 256 * a.N;
+}
 __host__ __device__ inline int64_t probe_qb_bytes(const ProbeArgs& a) {
     return a.qbits ? (int64_t)kProbeWaves * a.nw * 8 : 0;
 }
@@ -44,10 +50,10 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
     const bool qv = q < a.Q;
     const int D = a.D;
     auto Y = static_cast<const typename E::raw*>(a.Y);
-    // the same for every thread of the launch: whether the walk runs
-    const bool walk = (a.jstop || a.ncand || a.nprobe) && a.budget < a.N;
-    const bool lex_lds = probe_lex_in_lds(a.n_sub, L);
-    if (walk) {
+    // the same for every thread of the launch: whether the tables are copied
+    const bool tab = probe_tables_in_lds(a);
+    const bool lex_lds = tab && probe_lex_in_lds(a.n_sub, L);
+    if (tab) {
         for (int i = threadIdx.x; i < probe_binom_rows(D, L) * 8; i += blockDim.x) s_binom[i] = a.binom[i];
         for (int i = threadIdx.x; i < 128; i += blockDim.x) s_mask[i] = a.maskord[i];
         if (lex_lds)
@@ -132,9 +138,9 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
     }
 
     // 5. walk the probe sequence 64 positions at a time until the budget is
-    // met; two steps' cones are generated and their bucket bounds (and
-    // non-empty ids) loaded before either is scanned, so their loads are in
-    // flight together
+    // met; in a long walk two steps' cones are generated and their bucket
+    // bounds (and non-empty ids) loaded before either is scanned, so their
+    // loads are in flight together
     const uint64_t budget = (uint64_t)a.budget;
     const uint32_t* offs = a.offsets + (a.cone_base ? a.cone_base[q] : 0u);  // this query's buckets
     uint64_t carry = 0;
@@ -158,12 +164,25 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
         stop_at = (uint32_t)(j0 + 64 < a.n_cones ? j0 + 64 : a.n_cones);
         return true;
     };
-    for (int64_t j0 = 0; j0 < a.n_cones; j0 += 128) {
+    // a short walk takes one step at a time (it mostly ends in its first)
+    for (int64_t j0 = 0; !tab && j0 < a.n_cones; j0 += 64) {
+        const int64_t ja = j0 + l;
+        uint32_t ca = 0, lena = 0, ea = 0;
+        if (ja < a.n_cones) {
+            ca = probe_cone(ja, L, order[w], sbit[w], a.n_sub, a.lexsub, a.maskord, a.binom);
+            lena = offs[ca + 1] - offs[ca];
+            if (a.qbits) ea = a.ne_id[ca];
+        }
+        if (!step(j0, lena, ea)) break;
+    }
+    for (int64_t j0 = 0; tab && j0 < a.n_cones; j0 += 128) {
         const int64_t ja = j0 + l, jb = j0 + 64 + l;
         uint32_t ca = 0, cb = 0, lena = 0, lenb = 0, ea = 0, eb = 0;
         const uint8_t* lex = lex_lds ? s_lex : a.lexsub;
-        if (ja < a.n_cones) ca = probe_cone(ja, L, order[w], sbit[w], a.n_sub, lex, s_mask, s_binom);
-        if (jb < a.n_cones) cb = probe_cone(jb, L, order[w], sbit[w], a.n_sub, lex, s_mask, s_binom);
+        const uint8_t* mask = tab ? s_mask : a.maskord;
+        const uint32_t* bin = tab ? s_binom : a.binom;
+        if (ja < a.n_cones) ca = probe_cone(ja, L, order[w], sbit[w], a.n_sub, lex, mask, bin);
+        if (jb < a.n_cones) cb = probe_cone(jb, L, order[w], sbit[w], a.n_sub, lex, mask, bin);
         if (ja < a.n_cones) {
             lena = offs[ca + 1] - offs[ca];
             if (a.qbits) ea = a.ne_id[ca];
@@ -191,8 +210,10 @@ __global__ __launch_bounds__(64 * kProbeWaves) void probe_kernel(ProbeArgs a) {
 template <typename E>
 static hipError_t dispatch_probe(const ProbeArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.Q + kProbeWaves - 1) / kProbeWaves)), block(64 * kProbeWaves);
-    const size_t lds = (size_t)probe_qb_bytes(a) + (size_t)probe_binom_rows(a.D, a.L) * 8 * 4 + 128 +
-                       (probe_lex_in_lds(a.n_sub, a.L) ? (size_t)(a.n_sub * a.L) : 0);
+    const size_t lds = (size_t)probe_qb_bytes(a) +
+                       (probe_tables_in_lds(a) ? (size_t)probe_binom_rows(a.D, a.L) * 8 * 4 + 128 +
+                                                     (probe_lex_in_lds(a.n_sub, a.L) ? (size_t)(a.n_sub * a.L) : 0)
+                                               : 0);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     switch (a.L) {
 #define OSANN_PROBE_CASE(LL)                                                  \
