@@ -313,3 +313,36 @@ def test_screen_kernels_agree(orc, monkeypatch, case):
             assert np.array_equal(a, b), case
     finally:
         B.os_ann_free(h)
+
+
+@pytest.mark.parametrize("case", ["gauss64", "patch_f16"])
+def test_seed_does_not_change_results(orc, monkeypatch, case):
+    # the seed pass only tightens the starting bounds (the class minima start
+    # at +inf without it), so the tuner may drop it: rows, distances and
+    # candidate counts are the same with and without it, and pass the
+    # screened comparison with the oracle
+    if case == "gauss64":
+        X, Y, L, budget = W.gaussian_db(40000, 64, seed=2701), W.gaussian_queries(500, 64, seed=2702), 2, 6000
+    else:
+        img = W.patch_field(160)
+        X = W.patch_rows(img)
+        Y = W.patch_rows(np.roll(img, (2, 3), axis=(0, 1)))[::23]
+        L, budget = 2, 256
+    h = B.os_ann_build_ex(dev(X), L, want_lowp=True)
+    try:
+        outs = {}
+        for rows in ("0", "64"):
+            monkeypatch.setenv("OSANN_TILED_SEED_ROWS", rows)
+            say(f"[tiled] {case} seed rows={rows} Q={len(Y)} budget={budget}")
+            i, d, n = B.os_ann_search_ex(h, dev(Y), budget, mode=B.OS_ANN_MODE_TILED, rerank_r=8)
+            torch.cuda.synchronize()
+            outs[rows] = (i.cpu().numpy(), d.cpu().numpy(), n.cpu().numpy())
+        monkeypatch.delenv("OSANN_TILED_SEED_ROWS")
+        for a, b in zip(outs["0"], outs["64"]):
+            assert np.array_equal(a, b), case
+        o = orc.build_index(X, L)
+        oi, od32, od64, on, dtr, top = orc.search_tiled(X, o, Y, budget, R=8)
+        check_screened(orc, X, Y, outs["0"], (oi, od32, od64, on, dtr, top), (case, budget),
+                       is_candidate=candidates_of(orc, o, Y, budget))
+    finally:
+        B.os_ann_free(h)
