@@ -330,25 +330,32 @@ __global__ __launch_bounds__(256, cone_waves_per_simd<KS>()) void cone_screen_ke
         }
     };
 
-    // two register buffers alternated by name: no register with a load in
-    // flight is ever copied, and the next tile (of this cone or the next)
-    // is in flight while the current one is screened.  Every step issues
-    // its loads (a cursor past the end reloads padded position 0, a valid
-    // tile), so the number of loads in flight is fixed and the wait before
-    // a tile's products covers that tile's loads only.
-    Tile tA, tB;
-    uint4 avA[KS], avB[KS];
-    float4 nvA, nvB;
+    // three register buffers rotated by name: no register with a load in
+    // flight is ever copied, and the next two tiles (of this cone or the
+    // next ones) are in flight while the current one is screened (164
+    // VGPRs, still three waves per SIMD).  Every step issues its loads (a
+    // cursor past the end reloads padded position 0, a valid tile), so the
+    // number of loads in flight is fixed and the wait before a tile's
+    // products covers that tile's loads only.
+    Tile tA, tB, tC;
+    uint4 avA[KS], avB[KS], avC[KS];
+    float4 nvA, nvB, nvC;
     next_tile(tA);
     load(tA.c >= 0 ? tA.p : 0u, avA, nvA);
+    next_tile(tB);
+    load(tB.c >= 0 ? tB.p : 0u, avB, nvB);
     while (tA.c >= 0) {
-        next_tile(tB);
-        load(tB.c >= 0 ? tB.p : 0u, avB, nvB);
+        next_tile(tC);
+        load(tC.c >= 0 ? tC.p : 0u, avC, nvC);
         screen(tA, avA, nvA);
         if (tB.c < 0) break;
         next_tile(tA);
         load(tA.c >= 0 ? tA.p : 0u, avA, nvA);
         screen(tB, avB, nvB);
+        if (tC.c < 0) break;
+        next_tile(tB);
+        load(tB.c >= 0 ? tB.p : 0u, avB, nvB);
+        screen(tC, avC, nvC);
     }
     if (nhit > 0) flush();
 
