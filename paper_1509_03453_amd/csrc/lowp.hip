@@ -191,7 +191,7 @@ __device__ inline uint16_t lowp_code(float x, int to_f16, float* v) {
 // stores the FP32 sum of squares of the rounded values taken in ascending
 // component order, and the position map; then the block writes the tile's
 // rows to their padded positions with consecutive lanes on consecutive
-// 32-bit words (rows of a cone are consecutive there).  The tile's row
+// 16-byte units (rows of a cone are consecutive there).  The tile's row
 // stride is dk/2 + 1 words, so the lanes of the first phase, one row each,
 // hit different banks.
 template <typename E>
@@ -264,11 +264,17 @@ __global__ __launch_bounds__(256) void lowp_rows_kernel(const uint4* __restrict_
         s_p[threadIdx.x] = -1;
     }
     __syncthreads();
-    uint32_t* xw = reinterpret_cast<uint32_t*>(xl);
-    for (int f = threadIdx.x; f < 256 * words; f += 256) {
-        const int r = f / words, wd = f - r * words;
+    // 16-byte stores: dk is a multiple of 32, so a row is a whole number of
+    // 16-byte units and every row starts on one
+    uint4* xq = reinterpret_cast<uint4*>(xl);
+    const int quads = words / 4;
+    for (int f = threadIdx.x; f < 256 * quads; f += 256) {
+        const int r = f / quads, qd = f - r * quads;
         const int64_t p = s_p[r];
-        if (p >= 0) xw[p * words + wd] = tile[r * stride + wd];
+        if (p >= 0) {
+            const uint32_t* t = tile + r * stride + 4 * qd;
+            xq[p * quads + qd] = make_uint4(t[0], t[1], t[2], t[3]);
+        }
     }
 }
 
