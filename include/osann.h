@@ -416,9 +416,9 @@ void os_ann_free(os_ann_index *idx);
 int os_ann_trim(void);
 
 /*
- * Device memory from the caller's allocator.  The north star of this library
- * has PyTorch supply device memory; the paper's problem statement (Section 2,
- * eq. (1)) puts no constraint on where the index lives.
+ * Device memory from the caller's allocator, so that a host framework such as
+ * PyTorch can supply the device memory; the paper's problem statement
+ * (Section 2, eq. (1)) puts no constraint on where the index lives.
  *
  * alloc(bytes, stream, ctx) must return a block of at least `bytes` bytes of
  * device memory on the current device, aligned to 256 bytes, usable by work

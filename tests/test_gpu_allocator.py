@@ -1,5 +1,5 @@
 """Device memory from the caller's allocator (os_ann_set_allocator) and the
-plain spec entry points os_ann_build / os_ann_search.
+plain entry points os_ann_build / os_ann_search.
 
 * Every block the library asks for comes from the hook and goes back to it:
   after os_ann_free nothing the hook handed out is still held.
@@ -56,7 +56,7 @@ def _search(h, Y, budget, mode=B.OS_ANN_MODE_FP32):
 
 
 def test_plain_build_and_search_match_oracle(orc):
-    # the spec signatures: os_ann_build(db, N, D, L) and
+    # the plain signatures: os_ann_build(db, N, D, L) and
     # os_ann_search(index, queries, Q, max_candidates, out_idx, out_dist)
     X = W.gaussian_db(40000, 32, seed=8101)
     Y = W.gaussian_queries(777, 32, seed=8102)
