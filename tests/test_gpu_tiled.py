@@ -315,6 +315,35 @@ def test_screen_kernels_agree(orc, monkeypatch, case):
         B.os_ann_free(h)
 
 
+@pytest.mark.parametrize("N", [400, 900, 1400])
+def test_cone_screen_short_tile_sequences(orc, monkeypatch, N):
+    # D = 16, L = 1: 32 cones in one 64-cone word, about 12, 28 or 44 rows
+    # each (1, 2 or 3 tiles of 16 rows), so with one or a few queries and
+    # small budgets a wave screens 1 to 9 tiles: every exit of the cone-major
+    # screen's rotation over three row-tile buffers is taken
+    R = 4
+    X = W.gaussian_db(N, 16, seed=2801 + N)
+    h = B.os_ann_build_ex(dev(X), 1)
+    try:
+        ix = orc.build_index(X, 1)
+        per = N // 32
+        for Q in (1, 3):
+            Y = W.gaussian_queries(Q, 16, seed=2811 + Q)
+            yd = dev(Y)
+            for budget in (1, per + 1, 2 * per + 1, 3 * per + 1):
+                monkeypatch.setenv("OSANN_TILED_KERNEL", "cone")
+                say(f"[tiled] short tile sequences N={N} Q={Q} budget={budget}")
+                i, d, n = B.os_ann_search_ex(h, yd, budget, mode=B.OS_ANN_MODE_TILED, rerank_r=R)
+                torch.cuda.synchronize()
+                assert B.os_ann_last_tiling(h)["kernel"] == 1, (N, Q, budget)  # the cone-major screen ran
+                monkeypatch.delenv("OSANN_TILED_KERNEL")
+                o = orc.search_tiled(X, ix, Y, budget, R=R)
+                check_screened(orc, X, Y, (i.cpu().numpy(), d.cpu().numpy(), n.cpu().numpy()), o,
+                               (N, Q, budget), is_candidate=candidates_of(orc, ix, Y, budget))
+    finally:
+        B.os_ann_free(h)
+
+
 @pytest.mark.parametrize("case", ["gauss64", "patch_f16"])
 def test_seed_does_not_change_results(orc, monkeypatch, case):
     # the seed pass only tightens the starting bounds (the class minima start
